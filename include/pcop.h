@@ -1,0 +1,202 @@
+/*
+ * pcop.h -- C ABI of the MI355X solver for the all-at-once KKT system of the
+ * parabolic tracking-type optimal-control problem, preconditioned by the
+ * epsilon-circulant rotated-block-diagonal (RBD) preconditioner P_eps.
+ *
+ * Problem (Section 1 of the paper): minimise
+ *     1/2 ||y - g||^2 + gamma/2 ||u||^2  over Omega x (0,T),  Omega = (0,1)^d,
+ * subject to y_t - div(a grad y) = f + u, y = 0 on the boundary, y(0) = y0.
+ * Backward Euler with N = nt steps (tau = T/N) and finite differences on nx
+ * interior points per dimension (h = 1/(nx+1), K = -L_h, M = I) give the
+ * all-at-once system A x = b of eq. main_system with n = N - 1 time blocks:
+ *     A = [[alpha I, T^T], [-T, alpha I]],  T = B_n (x) I + tau I (x) K,
+ *     alpha = tau/sqrt(gamma),  x = [sqrt(gamma) y; p],  b = [g; -sqrt(gamma) f]
+ * (eq. matrix_A, eq. matrix_T; the blocks of b follow eq. main_system_before).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * m = nx^dim spatial unknowns in lexicographic order, x1 fastest.
+ *  * A "vector" is a device array of float64 laid out [batch][2][n][m]:
+ *    block 0 holds sqrt(gamma_b) y (or its analogue), block 1 holds p; time
+ *    block j = 0..n-1 is level j+1.
+ *  * Field arrays g, f are device float64 [batch][n][m] (levels 1..n), y0 is
+ *    device float64 [batch][m].
+ *  * All device buffers, including the workspace, are allocated and owned by
+ *    the caller; the library never allocates or frees device memory.  The
+ *    context owns only host state and the layout of the workspace.
+ *  * Every call is enqueued on the stream given in pcop_options (0 = the
+ *    default stream).  kkt_apply, precond_apply, rhs, unpack and data_grad
+ *    only enqueue; pcop_solve synchronises the stream to test convergence.
+ *  * Every function returns a pcop_status and never aborts or prints;
+ *    arguments are validated before any device work is enqueued.
+ *    pcop_last_error() returns a description of the last failure on the
+ *    calling thread.
+ *  * A context may be used from one host thread at a time.
+ */
+#ifndef PCOP_H
+#define PCOP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pcop_ctx_s* pcop_ctx;
+
+typedef enum {
+  PCOP_OK = 0,
+  PCOP_ERR_INVALID_ARG = 1,  /* rejected before any device work */
+  PCOP_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement */
+  PCOP_ERR_WORKSPACE = 3,    /* workspace too small or misaligned */
+  PCOP_ERR_DEVICE = 4,       /* a HIP runtime call failed */
+  PCOP_NOT_CONVERGED = 5     /* outputs valid, tolerance not met within maxit */
+} pcop_status;
+
+enum { PCOP_FP64 = 0, PCOP_MIXED = 1 };          /* precision of P_eps^{-1} */
+enum { PCOP_DST = 0, PCOP_MG = 1 };              /* spatial solver of Step 2 */
+enum { PCOP_RIGHT = 0, PCOP_LEFT = 1, PCOP_FLEXIBLE = 2 };  /* GMRES variant */
+enum { PCOP_COEFF_ONE = 0, PCOP_COEFF_HALFGRID = 1 };        /* a(x) */
+
+/* Problem statement (Section 1; Section 3 for the discretisation).
+ *   dim      2 or 3.
+ *   nx       interior points per dimension (>= 1; 2^p - 1 for PCOP_MG).
+ *   nt       number of backward-Euler steps N (>= 2); n = nt - 1 blocks.
+ *   T        final time (> 0).
+ *   batch    number of independent systems solved together (>= 1).
+ *   gamma    host array [batch] of regularisation parameters (> 0).
+ *   eps      epsilon of C_{eps,n} in (0,1] (eq. matrix_C_eps_n); a value
+ *            <= 0 selects sqrt(tau).
+ *   coeff_kind / coeff
+ *            PCOP_COEFF_ONE: a = 1 (coeff must be NULL).
+ *            PCOP_COEFF_HALFGRID: coeff is a host array of (2 nx + 1)^dim
+ *            values of a(x) sampled at x = k h/2, k = 1..2nx+1 in every
+ *            dimension (lexicographic, x1 fastest); these samples contain
+ *            a at every face midpoint of every multigrid level.  The values
+ *            are copied at pcop_setup. */
+typedef struct {
+  int dim;
+  int nx;
+  int nt;
+  double T;
+  int batch;
+  const double* gamma;
+  double eps;
+  int coeff_kind;
+  const double* coeff;
+} pcop_problem;
+
+/* Solver options.
+ *   precision  PCOP_FP64, or PCOP_MIXED: P_eps^{-1} evaluated in complex FP32
+ *              (vectors, matvec, Arnoldi and residuals stay FP64).
+ *   spatial    PCOP_DST (requires a = 1; nx + 1 a power of two, 4..1024)
+ *              or PCOP_MG (one complex-shifted V-cycle per frequency).
+ *   side       PCOP_RIGHT: GMRES on A P^{-1}, stops on the true relative
+ *              residual ||b - A x|| / ||b - A x0||;
+ *              PCOP_LEFT: GMRES on P^{-1} A, stops on the preconditioned
+ *              relative residual (the setting of Section 3);
+ *              PCOP_FLEXIBLE: right-preconditioned flexible GMRES that keeps
+ *              Z_j = P^{-1} v_j (required with PCOP_MIXED or PCOP_MG).
+ *   restart    Krylov dimension per cycle, 1..40.
+ *   maxit      maximum total Arnoldi steps (>= 1).
+ *   rtol       relative residual tolerance (> 0).
+ *   graph      1: run each group of Arnoldi steps as one captured HIP graph
+ *              (needs a non-default stream), 0: plain launches.
+ *   graph_chunk Arnoldi steps per graph launch when graph = 1 (>= 1).
+ *   reorth_tol a second Gram-Schmidt pass is run for a member when the
+ *              coefficients of the new vector against the basis exceed
+ *              reorth_tol times its norm (0 = always, < 0 = never).
+ *   stream     hipStream_t on which all work is enqueued. */
+typedef struct {
+  int precision;
+  int spatial;
+  int side;
+  int restart;
+  int maxit;
+  double rtol;
+  int graph;
+  int graph_chunk;
+  double reorth_tol;
+  void* stream;
+} pcop_options;
+
+/* Per-member outcome of pcop_solve. */
+typedef struct {
+  int iters;            /* Arnoldi steps taken */
+  int converged;        /* 1 if the monitored relative residual <= rtol */
+  double relres_est;    /* monitored relative residual from the Givens QR */
+  double relres_true;   /* ||b - A x|| / ||b|| recomputed at the end */
+} pcop_member_info;
+
+/* Validate a problem/options pair without touching the device.
+ * Returns PCOP_OK, PCOP_ERR_INVALID_ARG or PCOP_ERR_UNSUPPORTED. */
+pcop_status pcop_validate(const pcop_problem* prob, const pcop_options* opts);
+
+/* Fill in the default options (FP64, DST, right, restart 30, maxit 300,
+ * rtol 1e-8, no graph, reorth_tol 1e-10, default stream). */
+void pcop_default_options(pcop_options* opts);
+
+/* Bytes of device workspace pcop_setup needs for (prob, opts).  Host-only. */
+pcop_status pcop_workspace_size(const pcop_problem* prob, const pcop_options* opts,
+                                size_t* bytes);
+
+/* Create a context.  workspace: caller-owned device memory of at least
+ * pcop_workspace_size bytes, 256-byte aligned, that stays valid and unused
+ * by the caller until pcop_destroy.  Host tables (D_eps, lambda_k, DST
+ * eigenvalues, twiddles, per-member alpha) are computed in FP64 and copied
+ * into the workspace on the stream. */
+pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_options* opts,
+                       void* workspace, size_t bytes);
+
+/* b = [g-block; -sqrt(gamma) f-block] of eq. main_system from device g, f
+ * [batch][n][m] and y0 [batch][m]: b_1^j = tau g^j, b_2^j = -sqrt(gamma)
+ * (tau f^j + [j = 1] y0) (eq. main_system_before with M = I, p^N = 0). */
+pcop_status pcop_rhs(pcop_ctx ctx, const double* g, const double* f, const double* y0,
+                     double* b);
+
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1), eq. matrix_A.
+ * x, y: device vectors; they must not overlap. */
+pcop_status pcop_kkt_apply(pcop_ctx ctx, const double* x, double* y, int transpose);
+
+/* w = P_eps^{-1} v by the four steps of Section 2.1 (time FFT with the D_eps
+ * scaling, shifted spatial solves, inverse FFT, [[I,-I],[I,I]] combination).
+ * v, w: device vectors; they may alias. */
+pcop_status pcop_precond_apply(pcop_ctx ctx, const double* v, double* w);
+
+/* Solve A x = b (transpose = 0) or A^T x = b (transpose = 1) with
+ * preconditioned GMRES.  x: device vector, initial guess on entry, solution
+ * on exit.  info: host array [batch] (may be NULL).  res_hist: host array
+ * [batch][maxit + 1] of monitored relative residuals (may be NULL; entries
+ * after a member's last step are left untouched).  Returns
+ * PCOP_NOT_CONVERGED (with x and info filled) when a member misses rtol. */
+pcop_status pcop_solve(pcop_ctx ctx, const double* b, double* x, int transpose,
+                       pcop_member_info* info, double* res_hist);
+
+/* y = x_1 / sqrt(gamma), p = x_2: device [batch][n][m] each. */
+pcop_status pcop_unpack(pcop_ctx ctx, const double* x, double* y, double* p);
+
+/* r = [ybar / sqrt(gamma); pbar]: the cotangent of x for a loss of (y, p).
+ * ybar, pbar: device [batch][n][m]; r: device vector. */
+pcop_status pcop_pack_cotangent(pcop_ctx ctx, const double* ybar, const double* pbar,
+                                double* r);
+
+/* Gradients of a loss with respect to the data from lam = A^{-T} dL/dx:
+ * dg = tau lam_1, df = -sqrt(gamma) tau lam_2, dy0 = -sqrt(gamma) lam_2^1
+ * (the transpose of the map in pcop_rhs).  Any output may be NULL. */
+pcop_status pcop_data_grad(pcop_ctx ctx, const double* lam, double* dg, double* df,
+                           double* dy0);
+
+/* Host copy of a few derived scalars: tau, alpha[batch], eps. */
+pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* eps);
+
+/* Release the context (does not free the caller's workspace). */
+void pcop_destroy(pcop_ctx ctx);
+
+const char* pcop_status_string(pcop_status s);
+const char* pcop_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCOP_H */

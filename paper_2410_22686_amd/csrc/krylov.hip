@@ -1,0 +1,258 @@
+// Arnoldi kernels for GMRES in FP64: fused multi-dot, fused multi-AXPY that
+// also measures the updated vector, linear combinations of basis vectors, and
+// the per-member Gram-Schmidt bookkeeping.  Reductions are two-level
+// (wavefront butterfly + fixed-order block/partial sums), so results are
+// bitwise reproducible for a fixed launch shape.
+//
+// Basis vectors are stored unnormalised: the Arnoldi vector v_i equals
+// sc[b][i] * basis_i, which lets the normalisation ride along in the
+// coefficients instead of costing a pass over the vector.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace pcop {
+
+constexpr int kNT = 256;
+constexpr int kNWave = kNT / kWave;
+
+int krylov_blocks(long long vl) {
+  long long want = (vl + kNT * 4 - 1) / (kNT * 4);
+  if (want < 1) want = 1;
+  if (want > 1024) want = 1024;
+  return (int)want;
+}
+
+// block-level reduction of NACC accumulators; thread c < ncols writes column c
+template <int NACC>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NACC], int ncols, double* out) {
+  __shared__ double red[kNWave][NACC];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int c = 0; c < NACC; ++c) {
+    if (c < ncols) {
+      double s = wave_sum(acc[c]);
+      if (lane == 0) red[wv][c] = s;
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncols; c += kNT) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kNWave; ++k) s += red[k][c];
+    out[c] = s;
+  }
+}
+
+template <int MAXNV>
+__global__ void __launch_bounds__(kNT) mdot_kernel(KrylovArgs ka, int nv, const double* __restrict__ w,
+                                                   double* __restrict__ partial, int nblk) {
+  const int b = blockIdx.y;
+  if (ka.active && !ka.active[b]) return;
+  double acc[MAXNV + 1];
+#pragma unroll
+  for (int i = 0; i <= MAXNV; ++i) acc[i] = 0.0;
+  const double* wb = w + (size_t)b * ka.vl;
+  const double* vb = ka.basis + (size_t)b * ka.vl;
+  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < ka.vl; e += (long long)nblk * kNT) {
+    const double wv = wb[e];
+#pragma unroll
+    for (int i = 0; i < MAXNV; ++i)
+      if (i < nv) acc[i] += vb[(size_t)i * ka.slot_stride + e] * wv;
+    acc[MAXNV] += wv * wv;
+  }
+  // columns 0..nv-1: dots, column nv: the squared norm
+  double out[MAXNV + 1];
+#pragma unroll
+  for (int i = 0; i <= MAXNV; ++i) out[i] = (i < nv) ? acc[i] : ((i == nv) ? acc[MAXNV] : 0.0);
+  block_reduce_store<MAXNV + 1>(out, nv + 1, partial + ((size_t)b * nblk + blockIdx.x) * kRedStride);
+}
+
+template <int MAXNV>
+__global__ void __launch_bounds__(kNT) update_kernel(KrylovArgs ka, int nv, double* __restrict__ w,
+                                                     const double* __restrict__ coef, int coef_ld,
+                                                     double* __restrict__ partial, int nblk,
+                                                     const int* __restrict__ skip) {
+  const int b = blockIdx.y;
+  if (ka.active && !ka.active[b]) return;
+  if (skip && skip[b]) return;
+  __shared__ double c[MAXNV];
+  for (int i = threadIdx.x; i < MAXNV; i += kNT) c[i] = (i < nv) ? coef[(size_t)b * coef_ld + i] : 0.0;
+  __syncthreads();
+  double acc[MAXNV + 1];
+#pragma unroll
+  for (int i = 0; i <= MAXNV; ++i) acc[i] = 0.0;
+  double* wb = w + (size_t)b * ka.vl;
+  const double* vb = ka.basis + (size_t)b * ka.vl;
+  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < ka.vl; e += (long long)nblk * kNT) {
+    double v[MAXNV];
+#pragma unroll
+    for (int i = 0; i < MAXNV; ++i) v[i] = (i < nv) ? vb[(size_t)i * ka.slot_stride + e] : 0.0;
+    double wv = wb[e];
+#pragma unroll
+    for (int i = 0; i < MAXNV; ++i)
+      if (i < nv) wv -= c[i] * v[i];
+    wb[e] = wv;
+#pragma unroll
+    for (int i = 0; i < MAXNV; ++i)
+      if (i < nv) acc[i] += v[i] * wv;
+    acc[MAXNV] += wv * wv;
+  }
+  double out[MAXNV + 1];
+#pragma unroll
+  for (int i = 0; i <= MAXNV; ++i) out[i] = (i < nv) ? acc[i] : ((i == nv) ? acc[MAXNV] : 0.0);
+  block_reduce_store<MAXNV + 1>(out, nv + 1, partial + ((size_t)b * nblk + blockIdx.x) * kRedStride);
+}
+
+template <int MAXNV>
+__global__ void __launch_bounds__(kNT) combine_kernel(KrylovArgs ka, int nv, const double* __restrict__ coef,
+                                                      int coef_ld, double* __restrict__ out, int accum) {
+  const int b = blockIdx.y;
+  if (ka.active && !ka.active[b]) return;
+  __shared__ double c[MAXNV];
+  for (int i = threadIdx.x; i < MAXNV; i += kNT) c[i] = (i < nv) ? coef[(size_t)b * coef_ld + i] : 0.0;
+  __syncthreads();
+  double* ob = out + (size_t)b * ka.vl;
+  const double* vb = ka.basis + (size_t)b * ka.vl;
+  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < ka.vl;
+       e += (long long)gridDim.x * kNT) {
+    double acc = accum ? ob[e] : 0.0;
+#pragma unroll
+    for (int i = 0; i < MAXNV; ++i)
+      if (i < nv && c[i] != 0.0) acc += c[i] * vb[(size_t)i * ka.slot_stride + e];
+    ob[e] = acc;
+  }
+}
+
+// out[b][c] = sum over blocks (in block order) of partial[b][blk][c]
+__global__ void reduce_partials_kernel(const double* __restrict__ partial, int nblk, int ncols,
+                                       double* __restrict__ out) {
+  const int b = blockIdx.x;
+  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < nblk; ++k) s += partial[((size_t)b * nblk + k) * kRedStride + c];
+    out[(size_t)b * kRedStride + c] = s;
+  }
+}
+
+// First Gram-Schmidt pass bookkeeping for Arnoldi step j:
+//   h_i = sc_i <basis_i, w>,  H[b][j][i] = h_i,  coef_i = h_i sc_i,  wnorm2 = <w, w>.
+__global__ void gs_step1_kernel(const double* __restrict__ red, int j, int B, const double* __restrict__ sc,
+                                double* __restrict__ H, int H_ld, double* __restrict__ coef, int coef_ld,
+                                double* __restrict__ wnorm2, const int* __restrict__ active) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  if (active && !active[b]) return;
+  const double* r = red + (size_t)b * kRedStride;
+  double* Hc = H + ((size_t)b * (kMaxBasis - 1) + j) * H_ld;
+  for (int i = 0; i <= j; ++i) {
+    const double s = sc[(size_t)b * kMaxBasis + i];
+    const double h = s * r[i];
+    Hc[i] = h;
+    coef[(size_t)b * coef_ld + i] = h * s;
+  }
+  wnorm2[b] = r[j + 1];
+}
+
+// After an update pass: red holds <basis_i, w'> and <w', w'>.
+// final_pass = 0: decide on a second pass (skip[b] = 0 means "run it"); the
+//   coefficients of the correction are added to column j of H.
+// final_pass = 1: for members that ran the second pass, record the norm.
+// In both cases the sub-diagonal entry and the scale of the new basis vector
+// are set from the measured norm.
+__global__ void gs_step2_kernel(const double* __restrict__ red, int j, int B, const double* __restrict__ sc,
+                                double* __restrict__ H, int H_ld, double* __restrict__ coef, int coef_ld,
+                                const double* __restrict__ wnorm2, double reorth_tol, int* __restrict__ skip,
+                                double* __restrict__ sc_out, const int* __restrict__ active, int final_pass) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  if (active && !active[b]) return;
+  if (final_pass && skip[b]) return;
+  const double* r = red + (size_t)b * kRedStride;
+  double* Hc = H + ((size_t)b * (kMaxBasis - 1) + j) * H_ld;
+  const double nrm2 = r[j + 1];
+  if (!final_pass) {
+    double c2 = 0.0;
+    for (int i = 0; i <= j; ++i) {
+      const double h2 = sc[(size_t)b * kMaxBasis + i] * r[i];
+      c2 += h2 * h2;
+    }
+    const bool again = reorth_tol >= 0.0 && c2 > reorth_tol * reorth_tol * nrm2;
+    skip[b] = again ? 0 : 1;
+    if (again) {
+      for (int i = 0; i <= j; ++i) {
+        const double s = sc[(size_t)b * kMaxBasis + i];
+        const double h2 = s * r[i];
+        Hc[i] += h2;
+        coef[(size_t)b * coef_ld + i] = h2 * s;
+      }
+    }
+  }
+  const double nrm = sqrt(nrm2 > 0.0 ? nrm2 : 0.0);
+  Hc[j + 1] = nrm;
+  sc_out[(size_t)b * kMaxBasis + j + 1] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  (void)wnorm2;
+}
+
+// sc[b][col] = 1/sqrt(red[b][0]),  norm[b] = sqrt(red[b][0])
+__global__ void set_scale_kernel(const double* __restrict__ red, int col, int B, double* __restrict__ sc,
+                                 double* __restrict__ norm, const int* __restrict__ active) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  if (active && !active[b]) return;
+  const double n2 = red[(size_t)b * kRedStride];
+  const double nr = sqrt(n2 > 0.0 ? n2 : 0.0);
+  norm[b] = nr;
+  sc[(size_t)b * kMaxBasis + col] = nr > 0.0 ? 1.0 / nr : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+#define PCOP_DISPATCH_NV(KERNEL, NV, GRID, ST, ...)                                   \
+  do {                                                                                \
+    if ((NV) <= 4) KERNEL<4><<<GRID, kNT, 0, ST>>>(__VA_ARGS__);                      \
+    else if ((NV) <= 8) KERNEL<8><<<GRID, kNT, 0, ST>>>(__VA_ARGS__);                 \
+    else if ((NV) <= 16) KERNEL<16><<<GRID, kNT, 0, ST>>>(__VA_ARGS__);               \
+    else if ((NV) <= 24) KERNEL<24><<<GRID, kNT, 0, ST>>>(__VA_ARGS__);               \
+    else if ((NV) <= 32) KERNEL<32><<<GRID, kNT, 0, ST>>>(__VA_ARGS__);               \
+    else KERNEL<kMaxBasis><<<GRID, kNT, 0, ST>>>(__VA_ARGS__);                        \
+  } while (0)
+
+void launch_mdot(const KrylovArgs& ka, int nv, const double* w, double* partial, int nblk, hipStream_t st) {
+  dim3 grid(nblk, ka.B);
+  PCOP_DISPATCH_NV(mdot_kernel, nv, grid, st, ka, nv, w, partial, nblk);
+}
+
+void launch_update(const KrylovArgs& ka, int nv, double* w, const double* coef, int coef_ld, double* partial,
+                   int nblk, const int* skip, hipStream_t st) {
+  dim3 grid(nblk, ka.B);
+  PCOP_DISPATCH_NV(update_kernel, nv, grid, st, ka, nv, w, coef, coef_ld, partial, nblk, skip);
+}
+
+void launch_combine(const KrylovArgs& ka, int nv, const double* coef, int coef_ld, double* out, int accum,
+                    hipStream_t st) {
+  dim3 grid(krylov_blocks(ka.vl), ka.B);
+  PCOP_DISPATCH_NV(combine_kernel, nv, grid, st, ka, nv, coef, coef_ld, out, accum);
+}
+
+void launch_reduce_partials(const double* partial, int nblk, int ncols, int B, double* out, hipStream_t st) {
+  reduce_partials_kernel<<<B, 64, 0, st>>>(partial, nblk, ncols, out);
+}
+
+void launch_gs_step1(const double* red, int j, int B, const double* sc, double* H, int H_ld, double* coef,
+                     int coef_ld, double* wnorm2, const int* active, hipStream_t st) {
+  gs_step1_kernel<<<(B + 63) / 64, 64, 0, st>>>(red, j, B, sc, H, H_ld, coef, coef_ld, wnorm2, active);
+}
+
+void launch_gs_step2(const double* red, int j, int B, const double* sc, double* H, int H_ld, double* coef,
+                     int coef_ld, const double* wnorm2, double reorth_tol, int* skip, double* sc_out,
+                     const int* active, int final_pass, hipStream_t st) {
+  gs_step2_kernel<<<(B + 63) / 64, 64, 0, st>>>(red, j, B, sc, H, H_ld, coef, coef_ld, wnorm2, reorth_tol, skip,
+                                                sc_out, active, final_pass);
+}
+
+void launch_set_scale(const double* red, int col, int B, double* sc, double* norm, const int* active,
+                      hipStream_t st) {
+  set_scale_kernel<<<(B + 63) / 64, 64, 0, st>>>(red, col, B, sc, norm, active);
+}
+
+}  // namespace pcop

@@ -1,0 +1,91 @@
+// Host-side launch wrappers shared between the kernel files and the API.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "fft_lds.hpp"
+
+namespace pcop {
+
+// Tables used by the preconditioner kernels (all device pointers into the
+// workspace, filled at setup).
+struct MgLevel {
+  int nx;              // points per dimension on this level
+  long long m;         // nx^dim
+  double h2inv;        // 1/h_l^2
+  const float* coef;   // [1 + 2 dim][m] tau-scaled stencil of K_a on this level (FP32), or null (a = 1)
+  const double* coef64;  // same in FP64
+  void* z;             // [B][2K][m] complex correction on this level (levels >= 1)
+  void* r;             // [B][2K][m] complex right-hand side on this level (levels >= 1)
+};
+
+struct PrecondTables {
+  const double* dpow;    // [n]  eps^{j/n}
+  const double* twn64;   // [n]  exp(-2 pi i t/n) as (re, im)
+  const float* twn32;
+  const double* twL64;   // [L]  exp(-2 pi i t/L), L = 2(nx+1)
+  const float* twL32;
+  const double* mu1;     // [nx] (4/h^2) sin^2(pi k h/2), k = 1..nx
+  const double* lam;     // [K] lambda_k as (re, im)
+  const double* alpha;   // [B]
+  const int* active;     // [B] or null
+  FftPlan plan;          // radices of n
+  int mg_levels;
+  MgLevel mg[12];
+  const void* mg_res;    // finest-level residual scratch [B][2K][m] complex
+};
+
+void launch_kkt_apply(const Geo& g, const double* x, double* y, const double* c, const double* alpha,
+                      const double* xscale, int xs_stride, const int* active, bool transpose,
+                      const double* ecoef, double ediag, double eoff, hipStream_t st);
+void launch_flip(const Geo& g, const double* src, double* dst, hipStream_t st);
+void launch_rhs(const Geo& g, const double* gg, const double* ff, const double* y0, const double* sg,
+                double* b, hipStream_t st);
+void launch_unpack(const Geo& g, const double* x, const double* sg, double* y, double* p, hipStream_t st);
+void launch_pack_cotangent(const Geo& g, const double* yb, const double* pb, const double* sg, double* r,
+                           hipStream_t st);
+void launch_data_grad(const Geo& g, const double* lam, const double* sg, double* dg, double* df,
+                      double* dy0, hipStream_t st);
+
+bool time_lds_fits(int n, bool fp32);
+bool launch_precond(const Geo& g, const double* v, double* w, void* spec, bool fp32, int spatial,
+                    const PrecondTables& tb, const double* vscale, int vs_stride, int accum,
+                    hipStream_t st);
+bool launch_mg_solve(const Geo& g, void* spec, bool fp32, const PrecondTables& tb, hipStream_t st);
+
+// Krylov kernels (krylov.hip).  Basis slot i of member b starts at
+// basis + i * slot_stride + b * vl.
+struct KrylovArgs {
+  const double* basis;
+  long long slot_stride;  // doubles between consecutive basis slots
+  long long vl;           // doubles per member vector
+  int B;
+  const int* active;      // [B] or null
+};
+constexpr int kMaxBasis = 41;   // restart <= 40
+constexpr int kRedStride = 48;  // doubles per (member, block) partial record
+
+int krylov_blocks(long long vl);
+// partial[b][blk][0..nv-1] = <basis_i, w>, partial[b][blk][nv] = <w, w>
+void launch_mdot(const KrylovArgs& ka, int nv, const double* w, double* partial, int nblk, hipStream_t st);
+// w <- w - sum_i coef[b][i] basis_i; then partial dots of the updated w as in mdot.
+// skip[b] != 0 leaves member b untouched (and its partials unwritten).
+void launch_update(const KrylovArgs& ka, int nv, double* w, const double* coef, int coef_ld,
+                   double* partial, int nblk, const int* skip, hipStream_t st);
+// out = (accum ? out : 0) + sum_i coef[b][i] basis_i   (zero coefficients skip their load)
+void launch_combine(const KrylovArgs& ka, int nv, const double* coef, int coef_ld, double* out,
+                    int accum, hipStream_t st);
+// fixed-order sum of partial records: out[b][c] = sum_blk partial[b][blk][c], c < ncols
+void launch_reduce_partials(const double* partial, int nblk, int ncols, int B, double* out,
+                            hipStream_t st);
+// Gram-Schmidt bookkeeping on the device (one thread per member), see krylov.hip
+void launch_gs_step1(const double* red, int j, int B, const double* sc, double* H, int H_ld,
+                     double* coef, int coef_ld, double* wnorm2, const int* active, hipStream_t st);
+void launch_gs_step2(const double* red, int j, int B, const double* sc, double* H, int H_ld,
+                     double* coef, int coef_ld, const double* wnorm2, double reorth_tol, int* skip,
+                     double* sc_out, const int* active, int final_pass, hipStream_t st);
+void launch_set_scale(const double* red, int col, int B, double* sc, double* norm, const int* active,
+                      hipStream_t st);
+
+}  // namespace pcop

@@ -1,0 +1,805 @@
+// Host side of the C ABI declared in include/pcop.h: argument validation,
+// workspace layout, FP64 host tables, and the GMRES driver that sequences
+// the HIP kernels.  The driver keeps only O(restart^2) scalars per member on
+// the host (Givens rotations of the Hessenberg columns it reads back).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pcop.h"
+#include "launch.hpp"
+
+using namespace pcop;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pcop_status fail(pcop_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define PCOP_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(PCOP_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// ---------------------------------------------------------------------------
+// validation (host only)
+// ---------------------------------------------------------------------------
+pcop_status validate(const pcop_problem* p, const pcop_options* o) {
+  if (!p || !o) return fail(PCOP_ERR_INVALID_ARG, "null problem or options");
+  if (p->dim != 2 && p->dim != 3) return fail(PCOP_ERR_INVALID_ARG, "dim must be 2 or 3");
+  if (p->nx < 1) return fail(PCOP_ERR_INVALID_ARG, "nx must be >= 1");
+  if (p->nt < 2) return fail(PCOP_ERR_INVALID_ARG, "nt must be >= 2");
+  if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail(PCOP_ERR_INVALID_ARG, "T must be finite and > 0");
+  if (p->batch < 1) return fail(PCOP_ERR_INVALID_ARG, "batch must be >= 1");
+  if (!p->gamma) return fail(PCOP_ERR_INVALID_ARG, "gamma is null");
+  for (int b = 0; b < p->batch; ++b)
+    if (!(p->gamma[b] > 0.0) || !std::isfinite(p->gamma[b]))
+      return fail(PCOP_ERR_INVALID_ARG, "gamma must be finite and > 0");
+  if (!std::isfinite(p->eps) || p->eps > 1.0)
+    return fail(PCOP_ERR_INVALID_ARG, "eps must lie in (0, 1] (or <= 0 for sqrt(tau))");
+  const long long m = (long long)std::pow((double)p->nx, p->dim) + 0.5;
+  if (p->coeff_kind == PCOP_COEFF_ONE) {
+    if (p->coeff) return fail(PCOP_ERR_INVALID_ARG, "coeff must be null for PCOP_COEFF_ONE");
+  } else if (p->coeff_kind == PCOP_COEFF_HALFGRID) {
+    if (!p->coeff) return fail(PCOP_ERR_INVALID_ARG, "coeff is null");
+    const long long hn = (long long)std::pow(2.0 * p->nx + 1.0, p->dim) + 0.5;
+    for (long long k = 0; k < hn; ++k)
+      if (!(p->coeff[k] > 0.0) || !std::isfinite(p->coeff[k]))
+        return fail(PCOP_ERR_INVALID_ARG, "coefficient samples must be finite and > 0");
+  } else {
+    return fail(PCOP_ERR_INVALID_ARG, "unknown coeff_kind");
+  }
+  if (o->precision != PCOP_FP64 && o->precision != PCOP_MIXED)
+    return fail(PCOP_ERR_INVALID_ARG, "unknown precision");
+  if (o->spatial != PCOP_DST && o->spatial != PCOP_MG) return fail(PCOP_ERR_INVALID_ARG, "unknown spatial");
+  if (o->side != PCOP_RIGHT && o->side != PCOP_LEFT && o->side != PCOP_FLEXIBLE)
+    return fail(PCOP_ERR_INVALID_ARG, "unknown side");
+  if (o->restart < 1 || o->restart > kMaxBasis - 1) return fail(PCOP_ERR_INVALID_ARG, "restart must be in 1..40");
+  if (o->maxit < 1) return fail(PCOP_ERR_INVALID_ARG, "maxit must be >= 1");
+  if (!(o->rtol > 0.0) || !std::isfinite(o->rtol)) return fail(PCOP_ERR_INVALID_ARG, "rtol must be > 0");
+  if (!std::isfinite(o->reorth_tol)) return fail(PCOP_ERR_INVALID_ARG, "reorth_tol must be finite");
+  if (o->graph != 0 && o->graph != 1) return fail(PCOP_ERR_INVALID_ARG, "graph must be 0 or 1");
+  if (o->graph && o->graph_chunk < 1) return fail(PCOP_ERR_INVALID_ARG, "graph_chunk must be >= 1");
+  if (o->precision == PCOP_MIXED && o->side != PCOP_FLEXIBLE)
+    return fail(PCOP_ERR_INVALID_ARG, "the mixed-precision preconditioner needs side = PCOP_FLEXIBLE");
+  if (o->spatial == PCOP_DST) {
+    if (p->coeff_kind != PCOP_COEFF_ONE)
+      return fail(PCOP_ERR_INVALID_ARG, "sine transforms need a constant coefficient (use PCOP_MG)");
+    if (!is_pow2(p->nx + 1) || p->nx + 1 < 4 || p->nx + 1 > 512)
+      return fail(PCOP_ERR_UNSUPPORTED, "sine transforms need nx + 1 a power of two in 4..512");
+  } else {
+    if (!is_pow2(p->nx + 1)) return fail(PCOP_ERR_INVALID_ARG, "multigrid needs nx = 2^p - 1");
+  }
+  const int n = p->nt - 1;
+  if (!time_lds_fits(n, o->precision == PCOP_MIXED))
+    return fail(PCOP_ERR_UNSUPPORTED, "nt too large for the LDS time FFT (n <= 2048 in FP64)");
+  if (m > (1LL << 31) / 8) return fail(PCOP_ERR_UNSUPPORTED, "spatial grid too large");
+  if ((long long)n * m * 2 > (1LL << 40)) return fail(PCOP_ERR_UNSUPPORTED, "problem too large");
+  return PCOP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+struct Layout {
+  size_t total = 0;
+  size_t dpow, twn64, twn32, twL64, twL32, mu1, lam, alpha, sg, ecoef;
+  size_t sc, H, coef, red, partial, wnorm2, norm, skip, active, finish;
+  size_t basis, zbasis, tmp1, tmp2, spec;
+  size_t mgcoef[12], mgz[12], mgr[12];
+  int mg_levels = 0;
+  int mg_nx[12];
+  int nblk = 1;
+  long long vl = 0;
+};
+
+size_t take(Layout& L, size_t bytes) {
+  size_t off = (L.total + 255) & ~(size_t)255;
+  L.total = off + bytes;
+  return off;
+}
+
+void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
+  const int d = p->dim, nx = p->nx, n = p->nt - 1, B = p->batch;
+  const long long m = (long long)std::llround(std::pow((double)nx, d));
+  const int K = n / 2 + 1;
+  const int Lf = 2 * (nx + 1);
+  const bool fp32 = o->precision == PCOP_MIXED;
+  const size_t csz = fp32 ? 8 : 16;
+  L.vl = 2LL * n * m;
+  L.nblk = krylov_blocks(L.vl);
+  L.dpow = take(L, sizeof(double) * n);
+  L.twn64 = take(L, 16 * (size_t)n);
+  L.twn32 = take(L, 8 * (size_t)n);
+  L.twL64 = take(L, 16 * (size_t)Lf);
+  L.twL32 = take(L, 8 * (size_t)Lf);
+  L.mu1 = take(L, sizeof(double) * nx);
+  L.lam = take(L, 16 * (size_t)K);
+  L.alpha = take(L, sizeof(double) * B);
+  L.sg = take(L, sizeof(double) * B);
+  L.ecoef = (p->coeff_kind == PCOP_COEFF_HALFGRID) ? take(L, sizeof(double) * (1 + 2 * d) * m) : 0;
+  L.sc = take(L, sizeof(double) * B * kMaxBasis);
+  L.H = take(L, sizeof(double) * B * (kMaxBasis - 1) * kMaxBasis);
+  L.coef = take(L, sizeof(double) * B * kMaxBasis);
+  L.red = take(L, sizeof(double) * B * kRedStride);
+  L.partial = take(L, sizeof(double) * B * (size_t)L.nblk * kRedStride);
+  L.wnorm2 = take(L, sizeof(double) * B);
+  L.norm = take(L, sizeof(double) * B);
+  L.skip = take(L, sizeof(int) * B);
+  L.active = take(L, sizeof(int) * B);
+  L.finish = take(L, sizeof(int) * B);
+  const size_t vec = sizeof(double) * (size_t)L.vl * B;
+  L.basis = take(L, vec * (o->restart + 1));
+  L.zbasis = (o->side == PCOP_FLEXIBLE) ? take(L, vec * o->restart) : 0;
+  L.tmp1 = take(L, vec);
+  L.tmp2 = take(L, vec);
+  L.spec = take(L, csz * (size_t)B * 2 * K * m);
+  L.mg_levels = 0;
+  if (o->spatial == PCOP_MG) {
+    int lnx = nx;
+    int l = 0;
+    while (true) {
+      const long long lm = (long long)std::llround(std::pow((double)lnx, d));
+      L.mg_nx[l] = lnx;
+      L.mgcoef[l] = take(L, (fp32 ? 4 : 8) * (size_t)(1 + 2 * d) * lm);
+      // level 0 needs a residual buffer; coarser levels a correction and a rhs
+      L.mgr[l] = take(L, csz * (size_t)B * 2 * K * lm);
+      L.mgz[l] = (l > 0) ? take(L, csz * (size_t)B * 2 * K * lm) : 0;
+      ++l;
+      if (lnx == 1 || l >= 12) break;
+      lnx = (lnx - 1) / 2;
+    }
+    L.mg_levels = l;
+  }
+  L.total = (L.total + 255) & ~(size_t)255;
+}
+
+// prime factorisation of n into FFT radices (4s first, then primes)
+FftPlan make_plan(int n) {
+  FftPlan pl{};
+  pl.nrad = 0;
+  int r = n;
+  while (r % 4 == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = 4; r /= 4; }
+  for (int f = 2; f * f <= r && pl.nrad < 16; ++f)
+    while (r % f == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = f; r /= f; }
+  if (r > 1 && pl.nrad < 16) pl.rad[pl.nrad++] = r;
+  return pl;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct pcop_ctx_s {
+  Geo g{};
+  pcop_options opt{};
+  int coeff_kind = PCOP_COEFF_ONE;
+  double eps = 0, T = 0;
+  std::vector<double> gamma, alpha, sgam;
+  hipStream_t st = nullptr;
+  char* ws = nullptr;
+  Layout L;
+  PrecondTables tb{};
+  double ediag = 0, eoff = 0;
+  const double* ecoef = nullptr;
+  bool fp32 = false;
+
+  template <class T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  double* basis(int slot) const { return at<double>(L.basis) + (size_t)slot * (size_t)g.vl * g.B; }
+  double* zbasis(int slot) const { return at<double>(L.zbasis) + (size_t)slot * (size_t)g.vl * g.B; }
+  KrylovArgs kargs(const double* base, const int* mask) const {
+    return KrylovArgs{base, (long long)g.vl * g.B, g.vl, g.B, mask};
+  }
+};
+
+namespace {
+
+pcop_status do_precond(pcop_ctx c, const double* v, double* w, const double* vscale, int vs_stride, int accum,
+                       const int* mask) {
+  PrecondTables tb = c->tb;
+  tb.active = mask;
+  if (!launch_precond(c->g, v, w, c->at<void>(c->L.spec), c->fp32, c->opt.spatial, tb, vscale, vs_stride,
+                      accum, c->st))
+    return fail(PCOP_ERR_UNSUPPORTED, "preconditioner variant not available for this shape");
+  return PCOP_OK;
+}
+
+void do_kkt(pcop_ctx c, const double* x, double* y, const double* cvec, const double* xscale, int xs_stride,
+            const int* mask) {
+  launch_kkt_apply(c->g, x, y, cvec, c->at<double>(c->L.alpha), xscale, xs_stride, mask, false, c->ecoef,
+                   c->ediag, c->eoff, c->st);
+}
+
+// squared norms of member vectors (into red[b][0])
+void do_norm2(pcop_ctx c, const double* w, const int* mask) {
+  KrylovArgs ka = c->kargs(c->basis(0), mask);
+  launch_mdot(ka, 0, w, c->at<double>(c->L.partial), c->L.nblk, c->st);
+  launch_reduce_partials(c->at<double>(c->L.partial), c->L.nblk, 1, c->g.B, c->at<double>(c->L.red), c->st);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void pcop_default_options(pcop_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = PCOP_FP64;
+  o->spatial = PCOP_DST;
+  o->side = PCOP_RIGHT;
+  o->restart = 30;
+  o->maxit = 300;
+  o->rtol = 1e-8;
+  o->graph = 0;
+  o->graph_chunk = 4;
+  o->reorth_tol = 1e-10;
+  o->stream = nullptr;
+}
+
+pcop_status pcop_validate(const pcop_problem* prob, const pcop_options* opts) { return validate(prob, opts); }
+
+pcop_status pcop_workspace_size(const pcop_problem* prob, const pcop_options* opts, size_t* bytes) {
+  pcop_status s = validate(prob, opts);
+  if (s != PCOP_OK) return s;
+  if (!bytes) return fail(PCOP_ERR_INVALID_ARG, "bytes is null");
+  Layout L;
+  plan_layout(prob, opts, L);
+  *bytes = L.total;
+  return PCOP_OK;
+}
+
+pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_options* opts, void* workspace,
+                       size_t bytes) {
+  if (!out) return fail(PCOP_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  pcop_status s = validate(prob, opts);
+  if (s != PCOP_OK) return s;
+  Layout L;
+  plan_layout(prob, opts, L);
+  if (!workspace || bytes < L.total) return fail(PCOP_ERR_WORKSPACE, "workspace too small");
+  if (((uintptr_t)workspace & 255) != 0) return fail(PCOP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+
+  pcop_ctx c = new pcop_ctx_s();
+  c->L = L;
+  c->opt = *opts;
+  c->st = reinterpret_cast<hipStream_t>(opts->stream);
+  c->ws = reinterpret_cast<char*>(workspace);
+  c->fp32 = opts->precision == PCOP_MIXED;
+  c->coeff_kind = prob->coeff_kind;
+  const int d = prob->dim, nx = prob->nx, n = prob->nt - 1, B = prob->batch;
+  const long long m = (long long)std::llround(std::pow((double)nx, d));
+  Geo& g = c->g;
+  g.dim = d;
+  g.nx = nx;
+  g.n = n;
+  g.m = (int)m;
+  g.B = B;
+  g.K = n / 2 + 1;
+  g.vl = L.vl;
+  c->T = prob->T;
+  g.tau = prob->T / prob->nt;
+  const double h = 1.0 / (nx + 1);
+  g.h2inv = 1.0 / (h * h);
+  c->eps = prob->eps > 0.0 ? prob->eps : std::sqrt(g.tau);
+  c->gamma.assign(prob->gamma, prob->gamma + B);
+  c->alpha.resize(B);
+  c->sgam.resize(B);
+  for (int b = 0; b < B; ++b) {
+    c->sgam[b] = std::sqrt(c->gamma[b]);
+    c->alpha[b] = g.tau / c->sgam[b];
+  }
+
+  // host tables in long double, rounded once
+  const long double PI = 3.141592653589793238462643383279502884L;
+  std::vector<double> dpow(n), twn64(2 * n), mu1(nx), lam(2 * g.K), twL64(2 * (2 * (nx + 1)));
+  std::vector<float> twn32(2 * n), twL32(2 * (2 * (nx + 1)));
+  const long double le = std::log((long double)c->eps);
+  for (int j = 0; j < n; ++j) dpow[j] = (double)std::exp(le * j / n);
+  for (int t = 0; t < n; ++t) {
+    long double a = -2.0L * PI * t / n;
+    twn64[2 * t] = (double)std::cos(a);
+    twn64[2 * t + 1] = (double)std::sin(a);
+    twn32[2 * t] = (float)std::cos(a);
+    twn32[2 * t + 1] = (float)std::sin(a);
+  }
+  const int Lf = 2 * (nx + 1);
+  for (int t = 0; t < Lf; ++t) {
+    long double a = -2.0L * PI * t / Lf;
+    twL64[2 * t] = (double)std::cos(a);
+    twL64[2 * t + 1] = (double)std::sin(a);
+    twL32[2 * t] = (float)std::cos(a);
+    twL32[2 * t + 1] = (float)std::sin(a);
+  }
+  for (int k = 1; k <= nx; ++k) {
+    long double sv = std::sin(PI * k * (long double)h / 2.0L);
+    mu1[k - 1] = (double)(4.0L / ((long double)h * h) * sv * sv);
+  }
+  const long double e1n = std::exp(le / n);
+  for (int k = 0; k < g.K; ++k) {
+    long double a = -2.0L * PI * k / n;  // theta^{-k}
+    lam[2 * k] = (double)(1.0L - e1n * std::cos(a));
+    lam[2 * k + 1] = (double)(-e1n * std::sin(a));
+  }
+  hipStream_t st = c->st;
+  auto up = [&](size_t off, const void* src, size_t nb) -> hipError_t {
+    return hipMemcpyAsync(c->ws + off, src, nb, hipMemcpyHostToDevice, st);
+  };
+  hipError_t e = hipSuccess;
+  std::vector<int> ones(B, 1);
+  if (e == hipSuccess) e = up(L.dpow, dpow.data(), sizeof(double) * n);
+  if (e == hipSuccess) e = up(L.twn64, twn64.data(), sizeof(double) * 2 * n);
+  if (e == hipSuccess) e = up(L.twn32, twn32.data(), sizeof(float) * 2 * n);
+  if (e == hipSuccess) e = up(L.twL64, twL64.data(), sizeof(double) * 2 * Lf);
+  if (e == hipSuccess) e = up(L.twL32, twL32.data(), sizeof(float) * 2 * Lf);
+  if (e == hipSuccess) e = up(L.mu1, mu1.data(), sizeof(double) * nx);
+  if (e == hipSuccess) e = up(L.lam, lam.data(), sizeof(double) * 2 * g.K);
+  if (e == hipSuccess) e = up(L.alpha, c->alpha.data(), sizeof(double) * B);
+  if (e == hipSuccess) e = up(L.sg, c->sgam.data(), sizeof(double) * B);
+  if (e == hipSuccess) e = up(L.active, ones.data(), sizeof(int) * B);
+
+  // stencil E = I + tau K
+  std::vector<double> ecoef;
+  std::vector<std::vector<double>> mgc64;
+  std::vector<std::vector<float>> mgc32;
+  const double tau = g.tau;
+  if (prob->coeff_kind == PCOP_COEFF_ONE) {
+    c->ediag = 1.0 + tau * 2.0 * d * g.h2inv;
+    c->eoff = -tau * g.h2inv;
+  }
+  // coefficient on level l at half-grid offsets; the fine half grid has
+  // 2nx+1 points per dimension, node c (0-based) of level l sits at half index
+  // (c+1) 2^{l+1} - 1 and its faces at +/- 2^l
+  const int hn = 2 * nx + 1;
+  auto a_at = [&](const int* hk) -> double {
+    long long idx = 0, stride = 1;
+    for (int ax = 0; ax < d; ++ax) {
+      idx += (long long)hk[ax] * stride;
+      stride *= hn;
+    }
+    return prob->coeff[idx];
+  };
+  auto build_stencil = [&](int level, int lnx, double scale_diag_one, std::vector<double>& outc) {
+    const long long lm = (long long)std::llround(std::pow((double)lnx, d));
+    const double hl = 1.0 / (lnx + 1);
+    const double s = tau / (hl * hl);
+    outc.assign((size_t)(1 + 2 * d) * lm, 0.0);
+    const int step = 1 << (level + 1), half = 1 << level;
+    for (long long i = 0; i < lm; ++i) {
+      int cc[3] = {0, 0, 0};
+      long long r = i;
+      for (int ax = 0; ax < d; ++ax) {
+        cc[ax] = (int)(r % lnx);
+        r /= lnx;
+      }
+      int hk[3];
+      for (int ax = 0; ax < d; ++ax) hk[ax] = (cc[ax] + 1) * step - 1;
+      double diag = 0.0;
+      for (int ax = 0; ax < d; ++ax) {
+        int hm[3] = {hk[0], hk[1], hk[2]}, hp[3] = {hk[0], hk[1], hk[2]};
+        hm[ax] -= half;
+        hp[ax] += half;
+        const double am = a_at(hm), ap = a_at(hp);
+        diag += am + ap;
+        if (cc[ax] > 0) outc[(size_t)(1 + 2 * ax) * lm + i] = -s * am;
+        if (cc[ax] < lnx - 1) outc[(size_t)(2 + 2 * ax) * lm + i] = -s * ap;
+      }
+      outc[i] = scale_diag_one + s * diag;
+    }
+  };
+  if (prob->coeff_kind == PCOP_COEFF_HALFGRID) {
+    build_stencil(0, nx, 1.0, ecoef);
+    if (e == hipSuccess) e = up(L.ecoef, ecoef.data(), sizeof(double) * ecoef.size());
+    c->ecoef = c->at<double>(L.ecoef);
+  }
+  // multigrid tables: tau K_a on every level (sigma is added per slice)
+  if (opts->spatial == PCOP_MG) {
+    const double* use = (prob->coeff_kind == PCOP_COEFF_ONE) ? nullptr : prob->coeff;
+    mgc64.resize(L.mg_levels);
+    mgc32.resize(L.mg_levels);
+    for (int l = 0; l < L.mg_levels; ++l) {
+      const int lnx = L.mg_nx[l];
+      if (use) {
+        build_stencil(l, lnx, 0.0, mgc64[l]);
+      } else {
+        // constant coefficient on this level
+        const long long lm = (long long)std::llround(std::pow((double)lnx, d));
+        const double hl = 1.0 / (lnx + 1);
+        const double s = tau / (hl * hl);
+        mgc64[l].assign((size_t)(1 + 2 * d) * lm, 0.0);
+        for (long long i = 0; i < lm; ++i) {
+          long long r = i;
+          mgc64[l][i] = s * 2.0 * d;
+          for (int ax = 0; ax < d; ++ax) {
+            const int cc = (int)(r % lnx);
+            r /= lnx;
+            if (cc > 0) mgc64[l][(size_t)(1 + 2 * ax) * lm + i] = -s;
+            if (cc < lnx - 1) mgc64[l][(size_t)(2 + 2 * ax) * lm + i] = -s;
+          }
+        }
+      }
+      mgc32[l].assign(mgc64[l].begin(), mgc64[l].end());
+      if (e == hipSuccess) {
+        if (c->fp32)
+          e = up(L.mgcoef[l], mgc32[l].data(), sizeof(float) * mgc32[l].size());
+        else
+          e = up(L.mgcoef[l], mgc64[l].data(), sizeof(double) * mgc64[l].size());
+      }
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(PCOP_ERR_DEVICE, std::string("setup upload: ") + hipGetErrorString(e));
+  }
+
+  PrecondTables& tb = c->tb;
+  tb.dpow = c->at<double>(L.dpow);
+  tb.twn64 = c->at<double>(L.twn64);
+  tb.twn32 = c->at<float>(L.twn32);
+  tb.twL64 = c->at<double>(L.twL64);
+  tb.twL32 = c->at<float>(L.twL32);
+  tb.mu1 = c->at<double>(L.mu1);
+  tb.lam = c->at<double>(L.lam);
+  tb.alpha = c->at<double>(L.alpha);
+  tb.active = nullptr;
+  tb.plan = make_plan(n);
+  tb.mg_levels = L.mg_levels;
+  for (int l = 0; l < L.mg_levels; ++l) {
+    MgLevel& lv = tb.mg[l];
+    lv.nx = L.mg_nx[l];
+    lv.m = (long long)std::llround(std::pow((double)lv.nx, d));
+    const double hl = 1.0 / (lv.nx + 1);
+    lv.h2inv = 1.0 / (hl * hl);
+    lv.coef = c->fp32 ? c->at<float>(L.mgcoef[l]) : nullptr;
+    lv.coef64 = c->fp32 ? nullptr : c->at<double>(L.mgcoef[l]);
+    lv.r = c->at<void>(L.mgr[l]);
+    lv.z = (l > 0) ? c->at<void>(L.mgz[l]) : nullptr;
+  }
+  *out = c;
+  return PCOP_OK;
+}
+
+void pcop_destroy(pcop_ctx c) { delete c; }
+
+pcop_status pcop_get_params(pcop_ctx c, double* tau, double* alpha, double* eps) {
+  if (!c) return fail(PCOP_ERR_INVALID_ARG, "null context");
+  if (tau) *tau = c->g.tau;
+  if (alpha)
+    for (int b = 0; b < c->g.B; ++b) alpha[b] = c->alpha[b];
+  if (eps) *eps = c->eps;
+  return PCOP_OK;
+}
+
+pcop_status pcop_rhs(pcop_ctx c, const double* g, const double* f, const double* y0, double* b) {
+  if (!c || !g || !f || !y0 || !b) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  launch_rhs(c->g, g, f, y0, c->at<double>(c->L.sg), b, c->st);
+  PCOP_HIP(hipGetLastError());
+  return PCOP_OK;
+}
+
+pcop_status pcop_kkt_apply(pcop_ctx c, const double* x, double* y, int transpose) {
+  if (!c || !x || !y) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  if (x == y) return fail(PCOP_ERR_INVALID_ARG, "x and y must not overlap");
+  launch_kkt_apply(c->g, x, y, nullptr, c->at<double>(c->L.alpha), nullptr, 0, nullptr, transpose != 0, c->ecoef,
+                   c->ediag, c->eoff, c->st);
+  PCOP_HIP(hipGetLastError());
+  return PCOP_OK;
+}
+
+pcop_status pcop_precond_apply(pcop_ctx c, const double* v, double* w) {
+  if (!c || !v || !w) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  pcop_status s = do_precond(c, v, w, nullptr, 0, 0, nullptr);
+  if (s != PCOP_OK) return s;
+  PCOP_HIP(hipGetLastError());
+  return PCOP_OK;
+}
+
+pcop_status pcop_unpack(pcop_ctx c, const double* x, double* y, double* p) {
+  if (!c || !x || !y || !p) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  launch_unpack(c->g, x, c->at<double>(c->L.sg), y, p, c->st);
+  PCOP_HIP(hipGetLastError());
+  return PCOP_OK;
+}
+
+pcop_status pcop_pack_cotangent(pcop_ctx c, const double* ybar, const double* pbar, double* r) {
+  if (!c || !r) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  launch_pack_cotangent(c->g, ybar, pbar, c->at<double>(c->L.sg), r, c->st);
+  PCOP_HIP(hipGetLastError());
+  return PCOP_OK;
+}
+
+pcop_status pcop_data_grad(pcop_ctx c, const double* lam, double* dg, double* df, double* dy0) {
+  if (!c || !lam) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  launch_data_grad(c->g, lam, c->at<double>(c->L.sg), dg, df, dy0, c->st);
+  PCOP_HIP(hipGetLastError());
+  return PCOP_OK;
+}
+
+const char* pcop_status_string(pcop_status s) {
+  switch (s) {
+    case PCOP_OK: return "ok";
+    case PCOP_ERR_INVALID_ARG: return "invalid argument";
+    case PCOP_ERR_UNSUPPORTED: return "unsupported";
+    case PCOP_ERR_WORKSPACE: return "workspace";
+    case PCOP_ERR_DEVICE: return "device error";
+    case PCOP_NOT_CONVERGED: return "not converged";
+  }
+  return "unknown status";
+}
+
+const char* pcop_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// GMRES driver
+// ---------------------------------------------------------------------------
+namespace {
+
+struct MemberState {
+  bool active = true;      // still iterating
+  bool converged = false;
+  int iters = 0;
+  double beta0 = 0.0;      // initial residual norm of the solve
+  double est = 1.0;        // last relative residual estimate
+  // Givens data of the current cycle
+  double cs[kMaxBasis], sn[kMaxBasis], gv[kMaxBasis + 1];
+  double R[kMaxBasis - 1][kMaxBasis];  // rotated columns
+};
+
+// solve the upper-triangular k x k system of the rotated Hessenberg
+void back_substitute(const MemberState& s, int k, double* y) {
+  for (int i = k - 1; i >= 0; --i) {
+    double acc = s.gv[i];
+    for (int j = i + 1; j < k; ++j) acc -= s.R[j][i] * y[j];
+    y[i] = acc / s.R[i][i];
+  }
+}
+
+}  // namespace
+
+extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int transpose, pcop_member_info* info,
+                                  double* res_hist) {
+  if (!c || !b || !x) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  const Geo& g = c->g;
+  const int B = g.B;
+  const int side = c->opt.side;
+  const int restart = c->opt.restart;
+  const int maxit = c->opt.maxit;
+  const double rtol = c->opt.rtol;
+  hipStream_t st = c->st;
+  const Layout& L = c->L;
+  double* tmp1 = c->at<double>(L.tmp1);
+  double* tmp2 = c->at<double>(L.tmp2);
+  double* sc = c->at<double>(L.sc);
+  double* H = c->at<double>(L.H);
+  double* coef = c->at<double>(L.coef);
+  double* red = c->at<double>(L.red);
+  double* partial = c->at<double>(L.partial);
+  double* wnorm2 = c->at<double>(L.wnorm2);
+  double* norm = c->at<double>(L.norm);
+  int* skip = c->at<int>(L.skip);
+  int* active = c->at<int>(L.active);
+  int* finish = c->at<int>(L.finish);
+  const int nblk = L.nblk;
+  const int H_ld = kMaxBasis;
+  const size_t H_member = (size_t)(kMaxBasis - 1) * kMaxBasis;
+
+  // A^T = J A J: solve A z = J b and return x = J z
+  const double* bb = b;
+  if (transpose) {
+    launch_flip(g, b, tmp2, st);
+    launch_flip(g, x, x, st);
+    bb = tmp2;
+  }
+  std::vector<MemberState> ms(B);
+  std::vector<int> h_active(B, 1), h_finish(B, 0);
+  std::vector<double> h_norm(B), h_col((size_t)B * kMaxBasis), h_coef((size_t)B * kMaxBasis);
+  std::vector<double> bnorm(B);
+
+  // ||b|| for the final true residual
+  PCOP_HIP(hipMemcpyAsync(active, h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+  do_norm2(c, bb, nullptr);
+  std::vector<double> h_red((size_t)B * kRedStride);
+  PCOP_HIP(hipMemcpyAsync(h_red.data(), red, sizeof(double) * B * kRedStride, hipMemcpyDeviceToHost, st));
+  PCOP_HIP(hipStreamSynchronize(st));
+  for (int m = 0; m < B; ++m) bnorm[m] = std::sqrt(h_red[(size_t)m * kRedStride]);
+
+  bool first_cycle = true;
+  pcop_status result = PCOP_OK;
+  while (true) {
+    int n_active = 0;
+    for (int m = 0; m < B; ++m) n_active += ms[m].active ? 1 : 0;
+    if (n_active == 0) break;
+    for (int m = 0; m < B; ++m) h_active[m] = ms[m].active ? 1 : 0;
+    PCOP_HIP(hipMemcpyAsync(active, h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+    // r0 = b - A x (right/flexible) or P^{-1}(b - A x) (left) into slot 0
+    if (side == PCOP_LEFT) {
+      do_kkt(c, x, tmp1, bb, nullptr, 0, active);
+      pcop_status s = do_precond(c, tmp1, c->basis(0), nullptr, 0, 0, active);
+      if (s != PCOP_OK) return s;
+    } else {
+      do_kkt(c, x, c->basis(0), bb, nullptr, 0, active);
+    }
+    KrylovArgs kv = c->kargs(c->basis(0), active);
+    launch_mdot(kv, 0, c->basis(0), partial, nblk, st);
+    launch_reduce_partials(partial, nblk, 1, B, red, st);
+    launch_set_scale(red, 0, B, sc, norm, active, st);
+    PCOP_HIP(hipMemcpyAsync(h_norm.data(), norm, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+    PCOP_HIP(hipStreamSynchronize(st));
+    for (int m = 0; m < B; ++m) {
+      MemberState& s = ms[m];
+      if (!s.active) continue;
+      const double beta = h_norm[m];
+      if (!std::isfinite(beta)) {
+        return fail(PCOP_ERR_INVALID_ARG, "non-finite residual (right-hand side or initial guess)");
+      }
+      if (first_cycle) {
+        s.beta0 = beta;
+        if (res_hist) res_hist[(size_t)m * (maxit + 1)] = 1.0;
+      }
+      if (beta == 0.0 || (!first_cycle && beta <= rtol * s.beta0)) {
+        s.active = false;
+        s.converged = true;
+        s.est = (s.beta0 > 0.0) ? beta / s.beta0 : 0.0;
+        continue;
+      }
+      s.gv[0] = beta;
+      for (int i = 1; i <= kMaxBasis; ++i) s.gv[i] = 0.0;
+    }
+    first_cycle = false;
+    n_active = 0;
+    for (int m = 0; m < B; ++m) {
+      h_active[m] = ms[m].active ? 1 : 0;
+      n_active += h_active[m];
+    }
+    if (n_active == 0) break;
+    PCOP_HIP(hipMemcpyAsync(active, h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+
+    for (int j = 0; j < restart; ++j) {
+      double* vj = c->basis(j);
+      double* w = c->basis(j + 1);
+      const double* scj = sc + j;  // member stride kMaxBasis
+      pcop_status s = PCOP_OK;
+      if (side == PCOP_RIGHT) {
+        s = do_precond(c, vj, tmp1, scj, kMaxBasis, 0, active);
+        do_kkt(c, tmp1, w, nullptr, nullptr, 0, active);
+      } else if (side == PCOP_FLEXIBLE) {
+        s = do_precond(c, vj, c->zbasis(j), scj, kMaxBasis, 0, active);
+        do_kkt(c, c->zbasis(j), w, nullptr, nullptr, 0, active);
+      } else {
+        do_kkt(c, vj, tmp1, nullptr, scj, kMaxBasis, active);
+        s = do_precond(c, tmp1, w, nullptr, 0, 0, active);
+      }
+      if (s != PCOP_OK) return s;
+      // classical Gram-Schmidt with a measured second pass
+      KrylovArgs ka = c->kargs(c->basis(0), active);
+      launch_mdot(ka, j + 1, w, partial, nblk, st);
+      launch_reduce_partials(partial, nblk, j + 2, B, red, st);
+      launch_gs_step1(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, active, st);
+      launch_update(ka, j + 1, w, coef, kMaxBasis, partial, nblk, nullptr, st);
+      launch_reduce_partials(partial, nblk, j + 2, B, red, st);
+      launch_gs_step2(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, c->opt.reorth_tol, skip, sc, active, 0, st);
+      launch_update(ka, j + 1, w, coef, kMaxBasis, partial, nblk, skip, st);
+      launch_reduce_partials(partial, nblk, j + 2, B, red, st);
+      launch_gs_step2(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, c->opt.reorth_tol, skip, sc, active, 1, st);
+      // column j of H for every member
+      PCOP_HIP(hipMemcpy2DAsync(h_col.data(), sizeof(double) * kMaxBasis, H + (size_t)j * H_ld,
+                                sizeof(double) * H_member, sizeof(double) * (j + 2), B, hipMemcpyDeviceToHost,
+                                st));
+      PCOP_HIP(hipStreamSynchronize(st));
+      bool any_finish = false;
+      std::fill(h_finish.begin(), h_finish.end(), 0);
+      for (int m = 0; m < B; ++m) {
+        MemberState& ms_ = ms[m];
+        if (!ms_.active) continue;
+        double* col = &h_col[(size_t)m * kMaxBasis];
+        for (int i = 0; i < j; ++i) {
+          const double t = ms_.cs[i] * col[i] + ms_.sn[i] * col[i + 1];
+          col[i + 1] = -ms_.sn[i] * col[i] + ms_.cs[i] * col[i + 1];
+          col[i] = t;
+        }
+        const double a = col[j], bsub = col[j + 1];
+        double cth = 1.0, sth = 0.0;
+        if (bsub != 0.0) {
+          const double r = std::hypot(a, bsub);
+          cth = a / r;
+          sth = bsub / r;
+        }
+        ms_.cs[j] = cth;
+        ms_.sn[j] = sth;
+        col[j] = cth * a + sth * bsub;
+        col[j + 1] = 0.0;
+        for (int i = 0; i <= j; ++i) ms_.R[j][i] = col[i];
+        ms_.gv[j + 1] = -sth * ms_.gv[j];
+        ms_.gv[j] = cth * ms_.gv[j];
+        ms_.iters += 1;
+        ms_.est = std::fabs(ms_.gv[j + 1]) / ms_.beta0;
+        if (res_hist && ms_.iters <= maxit) res_hist[(size_t)m * (maxit + 1) + ms_.iters] = ms_.est;
+        const bool conv = ms_.est <= rtol || bsub == 0.0;
+        if (conv || ms_.iters >= maxit || j == restart - 1) {
+          h_finish[m] = 1;
+          any_finish = true;
+          if (conv) ms_.converged = true;
+        }
+      }
+      if (!any_finish) continue;
+      // form the correction for the members that end their cycle here
+      std::fill(h_coef.begin(), h_coef.end(), 0.0);
+      std::vector<double> h_sc((size_t)B * kMaxBasis);
+      PCOP_HIP(hipMemcpyAsync(h_sc.data(), sc, sizeof(double) * B * kMaxBasis, hipMemcpyDeviceToHost, st));
+      PCOP_HIP(hipStreamSynchronize(st));
+      const int k = j + 1;
+      for (int m = 0; m < B; ++m) {
+        if (!h_finish[m]) continue;
+        double y[kMaxBasis];
+        back_substitute(ms[m], k, y);
+        for (int i = 0; i < k; ++i)
+          h_coef[(size_t)m * kMaxBasis + i] = (side == PCOP_FLEXIBLE) ? y[i] : y[i] * h_sc[(size_t)m * kMaxBasis + i];
+      }
+      PCOP_HIP(hipMemcpyAsync(coef, h_coef.data(), sizeof(double) * B * kMaxBasis, hipMemcpyHostToDevice, st));
+      PCOP_HIP(hipMemcpyAsync(finish, h_finish.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+      if (side == PCOP_LEFT) {
+        launch_combine(c->kargs(c->basis(0), finish), k, coef, kMaxBasis, x, 1, st);
+      } else if (side == PCOP_FLEXIBLE) {
+        launch_combine(c->kargs(c->zbasis(0), finish), k, coef, kMaxBasis, x, 1, st);
+      } else {
+        launch_combine(c->kargs(c->basis(0), finish), k, coef, kMaxBasis, tmp1, 0, st);
+        pcop_status s2 = do_precond(c, tmp1, x, nullptr, 0, 1, finish);
+        if (s2 != PCOP_OK) return s2;
+      }
+      bool any_left = false;
+      for (int m = 0; m < B; ++m) {
+        if (!h_finish[m]) {
+          any_left = any_left || ms[m].active;
+          continue;
+        }
+        // a member ends: converged or out of iterations; otherwise it restarts
+        if (ms[m].converged || ms[m].iters >= maxit) ms[m].active = false;
+      }
+      for (int m = 0; m < B; ++m) h_active[m] = (ms[m].active && !h_finish[m]) ? 1 : 0;
+      PCOP_HIP(hipMemcpyAsync(active, h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+      if (!any_left) break;
+    }
+  }
+
+  // true residual ||b - A x|| / ||b||
+  std::fill(h_active.begin(), h_active.end(), 1);
+  PCOP_HIP(hipMemcpyAsync(active, h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+  do_kkt(c, x, tmp1, bb, nullptr, 0, nullptr);
+  do_norm2(c, tmp1, nullptr);
+  PCOP_HIP(hipMemcpyAsync(h_red.data(), red, sizeof(double) * B * kRedStride, hipMemcpyDeviceToHost, st));
+  if (transpose) launch_flip(g, x, x, st);
+  PCOP_HIP(hipStreamSynchronize(st));
+  PCOP_HIP(hipGetLastError());
+  for (int m = 0; m < B; ++m) {
+    const double rt = std::sqrt(h_red[(size_t)m * kRedStride]);
+    if (info) {
+      info[m].iters = ms[m].iters;
+      info[m].converged = ms[m].converged ? 1 : 0;
+      info[m].relres_est = ms[m].est;
+      info[m].relres_true = bnorm[m] > 0.0 ? rt / bnorm[m] : rt;
+    }
+    if (!ms[m].converged) result = PCOP_NOT_CONVERGED;
+  }
+  if (result == PCOP_NOT_CONVERGED) g_last_error = "tolerance not met within maxit";
+  return result;
+}

@@ -1,0 +1,221 @@
+"""GPU parity: every entry point of the HIP path against the FP64 CPU oracle
+on the same seeded inputs.  Sizes span several tiles with ragged tails."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from oracle import adjoint as ADJ, discretize as D, krylov as KR, precond as P
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2410_22686_amd import Solver, kkt_solve  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def rel(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def to_dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def problems(dim, nx, nt, gammas, eps=None, coeff=None):
+    return [D.make_problem(dim, nx, nt, gm, eps=eps, coeff=coeff) for gm in gammas]
+
+
+KKT_CASES = [
+    (2, 15, 12, (1e-4,), None),
+    (2, 31, 32, (1e-2, 1e-8), None),
+    (3, 7, 9, (1e-3,), None),
+    (2, 15, 6, (1e-3,), W.coeff_sines3d),
+    (3, 7, 5, (1e-5, 1.0), W.coeff_sines3d),
+]
+
+
+@pytest.mark.parametrize("dim,nx,nt,gammas,coeff", KKT_CASES)
+@pytest.mark.parametrize("transpose", [False, True])
+def test_kkt_apply(dim, nx, nt, gammas, coeff, transpose):
+    print(f"kkt_apply dim={dim} nx={nx} nt={nt} B={len(gammas)} var={coeff is not None} T={transpose}", flush=True)
+    spatial = "dst" if coeff is None else "mg"
+    s = Solver(dim, nx, nt, list(gammas), coeff=coeff, spatial=spatial, device=DEV)
+    x = W.random_vector(dim, nx, nt, seed=1, batch=len(gammas))
+    y = s.kkt_apply(to_dev(x), transpose=transpose).cpu().numpy()
+    for b, pb in enumerate(problems(dim, nx, nt, gammas, coeff=coeff)):
+        yo = D.kkt_apply(pb, x[b].ravel(), transpose=transpose)
+        assert rel(y[b], yo) < 1e-14
+
+
+def test_rhs_unpack_cotangent_datagrad():
+    dim, nx, nt, gammas = 2, 15, 10, (1e-6, 1e-1)
+    s = Solver(dim, nx, nt, list(gammas), device=DEV)
+    fields = [W.random_fields(dim, nx, nt, seed=10 + b) for b in range(len(gammas))]
+    g = np.stack([f[0] for f in fields])
+    f = np.stack([f[1] for f in fields])
+    y0 = np.stack([f[2] for f in fields])
+    b = s.rhs(to_dev(g), to_dev(f), to_dev(y0)).cpu().numpy()
+    lam = W.random_vector(dim, nx, nt, seed=3, batch=len(gammas))
+    dg, df, dy0 = [t.cpu().numpy() for t in s.data_grad(to_dev(lam))]
+    yb, pbar = np.random.default_rng(4).standard_normal((2, len(gammas), nt - 1, nx * nx))
+    r = s.pack_cotangent(to_dev(yb), to_dev(pbar)).cpu().numpy()
+    yy, pp = [t.cpu().numpy() for t in s.unpack(to_dev(lam))]
+    for k, pb in enumerate(problems(dim, nx, nt, gammas)):
+        assert rel(b[k], D.rhs_scaled(pb, g[k], f[k], y0[k])) < 1e-15
+        og, of, oy0 = ADJ.data_gradients(pb, lam[k].ravel())
+        assert rel(dg[k], og) < 1e-15 and rel(df[k], of) < 1e-15 and rel(dy0[k], oy0) < 1e-15
+        assert rel(r[k], ADJ.loss_to_x_grad(pb, yb[k], pbar[k])) < 1e-15
+        uy, up = D.unpack_solution(pb, lam[k].ravel())
+        assert rel(yy[k], uy) < 1e-15 and rel(pp[k], up) < 1e-15
+
+
+PRECOND_CASES = [
+    # dim, nx, nt, gammas, eps
+    (2, 15, 16, (1e-4,), None),          # n = 15 = 3 * 5
+    (2, 31, 32, (1e-2, 1e-10), None),    # n = 31 prime, batch of two
+    (2, 7, 9, (1.0,), 0.5),              # n = 8 = 4 * 2 (even n: self-paired Nyquist)
+    (2, 15, 2, (1e-3,), None),           # n = 1
+    (2, 15, 3, (1e-3,), None),           # n = 2
+    (2, 63, 18, (1e-6,), 1.0 / 36),      # n = 17 prime, eps = tau/2
+    (3, 7, 8, (1e-4,), None),            # 3-D sine transforms
+    (2, 3, 13, (1e-4,), None),           # smallest sine length
+]
+
+
+@pytest.mark.parametrize("dim,nx,nt,gammas,eps", PRECOND_CASES)
+def test_precond_apply_fp64(dim, nx, nt, gammas, eps):
+    print(f"precond fp64 dim={dim} nx={nx} nt={nt} B={len(gammas)}", flush=True)
+    s = Solver(dim, nx, nt, list(gammas), eps=eps, device=DEV)
+    v = W.random_vector(dim, nx, nt, seed=7, batch=len(gammas))
+    w = s.precond_apply(to_dev(v)).cpu().numpy()
+    for b, pb in enumerate(problems(dim, nx, nt, gammas, eps=eps)):
+        wo = P.EpsCirculantRBD(pb).apply(v[b].ravel())
+        assert rel(w[b], wo) < 1e-11, rel(w[b], wo)
+
+
+@pytest.mark.parametrize("dim,nx,nt,gammas,eps", PRECOND_CASES[:3])
+def test_precond_apply_mixed(dim, nx, nt, gammas, eps):
+    s = Solver(dim, nx, nt, list(gammas), eps=eps, precision="mixed", side="flexible", device=DEV)
+    v = W.random_vector(dim, nx, nt, seed=8, batch=len(gammas))
+    w = s.precond_apply(to_dev(v)).cpu().numpy()
+    for b, pb in enumerate(problems(dim, nx, nt, gammas, eps=eps)):
+        err = rel(w[b], P.EpsCirculantRBD(pb).apply(v[b].ravel()))
+        print(f"mixed precond rel err {err:.2e}")
+        assert err < 1e-5
+
+
+def test_precond_in_place():
+    s = Solver(2, 15, 16, 1e-4, device=DEV)
+    v = to_dev(W.random_vector(2, 15, 16, seed=9))
+    w = s.precond_apply(v)
+    v2 = v.clone()
+    s.precond_apply(v2, out=v2)
+    assert torch.equal(w, v2)
+
+
+@pytest.mark.parametrize("side", ["right", "left", "flexible"])
+def test_fixed_k_iterates_match_oracle(side):
+    """Same side, same k Arnoldi steps, x0 = 0: the iterates agree (CGS on the
+    GPU, MGS in the oracle: equal in exact arithmetic)."""
+    dim, nx, nt, gamma = 2, 15, 16, 1e-4
+    g, f, y0 = W.random_fields(dim, nx, nt, seed=21)
+    pb = D.make_problem(dim, nx, nt, gamma)
+    A = D.kkt_scaled(pb)
+    bo = D.rhs_scaled(pb, g, f, y0)
+    pc = P.EpsCirculantRBD(pb)
+    for k in (1, 3, 6):
+        s = Solver(dim, nx, nt, gamma, side=side, maxit=k, rtol=1e-30, device=DEV)
+        b = s.rhs(to_dev(g[None]), to_dev(f[None]), to_dev(y0[None]))
+        x, infos, hist = s.solve(b, history=True)
+        res = KR.gmres(lambda v: A @ v, bo, pc.apply, side=side, fixed_iters=k)
+        assert infos[0].iters == k
+        assert rel(x.cpu().numpy(), res.x) < 1e-10
+        np.testing.assert_allclose(hist[0, : k + 1], res.history[: k + 1], rtol=1e-8)
+
+
+@pytest.mark.parametrize("side", ["right", "flexible"])
+def test_solve_converges_to_direct_solution(side):
+    dim, nx, nt, gammas = 2, 31, 32, (1e-2, 1e-6, 1e-10)
+    fields = [W.fields(W.CONFIGS[1], member=b) for b in range(3)]
+    s = Solver(dim, nx, nt, list(gammas), side=side, device=DEV)
+    g = np.stack([fl[0] for fl in fields])
+    f = np.stack([fl[1] for fl in fields])
+    y0 = np.stack([fl[2] for fl in fields])
+    b = s.rhs(to_dev(g), to_dev(f), to_dev(y0))
+    x, infos, _ = s.solve(b)
+    xs = x.cpu().numpy()
+    for k, pb in enumerate(problems(dim, nx, nt, gammas)):
+        assert infos[k].converged and infos[k].relres_true <= 1e-8 * 1.05, infos[k]
+        xo = spla.spsolve(D.kkt_scaled(pb).tocsc(), D.rhs_scaled(pb, g[k], f[k], y0[k]))
+        assert rel(xs[k], xo) < 1e-6
+
+
+def test_batched_member_equals_single_solve():
+    dim, nx, nt, gammas = 2, 15, 16, (1e-2, 1e-7, 1e-4)
+    fields = [W.random_fields(dim, nx, nt, seed=40 + b) for b in range(3)]
+    g = np.stack([fl[0] for fl in fields])
+    f = np.stack([fl[1] for fl in fields])
+    y0 = np.stack([fl[2] for fl in fields])
+    sb = Solver(dim, nx, nt, list(gammas), device=DEV)
+    xb, ib, _ = sb.solve(sb.rhs(to_dev(g), to_dev(f), to_dev(y0)))
+    for k, gm in enumerate(gammas):
+        s1 = Solver(dim, nx, nt, gm, device=DEV)
+        x1, i1, _ = s1.solve(s1.rhs(to_dev(g[k:k + 1]), to_dev(f[k:k + 1]), to_dev(y0[k:k + 1])))
+        assert i1[0].iters == ib[k].iters
+        assert rel(xb[k].cpu().numpy(), x1[0].cpu().numpy()) < 1e-13
+
+
+def test_transpose_solve():
+    dim, nx, nt, gamma = 2, 15, 16, 1e-3
+    pb = D.make_problem(dim, nx, nt, gamma)
+    r = W.random_vector(dim, nx, nt, seed=50)
+    s = Solver(dim, nx, nt, gamma, rtol=1e-12, device=DEV)
+    lam, infos, _ = s.solve(to_dev(r), transpose=True)
+    assert infos[0].converged
+    lo = ADJ.adjoint_solve(pb, r.ravel())
+    assert rel(lam.cpu().numpy(), lo) < 1e-9
+
+
+ROWS = [  # (gamma, nx, nt, iters) from Tables 1 and 3 (Example 1, eps = tau/2, left GMRES)
+    (1e-10, 31, 32, 6), (1e-8, 31, 64, 8), (1e-6, 31, 32, 10), (1e-6, 31, 256, 17),
+    (1e-4, 31, 32, 15), (1e-2, 31, 32, 16), (1.0, 31, 32, 10), (1e-6, 63, 64, 12),
+]
+
+
+@pytest.mark.parametrize("gamma,nx,nt,iters", ROWS)
+def test_paper_iteration_counts_left(gamma, nx, nt, iters):
+    tau = 1.0 / nt
+    g, f, y0 = W.example_fields(1, 2, nx, nt)
+    s = Solver(2, nx, nt, gamma, eps=min(0.5, tau / 2), side="left", device=DEV)
+    x, infos, _ = s.solve(s.rhs(to_dev(g[None]), to_dev(f[None]), to_dev(y0[None])))
+    assert infos[0].converged
+    assert infos[0].iters == iters
+
+
+def test_autograd_matches_oracle_and_envelope():
+    dim, nx, nt, gamma = 2, 15, 12, 1e-3
+    g, f, y0 = W.random_fields(dim, nx, nt, seed=60)
+    s = Solver(dim, nx, nt, gamma, rtol=1e-12, device=DEV)
+    tg = to_dev(g[None]).requires_grad_(True)
+    tf = to_dev(f[None]).requires_grad_(True)
+    ty0 = to_dev(y0[None]).requires_grad_(True)
+    y, p = kkt_solve(s, tg, tf, ty0)
+    # J* = tau/2 ||y - g||^2 + gamma tau/2 ||p/gamma||^2: its total derivative is
+    # the envelope closed form -tau (y - g), -tau p, -p^1
+    J = 0.5 * s.tau * ((y - tg) ** 2).sum() + 0.5 * gamma * s.tau * ((p / gamma) ** 2).sum()
+    J.backward()
+    pb = D.make_problem(dim, nx, nt, gamma)
+    yo, po = D.unpack_solution(pb, spla.spsolve(D.kkt_scaled(pb).tocsc(), D.rhs_scaled(pb, g, f, y0)))
+    eg, ef, ey0 = ADJ.envelope_gradients(pb, yo, po, g)
+    assert rel(tg.grad.cpu().numpy()[0], eg) < 1e-8
+    assert rel(tf.grad.cpu().numpy()[0], ef) < 1e-8
+    assert rel(ty0.grad.cpu().numpy()[0], ey0) < 1e-8
