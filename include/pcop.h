@@ -89,14 +89,14 @@ typedef struct {
 /* Solver options.
  *   precision  PCOP_FP64, or PCOP_MIXED: P_eps^{-1} evaluated in complex FP32
  *              (vectors, matvec, Arnoldi and residuals stay FP64).
- *   spatial    PCOP_DST (requires a = 1; nx + 1 a power of two, 4..1024)
+ *   spatial    PCOP_DST (requires a = 1; nx + 1 a power of two, 4..512)
  *              or PCOP_MG (one complex-shifted V-cycle per frequency).
  *   side       PCOP_RIGHT: GMRES on A P^{-1}, stops on the true relative
  *              residual ||b - A x|| / ||b - A x0||;
  *              PCOP_LEFT: GMRES on P^{-1} A, stops on the preconditioned
  *              relative residual (the setting of Section 3);
  *              PCOP_FLEXIBLE: right-preconditioned flexible GMRES that keeps
- *              Z_j = P^{-1} v_j (required with PCOP_MIXED or PCOP_MG).
+ *              Z_j = P^{-1} v_j (required with PCOP_MIXED).
  *   restart    Krylov dimension per cycle, 1..40.
  *   maxit      maximum total Arnoldi steps (>= 1).
  *   rtol       relative residual tolerance (> 0).
@@ -188,6 +188,22 @@ pcop_status pcop_data_grad(pcop_ctx ctx, const double* lam, double* dg, double* 
 
 /* Host copy of a few derived scalars: tau, alpha[batch], eps. */
 pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* eps);
+
+/* Per-kernel timing.  While enabled, every kernel the context launches is
+ * bracketed by HIP events on the context's stream; pcop_timing_read
+ * synchronises, and returns for each kernel family the number of launches,
+ * the summed event time in milliseconds and the summed algorithmic HBM
+ * bytes (what the method must read and write: each input and output vector
+ * once).  name points to static storage.  Enabling resets the counters. */
+typedef struct {
+  const char* name;
+  long long launches;
+  double ms;
+  double bytes;
+} pcop_kernel_stat;
+
+pcop_status pcop_timing_enable(pcop_ctx ctx, int enable);
+pcop_status pcop_timing_read(pcop_ctx ctx, pcop_kernel_stat* out, int cap, int* count, int reset);
 
 /* Release the context (does not free the caller's workspace). */
 void pcop_destroy(pcop_ctx ctx);

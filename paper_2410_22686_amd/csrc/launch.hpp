@@ -8,6 +8,25 @@
 
 namespace pcop {
 
+// Optional per-kernel timing: when set, launch wrappers bracket every kernel
+// with begin/end (HIP events on the launch stream) and report the kernel
+// family and its algorithmic HBM bytes.
+enum KFamily {
+  KF_KKT = 0, KF_TIME_FWD, KF_DST_ROWS, KF_DST_AX2, KF_DST_LAST, KF_TIME_INV, KF_MG_SMOOTH,
+  KF_MG_RESTRICT, KF_MG_PROLONG, KF_MDOT, KF_UPDATE, KF_COMBINE, KF_SMALL, KF_COUNT
+};
+struct KTimer {
+  void (*begin)(void* self, int family, double bytes);
+  void (*end)(void* self);
+  void* self;
+};
+inline void tbeg(const KTimer* t, int fam, double bytes) {
+  if (t && t->begin) t->begin(t->self, fam, bytes);
+}
+inline void tend(const KTimer* t) {
+  if (t && t->end) t->end(t->self);
+}
+
 // Tables used by the preconditioner kernels (all device pointers into the
 // workspace, filled at setup).
 struct MgLevel {
@@ -30,6 +49,8 @@ struct PrecondTables {
   const double* lam;     // [K] lambda_k as (re, im)
   const double* alpha;   // [B]
   const int* active;     // [B] or null
+  int nact;              // members with active != 0 (for byte accounting)
+  const KTimer* timer;   // or null
   FftPlan plan;          // radices of n
   int mg_levels;
   MgLevel mg[12];

@@ -182,6 +182,77 @@ FftPlan make_plan(int n) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// per-kernel event timing
+// ---------------------------------------------------------------------------
+const char* kFamilyName[KF_COUNT] = {"kkt_apply", "time_fwd", "dst_rows", "dst_ax2", "dst_last_solve",
+                                     "time_inv", "mg_smooth", "mg_restrict", "mg_prolong", "mdot",
+                                     "gs_update", "combine", "small"};
+
+struct EventTimer {
+  hipStream_t st = nullptr;
+  bool enabled = false;
+  std::vector<hipEvent_t> ev;   // start/stop pairs
+  std::vector<int> fam;
+  std::vector<double> bytes;
+  size_t used = 0;
+  long long launches[KF_COUNT] = {0};
+  double ms[KF_COUNT] = {0};
+  double tbytes[KF_COUNT] = {0};
+  hipError_t err = hipSuccess;
+
+  void flush() {
+    if (used == 0) return;
+    hipError_t e = hipEventSynchronize(ev[2 * used - 1]);
+    if (e != hipSuccess) err = e;
+    for (size_t i = 0; i < used; ++i) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) == hipSuccess) {
+        ms[fam[i]] += t;
+        launches[fam[i]] += 1;
+        tbytes[fam[i]] += bytes[i];
+      }
+    }
+    used = 0;
+  }
+  void reset() {
+    flush();
+    for (int f = 0; f < KF_COUNT; ++f) {
+      launches[f] = 0;
+      ms[f] = 0;
+      tbytes[f] = 0;
+    }
+  }
+  ~EventTimer() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  static void on_begin(void* self, int family, double nbytes) {
+    EventTimer* t = static_cast<EventTimer*>(self);
+    if (!t->enabled) return;
+    if (t->used >= 16384) t->flush();
+    if (2 * t->used + 2 > t->ev.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        t->enabled = false;
+        return;
+      }
+      t->ev.push_back(a);
+      t->ev.push_back(b);
+      t->fam.push_back(0);
+      t->bytes.push_back(0);
+    }
+    t->fam[t->used] = family;
+    t->bytes[t->used] = nbytes;
+    (void)hipEventRecord(t->ev[2 * t->used], t->st);
+  }
+  static void on_end(void* self) {
+    EventTimer* t = static_cast<EventTimer*>(self);
+    if (!t->enabled) return;
+    (void)hipEventRecord(t->ev[2 * t->used + 1], t->st);
+    t->used += 1;
+  }
+};
+
+// ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
 struct pcop_ctx_s {
@@ -197,6 +268,9 @@ struct pcop_ctx_s {
   double ediag = 0, eoff = 0;
   const double* ecoef = nullptr;
   bool fp32 = false;
+  EventTimer timer;
+  KTimer ktimer{&EventTimer::on_begin, &EventTimer::on_end, nullptr};
+  const KTimer* kt() const { return timer.enabled ? &ktimer : nullptr; }
 
   template <class T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -210,9 +284,11 @@ struct pcop_ctx_s {
 namespace {
 
 pcop_status do_precond(pcop_ctx c, const double* v, double* w, const double* vscale, int vs_stride, int accum,
-                       const int* mask) {
+                       const int* mask, int nact) {
   PrecondTables tb = c->tb;
   tb.active = mask;
+  tb.nact = nact;
+  tb.timer = c->kt();
   if (!launch_precond(c->g, v, w, c->at<void>(c->L.spec), c->fp32, c->opt.spatial, tb, vscale, vs_stride,
                       accum, c->st))
     return fail(PCOP_ERR_UNSUPPORTED, "preconditioner variant not available for this shape");
@@ -220,15 +296,30 @@ pcop_status do_precond(pcop_ctx c, const double* v, double* w, const double* vsc
 }
 
 void do_kkt(pcop_ctx c, const double* x, double* y, const double* cvec, const double* xscale, int xs_stride,
-            const int* mask) {
+            const int* mask, int nact) {
+  tbeg(c->kt(), KF_KKT, (cvec ? 24.0 : 16.0) * c->g.vl * nact);
   launch_kkt_apply(c->g, x, y, cvec, c->at<double>(c->L.alpha), xscale, xs_stride, mask, false, c->ecoef,
                    c->ediag, c->eoff, c->st);
+  tend(c->kt());
+}
+
+void do_mdot(pcop_ctx c, const KrylovArgs& ka, int nv, const double* w, int nact) {
+  tbeg(c->kt(), KF_MDOT, 8.0 * (nv + 1) * c->g.vl * nact);
+  launch_mdot(ka, nv, w, c->at<double>(c->L.partial), c->L.nblk, c->st);
+  tend(c->kt());
+}
+
+void do_update(pcop_ctx c, const KrylovArgs& ka, int nv, double* w, const int* skip, int nact) {
+  tbeg(c->kt(), KF_UPDATE, 8.0 * (nv + 2) * c->g.vl * nact);
+  launch_update(ka, nv, w, c->at<double>(c->L.coef), kMaxBasis, c->at<double>(c->L.partial), c->L.nblk, skip,
+                c->st);
+  tend(c->kt());
 }
 
 // squared norms of member vectors (into red[b][0])
-void do_norm2(pcop_ctx c, const double* w, const int* mask) {
+void do_norm2(pcop_ctx c, const double* w, const int* mask, int nact) {
   KrylovArgs ka = c->kargs(c->basis(0), mask);
-  launch_mdot(ka, 0, w, c->at<double>(c->L.partial), c->L.nblk, c->st);
+  do_mdot(c, ka, 0, w, nact);
   launch_reduce_partials(c->at<double>(c->L.partial), c->L.nblk, 1, c->g.B, c->at<double>(c->L.red), c->st);
 }
 
@@ -498,15 +589,17 @@ pcop_status pcop_rhs(pcop_ctx c, const double* g, const double* f, const double*
 pcop_status pcop_kkt_apply(pcop_ctx c, const double* x, double* y, int transpose) {
   if (!c || !x || !y) return fail(PCOP_ERR_INVALID_ARG, "null argument");
   if (x == y) return fail(PCOP_ERR_INVALID_ARG, "x and y must not overlap");
+  tbeg(c->kt(), KF_KKT, 16.0 * c->g.vl * c->g.B);
   launch_kkt_apply(c->g, x, y, nullptr, c->at<double>(c->L.alpha), nullptr, 0, nullptr, transpose != 0, c->ecoef,
                    c->ediag, c->eoff, c->st);
+  tend(c->kt());
   PCOP_HIP(hipGetLastError());
   return PCOP_OK;
 }
 
 pcop_status pcop_precond_apply(pcop_ctx c, const double* v, double* w) {
   if (!c || !v || !w) return fail(PCOP_ERR_INVALID_ARG, "null argument");
-  pcop_status s = do_precond(c, v, w, nullptr, 0, 0, nullptr);
+  pcop_status s = do_precond(c, v, w, nullptr, 0, 0, nullptr, c->g.B);
   if (s != PCOP_OK) return s;
   PCOP_HIP(hipGetLastError());
   return PCOP_OK;
@@ -546,6 +639,36 @@ const char* pcop_status_string(pcop_status s) {
 }
 
 const char* pcop_last_error(void) { return g_last_error.c_str(); }
+
+pcop_status pcop_timing_enable(pcop_ctx c, int enable) {
+  if (!c) return fail(PCOP_ERR_INVALID_ARG, "null context");
+  c->timer.st = c->st;
+  c->ktimer.self = &c->timer;
+  c->timer.reset();
+  c->timer.enabled = enable != 0;
+  if (c->timer.err != hipSuccess) return fail(PCOP_ERR_DEVICE, hipGetErrorString(c->timer.err));
+  return PCOP_OK;
+}
+
+pcop_status pcop_timing_read(pcop_ctx c, pcop_kernel_stat* out, int cap, int* count, int reset) {
+  if (!c || (!out && cap > 0)) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  c->timer.flush();
+  if (c->timer.err != hipSuccess) return fail(PCOP_ERR_DEVICE, hipGetErrorString(c->timer.err));
+  int k = 0;
+  for (int f = 0; f < KF_COUNT; ++f) {
+    if (c->timer.launches[f] == 0) continue;
+    if (k < cap) {
+      out[k].name = kFamilyName[f];
+      out[k].launches = c->timer.launches[f];
+      out[k].ms = c->timer.ms[f];
+      out[k].bytes = c->timer.tbytes[f];
+    }
+    ++k;
+  }
+  if (count) *count = k;
+  if (reset) c->timer.reset();
+  return PCOP_OK;
+}
 
 }  // extern "C"
 
@@ -617,7 +740,7 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
 
   // ||b|| for the final true residual
   PCOP_HIP(hipMemcpyAsync(active, h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
-  do_norm2(c, bb, nullptr);
+  do_norm2(c, bb, nullptr, B);
   std::vector<double> h_red((size_t)B * kRedStride);
   PCOP_HIP(hipMemcpyAsync(h_red.data(), red, sizeof(double) * B * kRedStride, hipMemcpyDeviceToHost, st));
   PCOP_HIP(hipStreamSynchronize(st));
@@ -633,14 +756,14 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
     PCOP_HIP(hipMemcpyAsync(active, h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
     // r0 = b - A x (right/flexible) or P^{-1}(b - A x) (left) into slot 0
     if (side == PCOP_LEFT) {
-      do_kkt(c, x, tmp1, bb, nullptr, 0, active);
-      pcop_status s = do_precond(c, tmp1, c->basis(0), nullptr, 0, 0, active);
+      do_kkt(c, x, tmp1, bb, nullptr, 0, active, n_active);
+      pcop_status s = do_precond(c, tmp1, c->basis(0), nullptr, 0, 0, active, n_active);
       if (s != PCOP_OK) return s;
     } else {
-      do_kkt(c, x, c->basis(0), bb, nullptr, 0, active);
+      do_kkt(c, x, c->basis(0), bb, nullptr, 0, active, n_active);
     }
     KrylovArgs kv = c->kargs(c->basis(0), active);
-    launch_mdot(kv, 0, c->basis(0), partial, nblk, st);
+    do_mdot(c, kv, 0, c->basis(0), n_active);
     launch_reduce_partials(partial, nblk, 1, B, red, st);
     launch_set_scale(red, 0, B, sc, norm, active, st);
     PCOP_HIP(hipMemcpyAsync(h_norm.data(), norm, sizeof(double) * B, hipMemcpyDeviceToHost, st));
@@ -675,27 +798,29 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
     PCOP_HIP(hipMemcpyAsync(active, h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
 
     for (int j = 0; j < restart; ++j) {
+      n_active = 0;
+      for (int m = 0; m < B; ++m) n_active += h_active[m];
       double* vj = c->basis(j);
       double* w = c->basis(j + 1);
       const double* scj = sc + j;  // member stride kMaxBasis
       pcop_status s = PCOP_OK;
       if (side == PCOP_RIGHT) {
-        s = do_precond(c, vj, tmp1, scj, kMaxBasis, 0, active);
-        do_kkt(c, tmp1, w, nullptr, nullptr, 0, active);
+        s = do_precond(c, vj, tmp1, scj, kMaxBasis, 0, active, n_active);
+        do_kkt(c, tmp1, w, nullptr, nullptr, 0, active, n_active);
       } else if (side == PCOP_FLEXIBLE) {
-        s = do_precond(c, vj, c->zbasis(j), scj, kMaxBasis, 0, active);
-        do_kkt(c, c->zbasis(j), w, nullptr, nullptr, 0, active);
+        s = do_precond(c, vj, c->zbasis(j), scj, kMaxBasis, 0, active, n_active);
+        do_kkt(c, c->zbasis(j), w, nullptr, nullptr, 0, active, n_active);
       } else {
-        do_kkt(c, vj, tmp1, nullptr, scj, kMaxBasis, active);
-        s = do_precond(c, tmp1, w, nullptr, 0, 0, active);
+        do_kkt(c, vj, tmp1, nullptr, scj, kMaxBasis, active, n_active);
+        s = do_precond(c, tmp1, w, nullptr, 0, 0, active, n_active);
       }
       if (s != PCOP_OK) return s;
       // classical Gram-Schmidt with a measured second pass
       KrylovArgs ka = c->kargs(c->basis(0), active);
-      launch_mdot(ka, j + 1, w, partial, nblk, st);
+      do_mdot(c, ka, j + 1, w, n_active);
       launch_reduce_partials(partial, nblk, j + 2, B, red, st);
       launch_gs_step1(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, active, st);
-      launch_update(ka, j + 1, w, coef, kMaxBasis, partial, nblk, nullptr, st);
+      do_update(c, ka, j + 1, w, nullptr, n_active);
       launch_reduce_partials(partial, nblk, j + 2, B, red, st);
       launch_gs_step2(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, c->opt.reorth_tol, skip, sc, active, 0, st);
       launch_update(ka, j + 1, w, coef, kMaxBasis, partial, nblk, skip, st);
@@ -707,6 +832,7 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
                                 st));
       PCOP_HIP(hipStreamSynchronize(st));
       bool any_finish = false;
+      int n_fin = 0;
       std::fill(h_finish.begin(), h_finish.end(), 0);
       for (int m = 0; m < B; ++m) {
         MemberState& ms_ = ms[m];
@@ -738,6 +864,7 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
         if (conv || ms_.iters >= maxit || j == restart - 1) {
           h_finish[m] = 1;
           any_finish = true;
+          ++n_fin;
           if (conv) ms_.converged = true;
         }
       }
@@ -758,12 +885,18 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
       PCOP_HIP(hipMemcpyAsync(coef, h_coef.data(), sizeof(double) * B * kMaxBasis, hipMemcpyHostToDevice, st));
       PCOP_HIP(hipMemcpyAsync(finish, h_finish.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
       if (side == PCOP_LEFT) {
+        tbeg(c->kt(), KF_COMBINE, 8.0 * (k + 2) * g.vl * n_fin);
         launch_combine(c->kargs(c->basis(0), finish), k, coef, kMaxBasis, x, 1, st);
+        tend(c->kt());
       } else if (side == PCOP_FLEXIBLE) {
+        tbeg(c->kt(), KF_COMBINE, 8.0 * (k + 2) * g.vl * n_fin);
         launch_combine(c->kargs(c->zbasis(0), finish), k, coef, kMaxBasis, x, 1, st);
+        tend(c->kt());
       } else {
+        tbeg(c->kt(), KF_COMBINE, 8.0 * (k + 1) * g.vl * n_fin);
         launch_combine(c->kargs(c->basis(0), finish), k, coef, kMaxBasis, tmp1, 0, st);
-        pcop_status s2 = do_precond(c, tmp1, x, nullptr, 0, 1, finish);
+        tend(c->kt());
+        pcop_status s2 = do_precond(c, tmp1, x, nullptr, 0, 1, finish, n_fin);
         if (s2 != PCOP_OK) return s2;
       }
       bool any_left = false;
@@ -784,8 +917,8 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
   // true residual ||b - A x|| / ||b||
   std::fill(h_active.begin(), h_active.end(), 1);
   PCOP_HIP(hipMemcpyAsync(active, h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
-  do_kkt(c, x, tmp1, bb, nullptr, 0, nullptr);
-  do_norm2(c, tmp1, nullptr);
+  do_kkt(c, x, tmp1, bb, nullptr, 0, nullptr, B);
+  do_norm2(c, tmp1, nullptr, B);
   PCOP_HIP(hipMemcpyAsync(h_red.data(), red, sizeof(double) * B * kRedStride, hipMemcpyDeviceToHost, st));
   if (transpose) launch_flip(g, x, x, st);
   PCOP_HIP(hipStreamSynchronize(st));

@@ -246,6 +246,7 @@ static void dst_pass_L(const Geo& g, cx<T>* data, const LineGeom& lg, bool rows,
   const long long tiles = (lg.lines + LINES - 1) / LINES;
   const long long blocks = tiles * lg.nplanes;
   dim3 grid((unsigned)blocks);
+  (void)g;
   if (rows) {
     if (divide)
       dst_lines_kernel<T, L, LINES, NT, true, true><<<grid, NT, 0, st>>>(g, data, lg, twL, dp);
@@ -293,11 +294,20 @@ static bool dst_solve(const Geo& g, cx<T>* spec, const PrecondTables& tb, hipStr
   const int lines_last = (g.dim == 3) ? nx * nx : nx;
   const int stride_last = (g.dim == 3) ? nx * nx : nx;
   LineGeom last{slices, (long long)g.m, lines_last, 1, stride_last};
-  bool ok = dst_pass<T>(g, spec, rows, true, false, twL, dp, st);
-  if (g.dim == 3) ok = ok && dst_pass<T>(g, spec, ax2, false, false, twL, dp, st);
-  ok = ok && dst_pass<T>(g, spec, last, false, true, twL, dp, st);
-  if (g.dim == 3) ok = ok && dst_pass<T>(g, spec, ax2, false, false, twL, dp, st);
-  ok = ok && dst_pass<T>(g, spec, rows, true, false, twL, dp, st);
+  // every pass reads and writes the spectrum of the counted members once
+  const double pass_bytes = 2.0 * sizeof(cx<T>) * 2.0 * g.K * (double)g.m * tb.nact;
+  bool ok = true;
+  auto run = [&](const LineGeom& lg, bool r, bool dv, int fam) {
+    if (!ok) return;
+    tbeg(tb.timer, fam, pass_bytes);
+    ok = dst_pass<T>(g, spec, lg, r, dv, twL, dp, st);
+    tend(tb.timer);
+  };
+  run(rows, true, false, KF_DST_ROWS);
+  if (g.dim == 3) run(ax2, false, false, KF_DST_AX2);
+  run(last, false, true, KF_DST_LAST);
+  if (g.dim == 3) run(ax2, false, false, KF_DST_AX2);
+  run(rows, true, false, KF_DST_ROWS);
   return ok;
 }
 
@@ -320,7 +330,10 @@ static void time_fwd(const Geo& g, const double* v, cx<T>* spec, const PrecondTa
   dim3 grid((g.m + P - 1) / P, g.B);
   size_t lds = (size_t)2 * g.n * P * sizeof(cx<T>);
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(sizeof(T) == 8 ? (const void*)tb.twn64 : (const void*)tb.twn32);
+  const double bytes = (8.0 * g.vl + sizeof(cx<T>) * 2.0 * g.K * (double)g.m) * tb.nact;
+  tbeg(tb.timer, KF_TIME_FWD, bytes);
   time_fwd_kernel<T><<<grid, 256, lds, st>>>(g, v, spec, tb.dpow, tw, tb.plan, P, vscale, vs_stride, tb.active);
+  tend(tb.timer);
 }
 
 template <class T>
@@ -330,7 +343,10 @@ static void time_inv(const Geo& g, const cx<T>* spec, double* w, const PrecondTa
   dim3 grid((g.m + P - 1) / P, g.B);
   size_t lds = (size_t)2 * g.n * P * sizeof(cx<T>);
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(sizeof(T) == 8 ? (const void*)tb.twn64 : (const void*)tb.twn32);
+  const double bytes = ((accum ? 16.0 : 8.0) * g.vl + sizeof(cx<T>) * 2.0 * g.K * (double)g.m) * tb.nact;
+  tbeg(tb.timer, KF_TIME_INV, bytes);
   time_inv_kernel<T><<<grid, 256, lds, st>>>(g, spec, w, tb.dpow, tw, tb.plan, P, accum, tb.active);
+  tend(tb.timer);
 }
 
 bool time_lds_fits(int n, bool fp32) {

@@ -29,6 +29,7 @@ EXPORTED = [
     "pcop_validate", "pcop_default_options", "pcop_workspace_size", "pcop_setup", "pcop_rhs",
     "pcop_kkt_apply", "pcop_precond_apply", "pcop_solve", "pcop_unpack", "pcop_pack_cotangent",
     "pcop_data_grad", "pcop_get_params", "pcop_destroy", "pcop_status_string", "pcop_last_error",
+    "pcop_timing_enable", "pcop_timing_read",
 ]
 
 
@@ -53,6 +54,11 @@ class c_options(ctypes.Structure):
                 ("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("graph", ctypes.c_int), ("graph_chunk", ctypes.c_int), ("reorth_tol", ctypes.c_double),
                 ("stream", ctypes.c_void_p)]
+
+
+class c_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_longlong), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
 
 
 class c_member_info(ctypes.Structure):
@@ -89,6 +95,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "pcop_destroy": (None, [vp]),
         "pcop_status_string": (ctypes.c_char_p, [ip]),
         "pcop_last_error": (ctypes.c_char_p, []),
+        "pcop_timing_enable": (ip, [vp, ip]),
+        "pcop_timing_read": (ip, [vp, ctypes.POINTER(c_kernel_stat), ip, ctypes.POINTER(ctypes.c_int), ip]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -288,6 +296,19 @@ class Solver:
         r = self.new_vector()
         _check(self.lib.pcop_pack_cotangent(self.ctx, _ptr(ybar), _ptr(pbar), _ptr(r)))
         return r
+
+    def timing_enable(self, enable: bool = True):
+        """Start (and reset) or stop per-kernel HIP-event timing."""
+        _check(self.lib.pcop_timing_enable(self.ctx, int(bool(enable))))
+
+    def timing_read(self, reset: bool = False):
+        """{family: {"launches", "ms", "bytes"}} accumulated since timing_enable."""
+        cap = 32
+        arr = (c_kernel_stat * cap)()
+        cnt = ctypes.c_int(0)
+        _check(self.lib.pcop_timing_read(self.ctx, arr, cap, ctypes.byref(cnt), int(bool(reset))))
+        return {arr[i].name.decode(): {"launches": int(arr[i].launches), "ms": float(arr[i].ms),
+                                       "bytes": float(arr[i].bytes)} for i in range(min(cnt.value, cap))}
 
     def data_grad(self, lam: torch.Tensor):
         self._vec(lam, "lam")
