@@ -124,14 +124,20 @@ __global__ void __launch_bounds__(kNT) combine_kernel(KrylovArgs ka, int nv, con
   }
 }
 
-// out[b][c] = sum over blocks (in block order) of partial[b][blk][c]
-__global__ void reduce_partials_kernel(const double* __restrict__ partial, int nblk, int ncols,
-                                       double* __restrict__ out) {
+// out[b][c] = sum over blocks of partial[b][blk][c]: wave w of the block owns
+// the columns c = w, w + 4, ...; lane l adds blocks l, l + 64, ... in order and
+// the wave butterfly finishes, so the order is fixed.
+__global__ void __launch_bounds__(kNT) reduce_partials_kernel(const double* __restrict__ partial, int nblk,
+                                                              int ncols, double* __restrict__ out) {
   const int b = blockIdx.x;
-  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const double* pb = partial + (size_t)b * nblk * kRedStride;
+  for (int c = wv; c < ncols; c += kNWave) {
     double s = 0.0;
-    for (int k = 0; k < nblk; ++k) s += partial[((size_t)b * nblk + k) * kRedStride + c];
-    out[(size_t)b * kRedStride + c] = s;
+    for (int k = lane; k < nblk; k += kWave) s += pb[(size_t)k * kRedStride + c];
+    s = wave_sum(s);
+    if (lane == 0) out[(size_t)b * kRedStride + c] = s;
   }
 }
 
@@ -194,6 +200,14 @@ __global__ void gs_step2_kernel(const double* __restrict__ red, int j, int B, co
   (void)wnorm2;
 }
 
+// out[b][i] = H[b][j][i], i <= j + 1 (the column the host reads back)
+__global__ void pack_hcol_kernel(const double* __restrict__ H, int H_ld, int j, int B, double* __restrict__ out) {
+  const int b = blockIdx.x;
+  const double* Hc = H + ((size_t)b * (kMaxBasis - 1) + j) * H_ld;
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) out[(size_t)b * kMaxBasis + i] = Hc[i];
+  (void)B;
+}
+
 // sc[b][col] = 1/sqrt(red[b][0]),  norm[b] = sqrt(red[b][0])
 __global__ void set_scale_kernel(const double* __restrict__ red, int col, int B, double* __restrict__ sc,
                                  double* __restrict__ norm, const int* __restrict__ active) {
@@ -235,7 +249,7 @@ void launch_combine(const KrylovArgs& ka, int nv, const double* coef, int coef_l
 }
 
 void launch_reduce_partials(const double* partial, int nblk, int ncols, int B, double* out, hipStream_t st) {
-  reduce_partials_kernel<<<B, 64, 0, st>>>(partial, nblk, ncols, out);
+  reduce_partials_kernel<<<B, kNT, 0, st>>>(partial, nblk, ncols, out);
 }
 
 void launch_gs_step1(const double* red, int j, int B, const double* sc, double* H, int H_ld, double* coef,
@@ -248,6 +262,10 @@ void launch_gs_step2(const double* red, int j, int B, const double* sc, double* 
                      const int* active, int final_pass, hipStream_t st) {
   gs_step2_kernel<<<(B + 63) / 64, 64, 0, st>>>(red, j, B, sc, H, H_ld, coef, coef_ld, wnorm2, reorth_tol, skip,
                                                 sc_out, active, final_pass);
+}
+
+void launch_pack_hcol(const double* H, int H_ld, int j, int B, double* out, hipStream_t st) {
+  pack_hcol_kernel<<<B, 64, 0, st>>>(H, H_ld, j, B, out);
 }
 
 void launch_set_scale(const double* red, int col, int B, double* sc, double* norm, const int* active,

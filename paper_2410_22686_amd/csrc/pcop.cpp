@@ -97,7 +97,7 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
 struct Layout {
   size_t total = 0;
   size_t dpow, twn64, twn32, twL64, twL32, mu1, lam, alpha, sg, ecoef;
-  size_t sc, H, coef, red, partial, wnorm2, norm, skip, active, finish;
+  size_t sc, H, coef, red, partial, wnorm2, norm, skip, active, finish, hcol;
   size_t basis, zbasis, tmp1, tmp2, spec;
   size_t mgcoef[12], mgz[12], mgr[12];
   int mg_levels = 0;
@@ -141,6 +141,7 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
   L.skip = take(L, sizeof(int) * B);
   L.active = take(L, sizeof(int) * B);
   L.finish = take(L, sizeof(int) * B);
+  L.hcol = take(L, sizeof(double) * B * kMaxBasis);
   const size_t vec = sizeof(double) * (size_t)L.vl * B;
   L.basis = take(L, vec * (o->restart + 1));
   L.zbasis = (o->side == PCOP_FLEXIBLE) ? take(L, vec * o->restart) : 0;
@@ -270,6 +271,18 @@ struct pcop_ctx_s {
   bool fp32 = false;
   EventTimer timer;
   KTimer ktimer{&EventTimer::on_begin, &EventTimer::on_end, nullptr};
+  // pinned host staging for every scalar transfer of the solver
+  double* pin = nullptr;
+  double* pin_col = nullptr;    // [B][kMaxBasis]  Hessenberg column
+  double* pin_sc = nullptr;     // [B][kMaxBasis]  basis scales
+  double* pin_coef = nullptr;   // [B][kMaxBasis]  combination coefficients
+  double* pin_red = nullptr;    // [B][kRedStride] reductions
+  double* pin_norm = nullptr;   // [B]
+  int* pin_active = nullptr;    // [B]
+  int* pin_finish = nullptr;    // [B]
+  ~pcop_ctx_s() {
+    if (pin) (void)hipHostFree(pin);
+  }
   const KTimer* kt() const { return timer.enabled ? &ktimer : nullptr; }
 
   template <class T>
@@ -541,6 +554,28 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
     return fail(PCOP_ERR_DEVICE, std::string("setup upload: ") + hipGetErrorString(e));
   }
 
+  {
+    const size_t nd = (size_t)B * (3 * kMaxBasis + kRedStride + 1) + 2 * (size_t)B + 8;
+    hipError_t pe = hipHostMalloc(reinterpret_cast<void**>(&c->pin), nd * sizeof(double), hipHostMallocDefault);
+    if (pe != hipSuccess) {
+      delete c;
+      return fail(PCOP_ERR_DEVICE, std::string("pinned staging: ") + hipGetErrorString(pe));
+    }
+    double* q = c->pin;
+    c->pin_col = q;
+    q += (size_t)B * kMaxBasis;
+    c->pin_sc = q;
+    q += (size_t)B * kMaxBasis;
+    c->pin_coef = q;
+    q += (size_t)B * kMaxBasis;
+    c->pin_red = q;
+    q += (size_t)B * kRedStride;
+    c->pin_norm = q;
+    q += B;
+    c->pin_active = reinterpret_cast<int*>(q);
+    q += B;
+    c->pin_finish = reinterpret_cast<int*>(q);
+  }
   PrecondTables& tb = c->tb;
   tb.dpow = c->at<double>(L.dpow);
   tb.twn64 = c->at<double>(L.twn64);
@@ -724,7 +759,6 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
   int* finish = c->at<int>(L.finish);
   const int nblk = L.nblk;
   const int H_ld = kMaxBasis;
-  const size_t H_member = (size_t)(kMaxBasis - 1) * kMaxBasis;
 
   // A^T = J A J: solve A z = J b and return x = J z
   const double* bb = b;
@@ -736,14 +770,36 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
   std::vector<MemberState> ms(B);
   std::vector<int> h_active(B, 1), h_finish(B, 0);
   std::vector<double> h_norm(B), h_col((size_t)B * kMaxBasis), h_coef((size_t)B * kMaxBasis);
-  std::vector<double> bnorm(B);
+  std::vector<double> bnorm(B), h_sc((size_t)B * kMaxBasis);
+  double* hcol = c->at<double>(L.hcol);
+  // Every host<->device transfer goes through pinned staging; an upload
+  // buffer is only rewritten after a stream synchronisation.
+  bool pending = false;
+  auto sync = [&]() -> hipError_t {
+    pending = false;
+    return hipStreamSynchronize(st);
+  };
+  auto upload_ints = [&](int* dev, const std::vector<int>& src, int* pinbuf) -> hipError_t {
+    if (pending) {
+      hipError_t e = sync();
+      if (e != hipSuccess) return e;
+    }
+    std::memcpy(pinbuf, src.data(), sizeof(int) * B);
+    pending = true;
+    return hipMemcpyAsync(dev, pinbuf, sizeof(int) * B, hipMemcpyHostToDevice, st);
+  };
+  auto download = [&](double* host, const double* dev, double* pinbuf, size_t count) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(pinbuf, dev, sizeof(double) * count, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = sync();
+    if (e == hipSuccess) std::memcpy(host, pinbuf, sizeof(double) * count);
+    return e;
+  };
+  std::vector<double> h_red((size_t)B * kRedStride);
 
   // ||b|| for the final true residual
-  PCOP_HIP(hipMemcpyAsync(active, h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+  PCOP_HIP(upload_ints(active, h_active, c->pin_active));
   do_norm2(c, bb, nullptr, B);
-  std::vector<double> h_red((size_t)B * kRedStride);
-  PCOP_HIP(hipMemcpyAsync(h_red.data(), red, sizeof(double) * B * kRedStride, hipMemcpyDeviceToHost, st));
-  PCOP_HIP(hipStreamSynchronize(st));
+  PCOP_HIP(download(h_red.data(), red, c->pin_red, (size_t)B * kRedStride));
   for (int m = 0; m < B; ++m) bnorm[m] = std::sqrt(h_red[(size_t)m * kRedStride]);
 
   bool first_cycle = true;
@@ -753,7 +809,7 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
     for (int m = 0; m < B; ++m) n_active += ms[m].active ? 1 : 0;
     if (n_active == 0) break;
     for (int m = 0; m < B; ++m) h_active[m] = ms[m].active ? 1 : 0;
-    PCOP_HIP(hipMemcpyAsync(active, h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+    PCOP_HIP(upload_ints(active, h_active, c->pin_active));
     // r0 = b - A x (right/flexible) or P^{-1}(b - A x) (left) into slot 0
     if (side == PCOP_LEFT) {
       do_kkt(c, x, tmp1, bb, nullptr, 0, active, n_active);
@@ -766,8 +822,7 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
     do_mdot(c, kv, 0, c->basis(0), n_active);
     launch_reduce_partials(partial, nblk, 1, B, red, st);
     launch_set_scale(red, 0, B, sc, norm, active, st);
-    PCOP_HIP(hipMemcpyAsync(h_norm.data(), norm, sizeof(double) * B, hipMemcpyDeviceToHost, st));
-    PCOP_HIP(hipStreamSynchronize(st));
+    PCOP_HIP(download(h_norm.data(), norm, c->pin_norm, (size_t)B));
     for (int m = 0; m < B; ++m) {
       MemberState& s = ms[m];
       if (!s.active) continue;
@@ -795,7 +850,7 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
       n_active += h_active[m];
     }
     if (n_active == 0) break;
-    PCOP_HIP(hipMemcpyAsync(active, h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+    PCOP_HIP(upload_ints(active, h_active, c->pin_active));
 
     for (int j = 0; j < restart; ++j) {
       n_active = 0;
@@ -827,10 +882,8 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
       launch_reduce_partials(partial, nblk, j + 2, B, red, st);
       launch_gs_step2(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, c->opt.reorth_tol, skip, sc, active, 1, st);
       // column j of H for every member
-      PCOP_HIP(hipMemcpy2DAsync(h_col.data(), sizeof(double) * kMaxBasis, H + (size_t)j * H_ld,
-                                sizeof(double) * H_member, sizeof(double) * (j + 2), B, hipMemcpyDeviceToHost,
-                                st));
-      PCOP_HIP(hipStreamSynchronize(st));
+      launch_pack_hcol(H, H_ld, j, B, hcol, st);
+      PCOP_HIP(download(h_col.data(), hcol, c->pin_col, (size_t)B * kMaxBasis));
       bool any_finish = false;
       int n_fin = 0;
       std::fill(h_finish.begin(), h_finish.end(), 0);
@@ -871,9 +924,7 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
       if (!any_finish) continue;
       // form the correction for the members that end their cycle here
       std::fill(h_coef.begin(), h_coef.end(), 0.0);
-      std::vector<double> h_sc((size_t)B * kMaxBasis);
-      PCOP_HIP(hipMemcpyAsync(h_sc.data(), sc, sizeof(double) * B * kMaxBasis, hipMemcpyDeviceToHost, st));
-      PCOP_HIP(hipStreamSynchronize(st));
+      PCOP_HIP(download(h_sc.data(), sc, c->pin_sc, (size_t)B * kMaxBasis));
       const int k = j + 1;
       for (int m = 0; m < B; ++m) {
         if (!h_finish[m]) continue;
@@ -882,8 +933,9 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
         for (int i = 0; i < k; ++i)
           h_coef[(size_t)m * kMaxBasis + i] = (side == PCOP_FLEXIBLE) ? y[i] : y[i] * h_sc[(size_t)m * kMaxBasis + i];
       }
-      PCOP_HIP(hipMemcpyAsync(coef, h_coef.data(), sizeof(double) * B * kMaxBasis, hipMemcpyHostToDevice, st));
-      PCOP_HIP(hipMemcpyAsync(finish, h_finish.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+      std::memcpy(c->pin_coef, h_coef.data(), sizeof(double) * B * kMaxBasis);
+      PCOP_HIP(hipMemcpyAsync(coef, c->pin_coef, sizeof(double) * B * kMaxBasis, hipMemcpyHostToDevice, st));
+      PCOP_HIP(upload_ints(finish, h_finish, c->pin_finish));
       if (side == PCOP_LEFT) {
         tbeg(c->kt(), KF_COMBINE, 8.0 * (k + 2) * g.vl * n_fin);
         launch_combine(c->kargs(c->basis(0), finish), k, coef, kMaxBasis, x, 1, st);
@@ -909,19 +961,18 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
         if (ms[m].converged || ms[m].iters >= maxit) ms[m].active = false;
       }
       for (int m = 0; m < B; ++m) h_active[m] = (ms[m].active && !h_finish[m]) ? 1 : 0;
-      PCOP_HIP(hipMemcpyAsync(active, h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+      PCOP_HIP(upload_ints(active, h_active, c->pin_active));
       if (!any_left) break;
     }
   }
 
   // true residual ||b - A x|| / ||b||
   std::fill(h_active.begin(), h_active.end(), 1);
-  PCOP_HIP(hipMemcpyAsync(active, h_active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+  PCOP_HIP(upload_ints(active, h_active, c->pin_active));
   do_kkt(c, x, tmp1, bb, nullptr, 0, nullptr, B);
   do_norm2(c, tmp1, nullptr, B);
-  PCOP_HIP(hipMemcpyAsync(h_red.data(), red, sizeof(double) * B * kRedStride, hipMemcpyDeviceToHost, st));
   if (transpose) launch_flip(g, x, x, st);
-  PCOP_HIP(hipStreamSynchronize(st));
+  PCOP_HIP(download(h_red.data(), red, c->pin_red, (size_t)B * kRedStride));
   PCOP_HIP(hipGetLastError());
   for (int m = 0; m < B; ++m) {
     const double rt = std::sqrt(h_red[(size_t)m * kRedStride]);
