@@ -16,58 +16,14 @@
 
 namespace pcop {
 
+// Time-axis FFT plan: Stockham radices (each <= 17) or, when n has a larger
+// prime factor, Bluestein's chirp-z transform with a power-of-two length M.
 struct FftPlan {
   int nrad;
   int rad[16];
+  int bluestein;
+  int M;
 };
-
-template <class T, bool INV>
-__device__ __forceinline__ void tpo_stage(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int n,
-                                          int P, int R, int Ns, const cx<T>* __restrict__ tw) {
-  const int nR = n / R;
-  const int NsR = Ns * R;
-  const int tstep = n / NsR;
-  const int total = n * P;
-  for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int o = t / P;
-    const int p = t - o * P;
-    const int blk = o / NsR;
-    const int rem = o - blk * NsR;
-    const int r2 = rem / Ns;
-    const int jl = rem - r2 * Ns;
-    const int jb = blk * Ns + jl;
-    const int E = (jl + r2 * Ns) * tstep;  // < n
-    cx<T> acc = in[jb * P + p];
-    int e = E;
-    for (int r = 1; r < R; ++r) {
-      cx<T> w = tw[e];
-      if (INV) w.y = -w.y;
-      acc = acc + in[(jb + r * nR) * P + p] * w;
-      e += E;
-      if (e >= n) e -= n;
-    }
-    out[t] = acc;
-  }
-}
-
-// Runs all stages; returns the buffer holding the result (a or b).
-template <class T, bool INV>
-__device__ cx<T>* tpo_fft(cx<T>* a, cx<T>* b, int n, int P, const FftPlan& plan,
-                          const cx<T>* __restrict__ tw) {
-  int Ns = 1;
-  cx<T>* src = a;
-  cx<T>* dst = b;
-  for (int s = 0; s < plan.nrad; ++s) {
-    const int R = plan.rad[s];
-    tpo_stage<T, INV>(src, dst, n, P, R, Ns, tw);
-    __syncthreads();
-    Ns *= R;
-    cx<T>* t = src;
-    src = dst;
-    dst = t;
-  }
-  return src;
-}
 
 // ---------------------------------------------------------------------------
 // small DFTs, sign SG = -1 (forward) or +1 (inverse)
@@ -110,11 +66,124 @@ __device__ __forceinline__ void dft8(cx<T>* a) {
   a[7] = e3 - w3o3;
 }
 
+template <class T, int SG>
+__device__ __forceinline__ void dft3(cx<T>* a) {
+  const T h = (T)0.86602540378443864676L;  // sin(2 pi/3)
+  const cx<T> t1 = a[1] + a[2];
+  const cx<T> t2 = a[0] - scale(t1, (T)0.5);
+  const cx<T> t3 = scale(mul_i<T, SG>(a[1] - a[2]), h);
+  a[0] = a[0] + t1;
+  a[1] = t2 + t3;
+  a[2] = t2 - t3;
+}
+
+template <class T, int SG>
+__device__ __forceinline__ void dft5(cx<T>* a) {
+  const T c1 = (T)0.30901699437494742410L, c2 = (T)-0.80901699437494742410L;
+  const T s1 = (T)0.95105651629515357212L, s2 = (T)0.58778525229247312917L;
+  const cx<T> t1 = a[1] + a[4], t2 = a[2] + a[3], t3 = a[1] - a[4], t4 = a[2] - a[3];
+  const cx<T> u1 = a[0] + scale(t1, c1) + scale(t2, c2);
+  const cx<T> u2 = a[0] + scale(t1, c2) + scale(t2, c1);
+  const cx<T> v1 = mul_i<T, SG>(scale(t3, s1) + scale(t4, s2));
+  const cx<T> v2 = mul_i<T, SG>(scale(t3, s2) - scale(t4, s1));
+  a[0] = a[0] + t1 + t2;
+  a[1] = u1 + v1;
+  a[4] = u1 - v1;
+  a[2] = u2 + v2;
+  a[3] = u2 - v2;
+}
+
+// generic R-point DFT; W_R^t = twn[t * stride] (twn: exp(-2 pi i t/n), n = R stride)
+template <class T, int SG, int R>
+__device__ __forceinline__ void dft_generic(cx<T>* a, const cx<T>* __restrict__ twn, int stride) {
+  cx<T> out[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    cx<T> acc = a[0];
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      cx<T> w = twn[((r * k) % R) * stride];
+      if (SG > 0) w.y = -w.y;
+      acc = acc + a[r] * w;
+    }
+    out[k] = acc;
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) a[k] = out[k];
+}
+
 template <class T, int SG, int R>
 __device__ __forceinline__ void dftR(cx<T>* a) {
   if constexpr (R == 2) dft2<T, SG>(a[0], a[1]);
   else if constexpr (R == 4) dft4<T, SG>(a[0], a[1], a[2], a[3]);
   else dft8<T, SG>(a);
+}
+
+template <class T, int SG, int R>
+__device__ __forceinline__ void dft_any(cx<T>* a, const cx<T>* __restrict__ twn, int stride) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2 || R == 4 || R == 8) {
+    dftR<T, SG, R>(a);
+  } else if constexpr (R == 3) {
+    dft3<T, SG>(a);
+  } else if constexpr (R == 5) {
+    dft5<T, SG>(a);
+  } else {
+    dft_generic<T, SG, R>(a, twn, stride);
+  }
+}
+
+// One Stockham stage with radix R after Ns = prod(previous radices) on a
+// length-n transform of P columns; each thread owns whole butterflies.
+// load(j, p) / store(j, p, v) read the stage input and write its output, so
+// the same code serves global->LDS, LDS->LDS and LDS->global stages.
+// twn[t] = exp(-2 pi i t/n); the inter-stage twiddles W_{Ns R}^{r jl} are
+// formed by powering W_{Ns R}^{jl}.
+template <class T, int R, int P, int SG, class LD, class ST>
+__device__ __forceinline__ void sk_stage(int n, int Ns, const cx<T>* __restrict__ twn, LD load, ST store) {
+  const int nR = n / R;
+  const int tstep = n / (Ns * R);
+  for (int bf = threadIdx.x; bf < nR * P; bf += blockDim.x) {
+    const int p = bf % P;
+    const int jb = bf / P;
+    const int jl = jb % Ns;
+    cx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = load(jb + r * nR, p);
+    if (R > 1 && jl != 0) {
+      cx<T> w1 = twn[jl * tstep];
+      if (SG > 0) w1.y = -w1.y;
+      cx<T> w = w1;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        v[r] = v[r] * w;
+        w = w * w1;
+      }
+    }
+    dft_any<T, SG, R>(v, twn, nR);
+    const int base = (jb - jl) * R + jl;
+#pragma unroll
+    for (int r = 0; r < R; ++r) store(base + r * Ns, p, v[r]);
+  }
+}
+
+// runtime radix dispatch (radices produced by the host planner)
+template <class T, int P, int SG, class LD, class ST>
+__device__ __forceinline__ void sk_stage_rt(int R, int n, int Ns, const cx<T>* __restrict__ twn, LD load,
+                                            ST store) {
+  switch (R) {
+    case 1: sk_stage<T, 1, P, SG>(n, Ns, twn, load, store); break;
+    case 2: sk_stage<T, 2, P, SG>(n, Ns, twn, load, store); break;
+    case 3: sk_stage<T, 3, P, SG>(n, Ns, twn, load, store); break;
+    case 4: sk_stage<T, 4, P, SG>(n, Ns, twn, load, store); break;
+    case 5: sk_stage<T, 5, P, SG>(n, Ns, twn, load, store); break;
+    case 7: sk_stage<T, 7, P, SG>(n, Ns, twn, load, store); break;
+    case 8: sk_stage<T, 8, P, SG>(n, Ns, twn, load, store); break;
+    case 11: sk_stage<T, 11, P, SG>(n, Ns, twn, load, store); break;
+    case 13: sk_stage<T, 13, P, SG>(n, Ns, twn, load, store); break;
+    case 17: sk_stage<T, 17, P, SG>(n, Ns, twn, load, store); break;
+    default: break;
+  }
 }
 
 // One in-place Stockham stage with radix R over LINES lines of length L held

@@ -43,6 +43,12 @@ struct PrecondTables {
   const double* dpow;    // [n]  eps^{j/n}
   const double* twn64;   // [n]  exp(-2 pi i t/n) as (re, im)
   const float* twn32;
+  const double* twM64;   // [M]  exp(-2 pi i t/M)      (Bluestein)
+  const float* twM32;
+  const double* chirp64; // [n]  exp(-i pi (t^2 mod 2n)/n)
+  const float* chirp32;
+  const double* bhat64;  // [M]  FFT_M of the chirp filter
+  const float* bhat32;
   const double* twL64;   // [L]  exp(-2 pi i t/L), L = 2(nx+1)
   const float* twL32;
   const double* mu1;     // [nx] (4/h^2) sin^2(pi k h/2), k = 1..nx
@@ -70,6 +76,7 @@ void launch_data_grad(const Geo& g, const double* lam, const double* sg, double*
                       double* dy0, hipStream_t st);
 
 bool time_lds_fits(int n, bool fp32);
+FftPlan make_time_plan(int n);
 bool launch_precond(const Geo& g, const double* v, double* w, void* spec, bool fp32, int spatial,
                     const PrecondTables& tb, const double* vscale, int vs_stride, int accum,
                     hipStream_t st);

@@ -85,7 +85,7 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
   }
   const int n = p->nt - 1;
   if (!time_lds_fits(n, o->precision == PCOP_MIXED))
-    return fail(PCOP_ERR_UNSUPPORTED, "nt too large for the LDS time FFT (n <= 2048 in FP64)");
+    return fail(PCOP_ERR_UNSUPPORTED, "nt too large for the LDS time FFT");
   if (m > (1LL << 31) / 8) return fail(PCOP_ERR_UNSUPPORTED, "spatial grid too large");
   if ((long long)n * m * 2 > (1LL << 40)) return fail(PCOP_ERR_UNSUPPORTED, "problem too large");
   return PCOP_OK;
@@ -97,6 +97,8 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
 struct Layout {
   size_t total = 0;
   size_t dpow, twn64, twn32, twL64, twL32, mu1, lam, alpha, sg, ecoef;
+  size_t twM64, twM32, chirp64, chirp32, bhat64, bhat32;
+  int M = 1;
   size_t sc, H, coef, red, partial, wnorm2, norm, skip, active, finish, hcol;
   size_t basis, zbasis, tmp1, tmp2, spec;
   size_t mgcoef[12], mgz[12], mgr[12];
@@ -124,6 +126,14 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
   L.dpow = take(L, sizeof(double) * n);
   L.twn64 = take(L, 16 * (size_t)n);
   L.twn32 = take(L, 8 * (size_t)n);
+  const FftPlan tp = make_time_plan(n);
+  L.M = tp.bluestein ? tp.M : 1;
+  L.twM64 = take(L, 16 * (size_t)L.M);
+  L.twM32 = take(L, 8 * (size_t)L.M);
+  L.chirp64 = take(L, 16 * (size_t)n);
+  L.chirp32 = take(L, 8 * (size_t)n);
+  L.bhat64 = take(L, 16 * (size_t)L.M);
+  L.bhat32 = take(L, 8 * (size_t)L.M);
   L.twL64 = take(L, 16 * (size_t)Lf);
   L.twL32 = take(L, 8 * (size_t)Lf);
   L.mu1 = take(L, sizeof(double) * nx);
@@ -166,18 +176,6 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
     L.mg_levels = l;
   }
   L.total = (L.total + 255) & ~(size_t)255;
-}
-
-// prime factorisation of n into FFT radices (4s first, then primes)
-FftPlan make_plan(int n) {
-  FftPlan pl{};
-  pl.nrad = 0;
-  int r = n;
-  while (r % 4 == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = 4; r /= 4; }
-  for (int f = 2; f * f <= r && pl.nrad < 16; ++f)
-    while (r % f == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = f; r /= f; }
-  if (r > 1 && pl.nrad < 16) pl.rad[pl.nrad++] = r;
-  return pl;
 }
 
 }  // namespace
@@ -424,6 +422,57 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
     twn32[2 * t] = (float)std::cos(a);
     twn32[2 * t + 1] = (float)std::sin(a);
   }
+  // Bluestein tables: chirp w_t = exp(-i pi (t^2 mod 2n)/n), filter
+  // bb[m] = conj(w_m) for |m| < n wrapped cyclically into length M, bhat = FFT_M(bb)
+  const int M = L.M;
+  std::vector<double> twM64(2 * M), chirp64(2 * n), bhat64(2 * M);
+  std::vector<float> twM32(2 * M), chirp32(2 * n), bhat32(2 * M);
+  {
+    std::vector<long double> cM(M), sM(M);
+    for (int t = 0; t < M; ++t) {
+      long double a = -2.0L * PI * t / M;
+      cM[t] = std::cos(a);
+      sM[t] = std::sin(a);
+      twM64[2 * t] = (double)cM[t];
+      twM64[2 * t + 1] = (double)sM[t];
+      twM32[2 * t] = (float)cM[t];
+      twM32[2 * t + 1] = (float)sM[t];
+    }
+    std::vector<long double> cw(n), sw(n);
+    for (int t = 0; t < n; ++t) {
+      const long long q = ((long long)t * t) % (2LL * n);
+      long double a = -PI * (long double)q / n;
+      cw[t] = std::cos(a);
+      sw[t] = std::sin(a);
+      chirp64[2 * t] = (double)cw[t];
+      chirp64[2 * t + 1] = (double)sw[t];
+      chirp32[2 * t] = (float)cw[t];
+      chirp32[2 * t + 1] = (float)sw[t];
+    }
+    if (M > 1) {
+      std::vector<long double> br(M, 0.0L), bi(M, 0.0L);
+      for (int t = 0; t < n; ++t) {
+        br[t] = cw[t];
+        bi[t] = -sw[t];
+        if (t > 0) {
+          br[M - t] = cw[t];
+          bi[M - t] = -sw[t];
+        }
+      }
+      for (int k = 0; k < M; ++k) {
+        long double re = 0.0L, im = 0.0L;
+        for (int t = 0; t < M; ++t) {
+          const int e = (int)(((long long)k * t) % M);
+          re += br[t] * cM[e] - bi[t] * sM[e];
+          im += br[t] * sM[e] + bi[t] * cM[e];
+        }
+        bhat64[2 * k] = (double)re;
+        bhat64[2 * k + 1] = (double)im;
+        bhat32[2 * k] = (float)re;
+        bhat32[2 * k + 1] = (float)im;
+      }
+    }
+  }
   const int Lf = 2 * (nx + 1);
   for (int t = 0; t < Lf; ++t) {
     long double a = -2.0L * PI * t / Lf;
@@ -451,6 +500,12 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   if (e == hipSuccess) e = up(L.dpow, dpow.data(), sizeof(double) * n);
   if (e == hipSuccess) e = up(L.twn64, twn64.data(), sizeof(double) * 2 * n);
   if (e == hipSuccess) e = up(L.twn32, twn32.data(), sizeof(float) * 2 * n);
+  if (e == hipSuccess) e = up(L.twM64, twM64.data(), sizeof(double) * 2 * M);
+  if (e == hipSuccess) e = up(L.twM32, twM32.data(), sizeof(float) * 2 * M);
+  if (e == hipSuccess) e = up(L.chirp64, chirp64.data(), sizeof(double) * 2 * n);
+  if (e == hipSuccess) e = up(L.chirp32, chirp32.data(), sizeof(float) * 2 * n);
+  if (e == hipSuccess) e = up(L.bhat64, bhat64.data(), sizeof(double) * 2 * M);
+  if (e == hipSuccess) e = up(L.bhat32, bhat32.data(), sizeof(float) * 2 * M);
   if (e == hipSuccess) e = up(L.twL64, twL64.data(), sizeof(double) * 2 * Lf);
   if (e == hipSuccess) e = up(L.twL32, twL32.data(), sizeof(float) * 2 * Lf);
   if (e == hipSuccess) e = up(L.mu1, mu1.data(), sizeof(double) * nx);
@@ -586,7 +641,13 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   tb.lam = c->at<double>(L.lam);
   tb.alpha = c->at<double>(L.alpha);
   tb.active = nullptr;
-  tb.plan = make_plan(n);
+  tb.plan = make_time_plan(n);
+  tb.twM64 = c->at<double>(L.twM64);
+  tb.twM32 = c->at<float>(L.twM32);
+  tb.chirp64 = c->at<double>(L.chirp64);
+  tb.chirp32 = c->at<float>(L.chirp32);
+  tb.bhat64 = c->at<double>(L.bhat64);
+  tb.bhat32 = c->at<float>(L.bhat32);
   tb.mg_levels = L.mg_levels;
   for (int l = 0; l < L.mg_levels; ++l) {
     MgLevel& lv = tb.mg[l];

@@ -22,64 +22,111 @@ namespace pcop {
 
 // ---------------------------------------------------------------------------
 // time passes
+//
+// A block owns P consecutive spatial points and all n time levels.
+// Stockham mode: LDS holds two [n][P] buffers; the first stage of the forward
+// pass reads HBM directly and the last stage of the inverse pass writes HBM
+// directly.  Bluestein mode (n has a prime factor > 17): a length-M
+// power-of-two convolution in one in-place [P][M+1] LDS buffer,
+//   X_k = w_k sum_j (x_j w_j) conj(w_{k-j}),  w_j = exp(-i pi j^2/n),
+// with the FFT of the chirp filter precomputed (bhat).
 // ---------------------------------------------------------------------------
+struct TimeTables {
+  const void* twn;    // [n]   exp(-2 pi i t/n)
+  const void* twM;    // [M]   exp(-2 pi i t/M)
+  const void* chirp;  // [n]   exp(-i pi (t^2 mod 2n)/n)
+  const void* bhat;   // [M]   FFT_M of the chirp filter
+};
+
+// c_j = s (d_j v2_j + i v1_j / d_j) at time level j, spatial point i
 template <class T>
-__global__ void __launch_bounds__(256) time_fwd_kernel(Geo g, const double* __restrict__ v,
-                                                       cx<T>* __restrict__ spec,
-                                                       const double* __restrict__ dpow,
-                                                       const cx<T>* __restrict__ tw, FftPlan plan,
-                                                       int P, const double* __restrict__ vscale, int vs_stride,
-                                                       const int* __restrict__ active) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
-  const int n = g.n, m = g.m, K = g.K;
-  cx<T>* buf0 = reinterpret_cast<cx<T>*>(smem);
-  cx<T>* buf1 = buf0 + n * P;
-  const int i0 = blockIdx.x * P;
-  const double s = vscale ? vscale[(size_t)b * vs_stride] : 1.0;
-  const double* v1 = v + (size_t)b * g.vl;
-  const double* v2 = v1 + (size_t)n * m;
-  for (int t = threadIdx.x; t < n * P; t += blockDim.x) {
-    const int j = t / P, p = t - j * P;
-    const int i = i0 + p;
-    double a1 = 0.0, a2 = 0.0;
-    if (i < m) {
-      a1 = v1[(size_t)j * m + i];
-      a2 = v2[(size_t)j * m + i];
-    }
-    const double d = dpow[j];
-    buf0[t] = cx<T>{(T)(s * d * a2), (T)(s * a1 / d)};
-  }
-  __syncthreads();
-  cx<T>* res = tpo_fft<T, false>(buf0, buf1, n, P, plan, tw);
-  cx<T>* out = spec + (size_t)b * (size_t)(2 * K) * m;
+__device__ __forceinline__ cx<T> pack_input(const double* v1, const double* v2, const double* dpow, double s,
+                                            int j, int i, int m) {
+  if (i >= m) return cx<T>{0, 0};
+  const double d = dpow[j];
+  const size_t o = (size_t)j * m + i;
+  return cx<T>{(T)(s * d * v2[o]), (T)(s * v1[o] / d)};
+}
+
+// split the packed spectrum X into the two block spectra and store slices 2k, 2k+1
+template <class T, class GET>
+__device__ __forceinline__ void unpack_store(cx<T>* out, int n, int K, int P, int i0, int m, GET get) {
   for (int t = threadIdx.x; t < K * P; t += blockDim.x) {
     const int k = t / P, p = t - k * P;
     const int i = i0 + p;
     if (i >= m) continue;
     const int kn = (k == 0) ? 0 : n - k;
-    const cx<T> X = res[k * P + p];
-    const cx<T> Y = conj(res[kn * P + p]);
+    const cx<T> X = get(k, p);
+    const cx<T> Y = conj(get(kn, p));
     const cx<T> sum = X + Y, dif = X - Y;
     out[(size_t)(2 * k) * m + i] = cx<T>{sum.x * (T)0.5, sum.y * (T)0.5};
     out[(size_t)(2 * k + 1) * m + i] = cx<T>{dif.y * (T)0.5, -dif.x * (T)0.5};  // dif / (2i)
   }
 }
 
-template <class T>
-__global__ void __launch_bounds__(256) time_inv_kernel(Geo g, const cx<T>* __restrict__ spec,
-                                                       double* __restrict__ w,
-                                                       const double* __restrict__ dpow,
-                                                       const cx<T>* __restrict__ tw, FftPlan plan,
-                                                       int P, int accum,
-                                                       const int* __restrict__ active) {
+// w_1 = z_1 - z_2, w_2 = z_1 + z_2 with z_2 = Re(e)/(n d_j), z_1 = Im(e) d_j/n
+__device__ __forceinline__ void combine_store(double* w1, double* w2, const double* dpow, int n, int m, int j,
+                                              int i, double ex, double ey, int accum) {
+  const double d = dpow[j];
+  const double inv_n = 1.0 / (double)n;
+  const double z2 = ex * inv_n / d;
+  const double z1 = ey * inv_n * d;
+  const size_t o = (size_t)j * m + i;
+  if (accum) {
+    w1[o] += z1 - z2;
+    w2[o] += z1 + z2;
+  } else {
+    w1[o] = z1 - z2;
+    w2[o] = z1 + z2;
+  }
+}
+
+template <class T, int P>
+__global__ void __launch_bounds__(256) time_fwd_sk(Geo g, const double* __restrict__ v, cx<T>* __restrict__ spec,
+                                                   const double* __restrict__ dpow, const cx<T>* __restrict__ twn,
+                                                   FftPlan plan, const double* __restrict__ vscale, int vs_stride,
+                                                   const int* __restrict__ active) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   const int n = g.n, m = g.m, K = g.K;
-  cx<T>* buf0 = reinterpret_cast<cx<T>*>(smem);
-  cx<T>* buf1 = buf0 + n * P;
+  cx<T>* bufA = reinterpret_cast<cx<T>*>(smem);
+  cx<T>* bufB = bufA + n * P;
+  const int i0 = blockIdx.x * P;
+  const double s = vscale ? vscale[(size_t)b * vs_stride] : 1.0;
+  const double* v1 = v + (size_t)b * g.vl;
+  const double* v2 = v1 + (size_t)n * m;
+  auto ld0 = [&](int j, int p) { return pack_input<T>(v1, v2, dpow, s, j, i0 + p, m); };
+  auto stA = [&](int j, int p, cx<T> val) { bufA[j * P + p] = val; };
+  sk_stage_rt<T, P, -1>(plan.rad[0], n, 1, twn, ld0, stA);
+  __syncthreads();
+  cx<T>* src = bufA;
+  cx<T>* dst = bufB;
+  int Ns = plan.rad[0];
+  for (int st = 1; st < plan.nrad; ++st) {
+    auto ld = [&](int j, int p) { return src[j * P + p]; };
+    auto sto = [&](int j, int p, cx<T> val) { dst[j * P + p] = val; };
+    sk_stage_rt<T, P, -1>(plan.rad[st], n, Ns, twn, ld, sto);
+    __syncthreads();
+    Ns *= plan.rad[st];
+    cx<T>* t = src;
+    src = dst;
+    dst = t;
+  }
+  cx<T>* out = spec + (size_t)b * (size_t)(2 * K) * m;
+  unpack_store<T>(out, n, K, P, i0, m, [&](int k, int p) { return src[k * P + p]; });
+}
+
+template <class T, int P>
+__global__ void __launch_bounds__(256) time_inv_sk(Geo g, const cx<T>* __restrict__ spec, double* __restrict__ w,
+                                                   const double* __restrict__ dpow, const cx<T>* __restrict__ twn,
+                                                   FftPlan plan, int accum, const int* __restrict__ active) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int n = g.n, m = g.m, K = g.K;
+  cx<T>* bufA = reinterpret_cast<cx<T>*>(smem);
+  cx<T>* bufB = bufA + n * P;
   const int i0 = blockIdx.x * P;
   const cx<T>* in = spec + (size_t)b * (size_t)(2 * K) * m;
   for (int t = threadIdx.x; t < K * P; t += blockDim.x) {
@@ -91,30 +138,129 @@ __global__ void __launch_bounds__(256) time_inv_kernel(Geo g, const cx<T>* __res
       z1 = in[(size_t)(2 * k + 1) * m + i];
     }
     // e_k = Z2 + i Z1 and, for the mirrored frequency, e_{n-k} = conj Z2 + i conj Z1
-    buf0[k * P + p] = cx<T>{z2.x - z1.y, z2.y + z1.x};
-    if (k != 0 && 2 * k != n) buf0[(n - k) * P + p] = cx<T>{z2.x + z1.y, z1.x - z2.y};
+    bufA[k * P + p] = cx<T>{z2.x - z1.y, z2.y + z1.x};
+    if (k != 0 && 2 * k != n) bufA[(n - k) * P + p] = cx<T>{z2.x + z1.y, z1.x - z2.y};
   }
   __syncthreads();
-  cx<T>* res = tpo_fft<T, true>(buf0, buf1, n, P, plan, tw);
   double* w1 = w + (size_t)b * g.vl;
   double* w2 = w1 + (size_t)n * m;
-  const double inv_n = 1.0 / (double)n;
+  cx<T>* src = bufA;
+  cx<T>* dst = bufB;
+  int Ns = 1;
+  for (int st = 0; st < plan.nrad; ++st) {
+    auto ld = [&](int j, int p) { return src[j * P + p]; };
+    if (st + 1 < plan.nrad) {
+      auto sto = [&](int j, int p, cx<T> val) { dst[j * P + p] = val; };
+      sk_stage_rt<T, P, 1>(plan.rad[st], n, Ns, twn, ld, sto);
+      __syncthreads();
+      cx<T>* t = src;
+      src = dst;
+      dst = t;
+    } else {
+      auto sto = [&](int j, int p, cx<T> val) {
+        const int i = i0 + p;
+        if (i < m) combine_store(w1, w2, dpow, n, m, j, i, (double)val.x, (double)val.y, accum);
+      };
+      sk_stage_rt<T, P, 1>(plan.rad[st], n, Ns, twn, ld, sto);
+    }
+    Ns *= plan.rad[st];
+  }
+}
+
+template <class T, int P, int M>
+__global__ void __launch_bounds__(256) time_fwd_bl(Geo g, const double* __restrict__ v, cx<T>* __restrict__ spec,
+                                                   const double* __restrict__ dpow, TimeTables tt,
+                                                   const double* __restrict__ vscale, int vs_stride,
+                                                   const int* __restrict__ active) {
+  constexpr int LD = M + 1;
+  __shared__ cx<T> buf[P * LD];
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int n = g.n, m = g.m, K = g.K;
+  const cx<T>* twM = reinterpret_cast<const cx<T>*>(tt.twM);
+  const cx<T>* chirp = reinterpret_cast<const cx<T>*>(tt.chirp);
+  const cx<T>* bhat = reinterpret_cast<const cx<T>*>(tt.bhat);
+  const int i0 = blockIdx.x * P;
+  const double s = vscale ? vscale[(size_t)b * vs_stride] : 1.0;
+  const double* v1 = v + (size_t)b * g.vl;
+  const double* v2 = v1 + (size_t)n * m;
+  for (int t = threadIdx.x; t < M * P; t += blockDim.x) {
+    const int j = t / P, p = t - j * P;
+    cx<T> a{0, 0};
+    if (j < n) a = pack_input<T>(v1, v2, dpow, s, j, i0 + p, m) * chirp[j];
+    buf[p * LD + j] = a;
+  }
+  __syncthreads();
+  p2_fft<T, -1, M, P, 256>(buf, LD, twM);
+  for (int t = threadIdx.x; t < M * P; t += blockDim.x) {
+    const int p = t / M, k = t - p * M;
+    buf[p * LD + k] = buf[p * LD + k] * bhat[k];
+  }
+  __syncthreads();
+  p2_fft<T, 1, M, P, 256>(buf, LD, twM);
+  const T invM = (T)1 / (T)M;
+  for (int t = threadIdx.x; t < n * P; t += blockDim.x) {
+    const int p = t / n, k = t - p * n;
+    buf[p * LD + k] = scale(buf[p * LD + k] * chirp[k], invM);
+  }
+  __syncthreads();
+  cx<T>* out = spec + (size_t)b * (size_t)(2 * K) * m;
+  unpack_store<T>(out, n, K, P, i0, m, [&](int k, int p) { return buf[p * LD + k]; });
+}
+
+// inverse DFT through the forward chirp transform: e = conj(DFT(conj(E)))
+template <class T, int P, int M>
+__global__ void __launch_bounds__(256) time_inv_bl(Geo g, const cx<T>* __restrict__ spec, double* __restrict__ w,
+                                                   const double* __restrict__ dpow, TimeTables tt, int accum,
+                                                   const int* __restrict__ active) {
+  constexpr int LD = M + 1;
+  __shared__ cx<T> buf[P * LD];
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int n = g.n, m = g.m, K = g.K;
+  const cx<T>* twM = reinterpret_cast<const cx<T>*>(tt.twM);
+  const cx<T>* chirp = reinterpret_cast<const cx<T>*>(tt.chirp);
+  const cx<T>* bhat = reinterpret_cast<const cx<T>*>(tt.bhat);
+  const int i0 = blockIdx.x * P;
+  const cx<T>* in = spec + (size_t)b * (size_t)(2 * K) * m;
+  for (int t = threadIdx.x; t < (M - n) * P; t += blockDim.x) {
+    const int j = n + t / P, p = t - (t / P) * P;
+    buf[p * LD + j] = cx<T>{0, 0};
+  }
+  for (int t = threadIdx.x; t < K * P; t += blockDim.x) {
+    const int k = t / P, p = t - k * P;
+    const int i = i0 + p;
+    cx<T> z2{0, 0}, z1{0, 0};
+    if (i < m) {
+      z2 = in[(size_t)(2 * k) * m + i];
+      z1 = in[(size_t)(2 * k + 1) * m + i];
+    }
+    // conj(e_k) = conj(Z2 + i Z1), conj(e_{n-k}) = conj(conj Z2 + i conj Z1)
+    const cx<T> ek{z2.x - z1.y, -(z2.y + z1.x)};
+    buf[p * LD + k] = ek * chirp[k];
+    if (k != 0 && 2 * k != n) {
+      const cx<T> enk{z2.x + z1.y, -(z1.x - z2.y)};
+      buf[p * LD + (n - k)] = enk * chirp[n - k];
+    }
+  }
+  __syncthreads();
+  p2_fft<T, -1, M, P, 256>(buf, LD, twM);
+  for (int t = threadIdx.x; t < M * P; t += blockDim.x) {
+    const int p = t / M, k = t - p * M;
+    buf[p * LD + k] = buf[p * LD + k] * bhat[k];
+  }
+  __syncthreads();
+  p2_fft<T, 1, M, P, 256>(buf, LD, twM);
+  double* w1 = w + (size_t)b * g.vl;
+  double* w2 = w1 + (size_t)n * m;
+  const double invM = 1.0 / (double)M;
   for (int t = threadIdx.x; t < n * P; t += blockDim.x) {
     const int j = t / P, p = t - j * P;
     const int i = i0 + p;
     if (i >= m) continue;
-    const cx<T> e = res[t];
-    const double d = dpow[j];
-    const double z2 = (double)e.x * inv_n / d;
-    const double z1 = (double)e.y * inv_n * d;
-    const size_t o = (size_t)j * m + i;
-    if (accum) {
-      w1[o] += z1 - z2;
-      w2[o] += z1 + z2;
-    } else {
-      w1[o] = z1 - z2;
-      w2[o] = z1 + z2;
-    }
+    const cx<T> e = buf[p * LD + j] * chirp[j];
+    // e_j = conj(chirp_j c_j / M)
+    combine_store(w1, w2, dpow, n, m, j, i, (double)e.x * invM, -(double)e.y * invM, accum);
   }
 }
 
@@ -157,8 +303,7 @@ __global__ void __launch_bounds__(NT) dst_lines_kernel(Geo g, cx<T>* __restrict_
   const int l0 = (int)(blockIdx.x - plane * tiles) * LINES;
   const long long pbase = plane * lg.plane_stride;
   if (DIVIDE && dp.active) {
-    const long long b = pbase / ((long long)2 * g.K * g.m);
-    if (!dp.active[b]) return;
+    if (!dp.active[(int)(plane / (2 * g.K))]) return;
   }
   for (int t = threadIdx.x; t < LINES * N; t += NT) {
     int l, e;
@@ -182,29 +327,28 @@ __global__ void __launch_bounds__(NT) dst_lines_kernel(Geo g, cx<T>* __restrict_
   __syncthreads();
   p2_fft<T, -1, L, LINES, NT>(buf, LD, twL);
   if (DIVIDE) {
-    const long long slice_len = (long long)2 * g.K * g.m;
+    // the last-axis pass has one plane per slice q of member b; the shift
+    // sigma_q = lambda_k + alpha_b (q even) or conj(lambda_k) + alpha_b (q odd)
+    // is uniform over the block
+    const int b = (int)(plane / (2 * g.K));
+    const int q = (int)(plane - (long long)b * 2 * g.K);
+    const int k = q >> 1;
+    const double sre = dp.lam[2 * k] + dp.alpha[b];
+    const double sim = (q & 1) ? -dp.lam[2 * k + 1] : dp.lam[2 * k + 1];
     for (int t = threadIdx.x; t < LINES * N; t += NT) {
       const int e = t / LINES;
       const int l = t - e * LINES;
       cx<T> y = buf[l * LD + e + 1];
-      if (l0 + l < lg.lines) {
-        const long long off = pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride;
-        const int b = (int)(off / slice_len);
-        const long long r = off - (long long)b * slice_len;
-        const int q = (int)(r / g.m);
-        const int i = (int)(r - (long long)q * g.m);
-        const int c1 = i % g.nx;
-        const int c2 = (i / g.nx) % g.nx;
-        double mu = dp.mu1[c1] + dp.mu1[c2];
-        if (g.dim == 3) mu += dp.mu1[i / (g.nx * g.nx)];
-        const int k = q >> 1;
-        const double lre = dp.lam[2 * k];
-        const double lim = (q & 1) ? -dp.lam[2 * k + 1] : dp.lam[2 * k + 1];
-        const double dre = lre + dp.alpha[b] + g.tau * mu;
-        const double den = dre * dre + lim * lim;
-        // cnorm / (dre + i lim) = cnorm (dre - i lim) / den
+      const int line = l0 + l;
+      if (line < lg.lines) {
+        // in-plane coordinates: line = x1 (+ nx x2 in 3-D), element = last axis
+        double mu = dp.mu1[e] + dp.mu1[line % g.nx];
+        if (g.dim == 3) mu += dp.mu1[line / g.nx];
+        const double dre = sre + g.tau * mu;
+        const double den = dre * dre + sim * sim;
+        // cnorm / (dre + i sim) = cnorm (dre - i sim) / den
         const double fre = dp.cnorm * dre / den;
-        const double fim = -dp.cnorm * lim / den;
+        const double fim = -dp.cnorm * sim / den;
         y = y * cx<T>{(T)fre, (T)fim};
       }
       buf[l * LD + e + 1] = y;
@@ -314,45 +458,135 @@ static bool dst_solve(const Geo& g, cx<T>* spec, const PrecondTables& tb, hipStr
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <class T>
-static int time_cols(int n) {
-  // two ping-pong buffers of n x P complex in <= 64 KiB of LDS
-  int P = 65536 / (2 * n * (int)sizeof(cx<T>));
-  int p2 = 1;
-  while (p2 * 2 <= P && p2 < 64) p2 *= 2;
-  return p2;
+// columns per block for the time passes (power of two, 4..16, LDS <= 64 KiB)
+static int time_cols_sk(int n, int csz) {
+  int P = 16;
+  while (P > 4 && (size_t)2 * n * P * csz > 65536) P /= 2;
+  return ((size_t)2 * n * P * csz <= 65536) ? P : 0;
 }
-
-template <class T>
-static void time_fwd(const Geo& g, const double* v, cx<T>* spec, const PrecondTables& tb,
-                     const double* vscale, int vs_stride, hipStream_t st) {
-  const int P = time_cols<T>(g.n);
-  dim3 grid((g.m + P - 1) / P, g.B);
-  size_t lds = (size_t)2 * g.n * P * sizeof(cx<T>);
-  const cx<T>* tw = reinterpret_cast<const cx<T>*>(sizeof(T) == 8 ? (const void*)tb.twn64 : (const void*)tb.twn32);
-  const double bytes = (8.0 * g.vl + sizeof(cx<T>) * 2.0 * g.K * (double)g.m) * tb.nact;
-  tbeg(tb.timer, KF_TIME_FWD, bytes);
-  time_fwd_kernel<T><<<grid, 256, lds, st>>>(g, v, spec, tb.dpow, tw, tb.plan, P, vscale, vs_stride, tb.active);
-  tend(tb.timer);
-}
-
-template <class T>
-static void time_inv(const Geo& g, const cx<T>* spec, double* w, const PrecondTables& tb, int accum,
-                     hipStream_t st) {
-  const int P = time_cols<T>(g.n);
-  dim3 grid((g.m + P - 1) / P, g.B);
-  size_t lds = (size_t)2 * g.n * P * sizeof(cx<T>);
-  const cx<T>* tw = reinterpret_cast<const cx<T>*>(sizeof(T) == 8 ? (const void*)tb.twn64 : (const void*)tb.twn32);
-  const double bytes = ((accum ? 16.0 : 8.0) * g.vl + sizeof(cx<T>) * 2.0 * g.K * (double)g.m) * tb.nact;
-  tbeg(tb.timer, KF_TIME_INV, bytes);
-  time_inv_kernel<T><<<grid, 256, lds, st>>>(g, spec, w, tb.dpow, tw, tb.plan, P, accum, tb.active);
-  tend(tb.timer);
+static int time_cols_bl(int M, int csz) {
+  int P = 16;
+  while (P > 4 && (size_t)(M + 1) * P * csz > 65536) P /= 2;
+  return ((size_t)(M + 1) * P * csz <= 65536) ? P : 0;
 }
 
 bool time_lds_fits(int n, bool fp32) {
-  const int P = fp32 ? time_cols<float>(n) : time_cols<double>(n);
-  const size_t bytes = (size_t)2 * n * P * (fp32 ? 8 : 16);
-  return P >= 1 && bytes <= 65536;
+  const FftPlan pl = make_time_plan(n);
+  const int csz = fp32 ? 8 : 16;
+  return pl.bluestein ? time_cols_bl(pl.M, csz) > 0 : time_cols_sk(n, csz) > 0;
+}
+
+FftPlan make_time_plan(int n) {
+  FftPlan pl{};
+  int r = n;
+  int big = 0;
+  for (int f = 2; f * f <= r; ++f)
+    while (r % f == 0) {
+      if (f > 17) big = 1;
+      r /= f;
+    }
+  if (r > 17) big = 1;
+  if (big) {
+    pl.bluestein = 1;
+    pl.M = 1;
+    while (pl.M < 2 * n - 1) pl.M *= 2;
+    pl.nrad = 0;
+    return pl;
+  }
+  r = n;
+  while (r % 8 == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = 8; r /= 8; }
+  while (r % 4 == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = 4; r /= 4; }
+  while (r % 2 == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = 2; r /= 2; }
+  for (int f = 3; f <= 17 && pl.nrad < 16; f += 2)
+    while (r % f == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = f; r /= f; }
+  if (pl.nrad == 0) pl.rad[pl.nrad++] = 1;  // n = 1
+  return pl;
+}
+
+template <class T, int P, int M>
+static void bl_launch(bool fwd, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
+                      const TimeTables& tt, const double* vscale, int vs_stride, int accum, hipStream_t st) {
+  // only shapes whose LDS tile fits 64 KiB are instantiated (time_cols_bl picks P accordingly)
+  if constexpr ((size_t)(M + 1) * P * sizeof(cx<T>) <= 65536) {
+    dim3 grid((g.m + P - 1) / P, g.B);
+    if (fwd)
+      time_fwd_bl<T, P, M><<<grid, 256, 0, st>>>(g, v, spec, tb.dpow, tt, vscale, vs_stride, tb.active);
+    else
+      time_inv_bl<T, P, M><<<grid, 256, 0, st>>>(g, spec, w, tb.dpow, tt, accum, tb.active);
+  }
+}
+
+template <class T, int P>
+static bool bl_dispatch_M(bool fwd, int M, const Geo& g, const double* v, cx<T>* spec, double* w,
+                          const PrecondTables& tb, const TimeTables& tt, const double* vscale, int vs_stride,
+                          int accum, hipStream_t st) {
+  switch (M) {
+    case 8: bl_launch<T, P, 8>(fwd, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st); return true;
+    case 16: bl_launch<T, P, 16>(fwd, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st); return true;
+    case 32: bl_launch<T, P, 32>(fwd, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st); return true;
+    case 64: bl_launch<T, P, 64>(fwd, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st); return true;
+    case 128: bl_launch<T, P, 128>(fwd, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st); return true;
+    case 256: bl_launch<T, P, 256>(fwd, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st); return true;
+    case 512: bl_launch<T, P, 512>(fwd, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st); return true;
+    case 1024: bl_launch<T, P, 1024>(fwd, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st); return true;
+    case 2048: bl_launch<T, P, 2048>(fwd, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st); return true;
+    default: return false;
+  }
+}
+
+template <class T>
+static bool time_pass(bool fwd, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
+                      const double* vscale, int vs_stride, int accum, hipStream_t st) {
+  const bool f32 = sizeof(T) == 4;
+  TimeTables tt{f32 ? (const void*)tb.twn32 : (const void*)tb.twn64, f32 ? (const void*)tb.twM32 : (const void*)tb.twM64,
+                f32 ? (const void*)tb.chirp32 : (const void*)tb.chirp64, f32 ? (const void*)tb.bhat32 : (const void*)tb.bhat64};
+  const int csz = (int)sizeof(cx<T>);
+  if (tb.plan.bluestein) {
+    const int P = time_cols_bl(tb.plan.M, csz);
+    if (P == 16) return bl_dispatch_M<T, 16>(fwd, tb.plan.M, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st);
+    if (P == 8) return bl_dispatch_M<T, 8>(fwd, tb.plan.M, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st);
+    if (P == 4) return bl_dispatch_M<T, 4>(fwd, tb.plan.M, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st);
+    return false;
+  }
+  const int P = time_cols_sk(g.n, csz);
+  if (P == 0) return false;
+  dim3 grid((g.m + P - 1) / P, g.B);
+  const size_t lds = (size_t)2 * g.n * P * csz;
+  const cx<T>* twn = reinterpret_cast<const cx<T>*>(tt.twn);
+#define PCOP_TIME_SK(PP)                                                                                   \
+  if (fwd)                                                                                                 \
+    time_fwd_sk<T, PP><<<grid, 256, lds, st>>>(g, v, spec, tb.dpow, twn, tb.plan, vscale, vs_stride, tb.active); \
+  else                                                                                                     \
+    time_inv_sk<T, PP><<<grid, 256, lds, st>>>(g, spec, w, tb.dpow, twn, tb.plan, accum, tb.active);
+  if (P == 16) {
+    PCOP_TIME_SK(16)
+  } else if (P == 8) {
+    PCOP_TIME_SK(8)
+  } else {
+    PCOP_TIME_SK(4)
+  }
+#undef PCOP_TIME_SK
+  return true;
+}
+
+template <class T>
+static bool time_fwd(const Geo& g, const double* v, cx<T>* spec, const PrecondTables& tb,
+                     const double* vscale, int vs_stride, hipStream_t st) {
+  const double bytes = (8.0 * g.vl + sizeof(cx<T>) * 2.0 * g.K * (double)g.m) * tb.nact;
+  tbeg(tb.timer, KF_TIME_FWD, bytes);
+  const bool ok = time_pass<T>(true, g, v, spec, nullptr, tb, vscale, vs_stride, 0, st);
+  tend(tb.timer);
+  return ok;
+}
+
+template <class T>
+static bool time_inv(const Geo& g, const cx<T>* spec, double* w, const PrecondTables& tb, int accum,
+                     hipStream_t st) {
+  const double bytes = ((accum ? 16.0 : 8.0) * g.vl + sizeof(cx<T>) * 2.0 * g.K * (double)g.m) * tb.nact;
+  tbeg(tb.timer, KF_TIME_INV, bytes);
+  const bool ok = time_pass<T>(false, g, nullptr, const_cast<cx<T>*>(spec), w, tb, nullptr, 0, accum, st);
+  tend(tb.timer);
+  return ok;
 }
 
 bool launch_precond(const Geo& g, const double* v, double* w, void* spec, bool fp32, int spatial,
@@ -360,16 +594,16 @@ bool launch_precond(const Geo& g, const double* v, double* w, void* spec, bool f
                     hipStream_t st) {
   if (fp32) {
     cx<float>* s = reinterpret_cast<cx<float>*>(spec);
-    time_fwd<float>(g, v, s, tb, vscale, vs_stride, st);
+    if (!time_fwd<float>(g, v, s, tb, vscale, vs_stride, st)) return false;
     bool ok = (spatial == 0) ? dst_solve<float>(g, s, tb, st) : launch_mg_solve(g, spec, true, tb, st);
     if (!ok) return false;
-    time_inv<float>(g, s, w, tb, accum, st);
+    if (!time_inv<float>(g, s, w, tb, accum, st)) return false;
   } else {
     cx<double>* s = reinterpret_cast<cx<double>*>(spec);
-    time_fwd<double>(g, v, s, tb, vscale, vs_stride, st);
+    if (!time_fwd<double>(g, v, s, tb, vscale, vs_stride, st)) return false;
     bool ok = (spatial == 0) ? dst_solve<double>(g, s, tb, st) : launch_mg_solve(g, spec, false, tb, st);
     if (!ok) return false;
-    time_inv<double>(g, s, w, tb, accum, st);
+    if (!time_inv<double>(g, s, w, tb, accum, st)) return false;
   }
   return true;
 }

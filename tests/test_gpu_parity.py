@@ -88,6 +88,12 @@ PRECOND_CASES = [
     (2, 63, 18, (1e-6,), 1.0 / 36),      # n = 17 prime, eps = tau/2
     (3, 7, 8, (1e-4,), None),            # 3-D sine transforms
     (2, 3, 13, (1e-4,), None),           # smallest sine length
+    (2, 7, 20, (1e-4,), None),           # n = 19: chirp-z (Bluestein) time transform
+    (2, 3, 128, (1e-6, 1e-2), None),     # n = 127: chirp-z, M = 256
+    (2, 3, 512, (1e-6,), None),          # n = 511 = 7 * 73: chirp-z, M = 1024
+    (2, 7, 256, (1e-2,), None),          # n = 255 = 3 * 5 * 17
+    (2, 7, 65, (1e-3,), None),           # n = 64 = 8 * 8
+    (2, 15, 12, (1e-3,), None),          # n = 11 (generic radix 11)
 ]
 
 
@@ -102,7 +108,7 @@ def test_precond_apply_fp64(dim, nx, nt, gammas, eps):
         assert rel(w[b], wo) < 1e-11, rel(w[b], wo)
 
 
-@pytest.mark.parametrize("dim,nx,nt,gammas,eps", PRECOND_CASES[:3])
+@pytest.mark.parametrize("dim,nx,nt,gammas,eps", PRECOND_CASES[:3] + PRECOND_CASES[8:11])
 def test_precond_apply_mixed(dim, nx, nt, gammas, eps):
     s = Solver(dim, nx, nt, list(gammas), eps=eps, precision="mixed", side="flexible", device=DEV)
     v = W.random_vector(dim, nx, nt, seed=8, batch=len(gammas))
