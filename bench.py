@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain device copy of 1 GiB (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -159,6 +161,12 @@ def main():
 
     cfg = W.CONFIGS[args.config]
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     members = list(range(len(cfg.gammas)))
     print(f"# bench: {cfg.name} members={len(members)} generating inputs", file=sys.stderr, flush=True)
     g = np.empty((len(members), cfg.n, cfg.m))

@@ -165,7 +165,7 @@ pcop_status pcop_precond_apply(pcop_ctx ctx, const double* v, double* w);
 
 /* Solve A x = b (transpose = 0) or A^T x = b (transpose = 1) with
  * preconditioned GMRES.  x: device vector, initial guess on entry, solution
- * on exit.  info: host array [batch] (may be NULL).  res_hist: host array
+ * on exit.  b and x must be 16-byte aligned (PCOP_ERR_INVALID_ARG otherwise).  info: host array [batch] (may be NULL).  res_hist: host array
  * [batch][maxit + 1] of monitored relative residuals (may be NULL; entries
  * after a member's last step are left untouched).  Returns
  * PCOP_NOT_CONVERGED (with x and info filled) when a member misses rtol. */

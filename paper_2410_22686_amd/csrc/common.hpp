@@ -54,6 +54,15 @@ struct Geo {
   double h2inv;  // 1/h^2
 };
 
+// Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
+// For kernels whose neighbouring blocks share data, remap the hardware block
+// order so that every XCD walks one contiguous range of logical blocks.
+__device__ __forceinline__ int xcd_remap(int hw, int total) {
+  const int per = total / 8;
+  if (hw >= per * 8) return hw;
+  return (hw % 8) * per + hw / 8;
+}
+
 // fixed-order wavefront sum (xor butterfly over 64 lanes)
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

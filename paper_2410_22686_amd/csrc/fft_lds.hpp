@@ -151,13 +151,28 @@ __device__ __forceinline__ void sk_stage(int n, int Ns, const cx<T>* __restrict_
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = load(jb + r * nR, p);
     if (R > 1 && jl != 0) {
-      cx<T> w1 = twn[jl * tstep];
-      if (SG > 0) w1.y = -w1.y;
-      cx<T> w = w1;
+      if constexpr (sizeof(T) == 8) {
+        // FP64: powers of one looked-up twiddle
+        cx<T> w1 = twn[jl * tstep];
+        if (SG > 0) w1.y = -w1.y;
+        cx<T> w = w1;
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        v[r] = v[r] * w;
-        w = w * w1;
+        for (int r = 1; r < R; ++r) {
+          v[r] = v[r] * w;
+          w = w * w1;
+        }
+      } else {
+        // FP32: every twiddle from the correctly rounded table
+        const int e1 = jl * tstep;
+        int e = e1;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cx<T> w = twn[e];
+          if (SG > 0) w.y = -w.y;
+          v[r] = v[r] * w;
+          e += e1;
+          if (e >= n) e -= n;
+        }
       }
     }
     dft_any<T, SG, R>(v, twn, nR);
@@ -214,11 +229,24 @@ __device__ __forceinline__ void p2_stage(cx<T>* buf, int ld, int Ns, const cx<T>
       const int jb = bf - line * (L / R);
       const int jl = jb % Ns;
       const int tstep = L / (Ns * R);
+      if (jl != 0) {
+        if constexpr (sizeof(T) == 8) {
+          cx<T> w1 = twL[jl * tstep];
+          if (SG > 0) w1.y = -w1.y;
+          cx<T> w = w1;
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        cx<T> w = twL[(r * jl * tstep) & (L - 1)];
-        if (SG > 0) w.y = -w.y;
-        v[q][r] = v[q][r] * w;
+          for (int r = 1; r < R; ++r) {
+            v[q][r] = v[q][r] * w;
+            w = w * w1;
+          }
+        } else {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            cx<T> w = twL[(r * jl * tstep) & (L - 1)];
+            if (SG > 0) w.y = -w.y;
+            v[q][r] = v[q][r] * w;
+          }
+        }
       }
       dftR<T, SG, R>(v[q]);
       const int base = (jb / Ns) * Ns * R + jl;

@@ -49,13 +49,19 @@ __global__ void __launch_bounds__(256) kkt_apply_kernel(
     const double* __restrict__ alpha, const double* __restrict__ xscale, int xs_stride,
     const int* __restrict__ active, double sgn, const double* __restrict__ ecoef, double ediag,
     double eoff, int jchunk) {
-  const int b = blockIdx.z;
+  // logical block (x: spatial tile, y: time chunk, z: member) in XCD-friendly order
+  const int total = gridDim.x * gridDim.y * gridDim.z;
+  const int hw = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int lg = xcd_remap(hw, total);
+  const int bx = lg % gridDim.x;
+  const int by = (lg / gridDim.x) % gridDim.y;
+  const int b = lg / (gridDim.x * gridDim.y);
   if (active && !active[b]) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = bx * blockDim.x + threadIdx.x;
   if (i >= g.m) return;
   const int nx = g.nx, n = g.n, m = g.m;
   const int c1 = i % nx, c2 = (i / nx) % nx, c3 = (DIM == 3) ? i / (nx * nx) : 0;
-  const int j0 = blockIdx.y * jchunk;
+  const int j0 = by * jchunk;
   const int j1 = min(n, j0 + jchunk);
   const double a = alpha[b];
   const double s = xscale ? xscale[(size_t)b * xs_stride] : 1.0;

@@ -16,7 +16,7 @@ constexpr int kNT = 256;
 constexpr int kNWave = kNT / kWave;
 
 int krylov_blocks(long long vl) {
-  long long want = (vl + kNT * 4 - 1) / (kNT * 4);
+  long long want = (vl / 2 + kNT * 4 - 1) / (kNT * 4);
   if (want < 1) want = 1;
   if (want > 1024) want = 1024;
   return (int)want;
@@ -44,6 +44,8 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NACC], int ncol
   }
 }
 
+// Vectors are read as double2 (the length 2 n m of a member vector is even
+// and every base address is 16-byte aligned).
 template <int MAXNV>
 __global__ void __launch_bounds__(kNT) mdot_kernel(KrylovArgs ka, int nv, const double* __restrict__ w,
                                                    double* __restrict__ partial, int nblk) {
@@ -52,14 +54,19 @@ __global__ void __launch_bounds__(kNT) mdot_kernel(KrylovArgs ka, int nv, const 
   double acc[MAXNV + 1];
 #pragma unroll
   for (int i = 0; i <= MAXNV; ++i) acc[i] = 0.0;
-  const double* wb = w + (size_t)b * ka.vl;
-  const double* vb = ka.basis + (size_t)b * ka.vl;
-  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < ka.vl; e += (long long)nblk * kNT) {
-    const double wv = wb[e];
+  const double2* wb = reinterpret_cast<const double2*>(w + (size_t)b * ka.vl);
+  const double2* vb = reinterpret_cast<const double2*>(ka.basis + (size_t)b * ka.vl);
+  const long long n2 = ka.vl / 2;
+  const long long ss = ka.slot_stride / 2;
+  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < n2; e += (long long)nblk * kNT) {
+    const double2 wv = wb[e];
 #pragma unroll
     for (int i = 0; i < MAXNV; ++i)
-      if (i < nv) acc[i] += vb[(size_t)i * ka.slot_stride + e] * wv;
-    acc[MAXNV] += wv * wv;
+      if (i < nv) {
+        const double2 v = vb[(size_t)i * ss + e];
+        acc[i] += v.x * wv.x + v.y * wv.y;
+      }
+    acc[MAXNV] += wv.x * wv.x + wv.y * wv.y;
   }
   // columns 0..nv-1: dots, column nv: the squared norm
   double out[MAXNV + 1];
@@ -68,6 +75,8 @@ __global__ void __launch_bounds__(kNT) mdot_kernel(KrylovArgs ka, int nv, const 
   block_reduce_store<MAXNV + 1>(out, nv + 1, partial + ((size_t)b * nblk + blockIdx.x) * kRedStride);
 }
 
+// the update keeps the basis values of its element in registers for the
+// second product, so it works on one double per thread and iteration
 template <int MAXNV>
 __global__ void __launch_bounds__(kNT) update_kernel(KrylovArgs ka, int nv, double* __restrict__ w,
                                                      const double* __restrict__ coef, int coef_ld,
@@ -112,14 +121,19 @@ __global__ void __launch_bounds__(kNT) combine_kernel(KrylovArgs ka, int nv, con
   __shared__ double c[MAXNV];
   for (int i = threadIdx.x; i < MAXNV; i += kNT) c[i] = (i < nv) ? coef[(size_t)b * coef_ld + i] : 0.0;
   __syncthreads();
-  double* ob = out + (size_t)b * ka.vl;
-  const double* vb = ka.basis + (size_t)b * ka.vl;
-  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < ka.vl;
-       e += (long long)gridDim.x * kNT) {
-    double acc = accum ? ob[e] : 0.0;
+  double2* ob = reinterpret_cast<double2*>(out + (size_t)b * ka.vl);
+  const double2* vb = reinterpret_cast<const double2*>(ka.basis + (size_t)b * ka.vl);
+  const long long n2 = ka.vl / 2;
+  const long long ss = ka.slot_stride / 2;
+  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < n2; e += (long long)gridDim.x * kNT) {
+    double2 acc = accum ? ob[e] : double2{0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < MAXNV; ++i)
-      if (i < nv && c[i] != 0.0) acc += c[i] * vb[(size_t)i * ka.slot_stride + e];
+      if (i < nv && c[i] != 0.0) {
+        const double2 v = vb[(size_t)i * ss + e];
+        acc.x += c[i] * v.x;
+        acc.y += c[i] * v.y;
+      }
     ob[e] = acc;
   }
 }
@@ -200,11 +214,14 @@ __global__ void gs_step2_kernel(const double* __restrict__ red, int j, int B, co
   (void)wnorm2;
 }
 
-// out[b][i] = H[b][j][i], i <= j + 1 (the column the host reads back)
-__global__ void pack_hcol_kernel(const double* __restrict__ H, int H_ld, int j, int B, double* __restrict__ out) {
+// out[b][i] = H[b][j][i] for i <= j + 1 (the column the host reads back) and
+// out[b][kMaxBasis] = skip[b] (1: no second Gram-Schmidt pass needed)
+__global__ void pack_hcol_kernel(const double* __restrict__ H, int H_ld, int j, int B, const int* __restrict__ skip,
+                                 double* __restrict__ out) {
   const int b = blockIdx.x;
   const double* Hc = H + ((size_t)b * (kMaxBasis - 1) + j) * H_ld;
-  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) out[(size_t)b * kMaxBasis + i] = Hc[i];
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) out[(size_t)b * (kMaxBasis + 1) + i] = Hc[i];
+  if (threadIdx.x == 0) out[(size_t)b * (kMaxBasis + 1) + kMaxBasis] = skip ? (double)skip[b] : 1.0;
   (void)B;
 }
 
@@ -264,8 +281,8 @@ void launch_gs_step2(const double* red, int j, int B, const double* sc, double* 
                                                 sc_out, active, final_pass);
 }
 
-void launch_pack_hcol(const double* H, int H_ld, int j, int B, double* out, hipStream_t st) {
-  pack_hcol_kernel<<<B, 64, 0, st>>>(H, H_ld, j, B, out);
+void launch_pack_hcol(const double* H, int H_ld, int j, int B, const int* skip, double* out, hipStream_t st) {
+  pack_hcol_kernel<<<B, 64, 0, st>>>(H, H_ld, j, B, skip, out);
 }
 
 void launch_set_scale(const double* red, int col, int B, double* sc, double* norm, const int* active,

@@ -113,7 +113,7 @@ void launch_gs_step1(const double* red, int j, int B, const double* sc, double* 
 void launch_gs_step2(const double* red, int j, int B, const double* sc, double* H, int H_ld,
                      double* coef, int coef_ld, const double* wnorm2, double reorth_tol, int* skip,
                      double* sc_out, const int* active, int final_pass, hipStream_t st);
-void launch_pack_hcol(const double* H, int H_ld, int j, int B, double* out, hipStream_t st);
+void launch_pack_hcol(const double* H, int H_ld, int j, int B, const int* skip, double* out, hipStream_t st);
 void launch_set_scale(const double* red, int col, int B, double* sc, double* norm, const int* active,
                       hipStream_t st);
 

@@ -151,7 +151,7 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
   L.skip = take(L, sizeof(int) * B);
   L.active = take(L, sizeof(int) * B);
   L.finish = take(L, sizeof(int) * B);
-  L.hcol = take(L, sizeof(double) * B * kMaxBasis);
+  L.hcol = take(L, sizeof(double) * B * (kMaxBasis + 1));
   const size_t vec = sizeof(double) * (size_t)L.vl * B;
   L.basis = take(L, vec * (o->restart + 1));
   L.zbasis = (o->side == PCOP_FLEXIBLE) ? take(L, vec * o->restart) : 0;
@@ -610,7 +610,7 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   }
 
   {
-    const size_t nd = (size_t)B * (3 * kMaxBasis + kRedStride + 1) + 2 * (size_t)B + 8;
+    const size_t nd = (size_t)B * (3 * kMaxBasis + 1 + kRedStride + 1) + 2 * (size_t)B + 8;
     hipError_t pe = hipHostMalloc(reinterpret_cast<void**>(&c->pin), nd * sizeof(double), hipHostMallocDefault);
     if (pe != hipSuccess) {
       delete c;
@@ -618,7 +618,7 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
     }
     double* q = c->pin;
     c->pin_col = q;
-    q += (size_t)B * kMaxBasis;
+    q += (size_t)B * (kMaxBasis + 1);
     c->pin_sc = q;
     q += (size_t)B * kMaxBasis;
     c->pin_coef = q;
@@ -798,6 +798,7 @@ void back_substitute(const MemberState& s, int k, double* y) {
 extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int transpose, pcop_member_info* info,
                                   double* res_hist) {
   if (!c || !b || !x) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  if (((uintptr_t)b | (uintptr_t)x) & 15) return fail(PCOP_ERR_INVALID_ARG, "b and x must be 16-byte aligned");
   const Geo& g = c->g;
   const int B = g.B;
   const int side = c->opt.side;
@@ -830,7 +831,7 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
   }
   std::vector<MemberState> ms(B);
   std::vector<int> h_active(B, 1), h_finish(B, 0);
-  std::vector<double> h_norm(B), h_col((size_t)B * kMaxBasis), h_coef((size_t)B * kMaxBasis);
+  std::vector<double> h_norm(B), h_col((size_t)B * (kMaxBasis + 1)), h_coef((size_t)B * kMaxBasis);
   std::vector<double> bnorm(B), h_sc((size_t)B * kMaxBasis);
   double* hcol = c->at<double>(L.hcol);
   // Every host<->device transfer goes through pinned staging; an upload
@@ -939,19 +940,27 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
       do_update(c, ka, j + 1, w, nullptr, n_active);
       launch_reduce_partials(partial, nblk, j + 2, B, red, st);
       launch_gs_step2(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, c->opt.reorth_tol, skip, sc, active, 0, st);
-      launch_update(ka, j + 1, w, coef, kMaxBasis, partial, nblk, skip, st);
-      launch_reduce_partials(partial, nblk, j + 2, B, red, st);
-      launch_gs_step2(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, c->opt.reorth_tol, skip, sc, active, 1, st);
-      // column j of H for every member
-      launch_pack_hcol(H, H_ld, j, B, hcol, st);
-      PCOP_HIP(download(h_col.data(), hcol, c->pin_col, (size_t)B * kMaxBasis));
+      // column j of H for every member, with the flag for a second pass
+      launch_pack_hcol(H, H_ld, j, B, skip, hcol, st);
+      PCOP_HIP(download(h_col.data(), hcol, c->pin_col, (size_t)B * (kMaxBasis + 1)));
+      int n_again = 0;
+      for (int m = 0; m < B; ++m)
+        if (h_active[m] && h_col[(size_t)m * (kMaxBasis + 1) + kMaxBasis] == 0.0) ++n_again;
+      if (n_again > 0) {
+        // second classical Gram-Schmidt pass for the members that need it
+        do_update(c, ka, j + 1, w, skip, n_again);
+        launch_reduce_partials(partial, nblk, j + 2, B, red, st);
+        launch_gs_step2(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, c->opt.reorth_tol, skip, sc, active, 1, st);
+        launch_pack_hcol(H, H_ld, j, B, skip, hcol, st);
+        PCOP_HIP(download(h_col.data(), hcol, c->pin_col, (size_t)B * (kMaxBasis + 1)));
+      }
       bool any_finish = false;
       int n_fin = 0;
       std::fill(h_finish.begin(), h_finish.end(), 0);
       for (int m = 0; m < B; ++m) {
         MemberState& ms_ = ms[m];
         if (!ms_.active) continue;
-        double* col = &h_col[(size_t)m * kMaxBasis];
+        double* col = &h_col[(size_t)m * (kMaxBasis + 1)];
         for (int i = 0; i < j; ++i) {
           const double t = ms_.cs[i] * col[i] + ms_.sn[i] * col[i + 1];
           col[i + 1] = -ms_.sn[i] * col[i] + ms_.cs[i] * col[i + 1];

@@ -87,12 +87,15 @@ __global__ void __launch_bounds__(256) time_fwd_sk(Geo g, const double* __restri
                                                    FftPlan plan, const double* __restrict__ vscale, int vs_stride,
                                                    const int* __restrict__ active) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int b = blockIdx.y;
+  // neighbouring column tiles share 128-byte lines: keep them on one XCD
+  const int lg = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int bx = lg % gridDim.x;
+  const int b = lg / gridDim.x;
   if (active && !active[b]) return;
   const int n = g.n, m = g.m, K = g.K;
   cx<T>* bufA = reinterpret_cast<cx<T>*>(smem);
   cx<T>* bufB = bufA + n * P;
-  const int i0 = blockIdx.x * P;
+  const int i0 = bx * P;
   const double s = vscale ? vscale[(size_t)b * vs_stride] : 1.0;
   const double* v1 = v + (size_t)b * g.vl;
   const double* v2 = v1 + (size_t)n * m;
@@ -122,12 +125,15 @@ __global__ void __launch_bounds__(256) time_inv_sk(Geo g, const cx<T>* __restric
                                                    const double* __restrict__ dpow, const cx<T>* __restrict__ twn,
                                                    FftPlan plan, int accum, const int* __restrict__ active) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int b = blockIdx.y;
+  // neighbouring column tiles share 128-byte lines: keep them on one XCD
+  const int lg = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int bx = lg % gridDim.x;
+  const int b = lg / gridDim.x;
   if (active && !active[b]) return;
   const int n = g.n, m = g.m, K = g.K;
   cx<T>* bufA = reinterpret_cast<cx<T>*>(smem);
   cx<T>* bufB = bufA + n * P;
-  const int i0 = blockIdx.x * P;
+  const int i0 = bx * P;
   const cx<T>* in = spec + (size_t)b * (size_t)(2 * K) * m;
   for (int t = threadIdx.x; t < K * P; t += blockDim.x) {
     const int k = t / P, p = t - k * P;
@@ -174,13 +180,16 @@ __global__ void __launch_bounds__(256) time_fwd_bl(Geo g, const double* __restri
                                                    const int* __restrict__ active) {
   constexpr int LD = M + 1;
   __shared__ cx<T> buf[P * LD];
-  const int b = blockIdx.y;
+  // neighbouring column tiles share 128-byte lines: keep them on one XCD
+  const int lg = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int bx = lg % gridDim.x;
+  const int b = lg / gridDim.x;
   if (active && !active[b]) return;
   const int n = g.n, m = g.m, K = g.K;
   const cx<T>* twM = reinterpret_cast<const cx<T>*>(tt.twM);
   const cx<T>* chirp = reinterpret_cast<const cx<T>*>(tt.chirp);
   const cx<T>* bhat = reinterpret_cast<const cx<T>*>(tt.bhat);
-  const int i0 = blockIdx.x * P;
+  const int i0 = bx * P;
   const double s = vscale ? vscale[(size_t)b * vs_stride] : 1.0;
   const double* v1 = v + (size_t)b * g.vl;
   const double* v2 = v1 + (size_t)n * m;
@@ -215,13 +224,16 @@ __global__ void __launch_bounds__(256) time_inv_bl(Geo g, const cx<T>* __restric
                                                    const int* __restrict__ active) {
   constexpr int LD = M + 1;
   __shared__ cx<T> buf[P * LD];
-  const int b = blockIdx.y;
+  // neighbouring column tiles share 128-byte lines: keep them on one XCD
+  const int lg = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int bx = lg % gridDim.x;
+  const int b = lg / gridDim.x;
   if (active && !active[b]) return;
   const int n = g.n, m = g.m, K = g.K;
   const cx<T>* twM = reinterpret_cast<const cx<T>*>(tt.twM);
   const cx<T>* chirp = reinterpret_cast<const cx<T>*>(tt.chirp);
   const cx<T>* bhat = reinterpret_cast<const cx<T>*>(tt.bhat);
-  const int i0 = blockIdx.x * P;
+  const int i0 = bx * P;
   const cx<T>* in = spec + (size_t)b * (size_t)(2 * K) * m;
   for (int t = threadIdx.x; t < (M - n) * P; t += blockDim.x) {
     const int j = n + t / P, p = t - (t / P) * P;
@@ -299,8 +311,9 @@ __global__ void __launch_bounds__(NT) dst_lines_kernel(Geo g, cx<T>* __restrict_
   constexpr int LD = L + 1;  // odd stride for complex entries
   __shared__ cx<T> buf[LINES * LD];
   const int tiles = (lg.lines + LINES - 1) / LINES;
-  const long long plane = blockIdx.x / tiles;
-  const int l0 = (int)(blockIdx.x - plane * tiles) * LINES;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const long long plane = blk / tiles;
+  const int l0 = (int)(blk - plane * tiles) * LINES;
   const long long pbase = plane * lg.plane_stride;
   if (DIVIDE && dp.active) {
     if (!dp.active[(int)(plane / (2 * g.K))]) return;
@@ -375,10 +388,14 @@ __global__ void __launch_bounds__(NT) dst_lines_kernel(Geo g, cx<T>* __restrict_
   }
 }
 
+// lines per block: a multiple of 128 bytes of line heads (8 complex FP64 /
+// 16 complex FP32) when the tile fits 80 KiB of LDS, else as many as fit
 template <class T, int L>
 constexpr int dst_lines_per_block() {
-  constexpr int bytes = L * (int)sizeof(cx<T>);
-  constexpr int v = 49152 / bytes;
+  constexpr int bytes = (L + 1) * (int)sizeof(cx<T>);
+  constexpr int seg = 128 / (int)sizeof(cx<T>);
+  constexpr int fit = 81920 / bytes;
+  constexpr int v = fit >= seg ? (fit / seg) * seg : fit;
   return v < 1 ? 1 : (v > 64 ? 64 : v);
 }
 
@@ -464,10 +481,12 @@ static int time_cols_sk(int n, int csz) {
   while (P > 4 && (size_t)2 * n * P * csz > 65536) P /= 2;
   return ((size_t)2 * n * P * csz <= 65536) ? P : 0;
 }
+// the chirp-z tile is static LDS; up to 80 KiB keeps two blocks per CU
+constexpr size_t kBlueLds = 81920;
 static int time_cols_bl(int M, int csz) {
   int P = 16;
-  while (P > 4 && (size_t)(M + 1) * P * csz > 65536) P /= 2;
-  return ((size_t)(M + 1) * P * csz <= 65536) ? P : 0;
+  while (P > 4 && (size_t)(M + 1) * P * csz > kBlueLds) P /= 2;
+  return ((size_t)(M + 1) * P * csz <= kBlueLds) ? P : 0;
 }
 
 bool time_lds_fits(int n, bool fp32) {
@@ -507,7 +526,7 @@ template <class T, int P, int M>
 static void bl_launch(bool fwd, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
                       const TimeTables& tt, const double* vscale, int vs_stride, int accum, hipStream_t st) {
   // only shapes whose LDS tile fits 64 KiB are instantiated (time_cols_bl picks P accordingly)
-  if constexpr ((size_t)(M + 1) * P * sizeof(cx<T>) <= 65536) {
+  if constexpr ((size_t)(M + 1) * P * sizeof(cx<T>) <= kBlueLds) {
     dim3 grid((g.m + P - 1) / P, g.B);
     if (fwd)
       time_fwd_bl<T, P, M><<<grid, 256, 0, st>>>(g, v, spec, tb.dpow, tt, vscale, vs_stride, tb.active);

@@ -237,6 +237,8 @@ class Solver:
             raise ValueError(f"{name} must have {math.prod(shape)} elements (shape {shape}), got {tuple(t.shape)}")
         if not t.is_contiguous():
             raise ValueError(f"{name} must be contiguous")
+        if t.data_ptr() % 16:
+            raise ValueError(f"{name} must be 16-byte aligned")
         return t
 
     def new_vector(self) -> torch.Tensor:

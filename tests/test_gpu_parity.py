@@ -165,6 +165,24 @@ def test_solve_converges_to_direct_solution(side):
         assert rel(xs[k], xo) < 1e-6
 
 
+@pytest.mark.parametrize("reorth_tol", [0.0, -1.0])
+def test_reorthogonalisation_switch(reorth_tol):
+    """Always running the second Gram-Schmidt pass (0) or never (-1) gives the
+    same iterates as the measured default to rounding."""
+    dim, nx, nt, gamma = 2, 15, 16, 1e-3
+    g, f, y0 = W.random_fields(dim, nx, nt, seed=33)
+    xs = []
+    its = []
+    for tol in (1e-10, reorth_tol):
+        s = Solver(dim, nx, nt, gamma, reorth_tol=tol, device=DEV)
+        x, infos, _ = s.solve(s.rhs(to_dev(g[None]), to_dev(f[None]), to_dev(y0[None])))
+        assert infos[0].converged
+        xs.append(x.cpu().numpy())
+        its.append(infos[0].iters)
+    assert its[0] == its[1]
+    assert rel(xs[1], xs[0]) < 1e-11
+
+
 def test_batched_member_equals_single_solve():
     dim, nx, nt, gammas = 2, 15, 16, (1e-2, 1e-7, 1e-4)
     fields = [W.random_fields(dim, nx, nt, seed=40 + b) for b in range(3)]
