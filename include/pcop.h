@@ -133,7 +133,7 @@ typedef struct {
 pcop_status pcop_validate(const pcop_problem* prob, const pcop_options* opts);
 
 /* Fill in the default options (FP64, DST, right, restart 30, maxit 300,
- * rtol 1e-8, no graph, reorth_tol 1e-10, default stream). */
+ * rtol 1e-8, no graph, reorth_tol 1e-8, default stream). */
 void pcop_default_options(pcop_options* opts);
 
 /* Bytes of device workspace pcop_setup needs for (prob, opts).  Host-only. */

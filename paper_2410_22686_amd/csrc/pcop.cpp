@@ -352,7 +352,7 @@ void pcop_default_options(pcop_options* o) {
   o->rtol = 1e-8;
   o->graph = 0;
   o->graph_chunk = 4;
-  o->reorth_tol = 1e-10;
+  o->reorth_tol = 1e-8;
   o->stream = nullptr;
 }
 

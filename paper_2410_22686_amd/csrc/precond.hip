@@ -388,15 +388,13 @@ __global__ void __launch_bounds__(NT) dst_lines_kernel(Geo g, cx<T>* __restrict_
   }
 }
 
-// lines per block: a multiple of 128 bytes of line heads (8 complex FP64 /
-// 16 complex FP32) when the tile fits 80 KiB of LDS, else as many as fit
+// lines per block: as many as fit 48 KiB of LDS (three blocks per CU); the
+// XCD-aware block order lets neighbouring tiles share partially used lines
 template <class T, int L>
 constexpr int dst_lines_per_block() {
   constexpr int bytes = (L + 1) * (int)sizeof(cx<T>);
-  constexpr int seg = 128 / (int)sizeof(cx<T>);
-  constexpr int fit = 81920 / bytes;
-  constexpr int v = fit >= seg ? (fit / seg) * seg : fit;
-  return v < 1 ? 1 : (v > 64 ? 64 : v);
+  constexpr int fit = 49152 / bytes;
+  return fit < 1 ? 1 : (fit > 64 ? 64 : fit);
 }
 
 template <class T, int L>

@@ -154,7 +154,7 @@ class Solver:
     def __init__(self, dim: int, nx: int, nt: int, gamma: Union[float, Sequence[float]], T: float = 1.0,
                  eps: Optional[float] = None, coeff: Optional[Callable] = None, precision: str = "fp64",
                  spatial: str = "dst", side: str = "right", restart: int = 30, maxit: int = 300,
-                 rtol: float = 1e-8, graph: bool = False, graph_chunk: int = 4, reorth_tol: float = 1e-10,
+                 rtol: float = 1e-8, graph: bool = False, graph_chunk: int = 4, reorth_tol: float = 1e-8,
                  device: Union[str, torch.device] = "cuda", stream: Optional[torch.cuda.Stream] = None):
         import numpy as np
         self.lib = load_library()
