@@ -35,6 +35,39 @@ PRECOND_FAMILIES = ("time_fwd", "dst_rows", "dst_ax2", "dst_last_solve", "time_i
                     "mg_restrict", "mg_prolong")
 
 
+# kernel sources behind each timed family (to tell whether recorded counters
+# still describe the code that runs)
+FAMILY_SOURCES = {
+    "gs_update": ["krylov.hip"], "mdot": ["krylov.hip"], "combine": ["krylov.hip"], "kkt_apply": ["kkt.hip"],
+    "time_fwd": ["precond.hip", "fft_lds.hpp"], "time_inv": ["precond.hip", "fft_lds.hpp"],
+    "dst_rows": ["precond.hip", "fft_lds.hpp"], "dst_last_solve": ["precond.hip", "fft_lds.hpp"],
+    "dst_ax2": ["precond.hip", "fft_lds.hpp"], "mg_smooth": ["multigrid.hip"], "mg_restrict": ["multigrid.hip"],
+    "mg_prolong": ["multigrid.hip"],
+}
+
+
+def recorded_traffic(workload, family):
+    """HBM bytes per launch recorded by rocprofv3 FETCH_SIZE/WRITE_SIZE runs in
+    profiles/kernels_<workload>.md, or None when absent or when the kernel
+    sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"kernels_{workload}.md")
+    if not os.path.exists(path) or family not in FAMILY_SOURCES:
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("traffic: "):
+            rec = json.loads(line[len("traffic: "):])
+    if not rec or rec.get("workload") != workload or family not in rec.get("families", {}):
+        return None
+    h = hashlib.sha256()
+    for fn in FAMILY_SOURCES[family]:
+        with open(os.path.join(ROOT, "paper_2410_22686_amd", "csrc", fn), "rb") as fh:
+            h.update(fh.read())
+    entry = rec["families"][family]
+    return entry["bytes_per_launch"] if entry.get("source") == h.hexdigest()[:12] else None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,8 +241,10 @@ def main():
     dom_ms_per_launch = dom["ms"] / dom["launches"]
     dom_bytes_per_launch = dom["bytes"] / dom["launches"]
     achieved = dom_bytes_per_launch / (dom_ms_per_launch * 1e-3) / 1e9
+    traffic = recorded_traffic(cfg.name, dom_name)
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_unit": "bytes/launch",
                 "bytes_per_launch": dom_bytes_per_launch, "ms_per_launch": dom_ms_per_launch,
                 "launches": dom["launches"]}
     pre = {k: v for k, v in stats.items() if k in PRECOND_FAMILIES}
