@@ -1,13 +1,238 @@
-// Complex-shifted geometric multigrid for Step 2 with a variable coefficient
-// (one V-cycle per frequency slice).
+// Step 2 with a variable coefficient: one geometric-multigrid V-cycle per
+// frequency slice for (sigma_q I + tau K_a) z = r (Section 2.1 step 2;
+// Section 3, Example 2: one V-cycle, Gauss-Seidel pre-smoother, no
+// post-smoother).  All slices of all members go through one launch per level.
+//
+// Cycle (from z = 0):
+//   smooth    one red-black Gauss-Seidel sweep, red = even index sum first.
+//             Red points: z = r / d; black points use the red values
+//             z_nb = r_nb / d_nb, recomputed on the fly, so the sweep is one
+//             pass.  d = sigma_q + tau diag(K_a).
+//   restrict  residual r - A z (zero at black points after the sweep, equal
+//             to -sum_nb off z_nb at red points), full weighting to the coarse
+//             grid (tensor product of [1/4, 1/2, 1/4]).
+//   coarsest  one point: z = r / d.
+//   prolong   z += P z_coarse (multilinear interpolation); the finest level
+//             writes the result into the spectrum.
+// Coarse operators are re-discretised: tau K_a on each level comes from the
+// host with a at the level's face midpoints.  Coefficients per level:
+// coef[0][i] = tau diag, coef[1 + 2a][i] / coef[2 + 2a][i] = tau times the
+// minus / plus neighbour along axis a (zero where the neighbour is outside).
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace pcop {
 
+struct MgShift {
+  const double* lam;    // [K] (re, im)
+  const double* alpha;  // [B]
+  const int* active;    // [B] or null
+  int twoK;
+};
+
+template <class T>
+__device__ __forceinline__ cx<T> slice_sigma(const MgShift& sh, int slice) {
+  const int b = slice / sh.twoK;
+  const int q = slice - b * sh.twoK;
+  const int k = q >> 1;
+  const double re = sh.lam[2 * k] + sh.alpha[b];
+  const double im = (q & 1) ? -sh.lam[2 * k + 1] : sh.lam[2 * k + 1];
+  return cx<T>{(T)re, (T)im};
+}
+
+__device__ __forceinline__ void coords(int i, int nx, int dim, int* c) {
+  c[0] = i % nx;
+  c[1] = (i / nx) % nx;
+  c[2] = (dim == 3) ? i / (nx * nx) : 0;
+}
+
+// one red-black sweep from z = 0
+template <class T, int DIM>
+__global__ void __launch_bounds__(256) mg_smooth_kernel(int nx, int m, const T* __restrict__ coef,
+                                                        const cx<T>* __restrict__ r, cx<T>* __restrict__ z,
+                                                        MgShift sh) {
+  const int s = blockIdx.y;
+  if (sh.active && !sh.active[s / sh.twoK]) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const cx<T> sig = slice_sigma<T>(sh, s);
+  const cx<T>* rs = r + (size_t)s * m;
+  int c[3];
+  coords(i, nx, DIM, c);
+  const cx<T> di = cx<T>{sig.x + coef[i], sig.y};
+  const bool red = ((c[0] + c[1] + c[2]) & 1) == 0;
+  cx<T> acc = rs[i];
+  if (!red) {
+    int stride = 1;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      if (c[a] > 0) {
+        const int nb = i - stride;
+        const cx<T> dn = cx<T>{sig.x + coef[nb], sig.y};
+        acc = acc - scale(cdiv(rs[nb], dn), coef[(size_t)(1 + 2 * a) * m + i]);
+      }
+      if (c[a] < nx - 1) {
+        const int nb = i + stride;
+        const cx<T> dn = cx<T>{sig.x + coef[nb], sig.y};
+        acc = acc - scale(cdiv(rs[nb], dn), coef[(size_t)(2 + 2 * a) * m + i]);
+      }
+      stride *= nx;
+    }
+  }
+  z[(size_t)s * m + i] = cdiv(acc, di);
+}
+
+// residual at a fine point (nonzero only at red points)
+template <class T, int DIM>
+__device__ __forceinline__ cx<T> red_residual(const int* f, int nx, int m, const T* __restrict__ coef,
+                                              const cx<T>* __restrict__ zs) {
+  if (((f[0] + f[1] + f[2]) & 1) != 0) return cx<T>{0, 0};
+  const int i = f[0] + nx * (f[1] + nx * f[2]);
+  cx<T> acc{0, 0};
+  int stride = 1;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    if (f[a] > 0) acc = acc - scale(zs[i - stride], coef[(size_t)(1 + 2 * a) * m + i]);
+    if (f[a] < nx - 1) acc = acc - scale(zs[i + stride], coef[(size_t)(2 + 2 * a) * m + i]);
+    stride *= nx;
+  }
+  return acc;
+}
+
+// coarse right-hand side by full weighting of the fine residual
+template <class T, int DIM>
+__global__ void __launch_bounds__(256) mg_restrict_kernel(int nxf, int mf, int nxc, int mc,
+                                                          const T* __restrict__ coef, const cx<T>* __restrict__ z,
+                                                          cx<T>* __restrict__ rc, MgShift sh) {
+  const int s = blockIdx.y;
+  if (sh.active && !sh.active[s / sh.twoK]) return;
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= mc) return;
+  int C[3];
+  coords(I, nxc, DIM, C);
+  const cx<T>* zs = z + (size_t)s * mf;
+  cx<T> acc{0, 0};
+  const int o2 = (DIM == 3) ? 1 : 0;
+  for (int d2 = -o2; d2 <= o2; ++d2)
+    for (int d1 = -1; d1 <= 1; ++d1)
+      for (int d0 = -1; d0 <= 1; ++d0) {
+        int f[3] = {2 * C[0] + 1 + d0, 2 * C[1] + 1 + d1, (DIM == 3) ? 2 * C[2] + 1 + d2 : 0};
+        const T w = (d0 == 0 ? (T)1 : (T)0.5) * (d1 == 0 ? (T)1 : (T)0.5) * (d2 == 0 ? (T)1 : (T)0.5);
+        acc = acc + scale(red_residual<T, DIM>(f, nxf, mf, coef, zs), w);
+      }
+  const T inv = (DIM == 3) ? (T)0.125 : (T)0.25;
+  rc[(size_t)s * mc + I] = scale(acc, inv);
+}
+
+// out = z_fine + P z_coarse (out may alias z_fine)
+template <class T, int DIM>
+__global__ void __launch_bounds__(256) mg_prolong_kernel(int nxf, int mf, int nxc, int mc,
+                                                         const cx<T>* __restrict__ zf, const cx<T>* __restrict__ zc,
+                                                         cx<T>* out, MgShift sh) {
+  const int s = blockIdx.y;
+  if (sh.active && !sh.active[s / sh.twoK]) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= mf) return;
+  int f[3];
+  coords(i, nxf, DIM, f);
+  // per axis: coarse indices and weights contributing to fine index f
+  int ci[3][2];
+  T cw[3][2];
+  int cn[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a >= DIM) {
+      ci[a][0] = 0;
+      cw[a][0] = (T)1;
+      cn[a] = 1;
+      continue;
+    }
+    if (f[a] & 1) {  // fine 2I + 1 sits on coarse I
+      ci[a][0] = f[a] >> 1;
+      cw[a][0] = (T)1;
+      cn[a] = 1;
+    } else {         // fine 2I lies between coarse I - 1 and I
+      const int I = f[a] >> 1;
+      cn[a] = 0;
+      if (I - 1 >= 0) {
+        ci[a][cn[a]] = I - 1;
+        cw[a][cn[a]++] = (T)0.5;
+      }
+      if (I < nxc) {
+        ci[a][cn[a]] = I;
+        cw[a][cn[a]++] = (T)0.5;
+      }
+    }
+  }
+  const cx<T>* zcs = zc + (size_t)s * mc;
+  cx<T> acc = zf[(size_t)s * mf + i];
+  for (int u2 = 0; u2 < cn[2]; ++u2)
+    for (int u1 = 0; u1 < cn[1]; ++u1)
+      for (int u0 = 0; u0 < cn[0]; ++u0) {
+        const int I = ci[0][u0] + nxc * (ci[1][u1] + nxc * ci[2][u2]);
+        acc = acc + scale(zcs[I], cw[0][u0] * cw[1][u1] * cw[2][u2]);
+      }
+  out[(size_t)s * mf + i] = acc;
+}
+
+template <class T, int DIM>
+static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, hipStream_t st) {
+  const int NL = tb.mg_levels;
+  const int slices = g.B * 2 * g.K;
+  MgShift sh{tb.lam, tb.alpha, tb.active, 2 * g.K};
+  auto coefp = [&](int l) -> const T* {
+    return reinterpret_cast<const T*>(sizeof(T) == 4 ? (const void*)tb.mg[l].coef : (const void*)tb.mg[l].coef64);
+  };
+  auto zbuf = [&](int l) -> cx<T>* {
+    return reinterpret_cast<cx<T>*>(l == 0 ? tb.mg[0].r : tb.mg[l].z);
+  };
+  auto rbuf = [&](int l) -> cx<T>* { return l == 0 ? spec : reinterpret_cast<cx<T>*>(tb.mg[l].r); };
+  // pass bytes (algorithmic): complex data in and out of every kernel
+  const double cs = sizeof(cx<T>) * (double)slices * tb.nact / g.B;
+  for (int l = 0; l < NL; ++l) {
+    const int nx = tb.mg[l].nx;
+    const int m = (int)tb.mg[l].m;
+    dim3 grid((m + 255) / 256, slices);
+    tbeg(tb.timer, KF_MG_SMOOTH, 2.0 * cs * m);
+    mg_smooth_kernel<T, DIM><<<grid, 256, 0, st>>>(nx, m, coefp(l), rbuf(l), zbuf(l), sh);
+    tend(tb.timer);
+    if (l + 1 < NL) {
+      const int nxc = tb.mg[l + 1].nx;
+      const int mc = (int)tb.mg[l + 1].m;
+      dim3 gc((mc + 255) / 256, slices);
+      tbeg(tb.timer, KF_MG_RESTRICT, cs * (m + mc));
+      mg_restrict_kernel<T, DIM><<<gc, 256, 0, st>>>(nx, m, nxc, mc, coefp(l), zbuf(l), rbuf(l + 1), sh);
+      tend(tb.timer);
+    }
+  }
+  for (int l = NL - 2; l >= 0; --l) {
+    const int nx = tb.mg[l].nx;
+    const int m = (int)tb.mg[l].m;
+    const int nxc = tb.mg[l + 1].nx;
+    const int mc = (int)tb.mg[l + 1].m;
+    dim3 grid((m + 255) / 256, slices);
+    cx<T>* out = (l == 0) ? spec : zbuf(l);
+    tbeg(tb.timer, KF_MG_PROLONG, cs * (2.0 * m + mc));
+    mg_prolong_kernel<T, DIM><<<grid, 256, 0, st>>>(nx, m, nxc, mc, zbuf(l), zbuf(l + 1), out, sh);
+    tend(tb.timer);
+  }
+  if (NL == 1) {
+    // single-point grid: the smoothed value is the exact solve; copy it back
+    const int m = (int)tb.mg[0].m;
+    dim3 grid((m + 255) / 256, slices);
+    mg_prolong_kernel<T, DIM><<<grid, 256, 0, st>>>(1, m, 0, 0, zbuf(0), zbuf(0), spec, sh);
+  }
+}
+
 bool launch_mg_solve(const Geo& g, void* spec, bool fp32, const PrecondTables& tb, hipStream_t st) {
-  (void)g; (void)spec; (void)fp32; (void)tb; (void)st;
-  return false;
+  if (tb.mg_levels < 1) return false;
+  if (fp32) {
+    if (g.dim == 2) mg_cycle<float, 2>(g, reinterpret_cast<cx<float>*>(spec), tb, st);
+    else mg_cycle<float, 3>(g, reinterpret_cast<cx<float>*>(spec), tb, st);
+  } else {
+    if (g.dim == 2) mg_cycle<double, 2>(g, reinterpret_cast<cx<double>*>(spec), tb, st);
+    else mg_cycle<double, 3>(g, reinterpret_cast<cx<double>*>(spec), tb, st);
+  }
+  return true;
 }
 
 }  // namespace pcop

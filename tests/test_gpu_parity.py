@@ -119,6 +119,46 @@ def test_precond_apply_mixed(dim, nx, nt, gammas, eps):
         assert err < 1e-5
 
 
+MG_CASES = [
+    # dim, nx, nt, gammas, coefficient
+    (2, 15, 16, (1e-4,), None),
+    (2, 15, 12, (1e-3, 1e-8), W.coeff_sines3d),
+    (3, 7, 9, (1e-5,), W.coeff_sines3d),
+    (3, 15, 8, (1e-2,), W.coeff_sines3d),
+    (2, 1, 5, (1e-3,), W.coeff_sines3d),      # single-point grid: the cycle is an exact solve
+    (2, 31, 20, (1e-6,), W.coeff_example2),   # Example 2 coefficient, chirp-z time transform
+]
+
+
+@pytest.mark.parametrize("dim,nx,nt,gammas,coeff", MG_CASES)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_precond_apply_multigrid(dim, nx, nt, gammas, coeff, precision):
+    print(f"precond mg {precision} dim={dim} nx={nx} nt={nt} B={len(gammas)}", flush=True)
+    side = "flexible" if precision == "mixed" else "right"
+    s = Solver(dim, nx, nt, list(gammas), coeff=coeff, spatial="mg", precision=precision, side=side, device=DEV)
+    v = W.random_vector(dim, nx, nt, seed=17, batch=len(gammas))
+    w = s.precond_apply(to_dev(v)).cpu().numpy()
+    for b, pb in enumerate(problems(dim, nx, nt, gammas, coeff=coeff)):
+        wo = P.EpsCirculantRBD(pb, spatial="mg", coeff=coeff).apply(v[b].ravel())
+        err = rel(w[b], wo)
+        print(f"  member {b}: rel err {err:.2e}")
+        assert err < (1e-11 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_multigrid_flexible_solve(precision):
+    # 3-D sparse direct solves grow quickly on the host: keep the oracle side small
+    dim, nx, nt, gamma = 3, 7, 16, 1e-5
+    g, f, y0 = W.random_fields(dim, nx, nt, seed=71)
+    s = Solver(dim, nx, nt, gamma, coeff=W.coeff_sines3d, spatial="mg", precision=precision, side="flexible",
+               device=DEV)
+    x, infos, _ = s.solve(s.rhs(to_dev(g[None]), to_dev(f[None]), to_dev(y0[None])))
+    assert infos[0].converged and infos[0].relres_true <= 1.05e-8
+    pb = D.make_problem(dim, nx, nt, gamma, coeff=W.coeff_sines3d)
+    xo = spla.spsolve(D.kkt_scaled(pb).tocsc(), D.rhs_scaled(pb, g, f, y0))
+    assert rel(x.cpu().numpy(), xo) < 1e-6
+
+
 def test_precond_in_place():
     s = Solver(2, 15, 16, 1e-4, device=DEV)
     v = to_dev(W.random_vector(2, 15, 16, seed=9))
