@@ -275,10 +275,16 @@ struct pcop_ctx_s {
   double* pin_sc = nullptr;     // [B][kMaxBasis]  basis scales
   double* pin_coef = nullptr;   // [B][kMaxBasis]  combination coefficients
   double* pin_red = nullptr;    // [B][kRedStride] reductions
+  double* pin_H = nullptr;      // [B][kMaxBasis - 1][kMaxBasis] Hessenberg (graph mode)
   double* pin_norm = nullptr;   // [B]
   int* pin_active = nullptr;    // [B]
   int* pin_finish = nullptr;    // [B]
+  // HIP graphs of Arnoldi chunks (graph = 1): captured on a private stream
+  hipStream_t gst = nullptr;
+  std::vector<std::pair<int, hipGraphExec_t>> graphs;  // key j0 * 64 + count
   ~pcop_ctx_s() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    if (gst) (void)hipStreamDestroy(gst);
     if (pin) (void)hipHostFree(pin);
   }
   const KTimer* kt() const { return timer.enabled ? &ktimer : nullptr; }
@@ -610,7 +616,8 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   }
 
   {
-    const size_t nd = (size_t)B * (3 * kMaxBasis + 1 + kRedStride + 1) + 2 * (size_t)B + 8;
+    const size_t nd = (size_t)B * (3 * kMaxBasis + 1 + kRedStride + 1 + (kMaxBasis - 1) * kMaxBasis) +
+                      2 * (size_t)B + 8;
     hipError_t pe = hipHostMalloc(reinterpret_cast<void**>(&c->pin), nd * sizeof(double), hipHostMallocDefault);
     if (pe != hipSuccess) {
       delete c;
@@ -625,6 +632,8 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
     q += (size_t)B * kMaxBasis;
     c->pin_red = q;
     q += (size_t)B * kRedStride;
+    c->pin_H = q;
+    q += (size_t)B * (kMaxBasis - 1) * kMaxBasis;
     c->pin_norm = q;
     q += B;
     c->pin_active = reinterpret_cast<int*>(q);
@@ -659,6 +668,13 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
     lv.coef64 = c->fp32 ? nullptr : c->at<double>(L.mgcoef[l]);
     lv.r = c->at<void>(L.mgr[l]);
     lv.z = (l > 0) ? c->at<void>(L.mgz[l]) : nullptr;
+  }
+  if (opts->graph) {
+    hipError_t ge = hipStreamCreateWithFlags(&c->gst, hipStreamNonBlocking);
+    if (ge != hipSuccess) {
+      delete c;
+      return fail(PCOP_ERR_DEVICE, std::string("graph stream: ") + hipGetErrorString(ge));
+    }
   }
   *out = c;
   return PCOP_OK;
@@ -773,6 +789,87 @@ pcop_status pcop_timing_read(pcop_ctx c, pcop_kernel_stat* out, int cap, int* co
 // ---------------------------------------------------------------------------
 namespace {
 
+// Enqueue Arnoldi step j on stream st: operator, first Gram-Schmidt pass,
+// measured orthogonality, and (full = true) the member-masked second pass.
+pcop_status enqueue_iteration(pcop_ctx c, int j, bool full, int n_active, hipStream_t st) {
+  const Layout& L = c->L;
+  const int B = c->g.B;
+  double* tmp1 = c->at<double>(L.tmp1);
+  double* sc = c->at<double>(L.sc);
+  double* H = c->at<double>(L.H);
+  double* coef = c->at<double>(L.coef);
+  double* red = c->at<double>(L.red);
+  double* partial = c->at<double>(L.partial);
+  double* wnorm2 = c->at<double>(L.wnorm2);
+  int* skip = c->at<int>(L.skip);
+  int* active = c->at<int>(L.active);
+  const int nblk = L.nblk;
+  const int H_ld = kMaxBasis;
+  double* vj = c->basis(j);
+  double* w = c->basis(j + 1);
+  const double* scj = sc + j;  // member stride kMaxBasis
+  pcop_status s = PCOP_OK;
+  const int side = c->opt.side;
+  if (side == PCOP_RIGHT) {
+    s = do_precond(c, vj, tmp1, scj, kMaxBasis, 0, active, n_active);
+    do_kkt(c, tmp1, w, nullptr, nullptr, 0, active, n_active);
+  } else if (side == PCOP_FLEXIBLE) {
+    s = do_precond(c, vj, c->zbasis(j), scj, kMaxBasis, 0, active, n_active);
+    do_kkt(c, c->zbasis(j), w, nullptr, nullptr, 0, active, n_active);
+  } else {
+    do_kkt(c, vj, tmp1, nullptr, scj, kMaxBasis, active, n_active);
+    s = do_precond(c, tmp1, w, nullptr, 0, 0, active, n_active);
+  }
+  if (s != PCOP_OK) return s;
+  // classical Gram-Schmidt; the update pass also measures the new vector
+  KrylovArgs ka = c->kargs(c->basis(0), active);
+  do_mdot(c, ka, j + 1, w, n_active);
+  launch_reduce_partials(partial, nblk, j + 2, B, red, st);
+  launch_gs_step1(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, active, st);
+  do_update(c, ka, j + 1, w, nullptr, n_active);
+  launch_reduce_partials(partial, nblk, j + 2, B, red, st);
+  launch_gs_step2(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, c->opt.reorth_tol, skip, sc, active, 0, st);
+  if (full) {
+    launch_update(ka, j + 1, w, coef, kMaxBasis, partial, nblk, skip, st);
+    launch_reduce_partials(partial, nblk, j + 2, B, red, st);
+    launch_gs_step2(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, c->opt.reorth_tol, skip, sc, active, 1, st);
+  }
+  return PCOP_OK;
+}
+
+// The graph for Arnoldi steps j0 .. j0 + cnt - 1 (captured on first use).
+pcop_status chunk_graph(pcop_ctx c, int j0, int cnt, hipGraphExec_t* out) {
+  const int key = j0 * 64 + cnt;
+  for (auto& g : c->graphs)
+    if (g.first == key) {
+      *out = g.second;
+      return PCOP_OK;
+    }
+  const bool timing = c->timer.enabled;
+  c->timer.enabled = false;  // events are not recorded inside captured graphs
+  hipStream_t saved = c->st;
+  c->st = c->gst;
+  PCOP_HIP(hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal));
+  pcop_status s = PCOP_OK;
+  for (int j = j0; j < j0 + cnt && s == PCOP_OK; ++j) s = enqueue_iteration(c, j, true, c->g.B, c->gst);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(c->gst, &graph);
+  c->st = saved;
+  c->timer.enabled = timing;
+  if (s != PCOP_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return fail(PCOP_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(PCOP_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  c->graphs.push_back({key, exec});
+  *out = exec;
+  return PCOP_OK;
+}
+
 struct MemberState {
   bool active = true;      // still iterating
   bool converged = false;
@@ -799,6 +896,22 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
                                   double* res_hist) {
   if (!c || !b || !x) return fail(PCOP_ERR_INVALID_ARG, "null argument");
   if (((uintptr_t)b | (uintptr_t)x) & 15) return fail(PCOP_ERR_INVALID_ARG, "b and x must be 16-byte aligned");
+  // graph mode runs the whole solve on the context's private stream, after
+  // the caller's stream has delivered b and x
+  const bool use_graph = c->opt.graph && c->gst;
+  struct StreamSwap {
+    pcop_ctx c;
+    hipStream_t saved;
+    bool on;
+    ~StreamSwap() {
+      if (on) c->st = saved;
+    }
+  } swap{c, c->st, false};
+  if (use_graph) {
+    PCOP_HIP(hipStreamSynchronize(c->st));
+    c->st = c->gst;
+    swap.on = true;
+  }
   const Geo& g = c->g;
   const int B = g.B;
   const int side = c->opt.side;
@@ -833,6 +946,8 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
   std::vector<int> h_active(B, 1), h_finish(B, 0);
   std::vector<double> h_norm(B), h_col((size_t)B * (kMaxBasis + 1)), h_coef((size_t)B * kMaxBasis);
   std::vector<double> bnorm(B), h_sc((size_t)B * kMaxBasis);
+  const size_t H_member = (size_t)(kMaxBasis - 1) * kMaxBasis;
+  std::vector<double> h_H(use_graph ? (size_t)B * H_member : 0);
   double* hcol = c->at<double>(L.hcol);
   // Every host<->device transfer goes through pinned staging; an upload
   // buffer is only rewritten after a stream synchronisation.
@@ -914,90 +1029,101 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
     if (n_active == 0) break;
     PCOP_HIP(upload_ints(active, h_active, c->pin_active));
 
-    for (int j = 0; j < restart; ++j) {
+    int j = 0;
+    while (j < restart) {
       n_active = 0;
       for (int m = 0; m < B; ++m) n_active += h_active[m];
-      double* vj = c->basis(j);
-      double* w = c->basis(j + 1);
-      const double* scj = sc + j;  // member stride kMaxBasis
-      pcop_status s = PCOP_OK;
-      if (side == PCOP_RIGHT) {
-        s = do_precond(c, vj, tmp1, scj, kMaxBasis, 0, active, n_active);
-        do_kkt(c, tmp1, w, nullptr, nullptr, 0, active, n_active);
-      } else if (side == PCOP_FLEXIBLE) {
-        s = do_precond(c, vj, c->zbasis(j), scj, kMaxBasis, 0, active, n_active);
-        do_kkt(c, c->zbasis(j), w, nullptr, nullptr, 0, active, n_active);
+      int cnt = 1;
+      if (use_graph) {
+        // a chunk of Arnoldi steps as one graph; members that converge inside
+        // the chunk run to its end and their extra steps are ignored
+        cnt = std::min(c->opt.graph_chunk, restart - j);
+        hipGraphExec_t ge = nullptr;
+        pcop_status gs = chunk_graph(c, j, cnt, &ge);
+        if (gs != PCOP_OK) return gs;
+        PCOP_HIP(hipGraphLaunch(ge, st));
+        PCOP_HIP(download(h_H.data(), H, c->pin_H, (size_t)B * H_member));
       } else {
-        do_kkt(c, vj, tmp1, nullptr, scj, kMaxBasis, active, n_active);
-        s = do_precond(c, tmp1, w, nullptr, 0, 0, active, n_active);
-      }
-      if (s != PCOP_OK) return s;
-      // classical Gram-Schmidt with a measured second pass
-      KrylovArgs ka = c->kargs(c->basis(0), active);
-      do_mdot(c, ka, j + 1, w, n_active);
-      launch_reduce_partials(partial, nblk, j + 2, B, red, st);
-      launch_gs_step1(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, active, st);
-      do_update(c, ka, j + 1, w, nullptr, n_active);
-      launch_reduce_partials(partial, nblk, j + 2, B, red, st);
-      launch_gs_step2(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, c->opt.reorth_tol, skip, sc, active, 0, st);
-      // column j of H for every member, with the flag for a second pass
-      launch_pack_hcol(H, H_ld, j, B, skip, hcol, st);
-      PCOP_HIP(download(h_col.data(), hcol, c->pin_col, (size_t)B * (kMaxBasis + 1)));
-      int n_again = 0;
-      for (int m = 0; m < B; ++m)
-        if (h_active[m] && h_col[(size_t)m * (kMaxBasis + 1) + kMaxBasis] == 0.0) ++n_again;
-      if (n_again > 0) {
-        // second classical Gram-Schmidt pass for the members that need it
-        do_update(c, ka, j + 1, w, skip, n_again);
-        launch_reduce_partials(partial, nblk, j + 2, B, red, st);
-        launch_gs_step2(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, c->opt.reorth_tol, skip, sc, active, 1, st);
+        pcop_status s = enqueue_iteration(c, j, false, n_active, st);
+        if (s != PCOP_OK) return s;
+        // column j of H for every member, with the flag for a second pass
         launch_pack_hcol(H, H_ld, j, B, skip, hcol, st);
         PCOP_HIP(download(h_col.data(), hcol, c->pin_col, (size_t)B * (kMaxBasis + 1)));
+        int n_again = 0;
+        for (int m = 0; m < B; ++m)
+          if (h_active[m] && h_col[(size_t)m * (kMaxBasis + 1) + kMaxBasis] == 0.0) ++n_again;
+        if (n_again > 0) {
+          // second classical Gram-Schmidt pass for the members that need it
+          KrylovArgs ka = c->kargs(c->basis(0), active);
+          do_update(c, ka, j + 1, c->basis(j + 1), skip, n_again);
+          launch_reduce_partials(partial, nblk, j + 2, B, red, st);
+          launch_gs_step2(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, c->opt.reorth_tol, skip, sc, active, 1,
+                          st);
+          launch_pack_hcol(H, H_ld, j, B, skip, hcol, st);
+          PCOP_HIP(download(h_col.data(), hcol, c->pin_col, (size_t)B * (kMaxBasis + 1)));
+        }
       }
+      // Givens rotations of the new columns; a member ends its cycle at the
+      // first step that converges, exhausts maxit or reaches the restart
       bool any_finish = false;
       int n_fin = 0;
+      int kmax = 0;
       std::fill(h_finish.begin(), h_finish.end(), 0);
+      std::vector<int> kfin(B, 0);
       for (int m = 0; m < B; ++m) {
         MemberState& ms_ = ms[m];
-        if (!ms_.active) continue;
-        double* col = &h_col[(size_t)m * (kMaxBasis + 1)];
-        for (int i = 0; i < j; ++i) {
-          const double t = ms_.cs[i] * col[i] + ms_.sn[i] * col[i + 1];
-          col[i + 1] = -ms_.sn[i] * col[i] + ms_.cs[i] * col[i + 1];
-          col[i] = t;
-        }
-        const double a = col[j], bsub = col[j + 1];
-        double cth = 1.0, sth = 0.0;
-        if (bsub != 0.0) {
-          const double r = std::hypot(a, bsub);
-          cth = a / r;
-          sth = bsub / r;
-        }
-        ms_.cs[j] = cth;
-        ms_.sn[j] = sth;
-        col[j] = cth * a + sth * bsub;
-        col[j + 1] = 0.0;
-        for (int i = 0; i <= j; ++i) ms_.R[j][i] = col[i];
-        ms_.gv[j + 1] = -sth * ms_.gv[j];
-        ms_.gv[j] = cth * ms_.gv[j];
-        ms_.iters += 1;
-        ms_.est = std::fabs(ms_.gv[j + 1]) / ms_.beta0;
-        if (res_hist && ms_.iters <= maxit) res_hist[(size_t)m * (maxit + 1) + ms_.iters] = ms_.est;
-        const bool conv = ms_.est <= rtol || bsub == 0.0;
-        if (conv || ms_.iters >= maxit || j == restart - 1) {
-          h_finish[m] = 1;
-          any_finish = true;
-          ++n_fin;
-          if (conv) ms_.converged = true;
+        if (!h_active[m]) continue;
+        for (int jj = j; jj < j + cnt; ++jj) {
+          double colbuf[kMaxBasis + 1];
+          double* col = colbuf;
+          if (use_graph) {
+            const double* src = &h_H[(size_t)m * H_member + (size_t)jj * H_ld];
+            for (int i = 0; i <= jj + 1; ++i) col[i] = src[i];
+          } else {
+            col = &h_col[(size_t)m * (kMaxBasis + 1)];
+          }
+          for (int i = 0; i < jj; ++i) {
+            const double t = ms_.cs[i] * col[i] + ms_.sn[i] * col[i + 1];
+            col[i + 1] = -ms_.sn[i] * col[i] + ms_.cs[i] * col[i + 1];
+            col[i] = t;
+          }
+          const double a = col[jj], bsub = col[jj + 1];
+          double cth = 1.0, sth = 0.0;
+          if (bsub != 0.0) {
+            const double r = std::hypot(a, bsub);
+            cth = a / r;
+            sth = bsub / r;
+          }
+          ms_.cs[jj] = cth;
+          ms_.sn[jj] = sth;
+          col[jj] = cth * a + sth * bsub;
+          col[jj + 1] = 0.0;
+          for (int i = 0; i <= jj; ++i) ms_.R[jj][i] = col[i];
+          ms_.gv[jj + 1] = -sth * ms_.gv[jj];
+          ms_.gv[jj] = cth * ms_.gv[jj];
+          ms_.iters += 1;
+          ms_.est = std::fabs(ms_.gv[jj + 1]) / ms_.beta0;
+          if (res_hist && ms_.iters <= maxit) res_hist[(size_t)m * (maxit + 1) + ms_.iters] = ms_.est;
+          const bool conv = ms_.est <= rtol || bsub == 0.0;
+          if (conv || ms_.iters >= maxit || jj == restart - 1) {
+            h_finish[m] = 1;
+            kfin[m] = jj + 1;
+            kmax = std::max(kmax, jj + 1);
+            any_finish = true;
+            ++n_fin;
+            if (conv) ms_.converged = true;
+            break;
+          }
         }
       }
+      j += cnt;
       if (!any_finish) continue;
       // form the correction for the members that end their cycle here
       std::fill(h_coef.begin(), h_coef.end(), 0.0);
       PCOP_HIP(download(h_sc.data(), sc, c->pin_sc, (size_t)B * kMaxBasis));
-      const int k = j + 1;
       for (int m = 0; m < B; ++m) {
         if (!h_finish[m]) continue;
+        const int k = kfin[m];
         double y[kMaxBasis];
         back_substitute(ms[m], k, y);
         for (int i = 0; i < k; ++i)
@@ -1006,6 +1132,7 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
       std::memcpy(c->pin_coef, h_coef.data(), sizeof(double) * B * kMaxBasis);
       PCOP_HIP(hipMemcpyAsync(coef, c->pin_coef, sizeof(double) * B * kMaxBasis, hipMemcpyHostToDevice, st));
       PCOP_HIP(upload_ints(finish, h_finish, c->pin_finish));
+      const int k = kmax;
       if (side == PCOP_LEFT) {
         tbeg(c->kt(), KF_COMBINE, 8.0 * (k + 2) * g.vl * n_fin);
         launch_combine(c->kargs(c->basis(0), finish), k, coef, kMaxBasis, x, 1, st);
@@ -1030,7 +1157,7 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
         // a member ends: converged or out of iterations; otherwise it restarts
         if (ms[m].converged || ms[m].iters >= maxit) ms[m].active = false;
       }
-      for (int m = 0; m < B; ++m) h_active[m] = (ms[m].active && !h_finish[m]) ? 1 : 0;
+      for (int m = 0; m < B; ++m) h_active[m] = (ms[m].active && !h_finish[m] && h_active[m]) ? 1 : 0;
       PCOP_HIP(upload_ints(active, h_active, c->pin_active));
       if (!any_left) break;
     }

@@ -238,6 +238,30 @@ def test_batched_member_equals_single_solve():
         assert rel(xb[k].cpu().numpy(), x1[0].cpu().numpy()) < 1e-13
 
 
+@pytest.mark.parametrize("chunk", [1, 3, 4])
+def test_graph_solve_matches_eager(chunk):
+    """Arnoldi chunks replayed as captured HIP graphs give the eager solve's
+    iterates; the graphs are replayed across several solves with eager work
+    in between."""
+    dim, nx, nt, gammas = 2, 15, 16, (1e-2, 1e-7, 1e-4)
+    fields = [W.random_fields(dim, nx, nt, seed=80 + b) for b in range(3)]
+    g = np.stack([fl[0] for fl in fields])
+    f = np.stack([fl[1] for fl in fields])
+    y0 = np.stack([fl[2] for fl in fields])
+    se = Solver(dim, nx, nt, list(gammas), device=DEV)
+    xe, ie, he = se.solve(se.rhs(to_dev(g), to_dev(f), to_dev(y0)), history=True)
+    sg = Solver(dim, nx, nt, list(gammas), graph=True, graph_chunk=chunk, device=DEV)
+    b = sg.rhs(to_dev(g), to_dev(f), to_dev(y0))
+    for rep in range(3):
+        xg, ig, hg = sg.solve(b, history=True)
+        for k in range(3):
+            assert ig[k].converged and ig[k].iters == ie[k].iters
+            assert rel(xg[k].cpu().numpy(), xe[k].cpu().numpy()) < 1e-14
+        np.testing.assert_array_equal(np.nan_to_num(hg), np.nan_to_num(he))
+        sg.kkt_apply(b)  # eager work between replays
+        torch.cuda.synchronize()
+
+
 def test_transpose_solve():
     dim, nx, nt, gamma = 2, 15, 16, 1e-3
     pb = D.make_problem(dim, nx, nt, gamma)
