@@ -223,3 +223,24 @@ def kkt_apply(pb: Problem, x: np.ndarray, transpose: bool = False) -> np.ndarray
     """y = A x (or A^T x) with the assembled sparse A."""
     A = kkt_scaled(pb)
     return (A.T @ x) if transpose else (A @ x)
+
+
+def kkt_apply_blocks(pb: Problem, x: np.ndarray, transpose: bool = False) -> np.ndarray:
+    """y = A x (or A^T x) written out block by block from eq. matrix_A without
+    assembling A:  with E = I + tau K,
+        y_1^j = alpha x_1^j + E x_2^j - x_2^{j+1},
+        y_2^j = -(E x_1^j - x_1^{j-1}) + alpha x_2^j,
+    x^0 = x^{n+1} = 0 (B_n has ones on the diagonal and -1 below it); A^T flips
+    the sign of both off-diagonal blocks (M = I).  Used where the assembled
+    matrix is too large to build."""
+    n, m = pb.n, pb.m
+    X = np.asarray(x, dtype=np.float64).reshape(2, n, m)
+    x1, x2 = X[0], X[1]
+    Ex1 = x1 + pb.tau * (pb.K @ x1.T).T
+    Ex2 = x2 + pb.tau * (pb.K @ x2.T).T
+    x2next = np.vstack([x2[1:], np.zeros((1, m))])
+    x1prev = np.vstack([np.zeros((1, m)), x1[:-1]])
+    sgn = -1.0 if transpose else 1.0
+    y1 = pb.alpha * x1 + sgn * (Ex2 - x2next)
+    y2 = -sgn * (Ex1 - x1prev) + pb.alpha * x2
+    return np.concatenate([y1.ravel(), y2.ravel()])

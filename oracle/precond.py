@@ -144,3 +144,30 @@ class IdealRBD:
             r = v[0, j] + (z1[j + 1] if j < n - 1 else 0.0)
             z1[j] = self.lu.solve(r)
         return np.concatenate([(z1 - z2).ravel(), (z1 + z2).ravel()])
+
+
+def eps_circulant_apply(pb: Problem, w: np.ndarray) -> np.ndarray:
+    """v = P_eps w for P_eps of eq. matrix_P_eps without assembling it:
+    with [u_1; u_2] = [[I, I], [-I, I]] w,
+        v_1 = (C_eps^T + alpha I) u_1 / 2,  v_2 = (C_eps + alpha I) u_2 / 2,
+    C_eps = C_{eps,n} (x) I + tau I (x) K, and C_{eps,n} = B_n with -eps in the
+    top-right corner.  Checks a computed P_eps^{-1} v at any size."""
+    n, m = pb.n, pb.m
+    W = np.asarray(w, dtype=np.float64).reshape(2, n, m)
+    u1 = W[0] + W[1]
+    u2 = -W[0] + W[1]
+
+    def c_apply(u, transpose):
+        tK = pb.tau * (pb.K @ u.T).T
+        out = u + tK + pb.alpha * u
+        if not transpose:   # (C u)_j = u_j - u_{j-1}, j = 0 wraps with -eps
+            out[1:] -= u[:-1]
+            out[0] -= pb.eps * u[-1]
+        else:               # (C^T u)_j = u_j - u_{j+1}, j = n-1 wraps with -eps
+            out[:-1] -= u[1:]
+            out[-1] -= pb.eps * u[0]
+        return out
+
+    v1 = 0.5 * c_apply(u1, True)
+    v2 = 0.5 * c_apply(u2, False)
+    return np.concatenate([v1.ravel(), v2.ravel()])

@@ -114,3 +114,11 @@ def test_dof_column_matches_paper():
     33 292 800 at h = tau = 2^-8."""
     assert 2 * 31 ** 2 * 32 == 61504
     assert 2 * 255 ** 2 * 256 == 33292800
+
+
+@pytest.mark.parametrize("dim,nx,nt,coeff", [(2, 5, 7, None), (3, 3, 5, W.coeff_sines3d), (2, 4, 2, None)])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_blockwise_matvec_equals_assembled(dim, nx, nt, coeff, transpose):
+    pb = D.make_problem(dim, nx, nt, 1e-3, coeff=coeff)
+    x = np.random.default_rng(5).standard_normal(2 * pb.n * pb.m)
+    assert rel(D.kkt_apply_blocks(pb, x, transpose), D.kkt_apply(pb, x, transpose)) < 1e-14

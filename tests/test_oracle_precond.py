@@ -131,3 +131,12 @@ def test_multigrid_spatial_option_matches_lu_when_exact():
     a = P.EpsCirculantRBD(pb, spatial="lu").apply(v)
     b = P.EpsCirculantRBD(pb, spatial="mg").apply(v)
     assert rel(a, b) < 1e-13
+
+
+@pytest.mark.parametrize("dim,nx,nt,eps", [(2, 3, 6, 0.3), (1, 5, 9, 1.0), (3, 2, 4, 0.05)])
+def test_forward_preconditioner_equals_assembled(dim, nx, nt, eps):
+    pb = D.make_problem(dim, nx, nt, 1e-4, eps=eps)
+    w = np.random.default_rng(3).standard_normal(2 * pb.n * pb.m)
+    assert rel(P.eps_circulant_apply(pb, w), P.eps_circulant_dense(pb) @ w) < 1e-14
+    # and it inverts the four-step apply
+    assert rel(P.eps_circulant_apply(pb, P.EpsCirculantRBD(pb).apply(w)), w) < 1e-12
