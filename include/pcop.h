@@ -194,7 +194,9 @@ pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* ep
  * synchronises, and returns for each kernel family the number of launches,
  * the summed event time in milliseconds and the summed algorithmic HBM
  * bytes (what the method must read and write: each input and output vector
- * once).  name points to static storage.  Enabling resets the counters. */
+ * once).  name points to static storage.  Enabling resets the counters.
+ * While timing is enabled pcop_solve runs without graphs (graph = 1 is
+ * ignored), so that every kernel can be bracketed. */
 typedef struct {
   const char* name;
   long long launches;

@@ -898,7 +898,7 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
   if (((uintptr_t)b | (uintptr_t)x) & 15) return fail(PCOP_ERR_INVALID_ARG, "b and x must be 16-byte aligned");
   // graph mode runs the whole solve on the context's private stream, after
   // the caller's stream has delivered b and x
-  const bool use_graph = c->opt.graph && c->gst;
+  const bool use_graph = c->opt.graph && c->gst && !c->timer.enabled;
   struct StreamSwap {
     pcop_ctx c;
     hipStream_t saved;
