@@ -56,6 +56,8 @@ struct PrecondTables {
   const double* alpha;   // [B]
   const int* active;     // [B] or null
   int nact;              // members with active != 0 (for byte accounting)
+  int dst_variant;       // 0: register sine-transform kernels, 1: LDS-staged kernels
+  int time_cols;         // columns per block of the time passes (0: built-in choice)
   const KTimer* timer;   // or null
   FftPlan plan;          // radices of n
   int mg_levels;
