@@ -80,6 +80,12 @@ def parse():
                     help="override the workload's preconditioner precision")
     ap.add_argument("--graph", type=int, default=None, choices=[0, 1],
                     help="capture Arnoldi chunks as HIP graphs (default: on for the batched and smallest workloads)")
+    ap.add_argument("--tune", type=int, default=1, choices=[0, 1],
+                    help="time the candidate preconditioner kernels at setup and keep the fastest")
+    ap.add_argument("--time-cols", type=int, default=0, choices=[0, -1, -4, -8, -16, 4, 8, 16],
+                    help="time-pass kernels: 0 automatic, -P two LDS buffers, +P in place (P points per block)")
+    ap.add_argument("--dst-kernel", type=int, default=0, choices=[0, 1, 2],
+                    help="sine-transform kernels: 0 automatic, 1 register-resident, 2 LDS-staged")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain device copy of 1 GiB (reference for HBM byte counters)")
     return ap.parse_args()
@@ -219,7 +225,9 @@ def main():
     stream = torch.cuda.Stream(device=dev) if opts["graph"] else None
     s = Solver(cfg.dim, cfg.nx, cfg.nt, list(cfg.gammas), T=cfg.T, eps=cfg.eps,
                coeff=None if cfg.coeff == "one" else W.coeff_function(cfg.coeff),
-               restart=30, maxit=300, rtol=1e-8, device=dev, stream=stream, **opts)
+               restart=30, maxit=300, rtol=1e-8, device=dev, stream=stream, tune=bool(args.tune),
+               time_cols=args.time_cols, dst_kernel=args.dst_kernel, **opts)
+    print(f"# bench: kernels {s.kernels}", file=sys.stderr, flush=True)
     tg = torch.tensor(g, device=dev)
     tf = torch.tensor(f, device=dev)
     ty0 = torch.tensor(y0, device=dev)
@@ -296,7 +304,7 @@ def main():
                    "rtol": 1e-8, "batch": len(members), "global_batch": len(members)},
         "iters": iters, "relres_true": [i.relres_true for i in infos], "converged": ok,
         "kernel_table_source": "eager solve after the timed region" if opts["graph"] else "timed region",
-        "roofline": roofline, "precond_apply": precond, "kernels": kernels,
+        "roofline": roofline, "precond_apply": precond, "kernel_choice": s.kernels, "kernels": kernels,
     }
     if not args.no_cpu_baseline and cfg.spatial == "mg":
         out["cpu_baseline"] = {"value": None, "note": "the oracle's multigrid path is timed only for the DST workloads"}

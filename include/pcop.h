@@ -106,6 +106,21 @@ typedef struct {
  *   reorth_tol a second Gram-Schmidt pass is run for a member when the
  *              coefficients of the new vector against the basis exceed
  *              reorth_tol times its norm (0 = always, < 0 = never).
+ *   time_cols  kernels of the two time passes (steps 1 and 3-4 of P_eps^{-1}):
+ *              0 automatic; -1 Stockham with two LDS buffers and as many
+ *              spatial points per block as fit; -4 / -8 / -16 two buffers
+ *              with at most that many points per block; 4 / 8 / 16 in-place
+ *              Stockham (one LDS buffer) with at most that many points per
+ *              block.  A kind of kernel that does not fit LDS falls back to
+ *              the other.  Ignored when nt - 1 has a prime factor above 17
+ *              (chirp-z kernels).
+ *   dst_kernel sine-transform kernels of step 2 (PCOP_DST): 0 automatic,
+ *              1 register-resident lines, 2 lines staged through LDS.
+ *   tune       1: pcop_setup times every candidate left at 0 ("automatic")
+ *              above on the context's stream and keeps the fastest; the
+ *              choice is cached per device and shape for the process.
+ *              0: built-in choices.  All choices give the same iterates up
+ *              to rounding.
  *   stream     hipStream_t on which all work is enqueued. */
 typedef struct {
   int precision;
@@ -117,6 +132,9 @@ typedef struct {
   int graph;
   int graph_chunk;
   double reorth_tol;
+  int time_cols;
+  int dst_kernel;
+  int tune;
   void* stream;
 } pcop_options;
 
@@ -188,6 +206,13 @@ pcop_status pcop_data_grad(pcop_ctx ctx, const double* lam, double* dg, double* 
 
 /* Host copy of a few derived scalars: tau, alpha[batch], eps. */
 pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* eps);
+
+/* Kernel choices in effect (after tuning): time_cols -P (two LDS buffers,
+ * P points per block), +P (in place) or 0 (chirp-z); dst_kernel 1
+ * (register-resident), 2 (LDS-staged) or 0 (multigrid).  tuned_ms: the
+ * fastest preconditioner apply measured by the tuner, 0 when no tuning ran.
+ * Any output may be NULL. */
+pcop_status pcop_get_kernels(pcop_ctx ctx, int* time_cols, int* dst_kernel, double* tuned_ms);
 
 /* Per-kernel timing.  While enabled, every kernel the context launches is
  * bracketed by HIP events on the context's stream; pcop_timing_read

@@ -17,7 +17,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpcop.so")
-SOURCES = ["kkt.hip", "precond.hip", "multigrid.hip", "krylov.hip", "pcop.cpp"]
+# slowest translation units first, so the parallel build finishes sooner
+SOURCES = ["time_ip_fwd_f64.hip", "time_ip_inv_f64.hip", "time_ip_fwd_f32.hip", "time_ip_inv_f32.hip",
+           "time_sk.hip", "time_bl.hip", "dst.hip", "kkt.hip", "krylov.hip", "multigrid.hip", "precond.hip",
+           "pcop.cpp"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [

@@ -1,0 +1,402 @@
+// Step 2 of the preconditioner for a = 1: shifted spatial solves by sine
+// transforms, one launch per axis over every frequency slice of every member.
+#include "common.hpp"
+#include "fft_lds.hpp"
+#include "launch.hpp"
+
+namespace pcop {
+
+// ---------------------------------------------------------------------------
+// sine-transform passes (a = 1)
+//
+// Y = FFT_L of the odd extension [0, z_1..z_N, 0, -z_N..-z_1], L = 2(N+1),
+// gives Y_k = -2i sum_j z_j sin(pi j k/(N+1)); every pass stores Y_1..Y_N.
+// The constant (-2i)^{2d} and the orthonormalisation (2/(N+1))^d are folded
+// into the division of the last-axis pass:
+//     Z = c / (sigma_q + tau mu),  c = (-1/(2(N+1)))^d,
+//     mu = (4/h^2) sum_d sin^2(pi k_d h/2).
+// Lines: element e of line l of plane p sits at
+//     p * plane_stride + l * line_stride + e * elem_stride   (complex units).
+// ---------------------------------------------------------------------------
+struct LineGeom {
+  long long nplanes;
+  long long plane_stride;
+  int lines;  // lines per plane
+  int line_stride;
+  int elem_stride;
+};
+
+struct DivideParams {
+  const double* mu1;     // [nx] 1-D eigenvalues (4/h^2) sin^2(pi k h/2)
+  const double* lam;     // [2K] (re, im) of lambda_k
+  const double* alpha;   // [B]
+  const int* active;     // [B] or null
+  double cnorm;
+};
+
+template <class T, int L, int LINES, int NT, bool ROWS, bool DIVIDE>
+__global__ void __launch_bounds__(NT) dst_lines_kernel(Geo g, cx<T>* __restrict__ data, LineGeom lg,
+                                                       const cx<T>* __restrict__ twL, DivideParams dp) {
+  constexpr int N = L / 2 - 1;
+  constexpr int LD = L + 1;  // odd stride for complex entries
+  __shared__ cx<T> buf[LINES * LD];
+  const int tiles = (lg.lines + LINES - 1) / LINES;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const long long plane = blk / tiles;
+  const int l0 = (int)(blk - plane * tiles) * LINES;
+  const long long pbase = plane * lg.plane_stride;
+  if (DIVIDE && dp.active) {
+    if (!dp.active[(int)(plane / (2 * g.K))]) return;
+  }
+  for (int t = threadIdx.x; t < LINES * N; t += NT) {
+    int l, e;
+    if (ROWS) {
+      l = t / N;
+      e = t - l * N;
+    } else {
+      e = t / LINES;
+      l = t - e * LINES;
+    }
+    cx<T> val{0, 0};
+    if (l0 + l < lg.lines)
+      val = data[pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride];
+    buf[l * LD + e + 1] = val;
+    buf[l * LD + L - 1 - e] = cx<T>{-val.x, -val.y};
+  }
+  for (int l = threadIdx.x; l < LINES; l += NT) {
+    buf[l * LD] = cx<T>{0, 0};
+    buf[l * LD + N + 1] = cx<T>{0, 0};
+  }
+  __syncthreads();
+  p2_fft<T, -1, L, LINES, NT>(buf, LD, twL);
+  if (DIVIDE) {
+    // the last-axis pass has one plane per slice q of member b; the shift
+    // sigma_q = lambda_k + alpha_b (q even) or conj(lambda_k) + alpha_b (q odd)
+    // is uniform over the block
+    const int b = (int)(plane / (2 * g.K));
+    const int q = (int)(plane - (long long)b * 2 * g.K);
+    const int k = q >> 1;
+    const double sre = dp.lam[2 * k] + dp.alpha[b];
+    const double sim = (q & 1) ? -dp.lam[2 * k + 1] : dp.lam[2 * k + 1];
+    for (int t = threadIdx.x; t < LINES * N; t += NT) {
+      const int e = t / LINES;
+      const int l = t - e * LINES;
+      cx<T> y = buf[l * LD + e + 1];
+      const int line = l0 + l;
+      if (line < lg.lines) {
+        // in-plane coordinates: line = x1 (+ nx x2 in 3-D), element = last axis
+        double mu = dp.mu1[e] + dp.mu1[line % g.nx];
+        if (g.dim == 3) mu += dp.mu1[line / g.nx];
+        const double dre = sre + g.tau * mu;
+        const double den = dre * dre + sim * sim;
+        // cnorm / (dre + i sim) = cnorm (dre - i sim) / den
+        const double fre = dp.cnorm * dre / den;
+        const double fim = -dp.cnorm * sim / den;
+        y = y * cx<T>{(T)fre, (T)fim};
+      }
+      buf[l * LD + e + 1] = y;
+      buf[l * LD + L - 1 - e] = cx<T>{-y.x, -y.y};
+    }
+    for (int l = threadIdx.x; l < LINES; l += NT) {
+      buf[l * LD] = cx<T>{0, 0};
+      buf[l * LD + N + 1] = cx<T>{0, 0};
+    }
+    __syncthreads();
+    p2_fft<T, -1, L, LINES, NT>(buf, LD, twL);
+  }
+  for (int t = threadIdx.x; t < LINES * N; t += NT) {
+    int l, e;
+    if (ROWS) {
+      l = t / N;
+      e = t - l * N;
+    } else {
+      e = t / LINES;
+      l = t - e * LINES;
+    }
+    if (l0 + l < lg.lines)
+      data[pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride] = buf[l * LD + e + 1];
+  }
+}
+
+// lines per block: as many as fit 48 KiB of LDS (three blocks per CU); the
+// XCD-aware block order lets neighbouring tiles share partially used lines
+// ---------------------------------------------------------------------------
+// Register variant of the sine-transform pass.  A line of length L = 2(N+1)
+// is owned by TL = L/8 threads; thread t always holds the 8 values at the
+// positions t + TL s (s = 0..7).  In a Stockham stage with radix R the inputs
+// of the thread's butterflies jb = t + TL q (q < 8/R) sit exactly at those
+// positions (element s = q + r 8/R), so the first stage reads the odd
+// extension straight from the input and the last stage (Ns R = L) leaves the
+// transform in natural order in registers; between stages one LDS exchange.
+// LDS index is padded by one complex per 8 to spread the stage writes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int pidx(int pos) { return pos + (pos >> 3); }
+
+template <class T, int L, int TL, int SG, int NS>
+struct RegStages {
+  static __device__ __forceinline__ void run(cx<T> (&v)[8], int t, cx<T>* lbuf, const cx<T>* __restrict__ twL) {
+    constexpr int R = (L / NS >= 8) ? 8 : (L / NS);
+    constexpr int Q = 8 / R;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int jb = t + TL * q;
+      const int jl = jb % NS;
+      cx<T> a[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[r] = v[q + r * Q];
+      if (NS > 1 && jl != 0) {
+        constexpr int tstep = L / (NS * R);
+        if constexpr (sizeof(T) == 8) {
+          cx<T> w1 = twL[jl * tstep];
+          if (SG > 0) w1.y = -w1.y;
+          cx<T> w = w1;
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            a[r] = a[r] * w;
+            w = w * w1;
+          }
+        } else {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            cx<T> w = twL[(r * jl * tstep) & (L - 1)];
+            if (SG > 0) w.y = -w.y;
+            a[r] = a[r] * w;
+          }
+        }
+      }
+      dftR<T, SG, R>(a);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q + r * Q] = a[r];
+    }
+    if constexpr (NS * R < L) {
+      // exchange: outputs to LDS, next stage's inputs back
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int jb = t + TL * q;
+        const int jl = jb % NS;
+        const int base = (jb - jl) * R + jl;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lbuf[pidx(base + r * NS)] = v[q + r * Q];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < 8; ++s) v[s] = lbuf[pidx(t + TL * s)];
+      RegStages<T, L, TL, SG, NS * R>::run(v, t, lbuf, twL);
+    }
+  }
+};
+
+template <class T, int L, int ROWS_, int DIVIDE_>
+__global__ void __launch_bounds__(256) dst_reg_kernel(Geo g, cx<T>* __restrict__ data, LineGeom lg,
+                                                      const cx<T>* __restrict__ twL, DivideParams dp) {
+  constexpr bool ROWS = ROWS_ != 0;
+  constexpr bool DIVIDE = DIVIDE_ != 0;
+  constexpr int N = L / 2 - 1;
+  constexpr int TL = L / 8;
+  constexpr int LPB = 256 / TL;
+  constexpr int LD = L + L / 8 + 1;
+  __shared__ cx<T> buf[LPB * LD];
+  const int tiles = (lg.lines + LPB - 1) / LPB;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const long long plane = blk / tiles;
+  const int l0 = (int)(blk - plane * tiles) * LPB;
+  const long long pbase = plane * lg.plane_stride;
+  if (DIVIDE && dp.active) {
+    if (!dp.active[(int)(plane / (2 * g.K))]) return;
+  }
+  const int lid = threadIdx.x / TL;
+  const int t = threadIdx.x - lid * TL;
+  const int line = l0 + lid;
+  const bool valid = line < lg.lines;
+  cx<T>* lbuf = buf + lid * LD;
+  // column passes stage the [N][LPB] tile through LDS with coalesced loads
+  if (!ROWS) {
+    for (int idx = threadIdx.x; idx < N * LPB; idx += 256) {
+      const int e = idx / LPB;
+      const int l = idx - e * LPB;
+      cx<T> val{0, 0};
+      if (l0 + l < lg.lines)
+        val = data[pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride];
+      buf[l * LD + pidx(e)] = val;
+    }
+    __syncthreads();
+  }
+  auto zval = [&](int e) -> cx<T> {
+    if (ROWS) {
+      if (!valid) return cx<T>{0, 0};
+      return data[pbase + (long long)line * lg.line_stride + (long long)e * lg.elem_stride];
+    }
+    return lbuf[pidx(e)];
+  };
+  cx<T> v[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int pos = t + TL * s;
+    if (pos >= 1 && pos <= N) {
+      v[s] = zval(pos - 1);
+    } else if (pos >= N + 2) {
+      const cx<T> z = zval(L - 1 - pos);
+      v[s] = cx<T>{-z.x, -z.y};
+    } else {
+      v[s] = cx<T>{0, 0};
+    }
+  }
+  RegStages<T, L, TL, -1, 1>::run(v, t, lbuf, twL);
+  if (DIVIDE) {
+    const int b = (int)(plane / (2 * g.K));
+    const int q = (int)(plane - (long long)b * 2 * g.K);
+    const int k = q >> 1;
+    const double sre = dp.lam[2 * k] + dp.alpha[b];
+    const double sim = (q & 1) ? -dp.lam[2 * k + 1] : dp.lam[2 * k + 1];
+    double mul = dp.mu1[line % g.nx];
+    if (g.dim == 3) mul += dp.mu1[(line / g.nx) % g.nx];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int pos = t + TL * s;
+      if (pos >= 1 && pos <= N && valid) {
+        const double dre = sre + g.tau * (mul + dp.mu1[pos - 1]);
+        const double den = dre * dre + sim * sim;
+        v[s] = v[s] * cx<T>{(T)(dp.cnorm * dre / den), (T)(-dp.cnorm * sim / den)};
+      }
+    }
+    // odd extension of the divided values: the mirrored half comes from LDS
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int pos = t + TL * s;
+      if (pos >= 1 && pos <= N) lbuf[pidx(pos)] = v[s];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int pos = t + TL * s;
+      if (pos >= N + 2) {
+        const cx<T> z = lbuf[pidx(L - pos)];
+        v[s] = cx<T>{-z.x, -z.y};
+      } else if (pos == 0 || pos == N + 1) {
+        v[s] = cx<T>{0, 0};
+      }
+    }
+    RegStages<T, L, TL, -1, 1>::run(v, t, lbuf, twL);
+  }
+  if (ROWS) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int pos = t + TL * s;
+      if (pos >= 1 && pos <= N && valid)
+        data[pbase + (long long)line * lg.line_stride + (long long)(pos - 1) * lg.elem_stride] = v[s];
+    }
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int pos = t + TL * s;
+      if (pos >= 1 && pos <= N) lbuf[pidx(pos - 1)] = v[s];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < N * LPB; idx += 256) {
+      const int e = idx / LPB;
+      const int l = idx - e * LPB;
+      if (l0 + l < lg.lines)
+        data[pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride] = buf[l * LD + pidx(e)];
+    }
+  }
+}
+
+template <class T, int L>
+constexpr int dst_lines_per_block() {
+  constexpr int bytes = (L + 1) * (int)sizeof(cx<T>);
+  constexpr int fit = 49152 / bytes;
+  return fit < 1 ? 1 : (fit > 64 ? 64 : fit);
+}
+
+template <class T, int L>
+static void dst_pass_L(const Geo& g, cx<T>* data, const LineGeom& lg, bool rows, bool divide,
+                       const cx<T>* twL, const DivideParams& dp, int variant, hipStream_t st) {
+  if (variant == 1) {
+    // all stages staged through LDS ([LINES][L+1] tiles)
+    constexpr int LINES = dst_lines_per_block<T, L>();
+    constexpr int NT = 256;
+    const long long tiles = (lg.lines + LINES - 1) / LINES;
+    dim3 grid((unsigned)(tiles * lg.nplanes));
+    if (rows) {
+      if (divide) dst_lines_kernel<T, L, LINES, NT, true, true><<<grid, NT, 0, st>>>(g, data, lg, twL, dp);
+      else dst_lines_kernel<T, L, LINES, NT, true, false><<<grid, NT, 0, st>>>(g, data, lg, twL, dp);
+    } else {
+      if (divide) dst_lines_kernel<T, L, LINES, NT, false, true><<<grid, NT, 0, st>>>(g, data, lg, twL, dp);
+      else dst_lines_kernel<T, L, LINES, NT, false, false><<<grid, NT, 0, st>>>(g, data, lg, twL, dp);
+    }
+    return;
+  }
+  // register variant: L/8 threads per line
+  constexpr int LPB = 256 / (L / 8);
+  const long long tiles = (lg.lines + LPB - 1) / LPB;
+  dim3 grid((unsigned)(tiles * lg.nplanes));
+  if (rows) {
+    if (divide) dst_reg_kernel<T, L, 1, 1><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
+    else dst_reg_kernel<T, L, 1, 0><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
+  } else {
+    if (divide) dst_reg_kernel<T, L, 0, 1><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
+    else dst_reg_kernel<T, L, 0, 0><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
+  }
+}
+
+template <class T>
+static bool dst_pass(const Geo& g, cx<T>* data, const LineGeom& lg, bool rows, bool divide,
+                     const cx<T>* twL, const DivideParams& dp, int variant, hipStream_t st) {
+  switch (2 * (g.nx + 1)) {
+    case 8: dst_pass_L<T, 8>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
+    case 16: dst_pass_L<T, 16>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
+    case 32: dst_pass_L<T, 32>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
+    case 64: dst_pass_L<T, 64>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
+    case 128: dst_pass_L<T, 128>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
+    case 256: dst_pass_L<T, 256>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
+    case 512: dst_pass_L<T, 512>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
+    case 1024: dst_pass_L<T, 1024>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
+    default: return false;
+  }
+}
+
+// Step 2 with sine transforms: axes 1..d-1 forward, last axis forward +
+// divide + inverse, axes d-1..1 inverse (the transforms commute).
+template <class T>
+static bool dst_solve(const Geo& g, cx<T>* spec, const PrecondTables& tb, hipStream_t st) {
+  const int nx = g.nx;
+  const long long slices = (long long)g.B * 2 * g.K;
+  DivideParams dp{tb.mu1, tb.lam, tb.alpha, tb.active, 0.0};
+  dp.cnorm = (g.dim == 2) ? 1.0 / (4.0 * (nx + 1.0) * (nx + 1.0))
+                          : -1.0 / (8.0 * (nx + 1.0) * (nx + 1.0) * (nx + 1.0));
+  const cx<T>* twL = reinterpret_cast<const cx<T>*>(sizeof(T) == 8 ? (const void*)tb.twL64 : (const void*)tb.twL32);
+  // x1: contiguous rows
+  LineGeom rows{1, 0, (int)(slices * (g.dim == 3 ? nx * nx : nx)), nx, 1};
+  // x2 (3-D only as an outer axis): planes (b, q, x3), lines x1, stride nx
+  LineGeom ax2{slices * nx, (long long)nx * nx, nx, 1, nx};
+  // last axis with the division: planes (b, q), lines = nx^{d-1}
+  const int lines_last = (g.dim == 3) ? nx * nx : nx;
+  const int stride_last = (g.dim == 3) ? nx * nx : nx;
+  LineGeom last{slices, (long long)g.m, lines_last, 1, stride_last};
+  // every pass reads and writes the spectrum of the counted members once
+  const double pass_bytes = 2.0 * sizeof(cx<T>) * 2.0 * g.K * (double)g.m * tb.nact;
+  bool ok = true;
+  auto run = [&](const LineGeom& lg, bool r, bool dv, int fam) {
+    if (!ok) return;
+    tbeg(tb.timer, fam, pass_bytes);
+    ok = dst_pass<T>(g, spec, lg, r, dv, twL, dp, tb.dst_variant, st);
+    tend(tb.timer);
+  };
+  run(rows, true, false, KF_DST_ROWS);
+  if (g.dim == 3) run(ax2, false, false, KF_DST_AX2);
+  run(last, false, true, KF_DST_LAST);
+  if (g.dim == 3) run(ax2, false, false, KF_DST_AX2);
+  run(rows, true, false, KF_DST_ROWS);
+  return ok;
+}
+
+
+bool launch_dst_solve(const Geo& g, void* spec, bool fp32, const PrecondTables& tb, hipStream_t st) {
+  if (fp32) return dst_solve<float>(g, reinterpret_cast<cx<float>*>(spec), tb, st);
+  return dst_solve<double>(g, reinterpret_cast<cx<double>*>(spec), tb, st);
+}
+
+}  // namespace pcop

@@ -93,23 +93,46 @@ __device__ __forceinline__ void dft5(cx<T>* a) {
   a[3] = u2 - v2;
 }
 
-// generic R-point DFT; W_R^t = twn[t * stride] (twn: exp(-2 pi i t/n), n = R stride)
+// R-point DFT for odd R; W_R^t = twn[t * stride] (twn: exp(-2 pi i t/n),
+// n = R stride).  Inputs r and R - r are paired: with s_r = a_r + a_{R-r},
+// d_r = a_r - a_{R-r} and theta = 2 pi r k/R,
+//   X_k     = a_0 + sum_{r=1}^{H} s_r cos(theta) + SG i sum_{r=1}^{H} d_r sin(theta),
+//   X_{R-k} = the same with the sign of the sine sum flipped,  H = (R-1)/2,
+// so only H twiddles are loaded and 4 H^2 real FMAs replace 4 R (R-1).
 template <class T, int SG, int R>
-__device__ __forceinline__ void dft_generic(cx<T>* a, const cx<T>* __restrict__ twn, int stride) {
-  cx<T> out[R];
+__device__ __forceinline__ void dft_odd(cx<T>* a, const cx<T>* __restrict__ twn, int stride) {
+  constexpr int H = (R - 1) / 2;
+  T c[H + 1], sn[H + 1];  // cos, sin of 2 pi t/R, t = 1..H
 #pragma unroll
-  for (int k = 0; k < R; ++k) {
-    cx<T> acc = a[0];
+  for (int t = 1; t <= H; ++t) {
+    const cx<T> w = twn[t * stride];
+    c[t] = w.x;
+    sn[t] = -w.y;
+  }
+  cx<T> sm[H + 1], df[H + 1];
+  cx<T> x0 = a[0];
 #pragma unroll
-    for (int r = 1; r < R; ++r) {
-      cx<T> w = twn[((r * k) % R) * stride];
-      if (SG > 0) w.y = -w.y;
-      acc = acc + a[r] * w;
-    }
-    out[k] = acc;
+  for (int r = 1; r <= H; ++r) {
+    sm[r] = a[r] + a[R - r];
+    df[r] = a[r] - a[R - r];
+    x0 = x0 + sm[r];
   }
 #pragma unroll
-  for (int k = 0; k < R; ++k) a[k] = out[k];
+  for (int k = 1; k <= H; ++k) {
+    cx<T> p = a[0], q{0, 0};
+#pragma unroll
+    for (int r = 1; r <= H; ++r) {
+      const int t = (r * k) % R;  // cos is even and sin odd in t about R/2
+      const T ct = (t <= H) ? c[t] : c[R - t];
+      const T st = (t <= H) ? sn[t] : -sn[R - t];
+      p = p + scale(sm[r], ct);
+      q = q + scale(df[r], st);
+    }
+    const cx<T> iq = mul_i<T, SG>(q);  // SG i q
+    a[k] = p + iq;
+    a[R - k] = p - iq;
+  }
+  a[0] = x0;
 }
 
 template <class T, int SG, int R>
@@ -129,7 +152,8 @@ __device__ __forceinline__ void dft_any(cx<T>* a, const cx<T>* __restrict__ twn,
   } else if constexpr (R == 5) {
     dft5<T, SG>(a);
   } else {
-    dft_generic<T, SG, R>(a, twn, stride);
+    static_assert(R % 2 == 1, "radices other than 2, 4, 8 must be odd");
+    dft_odd<T, SG, R>(a, twn, stride);
   }
 }
 
@@ -197,6 +221,108 @@ __device__ __forceinline__ void sk_stage_rt(int R, int n, int Ns, const cx<T>* _
     case 11: sk_stage<T, 11, P, SG>(n, Ns, twn, load, store); break;
     case 13: sk_stage<T, 13, P, SG>(n, Ns, twn, load, store); break;
     case 17: sk_stage<T, 17, P, SG>(n, Ns, twn, load, store); break;
+    default: break;
+  }
+}
+
+// In-place Stockham stage over P columns ([n][P] in LDS): each thread loads
+// all of its (at most MB) butterflies into registers, the block waits, and the
+// outputs are written over the inputs.  load/store as in sk_stage; the caller
+// puts a barrier between consecutive LDS stages.
+template <class T, int R, int P, int SG, int MB, class LD, class ST>
+__device__ __forceinline__ void ip_stage(int n, int Ns, const cx<T>* __restrict__ twn, bool sync_between, LD load,
+                                         ST store) {
+  const int nR = n / R;
+  const int tstep = n / (Ns * R);
+  const int nb = nR * P;
+  cx<T> v[MB][R];
+#pragma unroll
+  for (int q = 0; q < MB; ++q) {
+    const int bf = threadIdx.x + q * blockDim.x;
+    if (bf < nb) {
+      const int p = bf % P;
+      const int jb = bf / P;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = load(jb + r * nR, p);
+    }
+  }
+  if (sync_between) __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MB; ++q) {
+    const int bf = threadIdx.x + q * blockDim.x;
+    if (bf < nb) {
+      const int p = bf % P;
+      const int jb = bf / P;
+      const int jl = jb % Ns;
+      if (R > 1 && jl != 0) {
+        if constexpr (sizeof(T) == 8) {
+          cx<T> w1 = twn[jl * tstep];
+          if (SG > 0) w1.y = -w1.y;
+          cx<T> w = w1;
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            v[q][r] = v[q][r] * w;
+            w = w * w1;
+          }
+        } else {
+          const int e1 = jl * tstep;
+          int e = e1;
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            cx<T> w = twn[e];
+            if (SG > 0) w.y = -w.y;
+            v[q][r] = v[q][r] * w;
+            e += e1;
+            if (e >= n) e -= n;
+          }
+        }
+      }
+      dft_any<T, SG, R>(v[q], twn, nR);
+      const int base = (jb - jl) * R + jl;
+#pragma unroll
+      for (int r = 0; r < R; ++r) store(base + r * Ns, p, v[q][r]);
+    }
+  }
+}
+
+// butterflies per thread a stage needs, rounded up to a supported bound
+__host__ __device__ inline int ip_mb(int n, int R, int P, int nt) {
+  const int need = (n / R * P + nt - 1) / nt;
+  return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 0;
+}
+
+template <class T, int R, int P, int SG, class LD, class ST>
+__device__ __forceinline__ bool ip_stage_mb(int mb, int n, int Ns, const cx<T>* __restrict__ twn, bool sync_between,
+                                            LD load, ST store) {
+  if constexpr (R >= 11) {
+    if (mb == 1) ip_stage<T, R, P, SG, 1>(n, Ns, twn, sync_between, load, store);
+    else if (mb == 2) ip_stage<T, R, P, SG, 2>(n, Ns, twn, sync_between, load, store);
+    else return false;
+  } else {
+    if (mb == 1) ip_stage<T, R, P, SG, 1>(n, Ns, twn, sync_between, load, store);
+    else if (mb == 2) ip_stage<T, R, P, SG, 2>(n, Ns, twn, sync_between, load, store);
+    else if (mb == 4) ip_stage<T, R, P, SG, 4>(n, Ns, twn, sync_between, load, store);
+    else if (mb == 8) ip_stage<T, R, P, SG, 8>(n, Ns, twn, sync_between, load, store);
+    else return false;
+  }
+  return true;
+}
+
+template <class T, int P, int SG, class LD, class ST>
+__device__ __forceinline__ void ip_stage_rt(int R, int n, int Ns, const cx<T>* __restrict__ twn, bool sync_between,
+                                            LD load, ST store) {
+  const int mb = ip_mb(n, R, P, blockDim.x);
+  switch (R) {
+    case 1: ip_stage_mb<T, 1, P, SG>(mb, n, Ns, twn, sync_between, load, store); break;
+    case 2: ip_stage_mb<T, 2, P, SG>(mb, n, Ns, twn, sync_between, load, store); break;
+    case 3: ip_stage_mb<T, 3, P, SG>(mb, n, Ns, twn, sync_between, load, store); break;
+    case 4: ip_stage_mb<T, 4, P, SG>(mb, n, Ns, twn, sync_between, load, store); break;
+    case 5: ip_stage_mb<T, 5, P, SG>(mb, n, Ns, twn, sync_between, load, store); break;
+    case 7: ip_stage_mb<T, 7, P, SG>(mb, n, Ns, twn, sync_between, load, store); break;
+    case 8: ip_stage_mb<T, 8, P, SG>(mb, n, Ns, twn, sync_between, load, store); break;
+    case 11: ip_stage_mb<T, 11, P, SG>(mb, n, Ns, twn, sync_between, load, store); break;
+    case 13: ip_stage_mb<T, 13, P, SG>(mb, n, Ns, twn, sync_between, load, store); break;
+    case 17: ip_stage_mb<T, 17, P, SG>(mb, n, Ns, twn, sync_between, load, store); break;
     default: break;
   }
 }

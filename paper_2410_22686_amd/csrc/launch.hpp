@@ -57,7 +57,7 @@ struct PrecondTables {
   const int* active;     // [B] or null
   int nact;              // members with active != 0 (for byte accounting)
   int dst_variant;       // 0: register sine-transform kernels, 1: LDS-staged kernels
-  int time_cols;         // columns per block of the time passes (0: built-in choice)
+  int time_cols;         // time-kernel request, as pcop_options::time_cols
   const KTimer* timer;   // or null
   FftPlan plan;          // radices of n
   int mg_levels;
@@ -78,11 +78,15 @@ void launch_data_grad(const Geo& g, const double* lam, const double* sg, double*
                       double* dy0, hipStream_t st);
 
 bool time_lds_fits(int n, bool fp32);
+// time-pass kernels that launch_precond runs for tb.time_cols: 0 chirp-z,
+// -P two LDS buffers, +P in place, with P points per block
+int time_choice(const Geo& g, const PrecondTables& tb, bool fp32);
 FftPlan make_time_plan(int n);
 bool launch_precond(const Geo& g, const double* v, double* w, void* spec, bool fp32, int spatial,
                     const PrecondTables& tb, const double* vscale, int vs_stride, int accum,
                     hipStream_t st);
 bool launch_mg_solve(const Geo& g, void* spec, bool fp32, const PrecondTables& tb, hipStream_t st);
+bool launch_dst_solve(const Geo& g, void* spec, bool fp32, const PrecondTables& tb, hipStream_t st);
 
 // Krylov kernels (krylov.hip).  Basis slot i of member b starts at
 // basis + i * slot_stride + b * vl.

@@ -5,9 +5,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -73,6 +76,13 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
   if (!std::isfinite(o->reorth_tol)) return fail(PCOP_ERR_INVALID_ARG, "reorth_tol must be finite");
   if (o->graph != 0 && o->graph != 1) return fail(PCOP_ERR_INVALID_ARG, "graph must be 0 or 1");
   if (o->graph && o->graph_chunk < 1) return fail(PCOP_ERR_INVALID_ARG, "graph_chunk must be >= 1");
+  {
+    const int tc = o->time_cols < 0 ? -o->time_cols : o->time_cols;
+    if (tc != 0 && tc != 1 && tc != 4 && tc != 8 && tc != 16)
+      return fail(PCOP_ERR_INVALID_ARG, "time_cols must be 0, -1, +-4, +-8 or +-16");
+  }
+  if (o->dst_kernel < 0 || o->dst_kernel > 2) return fail(PCOP_ERR_INVALID_ARG, "dst_kernel must be 0, 1 or 2");
+  if (o->tune != 0 && o->tune != 1) return fail(PCOP_ERR_INVALID_ARG, "tune must be 0 or 1");
   if (o->precision == PCOP_MIXED && o->side != PCOP_FLEXIBLE)
     return fail(PCOP_ERR_INVALID_ARG, "the mixed-precision preconditioner needs side = PCOP_FLEXIBLE");
   if (o->spatial == PCOP_DST) {
@@ -267,6 +277,7 @@ struct pcop_ctx_s {
   double ediag = 0, eoff = 0;
   const double* ecoef = nullptr;
   bool fp32 = false;
+  double tuned_ms = 0;
   EventTimer timer;
   KTimer ktimer{&EventTimer::on_begin, &EventTimer::on_end, nullptr};
   // pinned host staging for every scalar transfer of the solver
@@ -338,6 +349,99 @@ void do_norm2(pcop_ctx c, const double* w, const int* mask, int nact) {
   KrylovArgs ka = c->kargs(c->basis(0), mask);
   do_mdot(c, ka, 0, w, nact);
   launch_reduce_partials(c->at<double>(c->L.partial), c->L.nblk, 1, c->g.B, c->at<double>(c->L.red), c->st);
+}
+
+// ---------------------------------------------------------------------------
+// kernel autotuner: times every candidate pair (time-pass kernels, sine-
+// transform kernels) of the preconditioner on the context's stream and keeps
+// the fastest.  Candidates compute the same transforms with the same
+// arithmetic per element; only blocking and LDS use differ.
+// ---------------------------------------------------------------------------
+struct TuneResult {
+  int time_cols, dst_variant;
+  double ms;
+};
+std::mutex g_tune_mu;
+std::map<std::array<int, 10>, TuneResult> g_tune_cache;
+
+pcop_status tune_kernels(pcop_ctx c) {
+  const Geo& g = c->g;
+  int dev = 0;
+  PCOP_HIP(hipGetDevice(&dev));
+  const std::array<int, 10> key{dev, g.dim, g.nx, g.n, g.B, (int)c->fp32, c->opt.spatial, c->opt.time_cols,
+                                c->opt.dst_kernel, c->coeff_kind};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      c->tb.time_cols = it->second.time_cols;
+      c->tb.dst_variant = it->second.dst_variant;
+      c->tuned_ms = it->second.ms;
+      return PCOP_OK;
+    }
+  }
+  std::vector<int> tcs;
+  if (c->opt.time_cols != 0 || c->tb.plan.bluestein) {
+    tcs.push_back(c->tb.time_cols);
+  } else {
+    std::vector<int> seen;
+    for (int want : {-16, -8, -4, 16, 8, 4}) {
+      PrecondTables t = c->tb;
+      t.time_cols = want;
+      const int eff = time_choice(g, t, c->fp32);
+      if (eff == 0 || (eff < 0) != (want < 0)) continue;  // this kind of kernel does not fit
+      if (std::find(seen.begin(), seen.end(), eff) != seen.end()) continue;
+      seen.push_back(eff);
+      tcs.push_back(want);
+    }
+  }
+  std::vector<int> dvs;
+  if (c->opt.spatial == PCOP_DST && c->opt.dst_kernel == 0) dvs = {0, 1};
+  else dvs = {c->tb.dst_variant};
+  double* v = c->basis(0);
+  double* w = c->basis(1);
+  hipStream_t st = c->st;
+  PCOP_HIP(hipMemsetAsync(v, 0, sizeof(double) * (size_t)g.vl * g.B, st));
+  hipEvent_t e0, e1;
+  PCOP_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(PCOP_ERR_DEVICE, "tuner: event creation failed");
+  }
+  constexpr int kReps = 3;
+  TuneResult best{c->tb.time_cols, c->tb.dst_variant, 1e300};
+  hipError_t err = hipSuccess;
+  for (int tc : tcs) {
+    for (int dv : dvs) {
+      PrecondTables t = c->tb;
+      t.time_cols = tc;
+      t.dst_variant = dv;
+      t.active = nullptr;
+      t.nact = g.B;
+      t.timer = nullptr;
+      void* spec = c->at<void>(c->L.spec);
+      if (!launch_precond(g, v, w, spec, c->fp32, c->opt.spatial, t, nullptr, 0, 0, st)) continue;
+      if ((err = hipEventRecord(e0, st)) != hipSuccess) break;
+      for (int r = 0; r < kReps; ++r) launch_precond(g, v, w, spec, c->fp32, c->opt.spatial, t, nullptr, 0, 0, st);
+      if ((err = hipEventRecord(e1, st)) != hipSuccess) break;
+      if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+      float ms = 0.f;
+      if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+      if (ms / kReps < best.ms) best = TuneResult{tc, dv, ms / (double)kReps};
+    }
+    if (err != hipSuccess) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err == hipSuccess) err = hipGetLastError();
+  if (err != hipSuccess) return fail(PCOP_ERR_DEVICE, std::string("tuner: ") + hipGetErrorString(err));
+  if (best.ms >= 1e300) return fail(PCOP_ERR_UNSUPPORTED, "tuner: no preconditioner variant runs for this shape");
+  c->tb.time_cols = best.time_cols;
+  c->tb.dst_variant = best.dst_variant;
+  c->tuned_ms = best.ms;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = best;
+  return PCOP_OK;
 }
 
 }  // namespace
@@ -657,6 +761,8 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   tb.chirp32 = c->at<float>(L.chirp32);
   tb.bhat64 = c->at<double>(L.bhat64);
   tb.bhat32 = c->at<float>(L.bhat32);
+  tb.time_cols = opts->time_cols;
+  tb.dst_variant = (opts->dst_kernel == 2) ? 1 : 0;
   tb.mg_levels = L.mg_levels;
   for (int l = 0; l < L.mg_levels; ++l) {
     MgLevel& lv = tb.mg[l];
@@ -668,6 +774,13 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
     lv.coef64 = c->fp32 ? nullptr : c->at<double>(L.mgcoef[l]);
     lv.r = c->at<void>(L.mgr[l]);
     lv.z = (l > 0) ? c->at<void>(L.mgz[l]) : nullptr;
+  }
+  if (opts->tune) {
+    pcop_status ts = tune_kernels(c);
+    if (ts != PCOP_OK) {
+      delete c;
+      return ts;
+    }
   }
   if (opts->graph) {
     hipError_t ge = hipStreamCreateWithFlags(&c->gst, hipStreamNonBlocking);
@@ -688,6 +801,14 @@ pcop_status pcop_get_params(pcop_ctx c, double* tau, double* alpha, double* eps)
   if (alpha)
     for (int b = 0; b < c->g.B; ++b) alpha[b] = c->alpha[b];
   if (eps) *eps = c->eps;
+  return PCOP_OK;
+}
+
+pcop_status pcop_get_kernels(pcop_ctx c, int* time_cols, int* dst_kernel, double* tuned_ms) {
+  if (!c) return fail(PCOP_ERR_INVALID_ARG, "null context");
+  if (time_cols) *time_cols = time_choice(c->g, c->tb, c->fp32);
+  if (dst_kernel) *dst_kernel = (c->opt.spatial == PCOP_DST) ? c->tb.dst_variant + 1 : 0;
+  if (tuned_ms) *tuned_ms = c->tuned_ms;
   return PCOP_OK;
 }
 

@@ -29,7 +29,7 @@ EXPORTED = [
     "pcop_validate", "pcop_default_options", "pcop_workspace_size", "pcop_setup", "pcop_rhs",
     "pcop_kkt_apply", "pcop_precond_apply", "pcop_solve", "pcop_unpack", "pcop_pack_cotangent",
     "pcop_data_grad", "pcop_get_params", "pcop_destroy", "pcop_status_string", "pcop_last_error",
-    "pcop_timing_enable", "pcop_timing_read",
+    "pcop_timing_enable", "pcop_timing_read", "pcop_get_kernels",
 ]
 
 
@@ -53,6 +53,7 @@ class c_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("spatial", ctypes.c_int), ("side", ctypes.c_int),
                 ("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("graph", ctypes.c_int), ("graph_chunk", ctypes.c_int), ("reorth_tol", ctypes.c_double),
+                ("time_cols", ctypes.c_int), ("dst_kernel", ctypes.c_int), ("tune", ctypes.c_int),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -92,6 +93,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "pcop_pack_cotangent": (ip, [vp, vp, vp, vp]),
         "pcop_data_grad": (ip, [vp, vp, vp, vp, vp]),
         "pcop_get_params": (ip, [vp, dp, dp, dp]),
+        "pcop_get_kernels": (ip, [vp, ctypes.POINTER(ip), ctypes.POINTER(ip), dp]),
         "pcop_destroy": (None, [vp]),
         "pcop_status_string": (ctypes.c_char_p, [ip]),
         "pcop_last_error": (ctypes.c_char_p, []),
@@ -155,6 +157,7 @@ class Solver:
                  eps: Optional[float] = None, coeff: Optional[Callable] = None, precision: str = "fp64",
                  spatial: str = "dst", side: str = "right", restart: int = 30, maxit: int = 300,
                  rtol: float = 1e-8, graph: bool = False, graph_chunk: int = 4, reorth_tol: float = 1e-8,
+                 time_cols: int = 0, dst_kernel: int = 0, tune: bool = False,
                  device: Union[str, torch.device] = "cuda", stream: Optional[torch.cuda.Stream] = None):
         import numpy as np
         self.lib = load_library()
@@ -182,6 +185,7 @@ class Solver:
         opts.precision, opts.spatial, opts.side = _PREC[precision], _SPAT[spatial], _SIDE[side]
         opts.restart, opts.maxit, opts.rtol = int(restart), int(maxit), float(rtol)
         opts.graph, opts.graph_chunk, opts.reorth_tol = int(bool(graph)), int(graph_chunk), float(reorth_tol)
+        opts.time_cols, opts.dst_kernel, opts.tune = int(time_cols), int(dst_kernel), int(bool(tune))
         self.stream = stream
         with torch.cuda.device(self.device):
             st = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -204,6 +208,11 @@ class Solver:
         _check(self.lib.pcop_get_params(ctx, ctypes.byref(tau), alpha, ctypes.byref(eps_out)))
         self.tau, self.eps, self.alpha = tau.value, eps_out.value, list(alpha)
         self.gamma = gam
+        tc, dk, tms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(self.lib.pcop_get_kernels(ctx, ctypes.byref(tc), ctypes.byref(dk), ctypes.byref(tms)))
+        # kernel choices in effect: time_cols -P two-buffer / +P in place / 0 chirp-z;
+        # dst_kernel 1 register / 2 LDS-staged / 0 multigrid
+        self.kernels = {"time_cols": tc.value, "dst_kernel": dk.value, "tuned_ms": tms.value}
 
     # ------------------------------------------------------------------
     def __del__(self):

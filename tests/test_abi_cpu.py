@@ -82,8 +82,19 @@ def test_invalid_problems_are_rejected(lib, field, value, status):
 def test_invalid_options_are_rejected(lib):
     p = _prob()
     for kw in [dict(restart=0), dict(restart=41), dict(maxit=0), dict(rtol=0.0), dict(side=7),
-               dict(precision=1, side=0), dict(graph=1, graph_chunk=0)]:
+               dict(precision=1, side=0), dict(graph=1, graph_chunk=0), dict(time_cols=2),
+               dict(time_cols=-2), dict(time_cols=32), dict(dst_kernel=3), dict(dst_kernel=-1), dict(tune=2)]:
         assert lib.pcop_validate(ctypes.byref(p), ctypes.byref(_opts(lib, **kw))) == 1, kw
+
+
+def test_kernel_choice_options_validate(lib):
+    p = _prob()
+    o = _opts(lib)
+    assert (o.time_cols, o.dst_kernel, o.tune) == (0, 0, 0)
+    for kw in [dict(time_cols=-1), dict(time_cols=4), dict(time_cols=8), dict(time_cols=16),
+               dict(time_cols=-4), dict(time_cols=-8), dict(time_cols=-16),
+               dict(dst_kernel=1), dict(dst_kernel=2), dict(tune=1)]:
+        assert lib.pcop_validate(ctypes.byref(p), ctypes.byref(_opts(lib, **kw))) == 0, kw
 
 
 def test_gamma_must_be_positive(lib):

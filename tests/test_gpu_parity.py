@@ -93,7 +93,8 @@ PRECOND_CASES = [
     (2, 3, 512, (1e-6,), None),          # n = 511 = 7 * 73: chirp-z, M = 1024
     (2, 7, 256, (1e-2,), None),          # n = 255 = 3 * 5 * 17
     (2, 7, 65, (1e-3,), None),           # n = 64 = 8 * 8
-    (2, 15, 12, (1e-3,), None),          # n = 11 (generic radix 11)
+    (2, 15, 12, (1e-3,), None),          # n = 11 (odd radix 11)
+    (2, 7, 92, (1e-4,), None),           # n = 91 = 7 * 13
 ]
 
 
@@ -117,6 +118,71 @@ def test_precond_apply_mixed(dim, nx, nt, gammas, eps):
         err = rel(w[b], P.EpsCirculantRBD(pb).apply(v[b].ravel()))
         print(f"mixed precond rel err {err:.2e}")
         assert err < 1e-5
+
+
+KERNEL_CASES = [
+    # dim, nx, nt, gammas: time lengths with every radix mix the planner makes
+    (2, 15, 16, (1e-4, 1e-8)),   # n = 15 = 3 * 5, two members
+    (2, 7, 256, (1e-2,)),        # n = 255 = 3 * 5 * 17
+    (2, 7, 65, (1e-3,)),         # n = 64 = 8 * 8
+    (2, 15, 12, (1e-3,)),        # n = 11
+    (2, 7, 9, (1.0,)),           # n = 8
+    (2, 15, 2, (1e-3,)),         # n = 1
+    (3, 7, 8, (1e-4,)),          # 3-D
+    (2, 31, 513, (1e-6,)),       # n = 512: FP64 in-place blocks of 8 at most
+    (2, 7, 15, (1e-3,)),         # n = 14 = 2 * 7
+    (2, 3, 92, (1e-5,)),         # n = 91 = 7 * 13
+]
+
+
+@pytest.mark.parametrize("dim,nx,nt,gammas", KERNEL_CASES)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_precond_kernel_choices(dim, nx, nt, gammas, precision):
+    """Every time-pass kernel choice (two LDS buffers or in place, with 4, 8
+    or 16 points per block) with both sine-transform kernels matches the oracle,
+    and the choices agree with each other to rounding.  They do the same
+    operations, but contraction into FMAs may differ between kernels; in FP32
+    that rounding (~6e-8 per operation) is amplified by up to 1/eps = 16 in the
+    last time levels by D_eps^{-1}, hence 1e-5 there."""
+    print(f"kernel choices {precision} dim={dim} nx={nx} nt={nt} B={len(gammas)}", flush=True)
+    side = "flexible" if precision == "mixed" else "right"
+    v = W.random_vector(dim, nx, nt, seed=17, batch=len(gammas))
+    wos = [P.EpsCirculantRBD(pb).apply(v[b].ravel()) for b, pb in enumerate(problems(dim, nx, nt, gammas))]
+    tol = 1e-5 if precision == "mixed" else 1e-11
+    for dk in (1, 2):
+        ref = None
+        for tc in (-1, -16, -8, -4, 4, 8, 16):
+            s = Solver(dim, nx, nt, list(gammas), precision=precision, side=side, time_cols=tc, dst_kernel=dk,
+                       device=DEV)
+            assert s.kernels["dst_kernel"] == dk
+            eff = s.kernels["time_cols"]
+            assert eff in (-16, -8, -4, 4, 8, 16)
+            if (eff < 0) == (tc < 0) and tc != -1:
+                assert abs(eff) <= abs(tc)
+            w = s.precond_apply(to_dev(v)).cpu().numpy()
+            for b in range(len(gammas)):
+                assert rel(w[b], wos[b]) < tol, (dk, tc, eff, b, rel(w[b], wos[b]))
+            if ref is None:
+                ref = w
+            else:
+                assert rel(w, ref) < (1e-5 if precision == "mixed" else 1e-14), (dk, tc, eff)
+
+
+def test_tuned_solve_matches_default():
+    """tune = 1 picks kernels by timing; the solve gives the same iterate."""
+    dim, nx, nt, gammas = 2, 31, 64, (1e-2, 1e-6)
+    fields = [W.random_fields(dim, nx, nt, seed=40 + b) for b in range(len(gammas))]
+    g, f, y0 = (to_dev(np.stack([fl[i] for fl in fields])) for i in range(3))
+    out = {}
+    for tune in (False, True):
+        s = Solver(dim, nx, nt, list(gammas), tune=tune, device=DEV)
+        print(f"tune={tune} kernels {s.kernels}", flush=True)
+        if tune:
+            assert s.kernels["tuned_ms"] > 0
+        x, infos, _ = s.solve(s.rhs(g, f, y0))
+        out[tune] = (x.cpu().numpy(), [i.iters for i in infos])
+    assert out[True][1] == out[False][1]
+    assert rel(out[True][0], out[False][0]) < 1e-12
 
 
 MG_CASES = [
