@@ -56,6 +56,7 @@ struct PrecondTables {
   const double* alpha;   // [B]
   const int* active;     // [B] or null
   int nact;              // members with active != 0 (for byte accounting)
+  int ncu;               // compute units of the device (persistent grids)
   int dst_variant;       // 0: register sine-transform kernels, 1: LDS-staged kernels
   int time_cols;         // time-kernel request, as pcop_options::time_cols
   const KTimer* timer;   // or null

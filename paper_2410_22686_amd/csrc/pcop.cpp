@@ -763,6 +763,15 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   tb.bhat32 = c->at<float>(L.bhat32);
   tb.time_cols = opts->time_cols;
   tb.dst_variant = (opts->dst_kernel == 2) ? 1 : 0;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) {
+      delete c;
+      return fail(PCOP_ERR_DEVICE, "cannot query the number of compute units");
+    }
+    tb.ncu = ncu;
+  }
   tb.mg_levels = L.mg_levels;
   for (int l = 0; l < L.mg_levels; ++l) {
     MgLevel& lv = tb.mg[l];
