@@ -1,5 +1,7 @@
 // Step 2 of the preconditioner for a = 1: shifted spatial solves by sine
 // transforms, one launch per axis over every frequency slice of every member.
+#include <algorithm>
+
 #include "common.hpp"
 #include "fft_lds.hpp"
 #include "launch.hpp"
@@ -187,10 +189,57 @@ struct RegStages {
   }
 };
 
-template <class T, int L, int ROWS_, int DIVIDE_>
+// shift division of step 2 for one line held in registers:
+// v <- c v / (sigma_q + tau mu), mu = mu1[line axes] + mu1[element]
+template <class T, int L, int TL>
+__device__ __forceinline__ void divide_line(cx<T> (&v)[8], int t, const Geo& g, const DivideParams& dp,
+                                            long long plane, int line, bool valid) {
+  constexpr int N = L / 2 - 1;
+  const int b = (int)(plane / (2 * g.K));
+  const int q = (int)(plane - (long long)b * 2 * g.K);
+  const int k = q >> 1;
+  const double sre = dp.lam[2 * k] + dp.alpha[b];
+  const double sim = (q & 1) ? -dp.lam[2 * k + 1] : dp.lam[2 * k + 1];
+  double mul = dp.mu1[line % g.nx];
+  if (g.dim == 3) mul += dp.mu1[(line / g.nx) % g.nx];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int pos = t + TL * s;
+    if (pos >= 1 && pos <= N && valid) {
+      const double dre = sre + g.tau * (mul + dp.mu1[pos - 1]);
+      const double den = dre * dre + sim * sim;
+      v[s] = v[s] * cx<T>{(T)(dp.cnorm * dre / den), (T)(-dp.cnorm * sim / den)};
+    }
+  }
+}
+
+// odd extension of the values at positions 1..N, the mirrored half through LDS
+template <class T, int L, int TL>
+__device__ __forceinline__ void odd_extend(cx<T> (&v)[8], int t, cx<T>* lbuf) {
+  constexpr int N = L / 2 - 1;
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int pos = t + TL * s;
+    if (pos >= 1 && pos <= N) lbuf[pidx(pos)] = v[s];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int pos = t + TL * s;
+    if (pos >= N + 2) {
+      const cx<T> z = lbuf[pidx(L - pos)];
+      v[s] = cx<T>{-z.x, -z.y};
+    } else if (pos == 0 || pos == N + 1) {
+      v[s] = cx<T>{0, 0};
+    }
+  }
+}
+
+// contiguous lines (x1): each line's values go straight between HBM and registers
+template <class T, int L, int DIVIDE_>
 __global__ void __launch_bounds__(256) dst_reg_kernel(Geo g, cx<T>* __restrict__ data, LineGeom lg,
                                                       const cx<T>* __restrict__ twL, DivideParams dp) {
-  constexpr bool ROWS = ROWS_ != 0;
   constexpr bool DIVIDE = DIVIDE_ != 0;
   constexpr int N = L / 2 - 1;
   constexpr int TL = L / 8;
@@ -210,24 +259,9 @@ __global__ void __launch_bounds__(256) dst_reg_kernel(Geo g, cx<T>* __restrict__
   const int line = l0 + lid;
   const bool valid = line < lg.lines;
   cx<T>* lbuf = buf + lid * LD;
-  // column passes stage the [N][LPB] tile through LDS with coalesced loads
-  if (!ROWS) {
-    for (int idx = threadIdx.x; idx < N * LPB; idx += 256) {
-      const int e = idx / LPB;
-      const int l = idx - e * LPB;
-      cx<T> val{0, 0};
-      if (l0 + l < lg.lines)
-        val = data[pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride];
-      buf[l * LD + pidx(e)] = val;
-    }
-    __syncthreads();
-  }
   auto zval = [&](int e) -> cx<T> {
-    if (ROWS) {
-      if (!valid) return cx<T>{0, 0};
-      return data[pbase + (long long)line * lg.line_stride + (long long)e * lg.elem_stride];
-    }
-    return lbuf[pidx(e)];
+    if (!valid) return cx<T>{0, 0};
+    return data[pbase + (long long)line * lg.line_stride + (long long)e * lg.elem_stride];
   };
   cx<T> v[8];
 #pragma unroll
@@ -244,50 +278,94 @@ __global__ void __launch_bounds__(256) dst_reg_kernel(Geo g, cx<T>* __restrict__
   }
   RegStages<T, L, TL, -1, 1>::run(v, t, lbuf, twL);
   if (DIVIDE) {
-    const int b = (int)(plane / (2 * g.K));
-    const int q = (int)(plane - (long long)b * 2 * g.K);
-    const int k = q >> 1;
-    const double sre = dp.lam[2 * k] + dp.alpha[b];
-    const double sim = (q & 1) ? -dp.lam[2 * k + 1] : dp.lam[2 * k + 1];
-    double mul = dp.mu1[line % g.nx];
-    if (g.dim == 3) mul += dp.mu1[(line / g.nx) % g.nx];
+    divide_line<T, L, TL>(v, t, g, dp, plane, line, valid);
+    odd_extend<T, L, TL>(v, t, lbuf);
+    RegStages<T, L, TL, -1, 1>::run(v, t, lbuf, twL);
+  }
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int pos = t + TL * s;
-      if (pos >= 1 && pos <= N && valid) {
-        const double dre = sre + g.tau * (mul + dp.mu1[pos - 1]);
-        const double den = dre * dre + sim * sim;
-        v[s] = v[s] * cx<T>{(T)(dp.cnorm * dre / den), (T)(-dp.cnorm * sim / den)};
+  for (int s = 0; s < 8; ++s) {
+    const int pos = t + TL * s;
+    if (pos >= 1 && pos <= N && valid)
+      data[pbase + (long long)line * lg.line_stride + (long long)(pos - 1) * lg.elem_stride] = v[s];
+  }
+}
+
+// Strided lines (x2, x3; consecutive lines adjacent in memory): a tile of
+// LPB lines x N elements is staged through LDS with coalesced accesses.
+// Persistent blocks walk tiles blk, blk + grid, ... and fetch the next tile
+// into registers while the current one is transformed.
+template <class T, int L, int DIVIDE_>
+__global__ void __launch_bounds__(256) dst_col_kernel(Geo g, cx<T>* __restrict__ data, LineGeom lg,
+                                                      const cx<T>* __restrict__ twL, DivideParams dp) {
+  constexpr bool DIVIDE = DIVIDE_ != 0;
+  constexpr int N = L / 2 - 1;
+  constexpr int TL = L / 8;
+  constexpr int LPB = 256 / TL;
+  constexpr int LD = L + L / 8 + 1;
+  constexpr int QS = (N * LPB + 255) / 256;  // tile elements per thread
+  __shared__ cx<T> buf[LPB * LD];
+  const long long tiles = (lg.lines + LPB - 1) / LPB;
+  const long long total = tiles * lg.nplanes;
+  const int lid = threadIdx.x / TL;
+  const int t = threadIdx.x - lid * TL;
+  cx<T>* lbuf = buf + lid * LD;
+  auto next = [&](long long blk) {
+    if (DIVIDE && dp.active)
+      while (blk < total && !dp.active[(int)((blk / tiles) / (2 * g.K))]) blk += gridDim.x;
+    return blk;
+  };
+  cx<T> pre[QS];
+  auto fetch = [&](long long blk) {
+    const long long plane = blk / tiles;
+    const int l0 = (int)(blk - plane * tiles) * LPB;
+    const long long pbase = plane * lg.plane_stride;
+#pragma unroll
+    for (int q = 0; q < QS; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      const int e = idx / LPB, l = idx - (idx / LPB) * LPB;
+      const bool ok = idx < N * LPB && l0 + l < lg.lines;
+      pre[q] = ok ? data[pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride]
+                  : cx<T>{0, 0};
+    }
+  };
+  long long blk = next(xcd_remap(blockIdx.x, gridDim.x));
+  if (blk < total) fetch(blk);
+  while (blk < total) {
+    const long long plane = blk / tiles;
+    const int l0 = (int)(blk - plane * tiles) * LPB;
+    const long long pbase = plane * lg.plane_stride;
+    const int line = l0 + lid;
+    const bool valid = line < lg.lines;
+#pragma unroll
+    for (int q = 0; q < QS; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      if (idx < N * LPB) {
+        const int e = idx / LPB, l = idx - (idx / LPB) * LPB;
+        buf[l * LD + pidx(e)] = pre[q];
       }
     }
-    // odd extension of the divided values: the mirrored half comes from LDS
     __syncthreads();
+    const long long nxt = next(blk + gridDim.x);
+    if (nxt < total) fetch(nxt);
+    cx<T> v[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       const int pos = t + TL * s;
-      if (pos >= 1 && pos <= N) lbuf[pidx(pos)] = v[s];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int pos = t + TL * s;
-      if (pos >= N + 2) {
-        const cx<T> z = lbuf[pidx(L - pos)];
+      if (pos >= 1 && pos <= N) {
+        v[s] = lbuf[pidx(pos - 1)];
+      } else if (pos >= N + 2) {
+        const cx<T> z = lbuf[pidx(L - 1 - pos)];
         v[s] = cx<T>{-z.x, -z.y};
-      } else if (pos == 0 || pos == N + 1) {
+      } else {
         v[s] = cx<T>{0, 0};
       }
     }
     RegStages<T, L, TL, -1, 1>::run(v, t, lbuf, twL);
-  }
-  if (ROWS) {
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int pos = t + TL * s;
-      if (pos >= 1 && pos <= N && valid)
-        data[pbase + (long long)line * lg.line_stride + (long long)(pos - 1) * lg.elem_stride] = v[s];
+    if (DIVIDE) {
+      divide_line<T, L, TL>(v, t, g, dp, plane, line, valid);
+      odd_extend<T, L, TL>(v, t, lbuf);
+      RegStages<T, L, TL, -1, 1>::run(v, t, lbuf, twL);
     }
-  } else {
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
@@ -295,12 +373,15 @@ __global__ void __launch_bounds__(256) dst_reg_kernel(Geo g, cx<T>* __restrict__
       if (pos >= 1 && pos <= N) lbuf[pidx(pos - 1)] = v[s];
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < N * LPB; idx += 256) {
-      const int e = idx / LPB;
-      const int l = idx - e * LPB;
-      if (l0 + l < lg.lines)
+#pragma unroll
+    for (int q = 0; q < QS; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      const int e = idx / LPB, l = idx - (idx / LPB) * LPB;
+      if (idx < N * LPB && l0 + l < lg.lines)
         data[pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride] = buf[l * LD + pidx(e)];
     }
+    __syncthreads();
+    blk = nxt;
   }
 }
 
@@ -313,7 +394,7 @@ constexpr int dst_lines_per_block() {
 
 template <class T, int L>
 static void dst_pass_L(const Geo& g, cx<T>* data, const LineGeom& lg, bool rows, bool divide,
-                       const cx<T>* twL, const DivideParams& dp, int variant, hipStream_t st) {
+                       const cx<T>* twL, const DivideParams& dp, int variant, int ncu, hipStream_t st) {
   if (variant == 1) {
     // all stages staged through LDS ([LINES][L+1] tiles)
     constexpr int LINES = dst_lines_per_block<T, L>();
@@ -329,31 +410,36 @@ static void dst_pass_L(const Geo& g, cx<T>* data, const LineGeom& lg, bool rows,
     }
     return;
   }
-  // register variant: L/8 threads per line
+  // register variants: L/8 threads per line
   constexpr int LPB = 256 / (L / 8);
   const long long tiles = (lg.lines + LPB - 1) / LPB;
-  dim3 grid((unsigned)(tiles * lg.nplanes));
   if (rows) {
-    if (divide) dst_reg_kernel<T, L, 1, 1><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
-    else dst_reg_kernel<T, L, 1, 0><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
+    dim3 grid((unsigned)(tiles * lg.nplanes));
+    if (divide) dst_reg_kernel<T, L, 1><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
+    else dst_reg_kernel<T, L, 0><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
   } else {
-    if (divide) dst_reg_kernel<T, L, 0, 1><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
-    else dst_reg_kernel<T, L, 0, 0><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
+    // persistent grid: as many blocks as stay resident on every CU
+    static const int res1 = resident_blocks(dst_col_kernel<T, L, 1>, 256, 0);
+    static const int res0 = resident_blocks(dst_col_kernel<T, L, 0>, 256, 0);
+    const long long want = (long long)(divide ? res1 : res0) * std::max(1, ncu);
+    dim3 grid((unsigned)std::min(tiles * lg.nplanes, want));
+    if (divide) dst_col_kernel<T, L, 1><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
+    else dst_col_kernel<T, L, 0><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
   }
 }
 
 template <class T>
 static bool dst_pass(const Geo& g, cx<T>* data, const LineGeom& lg, bool rows, bool divide,
-                     const cx<T>* twL, const DivideParams& dp, int variant, hipStream_t st) {
+                     const cx<T>* twL, const DivideParams& dp, int variant, int ncu, hipStream_t st) {
   switch (2 * (g.nx + 1)) {
-    case 8: dst_pass_L<T, 8>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
-    case 16: dst_pass_L<T, 16>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
-    case 32: dst_pass_L<T, 32>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
-    case 64: dst_pass_L<T, 64>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
-    case 128: dst_pass_L<T, 128>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
-    case 256: dst_pass_L<T, 256>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
-    case 512: dst_pass_L<T, 512>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
-    case 1024: dst_pass_L<T, 1024>(g, data, lg, rows, divide, twL, dp, variant, st); return true;
+    case 8: dst_pass_L<T, 8>(g, data, lg, rows, divide, twL, dp, variant, ncu, st); return true;
+    case 16: dst_pass_L<T, 16>(g, data, lg, rows, divide, twL, dp, variant, ncu, st); return true;
+    case 32: dst_pass_L<T, 32>(g, data, lg, rows, divide, twL, dp, variant, ncu, st); return true;
+    case 64: dst_pass_L<T, 64>(g, data, lg, rows, divide, twL, dp, variant, ncu, st); return true;
+    case 128: dst_pass_L<T, 128>(g, data, lg, rows, divide, twL, dp, variant, ncu, st); return true;
+    case 256: dst_pass_L<T, 256>(g, data, lg, rows, divide, twL, dp, variant, ncu, st); return true;
+    case 512: dst_pass_L<T, 512>(g, data, lg, rows, divide, twL, dp, variant, ncu, st); return true;
+    case 1024: dst_pass_L<T, 1024>(g, data, lg, rows, divide, twL, dp, variant, ncu, st); return true;
     default: return false;
   }
 }
@@ -382,7 +468,7 @@ static bool dst_solve(const Geo& g, cx<T>* spec, const PrecondTables& tb, hipStr
   auto run = [&](const LineGeom& lg, bool r, bool dv, int fam) {
     if (!ok) return;
     tbeg(tb.timer, fam, pass_bytes);
-    ok = dst_pass<T>(g, spec, lg, r, dv, twL, dp, tb.dst_variant, st);
+    ok = dst_pass<T>(g, spec, lg, r, dv, twL, dp, tb.dst_variant, tb.ncu, st);
     tend(tb.timer);
   };
   run(rows, true, false, KF_DST_ROWS);

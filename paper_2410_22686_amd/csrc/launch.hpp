@@ -8,6 +8,18 @@
 
 namespace pcop {
 
+// blocks of `kernel` that stay resident on one CU (at least 1): the size of
+// a persistent grid is this times the number of CUs
+template <class K>
+inline int resident_blocks(K kernel, int threads, size_t dyn_lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, dyn_lds) != hipSuccess || nb < 1) {
+    (void)hipGetLastError();
+    nb = 1;
+  }
+  return nb;
+}
+
 // Optional per-kernel timing: when set, launch wrappers bracket every kernel
 // with begin/end (HIP events on the launch stream) and report the kernel
 // family and its algorithmic HBM bytes.

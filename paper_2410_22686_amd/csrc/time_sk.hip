@@ -174,15 +174,17 @@ void launch_time_sk(bool fwd, int P, const Geo& g, const double* v, cx<T>* spec,
   const size_t lds = (size_t)2 * g.n * P * sizeof(cx<T>);
   TileWalk tw{(g.m + P - 1) / P, 0, tb.active};
   tw.ntiles = tw.tpm * g.B;
-  // enough blocks to fill every CU to its LDS limit, at most 4 per CU
-  const int per_cu = std::max(1, std::min(4, (int)(163840 / lds)));
-  const int grid = std::min(tw.ntiles, per_cu * std::max(1, tb.ncu));
-#define PCOP_TIME_SK(PP)                                                                                    \
-  if (fwd)                                                                                                  \
-    time_fwd_sk<T, PP, sk_q_fwd<T>()><<<grid, 256, lds, st>>>(g, v, spec, tb.dpow, twn, tb.plan, vscale,    \
-                                                                vs_stride, tw);                              \
-  else                                                                                                      \
-    time_inv_sk<T, PP, sk_q_inv<T>()><<<grid, 256, lds, st>>>(g, spec, w, tb.dpow, twn, tb.plan, accum, tw);
+  // persistent grid: as many blocks as stay resident on every CU
+#define PCOP_TIME_SK(PP)                                                                                      \
+  if (fwd) {                                                                                                  \
+    auto kern = time_fwd_sk<T, PP, sk_q_fwd<T>()>;                                                            \
+    const int grid = std::min(tw.ntiles, resident_blocks(kern, 256, lds) * std::max(1, tb.ncu));              \
+    kern<<<grid, 256, lds, st>>>(g, v, spec, tb.dpow, twn, tb.plan, vscale, vs_stride, tw);                    \
+  } else {                                                                                                    \
+    auto kern = time_inv_sk<T, PP, sk_q_inv<T>()>;                                                            \
+    const int grid = std::min(tw.ntiles, resident_blocks(kern, 256, lds) * std::max(1, tb.ncu));              \
+    kern<<<grid, 256, lds, st>>>(g, spec, w, tb.dpow, twn, tb.plan, accum, tw);                               \
+  }
   if (P == 16) {
     PCOP_TIME_SK(16)
   } else if (P == 8) {
