@@ -86,6 +86,8 @@ def parse():
                     help="time-pass kernels: 0 automatic, -P two LDS buffers, +P in place (P points per block)")
     ap.add_argument("--dst-kernel", type=int, default=0, choices=[0, 1, 2],
                     help="sine-transform kernels: 0 automatic, 1 register-resident, 2 LDS-staged")
+    ap.add_argument("--precond", choices=["eps", "ideal"], default="eps",
+                    help="eps: the epsilon-circulant preconditioner; ideal: P of eq. matrix_P (sequential in time)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain device copy of 1 GiB (reference for HBM byte counters)")
     return ap.parse_args()
@@ -226,7 +228,7 @@ def main():
     s = Solver(cfg.dim, cfg.nx, cfg.nt, list(cfg.gammas), T=cfg.T, eps=cfg.eps,
                coeff=None if cfg.coeff == "one" else W.coeff_function(cfg.coeff),
                restart=30, maxit=300, rtol=1e-8, device=dev, stream=stream, tune=bool(args.tune),
-               time_cols=args.time_cols, dst_kernel=args.dst_kernel, **opts)
+               time_cols=args.time_cols, dst_kernel=args.dst_kernel, precond=args.precond, **opts)
     print(f"# bench: kernels {s.kernels}", file=sys.stderr, flush=True)
     tg = torch.tensor(g, device=dev)
     tf = torch.tensor(f, device=dev)
@@ -300,7 +302,7 @@ def main():
         "config": {"workload": cfg.name, "dim": cfg.dim, "nx": cfg.nx, "nt": cfg.nt, "T": cfg.T,
                    "gammas": list(cfg.gammas), "eps": "sqrt(tau)" if cfg.eps is None else cfg.eps,
                    "precision": opts["precision"], "spatial": opts["spatial"], "krylov": f"{opts['side']} GMRES(30)",
-                   "graph": opts["graph"],
+                   "graph": opts["graph"], "preconditioner": args.precond,
                    "rtol": 1e-8, "batch": len(members), "global_batch": len(members)},
         "iters": iters, "relres_true": [i.relres_true for i in infos], "converged": ok,
         "kernel_table_source": "eager solve after the timed region" if opts["graph"] else "timed region",

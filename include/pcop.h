@@ -57,6 +57,7 @@ enum { PCOP_FP64 = 0, PCOP_MIXED = 1 };          /* precision of P_eps^{-1} */
 enum { PCOP_DST = 0, PCOP_MG = 1 };              /* spatial solver of Step 2 */
 enum { PCOP_RIGHT = 0, PCOP_LEFT = 1, PCOP_FLEXIBLE = 2 };  /* GMRES variant */
 enum { PCOP_COEFF_ONE = 0, PCOP_COEFF_HALFGRID = 1 };        /* a(x) */
+enum { PCOP_PRECOND_EPS = 0, PCOP_PRECOND_IDEAL = 1 };      /* preconditioner */
 
 /* Problem statement (Section 1; Section 3 for the discretisation).
  *   dim      2 or 3.
@@ -121,6 +122,12 @@ typedef struct {
  *              choice is cached per device and shape for the process.
  *              0: built-in choices.  All choices give the same iterates up
  *              to rounding.
+ *   precond    PCOP_PRECOND_EPS: the epsilon-circulant RBD preconditioner
+ *              P_eps (Section 2.1; all time levels at once);
+ *              PCOP_PRECOND_IDEAL: the ideal RBD preconditioner P of
+ *              eq. matrix_P, applied by sequential substitution in time
+ *              (n dependent spatial solves with (1 + alpha) I + tau K; the
+ *              comparison method of Tables 4 and 8).  time_cols is ignored.
  *   stream     hipStream_t on which all work is enqueued. */
 typedef struct {
   int precision;
@@ -135,6 +142,7 @@ typedef struct {
   int time_cols;
   int dst_kernel;
   int tune;
+  int precond;
   void* stream;
 } pcop_options;
 
@@ -208,7 +216,8 @@ pcop_status pcop_data_grad(pcop_ctx ctx, const double* lam, double* dg, double* 
 pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* eps);
 
 /* Kernel choices in effect (after tuning): time_cols -P (two LDS buffers,
- * P points per block), +P (in place) or 0 (chirp-z); dst_kernel 1
+ * P points per block), +P (in place) or 0 (chirp-z, or no time transform
+ * with PCOP_PRECOND_IDEAL); dst_kernel 1
  * (register-resident), 2 (LDS-staged) or 0 (multigrid).  tuned_ms: the
  * fastest preconditioner apply measured by the tuner, 0 when no tuning ran.
  * Any output may be NULL. */

@@ -123,13 +123,30 @@ class IdealRBD:
     bidiagonal systems are solved by sequential substitution in time
     (T + alpha I forward from level 1, T^T + alpha I backward from level n),
     each step a solve with T_0 = (1 + alpha) I + tau K (Section 2, the
-    block lower-triangular Toeplitz structure of (T + alpha I)^{-1})."""
+    block lower-triangular Toeplitz structure of (T + alpha I)^{-1}).
 
-    def __init__(self, pb: Problem):
+    ``spatial="lu"`` solves with T_0 exactly (sparse LU); ``spatial="mg"``
+    takes one V-cycle of :mod:`oracle.multigrid` with the real shift
+    1 + alpha instead, as for the non-diagonalisable K of Example 2
+    (Section 3)."""
+
+    def __init__(self, pb: Problem, spatial: str = "lu", coeff=None):
         self.pb = pb
         m = pb.m
-        T0 = (1.0 + pb.alpha) * sp.identity(m, format="csc") + pb.tau * pb.K.tocsc()
-        self.lu = spla.splu(T0.tocsc())
+        self.spatial = spatial
+        if spatial == "lu":
+            T0 = (1.0 + pb.alpha) * sp.identity(m, format="csc") + pb.tau * pb.K.tocsc()
+            self.lu = spla.splu(T0.tocsc())
+        elif spatial == "mg":
+            from .multigrid import ShiftedVCycle
+            self.mg = ShiftedVCycle(pb.dim, pb.nx, pb.tau, coeff)
+        else:
+            raise ValueError(spatial)
+
+    def _solve(self, r: np.ndarray) -> np.ndarray:
+        if self.spatial == "lu":
+            return self.lu.solve(r)
+        return self.mg.apply(r, complex(1.0 + self.pb.alpha, 0.0)).real
 
     def apply(self, v: np.ndarray) -> np.ndarray:
         pb = self.pb
@@ -139,10 +156,10 @@ class IdealRBD:
         z2 = np.zeros((n, m))
         for j in range(n):                       # (T + alpha I) z2 = v2
             r = v[1, j] + (z2[j - 1] if j > 0 else 0.0)
-            z2[j] = self.lu.solve(r)
+            z2[j] = self._solve(r)
         for j in range(n - 1, -1, -1):           # (T^T + alpha I) z1 = v1
             r = v[0, j] + (z1[j + 1] if j < n - 1 else 0.0)
-            z1[j] = self.lu.solve(r)
+            z1[j] = self._solve(r)
         return np.concatenate([(z1 - z2).ravel(), (z1 + z2).ravel()])
 
 

@@ -34,6 +34,7 @@ struct DivideParams {
   const double* alpha;   // [B]
   const int* active;     // [B] or null
   double cnorm;
+  int spm;               // slices per member: plane p belongs to member p / spm, slice p mod spm
 };
 
 template <class T, int L, int LINES, int NT, bool ROWS, bool DIVIDE>
@@ -48,7 +49,7 @@ __global__ void __launch_bounds__(NT) dst_lines_kernel(Geo g, cx<T>* __restrict_
   const int l0 = (int)(blk - plane * tiles) * LINES;
   const long long pbase = plane * lg.plane_stride;
   if (DIVIDE && dp.active) {
-    if (!dp.active[(int)(plane / (2 * g.K))]) return;
+    if (!dp.active[(int)(plane / dp.spm)]) return;
   }
   for (int t = threadIdx.x; t < LINES * N; t += NT) {
     int l, e;
@@ -75,8 +76,8 @@ __global__ void __launch_bounds__(NT) dst_lines_kernel(Geo g, cx<T>* __restrict_
     // the last-axis pass has one plane per slice q of member b; the shift
     // sigma_q = lambda_k + alpha_b (q even) or conj(lambda_k) + alpha_b (q odd)
     // is uniform over the block
-    const int b = (int)(plane / (2 * g.K));
-    const int q = (int)(plane - (long long)b * 2 * g.K);
+    const int b = (int)(plane / dp.spm);
+    const int q = (int)(plane - (long long)b * dp.spm);
     const int k = q >> 1;
     const double sre = dp.lam[2 * k] + dp.alpha[b];
     const double sim = (q & 1) ? -dp.lam[2 * k + 1] : dp.lam[2 * k + 1];
@@ -195,8 +196,8 @@ template <class T, int L, int TL>
 __device__ __forceinline__ void divide_line(cx<T> (&v)[8], int t, const Geo& g, const DivideParams& dp,
                                             long long plane, int line, bool valid) {
   constexpr int N = L / 2 - 1;
-  const int b = (int)(plane / (2 * g.K));
-  const int q = (int)(plane - (long long)b * 2 * g.K);
+  const int b = (int)(plane / dp.spm);
+  const int q = (int)(plane - (long long)b * dp.spm);
   const int k = q >> 1;
   const double sre = dp.lam[2 * k] + dp.alpha[b];
   const double sim = (q & 1) ? -dp.lam[2 * k + 1] : dp.lam[2 * k + 1];
@@ -252,7 +253,7 @@ __global__ void __launch_bounds__(256) dst_reg_kernel(Geo g, cx<T>* __restrict__
   const int l0 = (int)(blk - plane * tiles) * LPB;
   const long long pbase = plane * lg.plane_stride;
   if (DIVIDE && dp.active) {
-    if (!dp.active[(int)(plane / (2 * g.K))]) return;
+    if (!dp.active[(int)(plane / dp.spm)]) return;
   }
   const int lid = threadIdx.x / TL;
   const int t = threadIdx.x - lid * TL;
@@ -311,7 +312,7 @@ __global__ void __launch_bounds__(256) dst_col_kernel(Geo g, cx<T>* __restrict__
   cx<T>* lbuf = buf + lid * LD;
   auto next = [&](long long blk) {
     if (DIVIDE && dp.active)
-      while (blk < total && !dp.active[(int)((blk / tiles) / (2 * g.K))]) blk += gridDim.x;
+      while (blk < total && !dp.active[(int)((blk / tiles) / dp.spm)]) blk += gridDim.x;
     return blk;
   };
   cx<T> pre[QS];
@@ -445,12 +446,15 @@ static bool dst_pass(const Geo& g, cx<T>* data, const LineGeom& lg, bool rows, b
 }
 
 // Step 2 with sine transforms: axes 1..d-1 forward, last axis forward +
-// divide + inverse, axes d-1..1 inverse (the transforms commute).
+// divide + inverse, axes d-1..1 inverse (the transforms commute).  spm
+// slices per member; slice q of member b is divided by
+// lam_{q/2} + alpha_b (q even) or its conjugate (q odd).
 template <class T>
-static bool dst_solve(const Geo& g, cx<T>* spec, const PrecondTables& tb, hipStream_t st) {
+static bool dst_solve(const Geo& g, cx<T>* spec, const PrecondTables& tb, int spm, const double* lam,
+                      hipStream_t st) {
   const int nx = g.nx;
-  const long long slices = (long long)g.B * 2 * g.K;
-  DivideParams dp{tb.mu1, tb.lam, tb.alpha, tb.active, 0.0};
+  const long long slices = (long long)g.B * spm;
+  DivideParams dp{tb.mu1, lam, tb.alpha, tb.active, 0.0, spm};
   dp.cnorm = (g.dim == 2) ? 1.0 / (4.0 * (nx + 1.0) * (nx + 1.0))
                           : -1.0 / (8.0 * (nx + 1.0) * (nx + 1.0) * (nx + 1.0));
   const cx<T>* twL = reinterpret_cast<const cx<T>*>(sizeof(T) == 8 ? (const void*)tb.twL64 : (const void*)tb.twL32);
@@ -462,8 +466,8 @@ static bool dst_solve(const Geo& g, cx<T>* spec, const PrecondTables& tb, hipStr
   const int lines_last = (g.dim == 3) ? nx * nx : nx;
   const int stride_last = (g.dim == 3) ? nx * nx : nx;
   LineGeom last{slices, (long long)g.m, lines_last, 1, stride_last};
-  // every pass reads and writes the spectrum of the counted members once
-  const double pass_bytes = 2.0 * sizeof(cx<T>) * 2.0 * g.K * (double)g.m * tb.nact;
+  // every pass reads and writes the slices of the counted members once
+  const double pass_bytes = 2.0 * sizeof(cx<T>) * spm * (double)g.m * tb.nact;
   bool ok = true;
   auto run = [&](const LineGeom& lg, bool r, bool dv, int fam) {
     if (!ok) return;
@@ -479,10 +483,10 @@ static bool dst_solve(const Geo& g, cx<T>* spec, const PrecondTables& tb, hipStr
   return ok;
 }
 
-
-bool launch_dst_solve(const Geo& g, void* spec, bool fp32, const PrecondTables& tb, hipStream_t st) {
-  if (fp32) return dst_solve<float>(g, reinterpret_cast<cx<float>*>(spec), tb, st);
-  return dst_solve<double>(g, reinterpret_cast<cx<double>*>(spec), tb, st);
+bool launch_dst_solve(const Geo& g, void* spec, bool fp32, const PrecondTables& tb, int spm, const double* lam,
+                      hipStream_t st) {
+  if (fp32) return dst_solve<float>(g, reinterpret_cast<cx<float>*>(spec), tb, spm, lam, st);
+  return dst_solve<double>(g, reinterpret_cast<cx<double>*>(spec), tb, spm, lam, st);
 }
 
 }  // namespace pcop

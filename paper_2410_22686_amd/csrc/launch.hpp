@@ -25,7 +25,7 @@ inline int resident_blocks(K kernel, int threads, size_t dyn_lds) {
 // family and its algorithmic HBM bytes.
 enum KFamily {
   KF_KKT = 0, KF_TIME_FWD, KF_DST_ROWS, KF_DST_AX2, KF_DST_LAST, KF_TIME_INV, KF_MG_SMOOTH,
-  KF_MG_RESTRICT, KF_MG_PROLONG, KF_MDOT, KF_UPDATE, KF_COMBINE, KF_SMALL, KF_COUNT
+  KF_MG_RESTRICT, KF_MG_PROLONG, KF_MDOT, KF_UPDATE, KF_COMBINE, KF_SMALL, KF_IDEAL_STEP, KF_COUNT
 };
 struct KTimer {
   void (*begin)(void* self, int family, double bytes);
@@ -98,8 +98,18 @@ FftPlan make_time_plan(int n);
 bool launch_precond(const Geo& g, const double* v, double* w, void* spec, bool fp32, int spatial,
                     const PrecondTables& tb, const double* vscale, int vs_stride, int accum,
                     hipStream_t st);
-bool launch_mg_solve(const Geo& g, void* spec, bool fp32, const PrecondTables& tb, hipStream_t st);
-bool launch_dst_solve(const Geo& g, void* spec, bool fp32, const PrecondTables& tb, hipStream_t st);
+// shifted spatial solves on spm complex slices per member, slice q of member
+// b shifted by lam_{q/2} + alpha_b (q even) or its conjugate (q odd)
+bool launch_mg_solve(const Geo& g, void* spec, bool fp32, const PrecondTables& tb, int spm, const double* lam,
+                     hipStream_t st);
+bool launch_dst_solve(const Geo& g, void* spec, bool fp32, const PrecondTables& tb, int spm, const double* lam,
+                      hipStream_t st);
+// ideal RBD preconditioner (sequential in time); unit = device (1.0, 0.0);
+// uses ideal_spec_bytes(g, fp32) bytes of spec
+bool launch_ideal_precond(const Geo& g, const double* v, double* w, void* spec, bool fp32, int spatial,
+                          const PrecondTables& tb, const double* unit, const double* vscale, int vs_stride,
+                          int accum, hipStream_t st);
+size_t ideal_spec_bytes(const Geo& g, bool fp32);
 
 // Krylov kernels (krylov.hip).  Basis slot i of member b starts at
 // basis + i * slot_stride + b * vl.

@@ -27,7 +27,7 @@ struct MgShift {
   const double* lam;    // [K] (re, im)
   const double* alpha;  // [B]
   const int* active;    // [B] or null
-  int twoK;
+  int twoK;             // slices per member
 };
 
 template <class T>
@@ -175,10 +175,11 @@ __global__ void __launch_bounds__(256) mg_prolong_kernel(int nxf, int mf, int nx
 }
 
 template <class T, int DIM>
-static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, hipStream_t st) {
+static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, int spm, const double* lam,
+                     hipStream_t st) {
   const int NL = tb.mg_levels;
-  const int slices = g.B * 2 * g.K;
-  MgShift sh{tb.lam, tb.alpha, tb.active, 2 * g.K};
+  const int slices = g.B * spm;
+  MgShift sh{lam, tb.alpha, tb.active, spm};
   auto coefp = [&](int l) -> const T* {
     return reinterpret_cast<const T*>(sizeof(T) == 4 ? (const void*)tb.mg[l].coef : (const void*)tb.mg[l].coef64);
   };
@@ -223,14 +224,15 @@ static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, hipStre
   }
 }
 
-bool launch_mg_solve(const Geo& g, void* spec, bool fp32, const PrecondTables& tb, hipStream_t st) {
+bool launch_mg_solve(const Geo& g, void* spec, bool fp32, const PrecondTables& tb, int spm, const double* lam,
+                     hipStream_t st) {
   if (tb.mg_levels < 1) return false;
   if (fp32) {
-    if (g.dim == 2) mg_cycle<float, 2>(g, reinterpret_cast<cx<float>*>(spec), tb, st);
-    else mg_cycle<float, 3>(g, reinterpret_cast<cx<float>*>(spec), tb, st);
+    if (g.dim == 2) mg_cycle<float, 2>(g, reinterpret_cast<cx<float>*>(spec), tb, spm, lam, st);
+    else mg_cycle<float, 3>(g, reinterpret_cast<cx<float>*>(spec), tb, spm, lam, st);
   } else {
-    if (g.dim == 2) mg_cycle<double, 2>(g, reinterpret_cast<cx<double>*>(spec), tb, st);
-    else mg_cycle<double, 3>(g, reinterpret_cast<cx<double>*>(spec), tb, st);
+    if (g.dim == 2) mg_cycle<double, 2>(g, reinterpret_cast<cx<double>*>(spec), tb, spm, lam, st);
+    else mg_cycle<double, 3>(g, reinterpret_cast<cx<double>*>(spec), tb, spm, lam, st);
   }
   return true;
 }

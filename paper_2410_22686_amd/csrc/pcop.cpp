@@ -83,6 +83,8 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
   }
   if (o->dst_kernel < 0 || o->dst_kernel > 2) return fail(PCOP_ERR_INVALID_ARG, "dst_kernel must be 0, 1 or 2");
   if (o->tune != 0 && o->tune != 1) return fail(PCOP_ERR_INVALID_ARG, "tune must be 0 or 1");
+  if (o->precond != PCOP_PRECOND_EPS && o->precond != PCOP_PRECOND_IDEAL)
+    return fail(PCOP_ERR_INVALID_ARG, "unknown precond");
   if (o->precision == PCOP_MIXED && o->side != PCOP_FLEXIBLE)
     return fail(PCOP_ERR_INVALID_ARG, "the mixed-precision preconditioner needs side = PCOP_FLEXIBLE");
   if (o->spatial == PCOP_DST) {
@@ -94,7 +96,7 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
     if (!is_pow2(p->nx + 1)) return fail(PCOP_ERR_INVALID_ARG, "multigrid needs nx = 2^p - 1");
   }
   const int n = p->nt - 1;
-  if (!time_lds_fits(n, o->precision == PCOP_MIXED))
+  if (o->precond == PCOP_PRECOND_EPS && !time_lds_fits(n, o->precision == PCOP_MIXED))
     return fail(PCOP_ERR_UNSUPPORTED, "nt too large for the LDS time FFT");
   if (m > (1LL << 31) / 8) return fail(PCOP_ERR_UNSUPPORTED, "spatial grid too large");
   if ((long long)n * m * 2 > (1LL << 40)) return fail(PCOP_ERR_UNSUPPORTED, "problem too large");
@@ -106,7 +108,7 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t total = 0;
-  size_t dpow, twn64, twn32, twL64, twL32, mu1, lam, alpha, sg, ecoef;
+  size_t dpow, twn64, twn32, twL64, twL32, mu1, lam, alpha, sg, ecoef, unit;
   size_t twM64, twM32, chirp64, chirp32, bhat64, bhat32;
   int M = 1;
   size_t sc, H, coef, red, partial, wnorm2, norm, skip, active, finish, hcol;
@@ -134,6 +136,7 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
   L.vl = 2LL * n * m;
   L.nblk = krylov_blocks(L.vl);
   L.dpow = take(L, sizeof(double) * n);
+  L.unit = take(L, 2 * sizeof(double));
   L.twn64 = take(L, 16 * (size_t)n);
   L.twn32 = take(L, 8 * (size_t)n);
   const FftPlan tp = make_time_plan(n);
@@ -167,7 +170,13 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
   L.zbasis = (o->side == PCOP_FLEXIBLE) ? take(L, vec * o->restart) : 0;
   L.tmp1 = take(L, vec);
   L.tmp2 = take(L, vec);
-  L.spec = take(L, csz * (size_t)B * 2 * K * m);
+  {
+    // epsilon-circulant spectrum [B][2K][m], or the ideal preconditioner's
+    // z[B][2][n][m] plus one slice [B][m] (real/complex of the same precision)
+    const size_t t = fp32 ? 4 : 8;
+    const size_t ideal = ((t * (size_t)B * 2 * n * m + 255) & ~(size_t)255) + 2 * t * (size_t)B * m;
+    L.spec = take(L, std::max<size_t>(csz * (size_t)B * 2 * K * m, o->precond == PCOP_PRECOND_IDEAL ? ideal : 0));
+  }
   L.mg_levels = 0;
   if (o->spatial == PCOP_MG) {
     int lnx = nx;
@@ -195,7 +204,7 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
 // ---------------------------------------------------------------------------
 const char* kFamilyName[KF_COUNT] = {"kkt_apply", "time_fwd", "dst_rows", "dst_ax2", "dst_last_solve",
                                      "time_inv", "mg_smooth", "mg_restrict", "mg_prolong", "mdot",
-                                     "gs_update", "combine", "small"};
+                                     "gs_update", "combine", "small", "ideal_step"};
 
 struct EventTimer {
   hipStream_t st = nullptr;
@@ -311,14 +320,23 @@ struct pcop_ctx_s {
 
 namespace {
 
+// the configured preconditioner with tables tb (epsilon-circulant or ideal)
+bool run_precond(pcop_ctx c, const PrecondTables& tb, const double* v, double* w, const double* vscale,
+                 int vs_stride, int accum) {
+  void* spec = c->at<void>(c->L.spec);
+  if (c->opt.precond == PCOP_PRECOND_IDEAL)
+    return launch_ideal_precond(c->g, v, w, spec, c->fp32, c->opt.spatial, tb, c->at<double>(c->L.unit), vscale,
+                                vs_stride, accum, c->st);
+  return launch_precond(c->g, v, w, spec, c->fp32, c->opt.spatial, tb, vscale, vs_stride, accum, c->st);
+}
+
 pcop_status do_precond(pcop_ctx c, const double* v, double* w, const double* vscale, int vs_stride, int accum,
                        const int* mask, int nact) {
   PrecondTables tb = c->tb;
   tb.active = mask;
   tb.nact = nact;
   tb.timer = c->kt();
-  if (!launch_precond(c->g, v, w, c->at<void>(c->L.spec), c->fp32, c->opt.spatial, tb, vscale, vs_stride,
-                      accum, c->st))
+  if (!run_precond(c, tb, v, w, vscale, vs_stride, accum))
     return fail(PCOP_ERR_UNSUPPORTED, "preconditioner variant not available for this shape");
   return PCOP_OK;
 }
@@ -362,14 +380,14 @@ struct TuneResult {
   double ms;
 };
 std::mutex g_tune_mu;
-std::map<std::array<int, 10>, TuneResult> g_tune_cache;
+std::map<std::array<int, 11>, TuneResult> g_tune_cache;
 
 pcop_status tune_kernels(pcop_ctx c) {
   const Geo& g = c->g;
   int dev = 0;
   PCOP_HIP(hipGetDevice(&dev));
-  const std::array<int, 10> key{dev, g.dim, g.nx, g.n, g.B, (int)c->fp32, c->opt.spatial, c->opt.time_cols,
-                                c->opt.dst_kernel, c->coeff_kind};
+  const std::array<int, 11> key{dev, g.dim, g.nx, g.n, g.B, (int)c->fp32, c->opt.spatial, c->opt.time_cols,
+                                c->opt.dst_kernel, c->coeff_kind, c->opt.precond};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -381,7 +399,7 @@ pcop_status tune_kernels(pcop_ctx c) {
     }
   }
   std::vector<int> tcs;
-  if (c->opt.time_cols != 0 || c->tb.plan.bluestein) {
+  if (c->opt.time_cols != 0 || c->tb.plan.bluestein || c->opt.precond == PCOP_PRECOND_IDEAL) {
     tcs.push_back(c->tb.time_cols);
   } else {
     std::vector<int> seen;
@@ -419,10 +437,9 @@ pcop_status tune_kernels(pcop_ctx c) {
       t.active = nullptr;
       t.nact = g.B;
       t.timer = nullptr;
-      void* spec = c->at<void>(c->L.spec);
-      if (!launch_precond(g, v, w, spec, c->fp32, c->opt.spatial, t, nullptr, 0, 0, st)) continue;
+      if (!run_precond(c, t, v, w, nullptr, 0, 0)) continue;
       if ((err = hipEventRecord(e0, st)) != hipSuccess) break;
-      for (int r = 0; r < kReps; ++r) launch_precond(g, v, w, spec, c->fp32, c->opt.spatial, t, nullptr, 0, 0, st);
+      for (int r = 0; r < kReps; ++r) run_precond(c, t, v, w, nullptr, 0, 0);
       if ((err = hipEventRecord(e1, st)) != hipSuccess) break;
       if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
       float ms = 0.f;
@@ -623,6 +640,8 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   if (e == hipSuccess) e = up(L.alpha, c->alpha.data(), sizeof(double) * B);
   if (e == hipSuccess) e = up(L.sg, c->sgam.data(), sizeof(double) * B);
   if (e == hipSuccess) e = up(L.active, ones.data(), sizeof(int) * B);
+  static const double kUnit[2] = {1.0, 0.0};
+  if (e == hipSuccess) e = up(L.unit, kUnit, sizeof(kUnit));
 
   // stencil E = I + tau K
   std::vector<double> ecoef;
@@ -815,7 +834,7 @@ pcop_status pcop_get_params(pcop_ctx c, double* tau, double* alpha, double* eps)
 
 pcop_status pcop_get_kernels(pcop_ctx c, int* time_cols, int* dst_kernel, double* tuned_ms) {
   if (!c) return fail(PCOP_ERR_INVALID_ARG, "null context");
-  if (time_cols) *time_cols = time_choice(c->g, c->tb, c->fp32);
+  if (time_cols) *time_cols = (c->opt.precond == PCOP_PRECOND_EPS) ? time_choice(c->g, c->tb, c->fp32) : 0;
   if (dst_kernel) *dst_kernel = (c->opt.spatial == PCOP_DST) ? c->tb.dst_variant + 1 : 0;
   if (tuned_ms) *tuned_ms = c->tuned_ms;
   return PCOP_OK;

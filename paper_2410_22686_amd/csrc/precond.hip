@@ -157,13 +157,15 @@ bool launch_precond(const Geo& g, const double* v, double* w, void* spec, bool f
   if (fp32) {
     cx<float>* s = reinterpret_cast<cx<float>*>(spec);
     if (!time_fwd<float>(g, v, s, tb, vscale, vs_stride, st)) return false;
-    bool ok = (spatial == 0) ? launch_dst_solve(g, spec, true, tb, st) : launch_mg_solve(g, spec, true, tb, st);
+    bool ok = (spatial == 0) ? launch_dst_solve(g, spec, true, tb, 2 * g.K, tb.lam, st)
+                              : launch_mg_solve(g, spec, true, tb, 2 * g.K, tb.lam, st);
     if (!ok) return false;
     if (!time_inv<float>(g, s, w, tb, accum, st)) return false;
   } else {
     cx<double>* s = reinterpret_cast<cx<double>*>(spec);
     if (!time_fwd<double>(g, v, s, tb, vscale, vs_stride, st)) return false;
-    bool ok = (spatial == 0) ? launch_dst_solve(g, spec, false, tb, st) : launch_mg_solve(g, spec, false, tb, st);
+    bool ok = (spatial == 0) ? launch_dst_solve(g, spec, false, tb, 2 * g.K, tb.lam, st)
+                              : launch_mg_solve(g, spec, false, tb, 2 * g.K, tb.lam, st);
     if (!ok) return false;
     if (!time_inv<double>(g, s, w, tb, accum, st)) return false;
   }

@@ -24,6 +24,7 @@ PCOP_FP64, PCOP_MIXED = 0, 1
 PCOP_DST, PCOP_MG = 0, 1
 PCOP_RIGHT, PCOP_LEFT, PCOP_FLEXIBLE = 0, 1, 2
 PCOP_COEFF_ONE, PCOP_COEFF_HALFGRID = 0, 1
+PCOP_PRECOND_EPS, PCOP_PRECOND_IDEAL = 0, 1
 
 EXPORTED = [
     "pcop_validate", "pcop_default_options", "pcop_workspace_size", "pcop_setup", "pcop_rhs",
@@ -54,7 +55,7 @@ class c_options(ctypes.Structure):
                 ("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("graph", ctypes.c_int), ("graph_chunk", ctypes.c_int), ("reorth_tol", ctypes.c_double),
                 ("time_cols", ctypes.c_int), ("dst_kernel", ctypes.c_int), ("tune", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("precond", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
 class c_kernel_stat(ctypes.Structure):
@@ -132,6 +133,7 @@ def halfgrid_samples(coeff: Callable, dim: int, nx: int):
 _PREC = {"fp64": PCOP_FP64, "mixed": PCOP_MIXED}
 _SPAT = {"dst": PCOP_DST, "mg": PCOP_MG}
 _SIDE = {"right": PCOP_RIGHT, "left": PCOP_LEFT, "flexible": PCOP_FLEXIBLE}
+_PRECOND = {"eps": PCOP_PRECOND_EPS, "ideal": PCOP_PRECOND_IDEAL}
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -157,7 +159,7 @@ class Solver:
                  eps: Optional[float] = None, coeff: Optional[Callable] = None, precision: str = "fp64",
                  spatial: str = "dst", side: str = "right", restart: int = 30, maxit: int = 300,
                  rtol: float = 1e-8, graph: bool = False, graph_chunk: int = 4, reorth_tol: float = 1e-8,
-                 time_cols: int = 0, dst_kernel: int = 0, tune: bool = False,
+                 time_cols: int = 0, dst_kernel: int = 0, tune: bool = False, precond: str = "eps",
                  device: Union[str, torch.device] = "cuda", stream: Optional[torch.cuda.Stream] = None):
         import numpy as np
         self.lib = load_library()
@@ -186,6 +188,7 @@ class Solver:
         opts.restart, opts.maxit, opts.rtol = int(restart), int(maxit), float(rtol)
         opts.graph, opts.graph_chunk, opts.reorth_tol = int(bool(graph)), int(graph_chunk), float(reorth_tol)
         opts.time_cols, opts.dst_kernel, opts.tune = int(time_cols), int(dst_kernel), int(bool(tune))
+        opts.precond = _PRECOND[precond]
         self.stream = stream
         with torch.cuda.device(self.device):
             st = stream if stream is not None else torch.cuda.current_stream(self.device)

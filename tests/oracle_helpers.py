@@ -21,15 +21,16 @@ def read_rows(name):
     return rows
 
 
-def example1_solve(nx, nt, gamma, eps=None, side="left", rtol=1e-8, dim=2):
-    """Solve Example 1 with the oracle; returns (iters, e_h, result, problem)."""
+def example1_solve(nx, nt, gamma, eps=None, side="left", rtol=1e-8, dim=2, precond="eps"):
+    """Solve Example 1 with the oracle; returns (iters, e_h, result, problem).
+    precond "eps": P_eps (Section 2.1), "ideal": P of eq. matrix_P."""
     tau = 1.0 / nt
     e = min(0.5, tau / 2) if eps is None else eps
     pb = D.make_problem(dim, nx, nt, gamma, eps=e)
     g, f, y0 = W.example_fields(1, dim, nx, nt)
     b = D.rhs_scaled(pb, g, f, y0)
     A = D.kkt_scaled(pb)
-    pc = P.EpsCirculantRBD(pb)
+    pc = P.EpsCirculantRBD(pb) if precond == "eps" else P.IdealRBD(pb)
     res = K.gmres(lambda v: A @ v, b, pc.apply, side=side, rtol=rtol)
     y, p = D.unpack_solution(pb, res.x)
     fN, _ = W.example1_source(dim, nx, 1.0)

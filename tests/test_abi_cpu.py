@@ -83,7 +83,8 @@ def test_invalid_options_are_rejected(lib):
     p = _prob()
     for kw in [dict(restart=0), dict(restart=41), dict(maxit=0), dict(rtol=0.0), dict(side=7),
                dict(precision=1, side=0), dict(graph=1, graph_chunk=0), dict(time_cols=2),
-               dict(time_cols=-2), dict(time_cols=32), dict(dst_kernel=3), dict(dst_kernel=-1), dict(tune=2)]:
+               dict(time_cols=-2), dict(time_cols=32), dict(dst_kernel=3), dict(dst_kernel=-1), dict(tune=2),
+               dict(precond=2), dict(precond=-1)]:
         assert lib.pcop_validate(ctypes.byref(p), ctypes.byref(_opts(lib, **kw))) == 1, kw
 
 
@@ -92,7 +93,7 @@ def test_kernel_choice_options_validate(lib):
     o = _opts(lib)
     assert (o.time_cols, o.dst_kernel, o.tune) == (0, 0, 0)
     for kw in [dict(time_cols=-1), dict(time_cols=4), dict(time_cols=8), dict(time_cols=16),
-               dict(time_cols=-4), dict(time_cols=-8), dict(time_cols=-16),
+               dict(time_cols=-4), dict(time_cols=-8), dict(time_cols=-16), dict(precond=1),
                dict(dst_kernel=1), dict(dst_kernel=2), dict(tune=1)]:
         assert lib.pcop_validate(ctypes.byref(p), ctypes.byref(_opts(lib, **kw))) == 0, kw
 
@@ -134,3 +135,10 @@ def test_workspace_size_scales_with_problem(lib):
 def test_status_strings(lib):
     for s in range(6):
         assert len(lib.pcop_status_string(s)) > 0
+
+
+def test_ideal_preconditioner_has_no_time_transform_limit(lib):
+    """P of eq. matrix_P needs no FFT along time, so long horizons validate."""
+    p = _prob(nx=31, nt=4096)
+    assert lib.pcop_validate(ctypes.byref(p), ctypes.byref(_opts(lib))) == 2
+    assert lib.pcop_validate(ctypes.byref(p), ctypes.byref(_opts(lib, precond=1))) == 0

@@ -118,3 +118,18 @@ def test_paper_table_rows(row):
     it, e, _, _ = example1_solve(nx, nt, float(gamma))
     assert it == iters
     assert float(f"{e:.2e}") == pytest.approx(float(eh), rel=1e-12)
+
+
+ROWS4 = [r for r in read_rows("paper_table4_rows.txt") if int(r[3]) <= 128]
+
+
+@pytest.mark.parametrize("row", ROWS4, ids=[" ".join(r[:4]) for r in ROWS4])
+def test_paper_table4_rows_ideal(row):
+    """Iteration count (exact) and e_h (3 significant digits) of GMRES-P with the
+    ideal RBD preconditioner on Example 1 as printed in Table 4."""
+    table, gamma, nx, nt, dof, iters, eh = row[:7]
+    nx, nt, dof, iters = int(nx), int(nt), int(dof), int(iters)
+    assert dof == 2 * nx * nx * nt
+    it, e, _, _ = example1_solve(nx, nt, float(gamma), precond="ideal")
+    assert it == iters
+    assert float(f"{e:.2e}") == pytest.approx(float(eh), rel=1e-12)

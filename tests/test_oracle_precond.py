@@ -62,6 +62,34 @@ def test_ideal_rbd_apply_equals_dense_inverse():
     assert rel(P.IdealRBD(pb).apply(v), np.linalg.solve(P.ideal_rbd_dense(pb), v)) < 1e-12
 
 
+def test_ideal_rbd_multigrid_single_point_is_exact():
+    """On a one-point grid the V-cycle is the exact solve, so the multigrid
+    variant of the ideal preconditioner equals the LU one."""
+    pb = D.make_problem(2, 1, 9, 1e-3, coeff=W.coeff_sines3d)
+    v = np.random.default_rng(2).standard_normal(2 * pb.n * pb.m)
+    a = P.IdealRBD(pb, spatial="mg", coeff=W.coeff_sines3d).apply(v)
+    assert rel(a, P.IdealRBD(pb).apply(v)) < 1e-14
+
+
+def test_ideal_rbd_multigrid_power_series():
+    """With M the (linear) V-cycle operator, forward substitution gives
+    z_2^j = sum_{i <= j} M^{j-i+1} v_2^i and backward substitution
+    z_1^j = sum_{i >= j} M^{i-j+1} v_1^i; w = [z_1 - z_2; z_1 + z_2]."""
+    from oracle.multigrid import ShiftedVCycle
+    pb = D.make_problem(2, 7, 6, 1e-2, coeff=W.coeff_sines3d)
+    n, m = pb.n, pb.m
+    mg = ShiftedVCycle(2, 7, pb.tau, W.coeff_sines3d)
+    M = np.stack([mg.apply(e, complex(1.0 + pb.alpha, 0.0)).real for e in np.eye(m)], axis=1)
+    pw = [np.eye(m)]
+    for _ in range(n):
+        pw.append(M @ pw[-1])
+    v = np.random.default_rng(3).standard_normal((2, n, m))
+    z2 = np.array([sum(pw[j - i + 1] @ v[1, i] for i in range(j + 1)) for j in range(n)])
+    z1 = np.array([sum(pw[i - j + 1] @ v[0, i] for i in range(j, n)) for j in range(n)])
+    w = P.IdealRBD(pb, spatial="mg", coeff=W.coeff_sines3d).apply(v.ravel())
+    assert rel(w, np.concatenate([(z1 - z2).ravel(), (z1 + z2).ravel()])) < 1e-13
+
+
 def test_ideal_rbd_spectrum():
     """sigma(P^{-1} A) lies on Re = 1 with |Im| <= 1 (thm:spectum_of_H_inv_B, M = I)."""
     for gamma in (1e-6, 1e-2, 1.0):
