@@ -212,6 +212,31 @@ pcop_status pcop_pack_cotangent(pcop_ctx ctx, const double* ybar, const double* 
 pcop_status pcop_data_grad(pcop_ctx ctx, const double* lam, double* dg, double* df,
                            double* dy0);
 
+/* End levels of the discrete solution from a solved x (Section 1, the two
+ * formulas after eq. Toeplitz_Mat_B, M = I, p^N = 0):
+ *   (I + tau K) y^N = y^{N-1} + tau f^N,   (I + tau K) p^0 = p^1 + tau (g^0 - y^0).
+ * x: [batch][2][n][m] solution of pcop_solve; fN, g0, y0: [batch][m] data at
+ * t = T, t = 0 and the initial state; outputs yN, p0: [batch][m].  All device
+ * FP64 pointers.  Solved by iterative refinement with an FP64 residual and
+ * the context's spatial solver (sine transforms in FP64, or one V-cycle per
+ * step) until the residual stops decreasing or falls below 1e-14 of the
+ * initial one.  relres (host [batch], may be NULL) receives the final
+ * ||rhs - E z|| / ||rhs||; PCOP_NOT_CONVERGED when any exceeds 1e-10 (outputs
+ * still written).  Uses the context's scratch buffers: not concurrent with
+ * pcop_solve on the same context.  Synchronises the stream. */
+pcop_status pcop_post_solve(pcop_ctx ctx, const double* x, const double* fN, const double* g0,
+                            const double* y0, double* yN, double* p0, double* relres);
+
+/* The error e_h of Section 3 per member:
+ *   e_h = h^{d/2} max_{1<=j<=N} max(||y^j - y(t_j)||_2, ||p^{j-1} - p(t_{j-1})||_2),
+ * with y^j = x_1^j / sqrt(gamma), p^j = x_2^j for 1 <= j <= n and the end
+ * levels yN, p0 of pcop_post_solve.  y_exact, p_exact: device
+ * [batch][N+1][m] FP64 values of the exact solution at t_j = j tau,
+ * j = 0..N (level N of p and level 0 of y are not read).  eh: host [batch].
+ * Fixed-order reductions; synchronises the stream. */
+pcop_status pcop_error_eh(pcop_ctx ctx, const double* x, const double* yN, const double* p0,
+                          const double* y_exact, const double* p_exact, double* eh);
+
 /* Host copy of a few derived scalars: tau, alpha[batch], eps. */
 pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* eps);
 

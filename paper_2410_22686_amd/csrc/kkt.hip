@@ -3,42 +3,9 @@
 // eq. main_system).  All FP64 and HBM-bound.
 #include "common.hpp"
 #include "launch.hpp"
+#include "stencil.hpp"
 
 namespace pcop {
-
-// E u at point i with E = I + tau K.  Constant coefficient: E = ediag I +
-// eoff * (sum of existing neighbours).  Variable coefficient: per-point
-// values ecoef[0][i] (diagonal) and ecoef[1 + 2d][i] / ecoef[2 + 2d][i]
-// (the minus / plus neighbour along axis d, zero at the boundary).
-template <int DIM, bool VAR>
-__device__ __forceinline__ double apply_E(const double* __restrict__ u, int i, int c1, int c2, int c3,
-                                          int nx, int m, const double* __restrict__ ecoef,
-                                          double ediag, double eoff) {
-  const int s2 = nx, s3 = nx * nx;
-  if (!VAR) {
-    double nb = 0.0;
-    if (c1 > 0) nb += u[i - 1];
-    if (c1 < nx - 1) nb += u[i + 1];
-    if (c2 > 0) nb += u[i - s2];
-    if (c2 < nx - 1) nb += u[i + s2];
-    if (DIM == 3) {
-      if (c3 > 0) nb += u[i - s3];
-      if (c3 < nx - 1) nb += u[i + s3];
-    }
-    return ediag * u[i] + eoff * nb;
-  } else {
-    double acc = ecoef[i] * u[i];
-    if (c1 > 0) acc += ecoef[(size_t)1 * m + i] * u[i - 1];
-    if (c1 < nx - 1) acc += ecoef[(size_t)2 * m + i] * u[i + 1];
-    if (c2 > 0) acc += ecoef[(size_t)3 * m + i] * u[i - s2];
-    if (c2 < nx - 1) acc += ecoef[(size_t)4 * m + i] * u[i + s2];
-    if (DIM == 3) {
-      if (c3 > 0) acc += ecoef[(size_t)5 * m + i] * u[i - s3];
-      if (c3 < nx - 1) acc += ecoef[(size_t)6 * m + i] * u[i + s3];
-    }
-    return acc;
-  }
-}
 
 // y = c - s A x  (c != nullptr)  or  y = s A x, with A or A^T (sgn = -1).
 // One thread per spatial point, marching over a chunk of time blocks so that

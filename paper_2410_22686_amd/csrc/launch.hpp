@@ -111,6 +111,27 @@ bool launch_ideal_precond(const Geo& g, const double* v, double* w, void* spec, 
                           int accum, hipStream_t st);
 size_t ideal_spec_bytes(const Geo& g, bool fp32);
 
+// post-solve of the end levels (post.hip): buffers of the refinement
+struct PostArgs {
+  double* rhs;          // [B][2][m] right-hand sides (real, imaginary planes)
+  double* z;            // [B][2][m] iterate
+  double* part;         // [B][ceil(m/256)] block partial sums
+  double* norm2;        // [B] squared residual norms
+  const double* ecoef;  // variable-coefficient stencil of E, or null
+  double ediag, eoff;   // constant-coefficient stencil of E
+};
+void launch_post_rhs(const Geo& g, const double* x, const double* fN, const double* g0, const double* y0,
+                     const double* sg, const PostArgs& a, hipStream_t st);
+// residual into the slice (norm2 = its squared norms), one spatial solve, z += slice
+bool launch_post_step(const Geo& g, const PostArgs& a, void* slice, bool fp32, int spatial,
+                      const PrecondTables& tb, const double* unit, hipStream_t st);
+// residual norms only
+void launch_post_residual(const Geo& g, const PostArgs& a, void* slice, hipStream_t st);
+void launch_post_store(const Geo& g, const PostArgs& a, double* yN, double* p0, hipStream_t st);
+// e_h per member into eh[B]; sq: [B][N][2] scratch
+void launch_error_eh(const Geo& g, const double* x, const double* yN, const double* p0, const double* sg,
+                     const double* yex, const double* pex, double* sq, double* eh, hipStream_t st);
+
 // Krylov kernels (krylov.hip).  Basis slot i of member b starts at
 // basis + i * slot_stride + b * vl.
 struct KrylovArgs {

@@ -108,7 +108,7 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t total = 0;
-  size_t dpow, twn64, twn32, twL64, twL32, mu1, lam, alpha, sg, ecoef, unit;
+  size_t dpow, twn64, twn32, twL64, twL32, mu1, lam, alpha, sg, ecoef, unit, zero, post;
   size_t twM64, twM32, chirp64, chirp32, bhat64, bhat32;
   int M = 1;
   size_t sc, H, coef, red, partial, wnorm2, norm, skip, active, finish, hcol;
@@ -137,6 +137,9 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
   L.nblk = krylov_blocks(L.vl);
   L.dpow = take(L, sizeof(double) * n);
   L.unit = take(L, 2 * sizeof(double));
+  L.zero = take(L, sizeof(double) * B);
+  // post-solve partial sums [B][ceil(m/256)], norms [B], e_h level sums [B][n+1][2], e_h [B]
+  L.post = take(L, sizeof(double) * ((size_t)B * ((m + 255) / 256) + B + 2 * (size_t)B * (n + 1) + B));
   L.twn64 = take(L, 16 * (size_t)n);
   L.twn32 = take(L, 8 * (size_t)n);
   const FftPlan tp = make_time_plan(n);
@@ -642,6 +645,8 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   if (e == hipSuccess) e = up(L.active, ones.data(), sizeof(int) * B);
   static const double kUnit[2] = {1.0, 0.0};
   if (e == hipSuccess) e = up(L.unit, kUnit, sizeof(kUnit));
+  std::vector<double> zeros(B, 0.0);
+  if (e == hipSuccess) e = up(L.zero, zeros.data(), sizeof(double) * B);
 
   // stencil E = I + tau K
   std::vector<double> ecoef;
@@ -837,6 +842,79 @@ pcop_status pcop_get_kernels(pcop_ctx c, int* time_cols, int* dst_kernel, double
   if (time_cols) *time_cols = (c->opt.precond == PCOP_PRECOND_EPS) ? time_choice(c->g, c->tb, c->fp32) : 0;
   if (dst_kernel) *dst_kernel = (c->opt.spatial == PCOP_DST) ? c->tb.dst_variant + 1 : 0;
   if (tuned_ms) *tuned_ms = c->tuned_ms;
+  return PCOP_OK;
+}
+
+pcop_status pcop_post_solve(pcop_ctx c, const double* x, const double* fN, const double* g0, const double* y0,
+                            double* yN, double* p0, double* relres) {
+  if (!c || !x || !fN || !g0 || !y0 || !yN || !p0) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  const Geo& g = c->g;
+  const int B = g.B;
+  hipStream_t st = c->st;
+  double* post = c->at<double>(c->L.post);
+  PostArgs a{c->at<double>(c->L.tmp1), c->at<double>(c->L.tmp2), post, post + (size_t)B * ((g.m + 255) / 256),
+             c->ecoef, c->ediag, c->eoff};
+  void* slice = c->at<void>(c->L.spec);
+  PrecondTables tb = c->tb;
+  tb.alpha = c->at<double>(c->L.zero);  // shift 1: E = I + tau K
+  tb.active = nullptr;
+  tb.nact = B;
+  tb.timer = nullptr;
+  const double* unit = c->at<double>(c->L.unit);
+  launch_post_rhs(g, x, fN, g0, y0, c->at<double>(c->L.sg), a, st);
+  PCOP_HIP(hipGetLastError());
+  auto read_norms = [&](std::vector<double>& out) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(c->pin_norm, a.norm2, sizeof(double) * B, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    for (int b = 0; b < B; ++b) out[b] = std::sqrt(c->pin_norm[b]);
+    return e;
+  };
+  // refinement: sine transforms solve E exactly (a second step removes the
+  // last rounding); the V-cycle contracts the error by a constant factor
+  const int max_steps = (c->opt.spatial == PCOP_DST) ? 3 : 200;
+  std::vector<double> r0(B), r(B), prev(B, 1e300);
+  for (int it = 0; it < max_steps; ++it) {
+    if (!launch_post_step(g, a, slice, c->fp32, c->opt.spatial, tb, unit, st))
+      return fail(PCOP_ERR_UNSUPPORTED, "post-solve: spatial solver not available for this shape");
+    PCOP_HIP(hipGetLastError());
+    PCOP_HIP(read_norms(it == 0 ? r0 : r));
+    if (it == 0) continue;
+    // stop at 1e-14 of the initial residual, or once it stalls at rounding level
+    bool done = true;
+    for (int b = 0; b < B; ++b)
+      if (r[b] > 1e-14 * r0[b] && r[b] < 0.9 * prev[b]) done = false;
+    prev = r;
+    if (done) break;
+  }
+  launch_post_residual(g, a, slice, st);
+  PCOP_HIP(hipGetLastError());
+  PCOP_HIP(read_norms(r));
+  launch_post_store(g, a, yN, p0, st);
+  PCOP_HIP(hipGetLastError());
+  double worst = 0.0;
+  for (int b = 0; b < B; ++b) {
+    const double rel = r0[b] > 0 ? r[b] / r0[b] : 0.0;
+    if (relres) relres[b] = rel;
+    worst = std::max(worst, rel);
+  }
+  if (worst > 1e-10) return fail(PCOP_NOT_CONVERGED, "post-solve residual above 1e-10");
+  return PCOP_OK;
+}
+
+pcop_status pcop_error_eh(pcop_ctx c, const double* x, const double* yN, const double* p0, const double* y_exact,
+                          const double* p_exact, double* eh) {
+  if (!c || !x || !yN || !p0 || !y_exact || !p_exact || !eh) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  const Geo& g = c->g;
+  const int B = g.B;
+  hipStream_t st = c->st;
+  double* post = c->at<double>(c->L.post);
+  double* sq = post + (size_t)B * ((g.m + 255) / 256) + B;
+  double* dev_eh = sq + 2 * (size_t)B * (g.n + 1);
+  launch_error_eh(g, x, yN, p0, c->at<double>(c->L.sg), y_exact, p_exact, sq, dev_eh, st);
+  PCOP_HIP(hipGetLastError());
+  PCOP_HIP(hipMemcpyAsync(c->pin_norm, dev_eh, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+  PCOP_HIP(hipStreamSynchronize(st));
+  for (int b = 0; b < B; ++b) eh[b] = c->pin_norm[b];
   return PCOP_OK;
 }
 

@@ -32,10 +32,12 @@ static int time_cols_sk(int n, int csz, int want) {
     if ((size_t)2 * n * P * csz <= 65536) return P;
   return 0;
 }
+// columns per block of the chirp-z kernels: 16..4, or down to 1 for M >= 2048
 static int time_cols_bl(int M, int csz) {
-  int P = 16;
-  while (P > 4 && (size_t)(M + 1) * P * csz > kBlueLds) P /= 2;
-  return ((size_t)(M + 1) * P * csz <= kBlueLds) ? P : 0;
+  const int pmin = (M >= 2048) ? 1 : 4;
+  for (int P = 16; P >= pmin; P /= 2)
+    if ((size_t)(M + 1) * P * csz <= kBlueLds && M <= 4096) return P;
+  return 0;
 }
 
 

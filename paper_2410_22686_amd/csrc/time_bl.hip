@@ -110,8 +110,9 @@ __global__ void __launch_bounds__(256) time_inv_bl(Geo g, const cx<T>* __restric
 template <class T, int P, int M>
 static void bl_launch(bool fwd, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
                       const TimeTables& tt, const double* vscale, int vs_stride, int accum, hipStream_t st) {
-  // only shapes whose LDS tile fits 64 KiB are instantiated (time_cols_bl picks P accordingly)
-  if constexpr ((size_t)(M + 1) * P * sizeof(cx<T>) <= kBlueLds) {
+  // only shapes whose LDS tile fits kBlueLds are instantiated (time_cols_bl
+  // picks P accordingly); fewer than 4 columns only for the longest lengths
+  if constexpr ((size_t)(M + 1) * P * sizeof(cx<T>) <= kBlueLds && (P >= 4 || M >= 2048)) {
     dim3 grid((g.m + P - 1) / P, g.B);
     if (fwd)
       time_fwd_bl<T, P, M><<<grid, 256, 0, st>>>(g, v, spec, tb.dpow, tt, vscale, vs_stride, tb.active);
@@ -134,6 +135,7 @@ static bool bl_dispatch_M(bool fwd, int M, const Geo& g, const double* v, cx<T>*
     case 512: bl_launch<T, P, 512>(fwd, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st); return true;
     case 1024: bl_launch<T, P, 1024>(fwd, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st); return true;
     case 2048: bl_launch<T, P, 2048>(fwd, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st); return true;
+    case 4096: bl_launch<T, P, 4096>(fwd, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st); return true;
     default: return false;
   }
 }
@@ -145,6 +147,8 @@ bool launch_time_bl(bool fwd, int P, const Geo& g, const double* v, cx<T>* spec,
   if (P == 16) return bl_dispatch_M<T, 16>(fwd, tb.plan.M, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st);
   if (P == 8) return bl_dispatch_M<T, 8>(fwd, tb.plan.M, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st);
   if (P == 4) return bl_dispatch_M<T, 4>(fwd, tb.plan.M, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st);
+  if (P == 2) return bl_dispatch_M<T, 2>(fwd, tb.plan.M, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st);
+  if (P == 1) return bl_dispatch_M<T, 1>(fwd, tb.plan.M, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st);
   return false;
 }
 

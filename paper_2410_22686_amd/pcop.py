@@ -30,7 +30,7 @@ EXPORTED = [
     "pcop_validate", "pcop_default_options", "pcop_workspace_size", "pcop_setup", "pcop_rhs",
     "pcop_kkt_apply", "pcop_precond_apply", "pcop_solve", "pcop_unpack", "pcop_pack_cotangent",
     "pcop_data_grad", "pcop_get_params", "pcop_destroy", "pcop_status_string", "pcop_last_error",
-    "pcop_timing_enable", "pcop_timing_read", "pcop_get_kernels",
+    "pcop_timing_enable", "pcop_timing_read", "pcop_get_kernels", "pcop_post_solve", "pcop_error_eh",
 ]
 
 
@@ -95,6 +95,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "pcop_data_grad": (ip, [vp, vp, vp, vp, vp]),
         "pcop_get_params": (ip, [vp, dp, dp, dp]),
         "pcop_get_kernels": (ip, [vp, ctypes.POINTER(ip), ctypes.POINTER(ip), dp]),
+        "pcop_post_solve": (ip, [vp, vp, vp, vp, vp, vp, vp, dp]),
+        "pcop_error_eh": (ip, [vp, vp, vp, vp, vp, vp, dp]),
         "pcop_destroy": (None, [vp]),
         "pcop_status_string": (ctypes.c_char_p, [ip]),
         "pcop_last_error": (ctypes.c_char_p, []),
@@ -270,6 +272,31 @@ class Solver:
         y = self.new_vector() if out is None else self._vec(out, "out")
         _check(self.lib.pcop_kkt_apply(self.ctx, _ptr(x), _ptr(y), int(bool(transpose))))
         return y
+
+    def post_solve(self, x: torch.Tensor, fN: torch.Tensor, g0: torch.Tensor, y0: torch.Tensor):
+        """End levels (y^N, p^0), each [batch][m], of the discrete solution x
+        (pcop_post_solve); also returns the final relative residuals."""
+        self._vec(x, "x")
+        for t, name in ((fN, "fN"), (g0, "g0"), (y0, "y0")):
+            self._vec(t, name, (self.batch, self.m))
+        yN = torch.empty((self.batch, self.m), dtype=torch.float64, device=self.device)
+        p0 = torch.empty_like(yN)
+        rel = (ctypes.c_double * self.batch)()
+        _check(self.lib.pcop_post_solve(self.ctx, _ptr(x), _ptr(fN), _ptr(g0), _ptr(y0), _ptr(yN), _ptr(p0), rel))
+        return yN, p0, list(rel)
+
+    def error_eh(self, x: torch.Tensor, yN: torch.Tensor, p0: torch.Tensor, y_exact: torch.Tensor,
+                 p_exact: torch.Tensor):
+        """e_h of Section 3 per member (pcop_error_eh); y_exact, p_exact are
+        [batch][nt+1][m] values of the exact solution at t_j = j tau."""
+        self._vec(x, "x")
+        self._vec(yN, "yN", (self.batch, self.m))
+        self._vec(p0, "p0", (self.batch, self.m))
+        self._vec(y_exact, "y_exact", (self.batch, self.nt + 1, self.m))
+        self._vec(p_exact, "p_exact", (self.batch, self.nt + 1, self.m))
+        eh = (ctypes.c_double * self.batch)()
+        _check(self.lib.pcop_error_eh(self.ctx, _ptr(x), _ptr(yN), _ptr(p0), _ptr(y_exact), _ptr(p_exact), eh))
+        return list(eh)
 
     def precond_apply(self, v: torch.Tensor, out: Optional[torch.Tensor] = None):
         self._vec(v, "v")

