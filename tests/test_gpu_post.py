@@ -78,12 +78,13 @@ def device_eh(s, x, fN, g0, y0, exact, nx, nt, dim=2):
     return s.error_eh(x, yN, p0, to_dev(np.array(ys)[None]), to_dev(np.array(ps)[None]))[0]
 
 
-ROWS1 = read_rows("paper_table_rows.txt")
+ROWS1 = read_rows("paper_table_rows.txt") + read_rows("paper_table3_long_rows.txt")
 
 
 @pytest.mark.parametrize("row", ROWS1, ids=[" ".join(r[:4]) for r in ROWS1])
 def test_example1_rows_on_device(row):
-    """Tables 1-3 (GMRES-P_eps, Example 1): counts exactly, e_h to 3 digits."""
+    """Tables 1-3 (GMRES-P_eps, Example 1, nt up to 2048): counts exactly, e_h
+    to 3 digits."""
     _, gamma, nx, nt, _, iters, eh = row[:7]
     if len(row) > 7:  # printed exponent off by one; same mantissa
         eh = row[7]
