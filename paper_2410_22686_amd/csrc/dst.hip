@@ -305,11 +305,23 @@ __global__ void __launch_bounds__(256) dst_col_kernel(Geo g, cx<T>* __restrict__
   constexpr int LD = L + L / 8 + 1;
   constexpr int QS = (N * LPB + 255) / 256;  // tile elements per thread
   __shared__ cx<T> buf[LPB * LD];
+  // twiddles and 1-D eigenvalues in LDS: inside the loop the only global
+  // loads are the prefetch (loads retire in order)
+  __shared__ cx<T> twl[L];
+  __shared__ double mul[DIVIDE ? N : 1];
+  for (int k = threadIdx.x; k < L; k += 256) twl[k] = twL[k];
+  if (DIVIDE)
+    for (int k = threadIdx.x; k < N; k += 256) mul[k] = dp.mu1[k];
+  __syncthreads();
+  DivideParams dl = dp;
+  dl.mu1 = mul;
   const long long tiles = (lg.lines + LPB - 1) / LPB;
   const long long total = tiles * lg.nplanes;
   const int lid = threadIdx.x / TL;
   const int t = threadIdx.x - lid * TL;
   cx<T>* lbuf = buf + lid * LD;
+  // tiles blk, blk + G, ...: consecutive logical blocks sit on one XCD and
+  // process neighbouring tiles (which share 128-byte lines) at the same time
   auto next = [&](long long blk) {
     if (DIVIDE && dp.active)
       while (blk < total && !dp.active[(int)((blk / tiles) / dp.spm)]) blk += gridDim.x;
@@ -361,11 +373,11 @@ __global__ void __launch_bounds__(256) dst_col_kernel(Geo g, cx<T>* __restrict__
         v[s] = cx<T>{0, 0};
       }
     }
-    RegStages<T, L, TL, -1, 1>::run(v, t, lbuf, twL);
+    RegStages<T, L, TL, -1, 1>::run(v, t, lbuf, twl);
     if (DIVIDE) {
-      divide_line<T, L, TL>(v, t, g, dp, plane, line, valid);
+      divide_line<T, L, TL>(v, t, g, dl, plane, line, valid);
       odd_extend<T, L, TL>(v, t, lbuf);
-      RegStages<T, L, TL, -1, 1>::run(v, t, lbuf, twL);
+      RegStages<T, L, TL, -1, 1>::run(v, t, lbuf, twl);
     }
     __syncthreads();
 #pragma unroll

@@ -26,10 +26,11 @@ namespace pcop {
 // time_ip_*.hip (one in-place buffer) and time_bl.hip (chirp-z)
 // ---------------------------------------------------------------------------
 // points per block of the two-buffer time kernels: the largest power of two
-// in 4..want whose two [n][P] buffers fit 64 KiB, else 0
+// in 4..want whose two [n][P] buffers fit 64 KiB and whose whole LDS (with
+// the tables) fits 80 KiB (two blocks per CU), else 0
 static int time_cols_sk(int n, int csz, int want) {
   for (int P = want; P >= 4; P /= 2)
-    if ((size_t)2 * n * P * csz <= 65536) return P;
+    if ((size_t)2 * n * P * csz <= 65536 && sk_lds_bytes(n, P, csz) <= 81920) return P;
   return 0;
 }
 // columns per block of the chirp-z kernels: 16..4, or down to 1 for M >= 2048

@@ -25,14 +25,15 @@ struct TimeTables {
   const void* bhat;   // [M]   FFT_M of the chirp filter
 };
 
-// c_j = s (d_j v2_j + i v1_j / d_j) at time level j, spatial point i
+// c_j = s (d_j v2_j + i v1_j / d_j) at time level j, spatial point i (the
+// factors s d_j and s / d_j are formed first, as in every time kernel)
 template <class T>
 __device__ __forceinline__ cx<T> pack_input(const double* v1, const double* v2, const double* dpow, double s,
                                             int j, int i, int m) {
   if (i >= m) return cx<T>{0, 0};
   const double d = dpow[j];
   const size_t o = (size_t)j * m + i;
-  return cx<T>{(T)(s * d * v2[o]), (T)(s * v1[o] / d)};
+  return cx<T>{(T)(s * d * v2[o]), (T)(s * (1.0 / d) * v1[o])};
 }
 
 // split the packed spectrum X into the two block spectra and store slices 2k, 2k+1
@@ -52,12 +53,12 @@ __device__ __forceinline__ void unpack_store(cx<T>* out, int n, int K, int P, in
 }
 
 // w_1 = z_1 - z_2, w_2 = z_1 + z_2 with z_2 = Re(e)/(n d_j), z_1 = Im(e) d_j/n
+// (factors 1/(n d_j) and d_j/n formed first, as in every time kernel)
 __device__ __forceinline__ void combine_store(double* w1, double* w2, const double* dpow, int n, int m, int j,
                                               int i, double ex, double ey, int accum) {
   const double d = dpow[j];
-  const double inv_n = 1.0 / (double)n;
-  const double z2 = ex * inv_n / d;
-  const double z1 = ey * inv_n * d;
+  const double z2 = ex * (1.0 / ((double)n * d));
+  const double z1 = ey * (d / (double)n);
   const size_t o = (size_t)j * m + i;
   if (accum) {
     w1[o] += z1 - z2;
@@ -81,5 +82,8 @@ bool launch_time_bl(bool fwd, int P, const Geo& g, const double* v, cx<T>* spec,
                     const TimeTables& tt, const double* vscale, int vs_stride, int accum, hipStream_t st);
 // chirp-z tiles are static LDS; up to 80 KiB keeps two blocks per CU
 constexpr size_t kBlueLds = 81920;
+// dynamic LDS of the two-buffer kernels: two [n][P] buffers, the n twiddles
+// and two tables of n scale factors (D_eps powers and their inverses)
+inline size_t sk_lds_bytes(int n, int P, size_t csz) { return (2 * (size_t)P + 1) * n * csz + 16 * (size_t)n; }
 
 }  // namespace pcop

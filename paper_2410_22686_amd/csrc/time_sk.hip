@@ -5,10 +5,14 @@
 
 namespace pcop {
 
-// Persistent blocks: each block walks column tiles lb, lb + grid, ... and
+// Persistent blocks: each block walks column tiles lb, lb + G, ... and
 // fetches the global inputs of its next tile into registers before running
 // the FFT stages of the current one in LDS, so HBM traffic overlaps the
-// stages (two [n][P] buffers allow only a few blocks per CU).
+// stages (two [n][P] buffers allow only a few blocks per CU).  A tile covers
+// P consecutive points of every row (64 bytes in FP64), so a 128-byte line
+// is shared by neighbouring tiles; consecutive logical blocks sit on one XCD
+// and process neighbouring tiles at the same time, so the halves of a line
+// meet in that XCD's L2.
 //
 // Tile t covers member t / tiles_per_member and spatial points
 // i0 .. i0 + P - 1 with i0 = (t mod tiles_per_member) P.
@@ -16,7 +20,7 @@ struct TileWalk {
   int tpm;     // tiles per member
   int ntiles;  // B * tpm
   const int* active;
-  // first tile at or after t whose member is active (ntiles if none)
+  // first tile at or after t (stepping by stride) whose member is active
   __device__ __forceinline__ int next(int t, int stride) const {
     while (t < ntiles && active && !active[t / tpm]) t += stride;
     return t;
@@ -34,7 +38,17 @@ __global__ void __launch_bounds__(256) time_fwd_sk(Geo g, const double* __restri
   const int nP = n * P;
   cx<T>* bufA = reinterpret_cast<cx<T>*>(smem);
   cx<T>* bufB = bufA + nP;
-  // consecutive logical blocks (whose tiles share 128-byte lines) on one XCD
+  // twiddles and D_eps powers live in LDS, so that inside the loop the only
+  // global loads are the prefetch (loads retire in order)
+  cx<T>* tw_l = bufB + nP;
+  double* dp_l = reinterpret_cast<double*>(tw_l + n);  // d_j
+  double* di_l = dp_l + n;                              // 1 / d_j
+  for (int t = threadIdx.x; t < n; t += 256) {
+    tw_l[t] = twn[t];
+    dp_l[t] = dpow[t];
+    di_l[t] = 1.0 / dpow[t];
+  }
+  __syncthreads();
   const int stride = gridDim.x;
   int tile = tw.next(xcd_remap(blockIdx.x, gridDim.x), stride);
   double r1[Q], r2[Q];  // v_1, v_2 at element e = threadIdx.x + q * 256 of the tile
@@ -62,8 +76,8 @@ __global__ void __launch_bounds__(256) time_fwd_sk(Geo g, const double* __restri
     for (int q = 0; q < Q; ++q) {
       const int e = threadIdx.x + q * 256;
       if (e < nP) {
-        const double d = dpow[e / P];
-        bufA[e] = cx<T>{(T)(s * d * r2[q]), (T)(s * r1[q] / d)};
+        const int j = e / P;
+        bufA[e] = cx<T>{(T)(s * dp_l[j] * r2[q]), (T)(s * di_l[j] * r1[q])};
       }
     }
     __syncthreads();
@@ -75,7 +89,7 @@ __global__ void __launch_bounds__(256) time_fwd_sk(Geo g, const double* __restri
     for (int st = 0; st < plan.nrad; ++st) {
       auto ld = [&](int j, int p) { return src[j * P + p]; };
       auto sto = [&](int j, int p, cx<T> val) { dst[j * P + p] = val; };
-      sk_stage_rt<T, P, -1>(plan.rad[st], n, Ns, twn, ld, sto);
+      sk_stage_rt<T, P, -1>(plan.rad[st], n, Ns, tw_l, ld, sto);
       __syncthreads();
       Ns *= plan.rad[st];
       cx<T>* t = src;
@@ -89,16 +103,27 @@ __global__ void __launch_bounds__(256) time_fwd_sk(Geo g, const double* __restri
   }
 }
 
-// Q = register slots per thread for one tile's spectrum: K P <= Q * 256
-template <class T, int P, int Q>
+// Q = register slots per thread for one tile's spectrum: K P <= Q * 256.
+// ACC: add into w instead of overwriting it (a compile-time switch, so the
+// common kernel issues no global loads besides the prefetch)
+template <class T, int P, int Q, int ACC>
 __global__ void __launch_bounds__(256) time_inv_sk(Geo g, const cx<T>* __restrict__ spec, double* __restrict__ w,
                                                    const double* __restrict__ dpow, const cx<T>* __restrict__ twn,
-                                                   FftPlan plan, int accum, TileWalk tw) {
+                                                   FftPlan plan, TileWalk tw) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = g.n, m = g.m, K = g.K;
   const int KP = K * P;
   cx<T>* bufA = reinterpret_cast<cx<T>*>(smem);
   cx<T>* bufB = bufA + n * P;
+  cx<T>* tw_l = bufB + n * P;
+  double* dn_l = reinterpret_cast<double*>(tw_l + n);  // d_j / n
+  double* di_l = dn_l + n;                              // 1 / (n d_j)
+  for (int t = threadIdx.x; t < n; t += 256) {
+    tw_l[t] = twn[t];
+    dn_l[t] = dpow[t] / (double)n;
+    di_l[t] = 1.0 / ((double)n * dpow[t]);
+  }
+  __syncthreads();
   const int stride = gridDim.x;
   int tile = tw.next(xcd_remap(blockIdx.x, gridDim.x), stride);
   cx<T> r2[Q], r1[Q];  // Z_2, Z_1 at element e = threadIdx.x + q * 256 = k P + p
@@ -142,7 +167,7 @@ __global__ void __launch_bounds__(256) time_inv_sk(Geo g, const cx<T>* __restric
       auto ld = [&](int j, int p) { return src[j * P + p]; };
       if (st + 1 < plan.nrad) {
         auto sto = [&](int j, int p, cx<T> val) { dst[j * P + p] = val; };
-        sk_stage_rt<T, P, 1>(plan.rad[st], n, Ns, twn, ld, sto);
+        sk_stage_rt<T, P, 1>(plan.rad[st], n, Ns, tw_l, ld, sto);
         __syncthreads();
         cx<T>* t = src;
         src = dst;
@@ -150,9 +175,20 @@ __global__ void __launch_bounds__(256) time_inv_sk(Geo g, const cx<T>* __restric
       } else {
         auto sto = [&](int j, int p, cx<T> val) {
           const int i = i0 + p;
-          if (i < m) combine_store(w1, w2, dpow, n, m, j, i, (double)val.x, (double)val.y, accum);
+          if (i < m) {
+            // z_2 = Re(e) / (n d_j), z_1 = Im(e) d_j / n; w_1 = z_1 - z_2, w_2 = z_1 + z_2
+            const double z2 = (double)val.x * di_l[j], z1 = (double)val.y * dn_l[j];
+            const size_t o = (size_t)j * m + i;
+            if (ACC) {
+              w1[o] += z1 - z2;
+              w2[o] += z1 + z2;
+            } else {
+              w1[o] = z1 - z2;
+              w2[o] = z1 + z2;
+            }
+          }
         };
-        sk_stage_rt<T, P, 1>(plan.rad[st], n, Ns, twn, ld, sto);
+        sk_stage_rt<T, P, 1>(plan.rad[st], n, Ns, tw_l, ld, sto);
       }
       Ns *= plan.rad[st];
     }
@@ -171,7 +207,7 @@ constexpr int sk_q_inv() { return sizeof(T) == 8 ? 5 : 9; }
 template <class T>
 void launch_time_sk(bool fwd, int P, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
                     const cx<T>* twn, const double* vscale, int vs_stride, int accum, hipStream_t st) {
-  const size_t lds = (size_t)2 * g.n * P * sizeof(cx<T>);
+  const size_t lds = sk_lds_bytes(g.n, P, sizeof(cx<T>));
   TileWalk tw{(g.m + P - 1) / P, 0, tb.active};
   tw.ntiles = tw.tpm * g.B;
   // persistent grid: as many blocks as stay resident on every CU
@@ -181,9 +217,9 @@ void launch_time_sk(bool fwd, int P, const Geo& g, const double* v, cx<T>* spec,
     const int grid = std::min(tw.ntiles, resident_blocks(kern, 256, lds) * std::max(1, tb.ncu));              \
     kern<<<grid, 256, lds, st>>>(g, v, spec, tb.dpow, twn, tb.plan, vscale, vs_stride, tw);                    \
   } else {                                                                                                    \
-    auto kern = time_inv_sk<T, PP, sk_q_inv<T>()>;                                                            \
+    auto kern = accum ? time_inv_sk<T, PP, sk_q_inv<T>(), 1> : time_inv_sk<T, PP, sk_q_inv<T>(), 0>;          \
     const int grid = std::min(tw.ntiles, resident_blocks(kern, 256, lds) * std::max(1, tb.ncu));              \
-    kern<<<grid, 256, lds, st>>>(g, spec, w, tb.dpow, twn, tb.plan, accum, tw);                               \
+    kern<<<grid, 256, lds, st>>>(g, spec, w, tb.dpow, twn, tb.plan, tw);                                      \
   }
   if (P == 16) {
     PCOP_TIME_SK(16)
