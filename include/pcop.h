@@ -118,10 +118,12 @@ typedef struct {
  *   dst_kernel sine-transform kernels of step 2 (PCOP_DST): 0 automatic,
  *              1 register-resident lines, 2 lines staged through LDS.
  *   tune       1: pcop_setup times every candidate left at 0 ("automatic")
- *              above on the context's stream and keeps the fastest; the
- *              choice is cached per device and shape for the process.
- *              0: built-in choices.  All choices give the same iterates up
- *              to rounding.
+ *              above, the KKT matvec's time levels per thread and the
+ *              Krylov reductions' blocks per member on the context's stream
+ *              and keeps the fastest; the choice is cached per device and
+ *              shape for the process.  0: built-in choices.  All choices give
+ *              the same iterates up to rounding (the reduction order follows
+ *              the block count).
  *   precond    PCOP_PRECOND_EPS: the epsilon-circulant RBD preconditioner
  *              P_eps (Section 2.1; all time levels at once);
  *              PCOP_PRECOND_IDEAL: the ideal RBD preconditioner P of
@@ -240,13 +242,22 @@ pcop_status pcop_error_eh(pcop_ctx ctx, const double* x, const double* yN, const
 /* Host copy of a few derived scalars: tau, alpha[batch], eps. */
 pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* eps);
 
-/* Kernel choices in effect (after tuning): time_cols -P (two LDS buffers,
- * P points per block), +P (in place) or 0 (chirp-z, or no time transform
- * with PCOP_PRECOND_IDEAL); dst_kernel 1
- * (register-resident), 2 (LDS-staged) or 0 (multigrid).  tuned_ms: the
- * fastest preconditioner apply measured by the tuner, 0 when no tuning ran.
- * Any output may be NULL. */
-pcop_status pcop_get_kernels(pcop_ctx ctx, int* time_cols, int* dst_kernel, double* tuned_ms);
+/* Kernel choices in effect (after tuning):
+ *   time_cols      -P (two LDS buffers, P points per block), +P (in place)
+ *                  or 0 (chirp-z, or no time transform with PCOP_PRECOND_IDEAL);
+ *   dst_kernel     1 (register-resident), 2 (LDS-staged) or 0 (multigrid);
+ *   kkt_jchunk     time levels per thread of the KKT matvec;
+ *   krylov_blocks  blocks per member of the Krylov reductions;
+ *   tuned_precond_ms  the fastest preconditioner apply measured by the
+ *                  tuner, 0 when no tuning ran. */
+typedef struct {
+  int time_cols;
+  int dst_kernel;
+  int kkt_jchunk;
+  int krylov_blocks;
+  double tuned_precond_ms;
+} pcop_kernel_choice;
+pcop_status pcop_get_kernels(pcop_ctx ctx, pcop_kernel_choice* out);
 
 /* Per-kernel timing.  While enabled, every kernel the context launches is
  * bracketed by HIP events on the context's stream; pcop_timing_read

@@ -66,8 +66,8 @@ __global__ void __launch_bounds__(256) kkt_apply_kernel(
 
 void launch_kkt_apply(const Geo& g, const double* x, double* y, const double* c, const double* alpha,
                       const double* xscale, int xs_stride, const int* active, bool transpose,
-                      const double* ecoef, double ediag, double eoff, hipStream_t st) {
-  const int jchunk = 16;
+                      const double* ecoef, double ediag, double eoff, int jchunk, hipStream_t st) {
+  if (jchunk < 1) jchunk = 16;
   dim3 grid((g.m + 255) / 256, (g.n + jchunk - 1) / jchunk, g.B);
   const double sgn = transpose ? -1.0 : 1.0;
   if (g.dim == 2) {

@@ -80,7 +80,7 @@ struct PrecondTables {
 
 void launch_kkt_apply(const Geo& g, const double* x, double* y, const double* c, const double* alpha,
                       const double* xscale, int xs_stride, const int* active, bool transpose,
-                      const double* ecoef, double ediag, double eoff, hipStream_t st);
+                      const double* ecoef, double ediag, double eoff, int jchunk, hipStream_t st);
 void launch_flip(const Geo& g, const double* src, double* dst, hipStream_t st);
 void launch_rhs(const Geo& g, const double* gg, const double* ff, const double* y0, const double* sg,
                 double* b, hipStream_t st);

@@ -116,7 +116,8 @@ struct Layout {
   size_t mgcoef[12], mgz[12], mgr[12];
   int mg_levels = 0;
   int mg_nx[12];
-  int nblk = 1;
+  int nblk = 1;      // default blocks per member of the Krylov reductions
+  int nblk_max = 1;  // the most the partial-sum buffer holds (tuner candidates)
   long long vl = 0;
 };
 
@@ -135,6 +136,7 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
   const size_t csz = fp32 ? 8 : 16;
   L.vl = 2LL * n * m;
   L.nblk = krylov_blocks(L.vl);
+  L.nblk_max = std::min(4 * L.nblk, 4096);
   L.dpow = take(L, sizeof(double) * n);
   L.unit = take(L, 2 * sizeof(double));
   L.zero = take(L, sizeof(double) * B);
@@ -161,7 +163,7 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
   L.H = take(L, sizeof(double) * B * (kMaxBasis - 1) * kMaxBasis);
   L.coef = take(L, sizeof(double) * B * kMaxBasis);
   L.red = take(L, sizeof(double) * B * kRedStride);
-  L.partial = take(L, sizeof(double) * B * (size_t)L.nblk * kRedStride);
+  L.partial = take(L, sizeof(double) * B * (size_t)L.nblk_max * kRedStride);
   L.wnorm2 = take(L, sizeof(double) * B);
   L.norm = take(L, sizeof(double) * B);
   L.skip = take(L, sizeof(int) * B);
@@ -290,6 +292,8 @@ struct pcop_ctx_s {
   const double* ecoef = nullptr;
   bool fp32 = false;
   double tuned_ms = 0;
+  int kkt_jchunk = 16;  // time levels per thread of the matvec
+  int nblk = 1;         // blocks per member of the Krylov reductions
   EventTimer timer;
   KTimer ktimer{&EventTimer::on_begin, &EventTimer::on_end, nullptr};
   // pinned host staging for every scalar transfer of the solver
@@ -348,19 +352,19 @@ void do_kkt(pcop_ctx c, const double* x, double* y, const double* cvec, const do
             const int* mask, int nact) {
   tbeg(c->kt(), KF_KKT, (cvec ? 24.0 : 16.0) * c->g.vl * nact);
   launch_kkt_apply(c->g, x, y, cvec, c->at<double>(c->L.alpha), xscale, xs_stride, mask, false, c->ecoef,
-                   c->ediag, c->eoff, c->st);
+                   c->ediag, c->eoff, c->kkt_jchunk, c->st);
   tend(c->kt());
 }
 
 void do_mdot(pcop_ctx c, const KrylovArgs& ka, int nv, const double* w, int nact) {
   tbeg(c->kt(), KF_MDOT, 8.0 * (nv + 1) * c->g.vl * nact);
-  launch_mdot(ka, nv, w, c->at<double>(c->L.partial), c->L.nblk, c->st);
+  launch_mdot(ka, nv, w, c->at<double>(c->L.partial), c->nblk, c->st);
   tend(c->kt());
 }
 
 void do_update(pcop_ctx c, const KrylovArgs& ka, int nv, double* w, const int* skip, int nact) {
   tbeg(c->kt(), KF_UPDATE, 8.0 * (nv + 2) * c->g.vl * nact);
-  launch_update(ka, nv, w, c->at<double>(c->L.coef), kMaxBasis, c->at<double>(c->L.partial), c->L.nblk, skip,
+  launch_update(ka, nv, w, c->at<double>(c->L.coef), kMaxBasis, c->at<double>(c->L.partial), c->nblk, skip,
                 c->st);
   tend(c->kt());
 }
@@ -369,7 +373,7 @@ void do_update(pcop_ctx c, const KrylovArgs& ka, int nv, double* w, const int* s
 void do_norm2(pcop_ctx c, const double* w, const int* mask, int nact) {
   KrylovArgs ka = c->kargs(c->basis(0), mask);
   do_mdot(c, ka, 0, w, nact);
-  launch_reduce_partials(c->at<double>(c->L.partial), c->L.nblk, 1, c->g.B, c->at<double>(c->L.red), c->st);
+  launch_reduce_partials(c->at<double>(c->L.partial), c->nblk, 1, c->g.B, c->at<double>(c->L.red), c->st);
 }
 
 // ---------------------------------------------------------------------------
@@ -380,7 +384,8 @@ void do_norm2(pcop_ctx c, const double* w, const int* mask, int nact) {
 // ---------------------------------------------------------------------------
 struct TuneResult {
   int time_cols, dst_variant;
-  double ms;
+  double ms;  // fastest preconditioner apply
+  int jchunk, nblk;
 };
 std::mutex g_tune_mu;
 std::map<std::array<int, 11>, TuneResult> g_tune_cache;
@@ -398,6 +403,8 @@ pcop_status tune_kernels(pcop_ctx c) {
       c->tb.time_cols = it->second.time_cols;
       c->tb.dst_variant = it->second.dst_variant;
       c->tuned_ms = it->second.ms;
+      c->kkt_jchunk = it->second.jchunk;
+      c->nblk = it->second.nblk;
       return PCOP_OK;
     }
   }
@@ -430,8 +437,21 @@ pcop_status tune_kernels(pcop_ctx c) {
     return fail(PCOP_ERR_DEVICE, "tuner: event creation failed");
   }
   constexpr int kReps = 3;
-  TuneResult best{c->tb.time_cols, c->tb.dst_variant, 1e300};
+  TuneResult best{c->tb.time_cols, c->tb.dst_variant, 1e300, c->kkt_jchunk, c->nblk};
   hipError_t err = hipSuccess;
+  // average milliseconds of kReps runs of f after one warm-up run
+  auto time_it = [&](auto&& f, double& ms_out) -> bool {
+    f();
+    if ((err = hipEventRecord(e0, st)) != hipSuccess) return false;
+    for (int r = 0; r < kReps; ++r) f();
+    if ((err = hipEventRecord(e1, st)) != hipSuccess) return false;
+    if ((err = hipEventSynchronize(e1)) != hipSuccess) return false;
+    float ms = 0.f;
+    if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return false;
+    ms_out = ms / (double)kReps;
+    return true;
+  };
+  // preconditioner kernels
   for (int tc : tcs) {
     for (int dv : dvs) {
       PrecondTables t = c->tb;
@@ -441,15 +461,58 @@ pcop_status tune_kernels(pcop_ctx c) {
       t.nact = g.B;
       t.timer = nullptr;
       if (!run_precond(c, t, v, w, nullptr, 0, 0)) continue;
-      if ((err = hipEventRecord(e0, st)) != hipSuccess) break;
-      for (int r = 0; r < kReps; ++r) run_precond(c, t, v, w, nullptr, 0, 0);
-      if ((err = hipEventRecord(e1, st)) != hipSuccess) break;
-      if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
-      float ms = 0.f;
-      if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-      if (ms / kReps < best.ms) best = TuneResult{tc, dv, ms / (double)kReps};
+      double ms = 0;
+      if (!time_it([&] { run_precond(c, t, v, w, nullptr, 0, 0); }, ms)) break;
+      if (ms < best.ms) {
+        best.time_cols = tc;
+        best.dst_variant = dv;
+        best.ms = ms;
+      }
     }
     if (err != hipSuccess) break;
+  }
+  // matvec: time levels per thread
+  double best_kkt = 1e300;
+  for (int jc : {4, 8, 16, 32}) {
+    if (err != hipSuccess) break;
+    double ms = 0;
+    if (!time_it([&] {
+          launch_kkt_apply(g, v, w, nullptr, c->at<double>(c->L.alpha), nullptr, 0, nullptr, false, c->ecoef,
+                           c->ediag, c->eoff, jc, st);
+        }, ms))
+      break;
+    if (ms < best_kkt) {
+      best_kkt = ms;
+      best.jchunk = jc;
+    }
+  }
+  // Krylov reductions: blocks per member, timed on a multi-dot and an update
+  // over nv basis vectors (zeroed first: the coefficients and skip flags too)
+  const int nv = std::min(10, c->opt.restart);
+  if (err == hipSuccess)
+    err = hipMemsetAsync(c->basis(0), 0, sizeof(double) * (size_t)g.vl * g.B * (nv + 1), st);
+  if (err == hipSuccess) err = hipMemsetAsync(c->at<double>(c->L.coef), 0, sizeof(double) * g.B * kMaxBasis, st);
+  if (err == hipSuccess) err = hipMemsetAsync(c->at<int>(c->L.skip), 0, sizeof(int) * g.B, st);
+  double best_kr = 1e300;
+  std::vector<int> tried;
+  for (int f : {1, 2, 4, 8}) {
+    if (err != hipSuccess) break;
+    const int nb = std::max(1, c->L.nblk * f / 2);  // half .. four times the default
+    if (nb > c->L.nblk_max || std::find(tried.begin(), tried.end(), nb) != tried.end()) continue;
+    tried.push_back(nb);
+    KrylovArgs ka = c->kargs(c->basis(0), nullptr);
+    double* wv = c->basis(nv);
+    double* part = c->at<double>(c->L.partial);
+    double ms = 0;
+    if (!time_it([&] {
+          launch_mdot(ka, nv, wv, part, nb, st);
+          launch_update(ka, nv, wv, c->at<double>(c->L.coef), kMaxBasis, part, nb, c->at<int>(c->L.skip), st);
+        }, ms))
+      break;
+    if (ms < best_kr) {
+      best_kr = ms;
+      best.nblk = nb;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -459,6 +522,8 @@ pcop_status tune_kernels(pcop_ctx c) {
   c->tb.time_cols = best.time_cols;
   c->tb.dst_variant = best.dst_variant;
   c->tuned_ms = best.ms;
+  c->kkt_jchunk = best.jchunk;
+  c->nblk = best.nblk;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune_cache[key] = best;
   return PCOP_OK;
@@ -787,6 +852,8 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   tb.bhat32 = c->at<float>(L.bhat32);
   tb.time_cols = opts->time_cols;
   tb.dst_variant = (opts->dst_kernel == 2) ? 1 : 0;
+  c->nblk = L.nblk;
+  c->kkt_jchunk = 16;
   {
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -837,11 +904,13 @@ pcop_status pcop_get_params(pcop_ctx c, double* tau, double* alpha, double* eps)
   return PCOP_OK;
 }
 
-pcop_status pcop_get_kernels(pcop_ctx c, int* time_cols, int* dst_kernel, double* tuned_ms) {
-  if (!c) return fail(PCOP_ERR_INVALID_ARG, "null context");
-  if (time_cols) *time_cols = (c->opt.precond == PCOP_PRECOND_EPS) ? time_choice(c->g, c->tb, c->fp32) : 0;
-  if (dst_kernel) *dst_kernel = (c->opt.spatial == PCOP_DST) ? c->tb.dst_variant + 1 : 0;
-  if (tuned_ms) *tuned_ms = c->tuned_ms;
+pcop_status pcop_get_kernels(pcop_ctx c, pcop_kernel_choice* out) {
+  if (!c || !out) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  out->time_cols = (c->opt.precond == PCOP_PRECOND_EPS) ? time_choice(c->g, c->tb, c->fp32) : 0;
+  out->dst_kernel = (c->opt.spatial == PCOP_DST) ? c->tb.dst_variant + 1 : 0;
+  out->kkt_jchunk = c->kkt_jchunk;
+  out->krylov_blocks = c->nblk;
+  out->tuned_precond_ms = c->tuned_ms;
   return PCOP_OK;
 }
 
@@ -930,7 +999,7 @@ pcop_status pcop_kkt_apply(pcop_ctx c, const double* x, double* y, int transpose
   if (x == y) return fail(PCOP_ERR_INVALID_ARG, "x and y must not overlap");
   tbeg(c->kt(), KF_KKT, 16.0 * c->g.vl * c->g.B);
   launch_kkt_apply(c->g, x, y, nullptr, c->at<double>(c->L.alpha), nullptr, 0, nullptr, transpose != 0, c->ecoef,
-                   c->ediag, c->eoff, c->st);
+                   c->ediag, c->eoff, c->kkt_jchunk, c->st);
   tend(c->kt());
   PCOP_HIP(hipGetLastError());
   return PCOP_OK;
@@ -1030,7 +1099,7 @@ pcop_status enqueue_iteration(pcop_ctx c, int j, bool full, int n_active, hipStr
   double* wnorm2 = c->at<double>(L.wnorm2);
   int* skip = c->at<int>(L.skip);
   int* active = c->at<int>(L.active);
-  const int nblk = L.nblk;
+  const int nblk = c->nblk;
   const int H_ld = kMaxBasis;
   double* vj = c->basis(j);
   double* w = c->basis(j + 1);
@@ -1159,7 +1228,7 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
   int* skip = c->at<int>(L.skip);
   int* active = c->at<int>(L.active);
   int* finish = c->at<int>(L.finish);
-  const int nblk = L.nblk;
+  const int nblk = c->nblk;
   const int H_ld = kMaxBasis;
 
   // A^T = J A J: solve A z = J b and return x = J z

@@ -63,6 +63,11 @@ class c_kernel_stat(ctypes.Structure):
                 ("bytes", ctypes.c_double)]
 
 
+class c_kernel_choice(ctypes.Structure):
+    _fields_ = [("time_cols", ctypes.c_int), ("dst_kernel", ctypes.c_int), ("kkt_jchunk", ctypes.c_int),
+                ("krylov_blocks", ctypes.c_int), ("tuned_precond_ms", ctypes.c_double)]
+
+
 class c_member_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("relres_est", ctypes.c_double),
                 ("relres_true", ctypes.c_double)]
@@ -94,7 +99,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "pcop_pack_cotangent": (ip, [vp, vp, vp, vp]),
         "pcop_data_grad": (ip, [vp, vp, vp, vp, vp]),
         "pcop_get_params": (ip, [vp, dp, dp, dp]),
-        "pcop_get_kernels": (ip, [vp, ctypes.POINTER(ip), ctypes.POINTER(ip), dp]),
+        "pcop_get_kernels": (ip, [vp, ctypes.POINTER(c_kernel_choice)]),
         "pcop_post_solve": (ip, [vp, vp, vp, vp, vp, vp, vp, dp]),
         "pcop_error_eh": (ip, [vp, vp, vp, vp, vp, vp, dp]),
         "pcop_destroy": (None, [vp]),
@@ -213,11 +218,12 @@ class Solver:
         _check(self.lib.pcop_get_params(ctx, ctypes.byref(tau), alpha, ctypes.byref(eps_out)))
         self.tau, self.eps, self.alpha = tau.value, eps_out.value, list(alpha)
         self.gamma = gam
-        tc, dk, tms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
-        _check(self.lib.pcop_get_kernels(ctx, ctypes.byref(tc), ctypes.byref(dk), ctypes.byref(tms)))
+        kc = c_kernel_choice()
+        _check(self.lib.pcop_get_kernels(ctx, ctypes.byref(kc)))
         # kernel choices in effect: time_cols -P two-buffer / +P in place / 0 chirp-z;
         # dst_kernel 1 register / 2 LDS-staged / 0 multigrid
-        self.kernels = {"time_cols": tc.value, "dst_kernel": dk.value, "tuned_ms": tms.value}
+        self.kernels = {"time_cols": kc.time_cols, "dst_kernel": kc.dst_kernel, "kkt_jchunk": kc.kkt_jchunk,
+                        "krylov_blocks": kc.krylov_blocks, "tuned_ms": kc.tuned_precond_ms}
 
     # ------------------------------------------------------------------
     def __del__(self):
