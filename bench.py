@@ -37,12 +37,14 @@ PRECOND_FAMILIES = ("time_fwd", "dst_rows", "dst_ax2", "dst_last_solve", "time_i
 
 # kernel sources behind each timed family (to tell whether recorded counters
 # still describe the code that runs)
+_TIME_SOURCES = ["precond.hip", "time_common.hpp", "time_sk.hip", "time_ip.hpp", "time_ip_fwd_f64.hip",
+                 "time_ip_inv_f64.hip", "time_ip_fwd_f32.hip", "time_ip_inv_f32.hip", "time_bl.hip", "fft_lds.hpp"]
 FAMILY_SOURCES = {
-    "gs_update": ["krylov.hip"], "mdot": ["krylov.hip"], "combine": ["krylov.hip"], "kkt_apply": ["kkt.hip"],
-    "time_fwd": ["precond.hip", "fft_lds.hpp"], "time_inv": ["precond.hip", "fft_lds.hpp"],
-    "dst_rows": ["precond.hip", "fft_lds.hpp"], "dst_last_solve": ["precond.hip", "fft_lds.hpp"],
-    "dst_ax2": ["precond.hip", "fft_lds.hpp"], "mg_smooth": ["multigrid.hip"], "mg_restrict": ["multigrid.hip"],
-    "mg_prolong": ["multigrid.hip"],
+    "gs_update": ["krylov.hip"], "mdot": ["krylov.hip"], "combine": ["krylov.hip"],
+    "kkt_apply": ["kkt.hip", "stencil.hpp"], "time_fwd": _TIME_SOURCES, "time_inv": _TIME_SOURCES,
+    "dst_rows": ["dst.hip", "fft_lds.hpp"], "dst_last_solve": ["dst.hip", "fft_lds.hpp"],
+    "dst_ax2": ["dst.hip", "fft_lds.hpp"], "mg_smooth": ["multigrid.hip"], "mg_restrict": ["multigrid.hip"],
+    "mg_prolong": ["multigrid.hip"], "ideal_step": ["ideal.hip"],
 }
 
 
@@ -86,6 +88,8 @@ def parse():
                     help="time-pass kernels: 0 automatic, -P two LDS buffers, +P in place (P points per block)")
     ap.add_argument("--dst-kernel", type=int, default=0, choices=[0, 1, 2],
                     help="sine-transform kernels: 0 automatic, 1 register-resident, 2 LDS-staged")
+    ap.add_argument("--kkt-jchunk", type=int, default=0, help="KKT matvec time levels per thread (0 automatic)")
+    ap.add_argument("--krylov-blocks", type=int, default=0, help="Krylov reduction blocks per member (0 automatic)")
     ap.add_argument("--precond", choices=["eps", "ideal"], default="eps",
                     help="eps: the epsilon-circulant preconditioner; ideal: P of eq. matrix_P (sequential in time)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -228,7 +232,8 @@ def main():
     s = Solver(cfg.dim, cfg.nx, cfg.nt, list(cfg.gammas), T=cfg.T, eps=cfg.eps,
                coeff=None if cfg.coeff == "one" else W.coeff_function(cfg.coeff),
                restart=30, maxit=300, rtol=1e-8, device=dev, stream=stream, tune=bool(args.tune),
-               time_cols=args.time_cols, dst_kernel=args.dst_kernel, precond=args.precond, **opts)
+               time_cols=args.time_cols, dst_kernel=args.dst_kernel, precond=args.precond,
+               kkt_jchunk=args.kkt_jchunk, krylov_blocks=args.krylov_blocks, **opts)
     print(f"# bench: kernels {s.kernels}", file=sys.stderr, flush=True)
     tg = torch.tensor(g, device=dev)
     tf = torch.tensor(f, device=dev)

@@ -117,10 +117,9 @@ typedef struct {
  *              (chirp-z kernels).
  *   dst_kernel sine-transform kernels of step 2 (PCOP_DST): 0 automatic,
  *              1 register-resident lines, 2 lines staged through LDS.
- *   tune       1: pcop_setup times every candidate left at 0 ("automatic")
- *              above, the KKT matvec's time levels per thread and the
- *              Krylov reductions' blocks per member on the context's stream
- *              and keeps the fastest; the choice is cached per device and
+ *   tune       1: pcop_setup times the candidates of every kernel choice
+ *              left at 0 ("automatic": time_cols, dst_kernel, kkt_jchunk,
+ *              krylov_blocks) on the context's stream and keeps the fastest; the choice is cached per device and
  *              shape for the process.  0: built-in choices.  All choices give
  *              the same iterates up to rounding (the reduction order follows
  *              the block count).
@@ -130,6 +129,11 @@ typedef struct {
  *              eq. matrix_P, applied by sequential substitution in time
  *              (n dependent spatial solves with (1 + alpha) I + tau K; the
  *              comparison method of Tables 4 and 8).  time_cols is ignored.
+ *   kkt_jchunk time levels per thread of the KKT matvec: 0 automatic (16, or
+ *              the tuner's choice), else 1..64.
+ *   krylov_blocks  blocks per member of the Krylov reductions: 0 automatic,
+ *              else 1..4096 (the reduction order, and so the rounding,
+ *              follows it).
  *   stream     hipStream_t on which all work is enqueued. */
 typedef struct {
   int precision;
@@ -145,6 +149,8 @@ typedef struct {
   int dst_kernel;
   int tune;
   int precond;
+  int kkt_jchunk;
+  int krylov_blocks;
   void* stream;
 } pcop_options;
 

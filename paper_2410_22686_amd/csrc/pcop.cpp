@@ -85,6 +85,9 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
   if (o->tune != 0 && o->tune != 1) return fail(PCOP_ERR_INVALID_ARG, "tune must be 0 or 1");
   if (o->precond != PCOP_PRECOND_EPS && o->precond != PCOP_PRECOND_IDEAL)
     return fail(PCOP_ERR_INVALID_ARG, "unknown precond");
+  if (o->kkt_jchunk < 0 || o->kkt_jchunk > 64) return fail(PCOP_ERR_INVALID_ARG, "kkt_jchunk must be in 0..64");
+  if (o->krylov_blocks < 0 || o->krylov_blocks > 4096)
+    return fail(PCOP_ERR_INVALID_ARG, "krylov_blocks must be in 0..4096");
   if (o->precision == PCOP_MIXED && o->side != PCOP_FLEXIBLE)
     return fail(PCOP_ERR_INVALID_ARG, "the mixed-precision preconditioner needs side = PCOP_FLEXIBLE");
   if (o->spatial == PCOP_DST) {
@@ -136,7 +139,7 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
   const size_t csz = fp32 ? 8 : 16;
   L.vl = 2LL * n * m;
   L.nblk = krylov_blocks(L.vl);
-  L.nblk_max = std::min(4 * L.nblk, 4096);
+  L.nblk_max = std::max(std::min(4 * L.nblk, 4096), o->krylov_blocks);
   L.dpow = take(L, sizeof(double) * n);
   L.unit = take(L, 2 * sizeof(double));
   L.zero = take(L, sizeof(double) * B);
@@ -388,14 +391,15 @@ struct TuneResult {
   int jchunk, nblk;
 };
 std::mutex g_tune_mu;
-std::map<std::array<int, 11>, TuneResult> g_tune_cache;
+std::map<std::array<int, 13>, TuneResult> g_tune_cache;
 
 pcop_status tune_kernels(pcop_ctx c) {
   const Geo& g = c->g;
   int dev = 0;
   PCOP_HIP(hipGetDevice(&dev));
-  const std::array<int, 11> key{dev, g.dim, g.nx, g.n, g.B, (int)c->fp32, c->opt.spatial, c->opt.time_cols,
-                                c->opt.dst_kernel, c->coeff_kind, c->opt.precond};
+  const std::array<int, 13> key{dev, g.dim, g.nx, g.n, g.B, (int)c->fp32, c->opt.spatial, c->opt.time_cols,
+                                c->opt.dst_kernel, c->coeff_kind, c->opt.precond, c->opt.kkt_jchunk,
+                                c->opt.krylov_blocks};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -474,7 +478,7 @@ pcop_status tune_kernels(pcop_ctx c) {
   // matvec: time levels per thread
   double best_kkt = 1e300;
   for (int jc : {4, 8, 16, 32}) {
-    if (err != hipSuccess) break;
+    if (err != hipSuccess || c->opt.kkt_jchunk != 0) break;
     double ms = 0;
     if (!time_it([&] {
           launch_kkt_apply(g, v, w, nullptr, c->at<double>(c->L.alpha), nullptr, 0, nullptr, false, c->ecoef,
@@ -496,7 +500,7 @@ pcop_status tune_kernels(pcop_ctx c) {
   double best_kr = 1e300;
   std::vector<int> tried;
   for (int f : {1, 2, 4, 8}) {
-    if (err != hipSuccess) break;
+    if (err != hipSuccess || c->opt.krylov_blocks != 0) break;
     const int nb = std::max(1, c->L.nblk * f / 2);  // half .. four times the default
     if (nb > c->L.nblk_max || std::find(tried.begin(), tried.end(), nb) != tried.end()) continue;
     tried.push_back(nb);
@@ -852,8 +856,8 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   tb.bhat32 = c->at<float>(L.bhat32);
   tb.time_cols = opts->time_cols;
   tb.dst_variant = (opts->dst_kernel == 2) ? 1 : 0;
-  c->nblk = L.nblk;
-  c->kkt_jchunk = 16;
+  c->nblk = opts->krylov_blocks > 0 ? opts->krylov_blocks : L.nblk;
+  c->kkt_jchunk = opts->kkt_jchunk > 0 ? opts->kkt_jchunk : 16;
   {
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||

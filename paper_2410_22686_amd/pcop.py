@@ -55,7 +55,8 @@ class c_options(ctypes.Structure):
                 ("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("graph", ctypes.c_int), ("graph_chunk", ctypes.c_int), ("reorth_tol", ctypes.c_double),
                 ("time_cols", ctypes.c_int), ("dst_kernel", ctypes.c_int), ("tune", ctypes.c_int),
-                ("precond", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("precond", ctypes.c_int), ("kkt_jchunk", ctypes.c_int), ("krylov_blocks", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
 
 
 class c_kernel_stat(ctypes.Structure):
@@ -167,6 +168,7 @@ class Solver:
                  spatial: str = "dst", side: str = "right", restart: int = 30, maxit: int = 300,
                  rtol: float = 1e-8, graph: bool = False, graph_chunk: int = 4, reorth_tol: float = 1e-8,
                  time_cols: int = 0, dst_kernel: int = 0, tune: bool = False, precond: str = "eps",
+                 kkt_jchunk: int = 0, krylov_blocks: int = 0,
                  device: Union[str, torch.device] = "cuda", stream: Optional[torch.cuda.Stream] = None):
         import numpy as np
         self.lib = load_library()
@@ -196,6 +198,7 @@ class Solver:
         opts.graph, opts.graph_chunk, opts.reorth_tol = int(bool(graph)), int(graph_chunk), float(reorth_tol)
         opts.time_cols, opts.dst_kernel, opts.tune = int(time_cols), int(dst_kernel), int(bool(tune))
         opts.precond = _PRECOND[precond]
+        opts.kkt_jchunk, opts.krylov_blocks = int(kkt_jchunk), int(krylov_blocks)
         self.stream = stream
         with torch.cuda.device(self.device):
             st = stream if stream is not None else torch.cuda.current_stream(self.device)
