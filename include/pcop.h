@@ -116,7 +116,9 @@ typedef struct {
  *              the other.  Ignored when nt - 1 has a prime factor above 17
  *              (chirp-z kernels).
  *   dst_kernel sine-transform kernels of step 2 (PCOP_DST): 0 automatic,
- *              1 register-resident lines, 2 lines staged through LDS.
+ *              1 register-resident lines, 2 lines staged through LDS,
+ *              3 register-resident lines with twice as many strided lines
+ *              per block (512 threads).
  *   tune       1: pcop_setup times the candidates of every kernel choice
  *              left at 0 ("automatic": time_cols, dst_kernel, kkt_jchunk,
  *              krylov_blocks) on the context's stream and keeps the fastest; the choice is cached per device and
@@ -251,7 +253,8 @@ pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* ep
 /* Kernel choices in effect (after tuning):
  *   time_cols      -P (two LDS buffers, P points per block), +P (in place)
  *                  or 0 (chirp-z, or no time transform with PCOP_PRECOND_IDEAL);
- *   dst_kernel     1 (register-resident), 2 (LDS-staged) or 0 (multigrid);
+ *   dst_kernel     1 (register-resident), 2 (LDS-staged), 3 (register, wide
+ *                  column tiles) or 0 (multigrid);
  *   kkt_jchunk     time levels per thread of the KKT matvec;
  *   krylov_blocks  blocks per member of the Krylov reductions;
  *   tuned_precond_ms  the fastest preconditioner apply measured by the

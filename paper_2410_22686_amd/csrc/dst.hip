@@ -295,23 +295,23 @@ __global__ void __launch_bounds__(256) dst_reg_kernel(Geo g, cx<T>* __restrict__
 // LPB lines x N elements is staged through LDS with coalesced accesses.
 // Persistent blocks walk tiles blk, blk + grid, ... and fetch the next tile
 // into registers while the current one is transformed.
-template <class T, int L, int DIVIDE_>
-__global__ void __launch_bounds__(256) dst_col_kernel(Geo g, cx<T>* __restrict__ data, LineGeom lg,
+template <class T, int L, int DIVIDE_, int NT>
+__global__ void __launch_bounds__(NT) dst_col_kernel(Geo g, cx<T>* __restrict__ data, LineGeom lg,
                                                       const cx<T>* __restrict__ twL, DivideParams dp) {
   constexpr bool DIVIDE = DIVIDE_ != 0;
   constexpr int N = L / 2 - 1;
   constexpr int TL = L / 8;
-  constexpr int LPB = 256 / TL;
+  constexpr int LPB = NT / TL;
   constexpr int LD = L + L / 8 + 1;
-  constexpr int QS = (N * LPB + 255) / 256;  // tile elements per thread
+  constexpr int QS = (N * LPB + NT - 1) / NT;  // tile elements per thread
   __shared__ cx<T> buf[LPB * LD];
   // twiddles and 1-D eigenvalues in LDS: inside the loop the only global
   // loads are the prefetch (loads retire in order)
   __shared__ cx<T> twl[L];
   __shared__ double mul[DIVIDE ? N : 1];
-  for (int k = threadIdx.x; k < L; k += 256) twl[k] = twL[k];
+  for (int k = threadIdx.x; k < L; k += NT) twl[k] = twL[k];
   if (DIVIDE)
-    for (int k = threadIdx.x; k < N; k += 256) mul[k] = dp.mu1[k];
+    for (int k = threadIdx.x; k < N; k += NT) mul[k] = dp.mu1[k];
   __syncthreads();
   DivideParams dl = dp;
   dl.mu1 = mul;
@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(256) dst_col_kernel(Geo g, cx<T>* __restrict__
     const long long pbase = plane * lg.plane_stride;
 #pragma unroll
     for (int q = 0; q < QS; ++q) {
-      const int idx = threadIdx.x + 256 * q;
+      const int idx = threadIdx.x + NT * q;
       const int e = idx / LPB, l = idx - (idx / LPB) * LPB;
       const bool ok = idx < N * LPB && l0 + l < lg.lines;
       pre[q] = ok ? data[pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride]
@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(256) dst_col_kernel(Geo g, cx<T>* __restrict__
     const bool valid = line < lg.lines;
 #pragma unroll
     for (int q = 0; q < QS; ++q) {
-      const int idx = threadIdx.x + 256 * q;
+      const int idx = threadIdx.x + NT * q;
       if (idx < N * LPB) {
         const int e = idx / LPB, l = idx - (idx / LPB) * LPB;
         buf[l * LD + pidx(e)] = pre[q];
@@ -388,7 +388,7 @@ __global__ void __launch_bounds__(256) dst_col_kernel(Geo g, cx<T>* __restrict__
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < QS; ++q) {
-      const int idx = threadIdx.x + 256 * q;
+      const int idx = threadIdx.x + NT * q;
       const int e = idx / LPB, l = idx - (idx / LPB) * LPB;
       if (idx < N * LPB && l0 + l < lg.lines)
         data[pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride] = buf[l * LD + pidx(e)];
@@ -431,13 +431,28 @@ static void dst_pass_L(const Geo& g, cx<T>* data, const LineGeom& lg, bool rows,
     if (divide) dst_reg_kernel<T, L, 1><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
     else dst_reg_kernel<T, L, 0><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
   } else {
-    // persistent grid: as many blocks as stay resident on every CU
-    static const int res1 = resident_blocks(dst_col_kernel<T, L, 1>, 256, 0);
-    static const int res0 = resident_blocks(dst_col_kernel<T, L, 0>, 256, 0);
+    // persistent grid: as many blocks as stay resident on every CU.  Variant
+    // 2 doubles the lines per tile (512 threads) so that each element row of
+    // a tile spans 128 bytes instead of 64
+    if constexpr (L >= 64) {
+      if (variant == 2) {
+      constexpr int LPB2 = 512 / (L / 8);
+      const long long tiles2 = (lg.lines + LPB2 - 1) / LPB2;
+      static const int r1 = resident_blocks(dst_col_kernel<T, L, 1, 512>, 512, 0);
+      static const int r0 = resident_blocks(dst_col_kernel<T, L, 0, 512>, 512, 0);
+      const long long want = (long long)(divide ? r1 : r0) * std::max(1, ncu);
+      dim3 grid((unsigned)std::min(tiles2 * lg.nplanes, want));
+      if (divide) dst_col_kernel<T, L, 1, 512><<<grid, 512, 0, st>>>(g, data, lg, twL, dp);
+      else dst_col_kernel<T, L, 0, 512><<<grid, 512, 0, st>>>(g, data, lg, twL, dp);
+      return;
+      }
+    }
+    static const int res1 = resident_blocks(dst_col_kernel<T, L, 1, 256>, 256, 0);
+    static const int res0 = resident_blocks(dst_col_kernel<T, L, 0, 256>, 256, 0);
     const long long want = (long long)(divide ? res1 : res0) * std::max(1, ncu);
     dim3 grid((unsigned)std::min(tiles * lg.nplanes, want));
-    if (divide) dst_col_kernel<T, L, 1><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
-    else dst_col_kernel<T, L, 0><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
+    if (divide) dst_col_kernel<T, L, 1, 256><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
+    else dst_col_kernel<T, L, 0, 256><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
   }
 }
 

@@ -69,7 +69,7 @@ struct PrecondTables {
   const int* active;     // [B] or null
   int nact;              // members with active != 0 (for byte accounting)
   int ncu;               // compute units of the device (persistent grids)
-  int dst_variant;       // 0: register sine-transform kernels, 1: LDS-staged kernels
+  int dst_variant;       // 0: register kernels, 1: LDS-staged kernels, 2: register, 8-line column tiles
   int time_cols;         // time-kernel request, as pcop_options::time_cols
   const KTimer* timer;   // or null
   FftPlan plan;          // radices of n

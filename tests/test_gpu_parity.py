@@ -149,7 +149,7 @@ def test_precond_kernel_choices(dim, nx, nt, gammas, precision):
     v = W.random_vector(dim, nx, nt, seed=17, batch=len(gammas))
     wos = [P.EpsCirculantRBD(pb).apply(v[b].ravel()) for b, pb in enumerate(problems(dim, nx, nt, gammas))]
     tol = 1e-5 if precision == "mixed" else 1e-11
-    for dk in (1, 2):
+    for dk in (1, 2, 3):
         ref = None
         for tc in (-1, -16, -8, -4, 4, 8, 16):
             s = Solver(dim, nx, nt, list(gammas), precision=precision, side=side, time_cols=tc, dst_kernel=dk,
