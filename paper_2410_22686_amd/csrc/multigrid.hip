@@ -9,8 +9,9 @@
 //             z_nb = r_nb / d_nb, recomputed on the fly, so the sweep is one
 //             pass.  d = sigma_q + tau diag(K_a).
 //   restrict  residual r - A z (zero at black points after the sweep, equal
-//             to -sum_nb off z_nb at red points), full weighting to the coarse
-//             grid (tensor product of [1/4, 1/2, 1/4]).
+//             to -sum_nb off z_nb at red points), written over the consumed
+//             right-hand side, then full weighting to the coarse grid
+//             (tensor product of [1/4, 1/2, 1/4]).
 //   coarsest  one point: z = r / d.
 //   prolong   z += P z_coarse (multilinear interpolation); the finest level
 //             writes the result into the spectrum.
@@ -99,26 +100,44 @@ __device__ __forceinline__ cx<T> red_residual(const int* f, int nx, int m, const
   return acc;
 }
 
-// coarse right-hand side by full weighting of the fine residual
+// fine residual after the sweep, written at red points only (it is zero at
+// black points); res may alias the level's right-hand side, which the sweep
+// has consumed
+template <class T, int DIM>
+__global__ void __launch_bounds__(256) mg_residual_kernel(int nx, int m, const T* __restrict__ coef,
+                                                          const cx<T>* __restrict__ z, cx<T>* res, MgShift sh) {
+  const int s = blockIdx.y;
+  if (sh.active && !sh.active[s / sh.twoK]) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  int f[3];
+  coords(i, nx, DIM, f);
+  if (((f[0] + f[1] + f[2]) & 1) != 0) return;
+  res[(size_t)s * m + i] = red_residual<T, DIM>(f, nx, m, coef, z + (size_t)s * m);
+}
+
+// coarse right-hand side by full weighting of the fine residual (red points
+// only; the black ones are zero)
 template <class T, int DIM>
 __global__ void __launch_bounds__(256) mg_restrict_kernel(int nxf, int mf, int nxc, int mc,
-                                                          const T* __restrict__ coef, const cx<T>* __restrict__ z,
-                                                          cx<T>* __restrict__ rc, MgShift sh) {
+                                                          const cx<T>* __restrict__ res, cx<T>* __restrict__ rc,
+                                                          MgShift sh) {
   const int s = blockIdx.y;
   if (sh.active && !sh.active[s / sh.twoK]) return;
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= mc) return;
   int C[3];
   coords(I, nxc, DIM, C);
-  const cx<T>* zs = z + (size_t)s * mf;
+  const cx<T>* rs = res + (size_t)s * mf;
   cx<T> acc{0, 0};
   const int o2 = (DIM == 3) ? 1 : 0;
   for (int d2 = -o2; d2 <= o2; ++d2)
     for (int d1 = -1; d1 <= 1; ++d1)
       for (int d0 = -1; d0 <= 1; ++d0) {
-        int f[3] = {2 * C[0] + 1 + d0, 2 * C[1] + 1 + d1, (DIM == 3) ? 2 * C[2] + 1 + d2 : 0};
+        const int f0 = 2 * C[0] + 1 + d0, f1 = 2 * C[1] + 1 + d1, f2 = (DIM == 3) ? 2 * C[2] + 1 + d2 : 0;
+        if (((f0 + f1 + f2) & 1) != 0) continue;
         const T w = (d0 == 0 ? (T)1 : (T)0.5) * (d1 == 0 ? (T)1 : (T)0.5) * (d2 == 0 ? (T)1 : (T)0.5);
-        acc = acc + scale(red_residual<T, DIM>(f, nxf, mf, coef, zs), w);
+        acc = acc + scale(rs[f0 + nxf * (f1 + nxf * f2)], w);
       }
   const T inv = (DIM == 3) ? (T)0.125 : (T)0.25;
   rc[(size_t)s * mc + I] = scale(acc, inv);
@@ -200,8 +219,11 @@ static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, int spm
       const int nxc = tb.mg[l + 1].nx;
       const int mc = (int)tb.mg[l + 1].m;
       dim3 gc((mc + 255) / 256, slices);
-      tbeg(tb.timer, KF_MG_RESTRICT, cs * (m + mc));
-      mg_restrict_kernel<T, DIM><<<gc, 256, 0, st>>>(nx, m, nxc, mc, coefp(l), zbuf(l), rbuf(l + 1), sh);
+      // residual into the consumed right-hand side (half the points), then
+      // full weighting
+      tbeg(tb.timer, KF_MG_RESTRICT, cs * (m + 0.5 * m + 0.5 * m + mc));
+      mg_residual_kernel<T, DIM><<<grid, 256, 0, st>>>(nx, m, coefp(l), zbuf(l), rbuf(l), sh);
+      mg_restrict_kernel<T, DIM><<<gc, 256, 0, st>>>(nx, m, nxc, mc, rbuf(l), rbuf(l + 1), sh);
       tend(tb.timer);
     }
   }
