@@ -40,14 +40,15 @@ __global__ void __launch_bounds__(256) kkt_apply_kernel(
   const double* cc1 = c ? c + mb : nullptr;
   const double* cc2 = c ? c + mb + (size_t)n * m : nullptr;
 
+  const StencilW sw = load_stencil<DIM, VAR>(i, m, ecoef, ediag, eoff);
   double x1prev = (j0 > 0) ? x1[(size_t)(j0 - 1) * m + i] : 0.0;
   double x2cur = x2[(size_t)j0 * m + i];
   for (int j = j0; j < j1; ++j) {
     const size_t o = (size_t)j * m;
     const double x1cur = x1[o + i];
     const double x2next = (j + 1 < n) ? x2[o + m + i] : 0.0;
-    const double ex2 = apply_E<DIM, VAR>(x2 + o, i, c1, c2, c3, nx, m, ecoef, ediag, eoff);
-    const double ex1 = apply_E<DIM, VAR>(x1 + o, i, c1, c2, c3, nx, m, ecoef, ediag, eoff);
+    const double ex2 = apply_E_w<DIM, VAR>(x2 + o, i, c1, c2, c3, nx, sw);
+    const double ex1 = apply_E_w<DIM, VAR>(x1 + o, i, c1, c2, c3, nx, sw);
     // block row 1: alpha x1 + T^T x2;  block row 2: -T x1 + alpha x2
     double r1 = a * x1cur + sgn * (ex2 - x2next);
     double r2 = a * x2cur - sgn * (ex1 - x1prev);

@@ -477,7 +477,7 @@ pcop_status tune_kernels(pcop_ctx c) {
   }
   // matvec: time levels per thread
   double best_kkt = 1e300;
-  for (int jc : {4, 8, 16, 32}) {
+  for (int jc : {1, 2, 4, 8, 16, 32}) {
     if (err != hipSuccess || c->opt.kkt_jchunk != 0) break;
     double ms = 0;
     if (!time_it([&] {

@@ -40,4 +40,59 @@ __device__ __forceinline__ double apply_E(const double* __restrict__ u, int i, i
   }
 }
 
+// the stencil weights of E at one point, loaded once for a march over time
+// levels: diagonal, and minus / plus neighbour along each axis
+struct StencilW {
+  double d, lo[3], hi[3];
+};
+
+template <int DIM, bool VAR>
+__device__ __forceinline__ StencilW load_stencil(int i, int m, const double* __restrict__ ecoef, double ediag,
+                                                 double eoff) {
+  StencilW w;
+  if (!VAR) {
+    w.d = ediag;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) w.lo[a] = w.hi[a] = eoff;
+  } else {
+    w.d = ecoef[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      w.lo[a] = (a < DIM) ? ecoef[(size_t)(1 + 2 * a) * m + i] : 0.0;
+      w.hi[a] = (a < DIM) ? ecoef[(size_t)(2 + 2 * a) * m + i] : 0.0;
+    }
+  }
+  return w;
+}
+
+// E u at point i with preloaded weights (same sums, same order as apply_E)
+template <int DIM, bool VAR>
+__device__ __forceinline__ double apply_E_w(const double* __restrict__ u, int i, int c1, int c2, int c3, int nx,
+                                            const StencilW& w) {
+  const int s2 = nx, s3 = nx * nx;
+  if (!VAR) {
+    double nb = 0.0;
+    if (c1 > 0) nb += u[i - 1];
+    if (c1 < nx - 1) nb += u[i + 1];
+    if (c2 > 0) nb += u[i - s2];
+    if (c2 < nx - 1) nb += u[i + s2];
+    if (DIM == 3) {
+      if (c3 > 0) nb += u[i - s3];
+      if (c3 < nx - 1) nb += u[i + s3];
+    }
+    return w.d * u[i] + w.lo[0] * nb;
+  } else {
+    double acc = w.d * u[i];
+    if (c1 > 0) acc += w.lo[0] * u[i - 1];
+    if (c1 < nx - 1) acc += w.hi[0] * u[i + 1];
+    if (c2 > 0) acc += w.lo[1] * u[i - s2];
+    if (c2 < nx - 1) acc += w.hi[1] * u[i + s2];
+    if (DIM == 3) {
+      if (c3 > 0) acc += w.lo[2] * u[i - s3];
+      if (c3 < nx - 1) acc += w.hi[2] * u[i + s3];
+    }
+    return acc;
+  }
+}
+
 }  // namespace pcop
