@@ -50,6 +50,7 @@ struct Geo {
   int B;         // batch members
   int K;         // frequencies kept, n/2 + 1
   long long vl;  // doubles per member vector: 2 n m
+  long long vs;  // doubles between consecutive members' vectors (>= vl; padded to 256 bytes inside the solver)
   double tau;
   double h2inv;  // 1/h^2
 };

@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(256) ideal_step_kernel(Geo g, int s, const dou
   }
   if (s < n) {
     const double sc = vscale ? vscale[(size_t)b * vs_stride] : 1.0;
-    const double* v1 = v + (size_t)b * g.vl;
+    const double* v1 = v + (size_t)b * g.vs;
     const double* v2 = v1 + (size_t)n * m;
     const double a2 = sc * v2[(size_t)s * m + i] + (double)p2;
     const double a1 = sc * v1[(size_t)(n - 1 - s) * m + i] + (double)p1;
@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(256) ideal_combine_kernel(Geo g, const T* __re
   if (e >= nm) return;
   const T* z1 = z + (size_t)b * 2 * nm;
   const double a = (double)z1[e], d = (double)z1[nm + e];
-  double* w1 = w + (size_t)b * g.vl;
+  double* w1 = w + (size_t)b * g.vs;
   double* w2 = w1 + nm;
   if (accum) {
     w1[e] += a - d;

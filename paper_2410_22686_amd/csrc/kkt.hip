@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(256) kkt_apply_kernel(
   const int j1 = min(n, j0 + jchunk);
   const double a = alpha[b];
   const double s = xscale ? xscale[(size_t)b * xs_stride] : 1.0;
-  const size_t mb = (size_t)b * (size_t)g.vl;
+  const size_t mb = (size_t)b * (size_t)g.vs;
   const double* x1 = x + mb;
   const double* x2 = x + mb + (size_t)n * m;
   double* y1 = y + mb;
@@ -101,7 +101,7 @@ __global__ void rhs_kernel(Geo g, const double* __restrict__ gg, const double* _
     const int i = (int)(r % g.m);
     const bool first = r < g.m;
     double fv = g.tau * ff[t] + (first ? y0[(size_t)b * g.m + i] : 0.0);
-    double* out = bvec + (size_t)b * g.vl;
+    double* out = bvec + (size_t)b * g.vs;
     out[r] = g.tau * gg[t];
     out[nm + r] = -sg[b] * fv;
   }
@@ -116,7 +116,7 @@ __global__ void unpack_kernel(Geo g, const double* __restrict__ x, const double*
        t += (long long)gridDim.x * blockDim.x) {
     const int b = (int)(t / nm);
     const long long r = t - (long long)b * nm;
-    const double* in = x + (size_t)b * g.vl;
+    const double* in = x + (size_t)b * g.vs;
     y[t] = in[r] / sg[b];
     p[t] = in[nm + r];
   }
@@ -131,7 +131,7 @@ __global__ void pack_cot_kernel(Geo g, const double* __restrict__ yb, const doub
        t += (long long)gridDim.x * blockDim.x) {
     const int b = (int)(t / nm);
     const long long q = t - (long long)b * nm;
-    double* out = r + (size_t)b * g.vl;
+    double* out = r + (size_t)b * g.vs;
     out[q] = yb ? yb[t] / sg[b] : 0.0;
     out[nm + q] = pb ? pb[t] : 0.0;
   }
@@ -147,21 +147,25 @@ __global__ void data_grad_kernel(Geo g, const double* __restrict__ lam, const do
        t += (long long)gridDim.x * blockDim.x) {
     const int b = (int)(t / nm);
     const long long q = t - (long long)b * nm;
-    const double* in = lam + (size_t)b * g.vl;
+    const double* in = lam + (size_t)b * g.vs;
     if (dg) dg[t] = g.tau * in[q];
     if (df) df[t] = -sg[b] * g.tau * in[nm + q];
     if (dy0 && q < g.m) dy0[(size_t)b * g.m + q] = -sg[b] * in[nm + q];
   }
 }
 
-// dst = J src = [src_1; -src_2] (in place allowed), members with mask[b] != 0
-__global__ void flip_kernel(Geo g, const double* src, double* dst) {
+// dst = src or J src = [src_1; -src_2], member b at dst + b dvs and
+// src + b svs (copies between the caller's layout and the padded one)
+__global__ void restride_kernel(Geo g, const double* __restrict__ src, long long svs, double* __restrict__ dst,
+                                long long dvs, int flip) {
   const long long nm = (long long)g.n * g.m;
   const long long total = 2 * nm * g.B;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
-    const long long r = t % (2 * nm);
-    dst[t] = (r < nm) ? src[t] : -src[t];
+    const int b = (int)(t / (2 * nm));
+    const long long r = t - (long long)b * 2 * nm;
+    const double v = src[(size_t)b * svs + r];
+    dst[(size_t)b * dvs + r] = (flip && r >= nm) ? -v : v;
   }
 }
 
@@ -171,8 +175,9 @@ static int ew_blocks(const Geo& g) {
   return (int)(blk < 8192 ? (blk < 1 ? 1 : blk) : 8192);
 }
 
-void launch_flip(const Geo& g, const double* src, double* dst, hipStream_t st) {
-  flip_kernel<<<ew_blocks(g), 256, 0, st>>>(g, src, dst);
+void launch_restride(const Geo& g, const double* src, long long svs, double* dst, long long dvs, bool flip,
+                     hipStream_t st) {
+  restride_kernel<<<ew_blocks(g), 256, 0, st>>>(g, src, svs, dst, dvs, flip ? 1 : 0);
 }
 void launch_rhs(const Geo& g, const double* gg, const double* ff, const double* y0, const double* sg,
                 double* b, hipStream_t st) {

@@ -54,8 +54,8 @@ __global__ void __launch_bounds__(kNT) mdot_kernel(KrylovArgs ka, int nv, const 
   double acc[MAXNV + 1];
 #pragma unroll
   for (int i = 0; i <= MAXNV; ++i) acc[i] = 0.0;
-  const double2* wb = reinterpret_cast<const double2*>(w + (size_t)b * ka.vl);
-  const double2* vb = reinterpret_cast<const double2*>(ka.basis + (size_t)b * ka.vl);
+  const double2* wb = reinterpret_cast<const double2*>(w + (size_t)b * ka.ms);
+  const double2* vb = reinterpret_cast<const double2*>(ka.basis + (size_t)b * ka.ms);
   const long long n2 = ka.vl / 2;
   const long long ss = ka.slot_stride / 2;
   for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < n2; e += (long long)nblk * kNT) {
@@ -91,8 +91,8 @@ __global__ void __launch_bounds__(kNT) update_kernel(KrylovArgs ka, int nv, doub
   double acc[MAXNV + 1];
 #pragma unroll
   for (int i = 0; i <= MAXNV; ++i) acc[i] = 0.0;
-  double* wb = w + (size_t)b * ka.vl;
-  const double* vb = ka.basis + (size_t)b * ka.vl;
+  double* wb = w + (size_t)b * ka.ms;
+  const double* vb = ka.basis + (size_t)b * ka.ms;
   for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < ka.vl; e += (long long)nblk * kNT) {
     double v[MAXNV];
 #pragma unroll
@@ -121,8 +121,8 @@ __global__ void __launch_bounds__(kNT) combine_kernel(KrylovArgs ka, int nv, con
   __shared__ double c[MAXNV];
   for (int i = threadIdx.x; i < MAXNV; i += kNT) c[i] = (i < nv) ? coef[(size_t)b * coef_ld + i] : 0.0;
   __syncthreads();
-  double2* ob = reinterpret_cast<double2*>(out + (size_t)b * ka.vl);
-  const double2* vb = reinterpret_cast<const double2*>(ka.basis + (size_t)b * ka.vl);
+  double2* ob = reinterpret_cast<double2*>(out + (size_t)b * ka.ms);
+  const double2* vb = reinterpret_cast<const double2*>(ka.basis + (size_t)b * ka.ms);
   const long long n2 = ka.vl / 2;
   const long long ss = ka.slot_stride / 2;
   for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < n2; e += (long long)gridDim.x * kNT) {

@@ -81,7 +81,9 @@ struct PrecondTables {
 void launch_kkt_apply(const Geo& g, const double* x, double* y, const double* c, const double* alpha,
                       const double* xscale, int xs_stride, const int* active, bool transpose,
                       const double* ecoef, double ediag, double eoff, int jchunk, hipStream_t st);
-void launch_flip(const Geo& g, const double* src, double* dst, hipStream_t st);
+// dst = src or J src (flip), members at b * dvs / b * svs
+void launch_restride(const Geo& g, const double* src, long long svs, double* dst, long long dvs, bool flip,
+                     hipStream_t st);
 void launch_rhs(const Geo& g, const double* gg, const double* ff, const double* y0, const double* sg,
                 double* b, hipStream_t st);
 void launch_unpack(const Geo& g, const double* x, const double* sg, double* y, double* p, hipStream_t st);
@@ -138,6 +140,7 @@ struct KrylovArgs {
   const double* basis;
   long long slot_stride;  // doubles between consecutive basis slots
   long long vl;           // doubles per member vector
+  long long ms;           // doubles between members' vectors
   int B;
   const int* active;      // [B] or null
 };

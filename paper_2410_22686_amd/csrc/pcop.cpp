@@ -115,13 +115,14 @@ struct Layout {
   size_t twM64, twM32, chirp64, chirp32, bhat64, bhat32;
   int M = 1;
   size_t sc, H, coef, red, partial, wnorm2, norm, skip, active, finish, hcol;
-  size_t basis, zbasis, tmp1, tmp2, spec;
+  size_t basis, zbasis, tmp1, tmp2, xpad, spec;
   size_t mgcoef[12], mgz[12], mgr[12];
   int mg_levels = 0;
   int mg_nx[12];
   int nblk = 1;      // default blocks per member of the Krylov reductions
   int nblk_max = 1;  // the most the partial-sum buffer holds (tuner candidates)
   long long vl = 0;
+  long long vs = 0;  // member stride of the solver's vectors: vl padded to 256 bytes
 };
 
 size_t take(Layout& L, size_t bytes) {
@@ -173,11 +174,13 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
   L.active = take(L, sizeof(int) * B);
   L.finish = take(L, sizeof(int) * B);
   L.hcol = take(L, sizeof(double) * B * (kMaxBasis + 1));
-  const size_t vec = sizeof(double) * (size_t)L.vl * B;
+  L.vs = (L.vl + 31) / 32 * 32;
+  const size_t vec = sizeof(double) * (size_t)L.vs * B;
   L.basis = take(L, vec * (o->restart + 1));
   L.zbasis = (o->side == PCOP_FLEXIBLE) ? take(L, vec * o->restart) : 0;
   L.tmp1 = take(L, vec);
   L.tmp2 = take(L, vec);
+  L.xpad = take(L, vec);  // the iterate x in the padded layout
   {
     // epsilon-circulant spectrum [B][2K][m], or the ideal preconditioner's
     // z[B][2][n][m] plus one slice [B][m] (real/complex of the same precision)
@@ -321,32 +324,40 @@ struct pcop_ctx_s {
 
   template <class T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
-  double* basis(int slot) const { return at<double>(L.basis) + (size_t)slot * (size_t)g.vl * g.B; }
-  double* zbasis(int slot) const { return at<double>(L.zbasis) + (size_t)slot * (size_t)g.vl * g.B; }
+  double* basis(int slot) const { return at<double>(L.basis) + (size_t)slot * (size_t)g.vs * g.B; }
+  double* zbasis(int slot) const { return at<double>(L.zbasis) + (size_t)slot * (size_t)g.vs * g.B; }
   KrylovArgs kargs(const double* base, const int* mask) const {
-    return KrylovArgs{base, (long long)g.vl * g.B, g.vl, g.B, mask};
+    return KrylovArgs{base, (long long)g.vs * g.B, g.vl, g.vs, g.B, mask};
+  }
+  // the geometry of the caller's unpadded vectors
+  Geo user_geo() const {
+    Geo u = g;
+    u.vs = u.vl;
+    return u;
   }
 };
 
 namespace {
 
 // the configured preconditioner with tables tb (epsilon-circulant or ideal)
-bool run_precond(pcop_ctx c, const PrecondTables& tb, const double* v, double* w, const double* vscale,
-                 int vs_stride, int accum) {
+bool run_precond(pcop_ctx c, const Geo& g, const PrecondTables& tb, const double* v, double* w,
+                 const double* vscale, int vs_stride, int accum) {
   void* spec = c->at<void>(c->L.spec);
   if (c->opt.precond == PCOP_PRECOND_IDEAL)
-    return launch_ideal_precond(c->g, v, w, spec, c->fp32, c->opt.spatial, tb, c->at<double>(c->L.unit), vscale,
+    return launch_ideal_precond(g, v, w, spec, c->fp32, c->opt.spatial, tb, c->at<double>(c->L.unit), vscale,
                                 vs_stride, accum, c->st);
-  return launch_precond(c->g, v, w, spec, c->fp32, c->opt.spatial, tb, vscale, vs_stride, accum, c->st);
+  return launch_precond(g, v, w, spec, c->fp32, c->opt.spatial, tb, vscale, vs_stride, accum, c->st);
 }
 
+// preconditioner on the solver's padded vectors, or (geo = the caller's
+// geometry) on unpadded ones
 pcop_status do_precond(pcop_ctx c, const double* v, double* w, const double* vscale, int vs_stride, int accum,
-                       const int* mask, int nact) {
+                       const int* mask, int nact, const Geo* geo = nullptr) {
   PrecondTables tb = c->tb;
   tb.active = mask;
   tb.nact = nact;
   tb.timer = c->kt();
-  if (!run_precond(c, tb, v, w, vscale, vs_stride, accum))
+  if (!run_precond(c, geo ? *geo : c->g, tb, v, w, vscale, vs_stride, accum))
     return fail(PCOP_ERR_UNSUPPORTED, "preconditioner variant not available for this shape");
   return PCOP_OK;
 }
@@ -433,7 +444,7 @@ pcop_status tune_kernels(pcop_ctx c) {
   double* v = c->basis(0);
   double* w = c->basis(1);
   hipStream_t st = c->st;
-  PCOP_HIP(hipMemsetAsync(v, 0, sizeof(double) * (size_t)g.vl * g.B, st));
+  PCOP_HIP(hipMemsetAsync(v, 0, sizeof(double) * (size_t)g.vs * g.B, st));
   hipEvent_t e0, e1;
   PCOP_HIP(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -464,9 +475,9 @@ pcop_status tune_kernels(pcop_ctx c) {
       t.active = nullptr;
       t.nact = g.B;
       t.timer = nullptr;
-      if (!run_precond(c, t, v, w, nullptr, 0, 0)) continue;
+      if (!run_precond(c, g, t, v, w, nullptr, 0, 0)) continue;
       double ms = 0;
-      if (!time_it([&] { run_precond(c, t, v, w, nullptr, 0, 0); }, ms)) break;
+      if (!time_it([&] { run_precond(c, g, t, v, w, nullptr, 0, 0); }, ms)) break;
       if (ms < best.ms) {
         best.time_cols = tc;
         best.dst_variant = dv;
@@ -494,7 +505,7 @@ pcop_status tune_kernels(pcop_ctx c) {
   // over nv basis vectors (zeroed first: the coefficients and skip flags too)
   const int nv = std::min(10, c->opt.restart);
   if (err == hipSuccess)
-    err = hipMemsetAsync(c->basis(0), 0, sizeof(double) * (size_t)g.vl * g.B * (nv + 1), st);
+    err = hipMemsetAsync(c->basis(0), 0, sizeof(double) * (size_t)g.vs * g.B * (nv + 1), st);
   if (err == hipSuccess) err = hipMemsetAsync(c->at<double>(c->L.coef), 0, sizeof(double) * g.B * kMaxBasis, st);
   if (err == hipSuccess) err = hipMemsetAsync(c->at<int>(c->L.skip), 0, sizeof(int) * g.B, st);
   double best_kr = 1e300;
@@ -595,6 +606,7 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   g.B = B;
   g.K = n / 2 + 1;
   g.vl = L.vl;
+  g.vs = L.vs;
   c->T = prob->T;
   g.tau = prob->T / prob->nt;
   const double h = 1.0 / (nx + 1);
@@ -934,7 +946,7 @@ pcop_status pcop_post_solve(pcop_ctx c, const double* x, const double* fN, const
   tb.nact = B;
   tb.timer = nullptr;
   const double* unit = c->at<double>(c->L.unit);
-  launch_post_rhs(g, x, fN, g0, y0, c->at<double>(c->L.sg), a, st);
+  launch_post_rhs(c->user_geo(), x, fN, g0, y0, c->at<double>(c->L.sg), a, st);
   PCOP_HIP(hipGetLastError());
   auto read_norms = [&](std::vector<double>& out) -> hipError_t {
     hipError_t e = hipMemcpyAsync(c->pin_norm, a.norm2, sizeof(double) * B, hipMemcpyDeviceToHost, st);
@@ -983,7 +995,7 @@ pcop_status pcop_error_eh(pcop_ctx c, const double* x, const double* yN, const d
   double* post = c->at<double>(c->L.post);
   double* sq = post + (size_t)B * ((g.m + 255) / 256) + B;
   double* dev_eh = sq + 2 * (size_t)B * (g.n + 1);
-  launch_error_eh(g, x, yN, p0, c->at<double>(c->L.sg), y_exact, p_exact, sq, dev_eh, st);
+  launch_error_eh(c->user_geo(), x, yN, p0, c->at<double>(c->L.sg), y_exact, p_exact, sq, dev_eh, st);
   PCOP_HIP(hipGetLastError());
   PCOP_HIP(hipMemcpyAsync(c->pin_norm, dev_eh, sizeof(double) * B, hipMemcpyDeviceToHost, st));
   PCOP_HIP(hipStreamSynchronize(st));
@@ -993,7 +1005,7 @@ pcop_status pcop_error_eh(pcop_ctx c, const double* x, const double* yN, const d
 
 pcop_status pcop_rhs(pcop_ctx c, const double* g, const double* f, const double* y0, double* b) {
   if (!c || !g || !f || !y0 || !b) return fail(PCOP_ERR_INVALID_ARG, "null argument");
-  launch_rhs(c->g, g, f, y0, c->at<double>(c->L.sg), b, c->st);
+  launch_rhs(c->user_geo(), g, f, y0, c->at<double>(c->L.sg), b, c->st);
   PCOP_HIP(hipGetLastError());
   return PCOP_OK;
 }
@@ -1002,8 +1014,8 @@ pcop_status pcop_kkt_apply(pcop_ctx c, const double* x, double* y, int transpose
   if (!c || !x || !y) return fail(PCOP_ERR_INVALID_ARG, "null argument");
   if (x == y) return fail(PCOP_ERR_INVALID_ARG, "x and y must not overlap");
   tbeg(c->kt(), KF_KKT, 16.0 * c->g.vl * c->g.B);
-  launch_kkt_apply(c->g, x, y, nullptr, c->at<double>(c->L.alpha), nullptr, 0, nullptr, transpose != 0, c->ecoef,
-                   c->ediag, c->eoff, c->kkt_jchunk, c->st);
+  launch_kkt_apply(c->user_geo(), x, y, nullptr, c->at<double>(c->L.alpha), nullptr, 0, nullptr, transpose != 0,
+                   c->ecoef, c->ediag, c->eoff, c->kkt_jchunk, c->st);
   tend(c->kt());
   PCOP_HIP(hipGetLastError());
   return PCOP_OK;
@@ -1011,7 +1023,8 @@ pcop_status pcop_kkt_apply(pcop_ctx c, const double* x, double* y, int transpose
 
 pcop_status pcop_precond_apply(pcop_ctx c, const double* v, double* w) {
   if (!c || !v || !w) return fail(PCOP_ERR_INVALID_ARG, "null argument");
-  pcop_status s = do_precond(c, v, w, nullptr, 0, 0, nullptr, c->g.B);
+  const Geo gu = c->user_geo();
+  pcop_status s = do_precond(c, v, w, nullptr, 0, 0, nullptr, c->g.B, &gu);
   if (s != PCOP_OK) return s;
   PCOP_HIP(hipGetLastError());
   return PCOP_OK;
@@ -1019,21 +1032,21 @@ pcop_status pcop_precond_apply(pcop_ctx c, const double* v, double* w) {
 
 pcop_status pcop_unpack(pcop_ctx c, const double* x, double* y, double* p) {
   if (!c || !x || !y || !p) return fail(PCOP_ERR_INVALID_ARG, "null argument");
-  launch_unpack(c->g, x, c->at<double>(c->L.sg), y, p, c->st);
+  launch_unpack(c->user_geo(), x, c->at<double>(c->L.sg), y, p, c->st);
   PCOP_HIP(hipGetLastError());
   return PCOP_OK;
 }
 
 pcop_status pcop_pack_cotangent(pcop_ctx c, const double* ybar, const double* pbar, double* r) {
   if (!c || !r) return fail(PCOP_ERR_INVALID_ARG, "null argument");
-  launch_pack_cotangent(c->g, ybar, pbar, c->at<double>(c->L.sg), r, c->st);
+  launch_pack_cotangent(c->user_geo(), ybar, pbar, c->at<double>(c->L.sg), r, c->st);
   PCOP_HIP(hipGetLastError());
   return PCOP_OK;
 }
 
 pcop_status pcop_data_grad(pcop_ctx c, const double* lam, double* dg, double* df, double* dy0) {
   if (!c || !lam) return fail(PCOP_ERR_INVALID_ARG, "null argument");
-  launch_data_grad(c->g, lam, c->at<double>(c->L.sg), dg, df, dy0, c->st);
+  launch_data_grad(c->user_geo(), lam, c->at<double>(c->L.sg), dg, df, dy0, c->st);
   PCOP_HIP(hipGetLastError());
   return PCOP_OK;
 }
@@ -1235,13 +1248,13 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
   const int nblk = c->nblk;
   const int H_ld = kMaxBasis;
 
+  // the solve runs on padded copies of b and x (member stride g.vs);
   // A^T = J A J: solve A z = J b and return x = J z
-  const double* bb = b;
-  if (transpose) {
-    launch_flip(g, b, tmp2, st);
-    launch_flip(g, x, x, st);
-    bb = tmp2;
-  }
+  const double* bb = tmp2;
+  double* const xu = x;
+  x = c->at<double>(L.xpad);
+  launch_restride(g, b, g.vl, tmp2, g.vs, transpose != 0, st);
+  launch_restride(g, xu, g.vl, x, g.vs, transpose != 0, st);
   std::vector<MemberState> ms(B);
   std::vector<int> h_active(B, 1), h_finish(B, 0);
   std::vector<double> h_norm(B), h_col((size_t)B * (kMaxBasis + 1)), h_coef((size_t)B * kMaxBasis);
@@ -1468,7 +1481,7 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
   PCOP_HIP(upload_ints(active, h_active, c->pin_active));
   do_kkt(c, x, tmp1, bb, nullptr, 0, nullptr, B);
   do_norm2(c, tmp1, nullptr, B);
-  if (transpose) launch_flip(g, x, x, st);
+  launch_restride(g, x, g.vs, xu, g.vl, transpose != 0, st);
   PCOP_HIP(download(h_red.data(), red, c->pin_red, (size_t)B * kRedStride));
   PCOP_HIP(hipGetLastError());
   for (int m = 0; m < B; ++m) {

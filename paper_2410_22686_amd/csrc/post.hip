@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(256) post_rhs_kernel(Geo g, const double* __re
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = g.n, m = g.m;
   if (i >= m) return;
-  const double* x1 = x + (size_t)b * g.vl;
+  const double* x1 = x + (size_t)b * g.vs;
   const double* x2 = x1 + (size_t)n * m;
   const size_t o = (size_t)b * m + i;
   double* rb = rhs + (size_t)b * 2 * m;
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(256) eh_level_kernel(Geo g, const double* __re
   const int j = blockIdx.x;  // 0..N-1
   const int b = blockIdx.y;
   const int n = g.n, m = g.m, N = g.n + 1;
-  const double* x1 = x + (size_t)b * g.vl;
+  const double* x1 = x + (size_t)b * g.vs;
   const double* x2 = x1 + (size_t)n * m;
   const double* ye = yex + ((size_t)b * (N + 1) + (j + 1)) * m;
   const double* pe = pex + ((size_t)b * (N + 1) + j) * m;

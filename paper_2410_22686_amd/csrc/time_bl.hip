@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(256) time_fwd_bl(Geo g, const double* __restri
   const cx<T>* bhat = reinterpret_cast<const cx<T>*>(tt.bhat);
   const int i0 = bx * P;
   const double s = vscale ? vscale[(size_t)b * vs_stride] : 1.0;
-  const double* v1 = v + (size_t)b * g.vl;
+  const double* v1 = v + (size_t)b * g.vs;
   const double* v2 = v1 + (size_t)n * m;
   for (int t = threadIdx.x; t < M * P; t += blockDim.x) {
     const int j = t / P, p = t - j * P;
@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(256) time_inv_bl(Geo g, const cx<T>* __restric
   }
   __syncthreads();
   p2_fft<T, 1, M, P, 256>(buf, LD, twM);
-  double* w1 = w + (size_t)b * g.vl;
+  double* w1 = w + (size_t)b * g.vs;
   double* w2 = w1 + (size_t)n * m;
   const double invM = 1.0 / (double)M;
   for (int t = threadIdx.x; t < n * P; t += blockDim.x) {

@@ -24,7 +24,7 @@ __global__ void __launch_bounds__(256) time_fwd_ip(Geo g, const double* __restri
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
   const int i0 = bx * P;
   const double s = vscale ? vscale[(size_t)b * vs_stride] : 1.0;
-  const double* v1 = v + (size_t)b * g.vl;
+  const double* v1 = v + (size_t)b * g.vs;
   const double* v2 = v1 + (size_t)n * m;
   auto ldg = [&](int j, int p) { return pack_input<T>(v1, v2, dpow, s, j, i0 + p, m); };
   auto lds = [&](int j, int p) { return buf[j * P + p]; };
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(256) time_inv_ip(Geo g, const cx<T>* __restric
     if (k != 0 && 2 * k != n) buf[(n - k) * P + p] = cx<T>{z2.x + z1.y, z1.x - z2.y};
   }
   __syncthreads();
-  double* w1 = w + (size_t)b * g.vl;
+  double* w1 = w + (size_t)b * g.vs;
   double* w2 = w1 + (size_t)n * m;
   auto lds = [&](int j, int p) { return buf[j * P + p]; };
   auto sts = [&](int j, int p, cx<T> val) { buf[j * P + p] = val; };

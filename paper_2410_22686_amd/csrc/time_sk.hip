@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(256) time_fwd_sk(Geo g, const double* __restri
   auto fetch = [&](int t) {
     const int b = t / tw.tpm;
     const int i0 = (t - b * tw.tpm) * P;
-    const double* v1 = v + (size_t)b * g.vl;
+    const double* v1 = v + (size_t)b * g.vs;
     const double* v2 = v1 + (size_t)n * m;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(256) time_inv_sk(Geo g, const cx<T>* __restric
     __syncthreads();
     const int nxt = tw.next(tile + stride, stride);
     if (nxt < tw.ntiles) fetch(nxt);
-    double* w1 = w + (size_t)b * g.vl;
+    double* w1 = w + (size_t)b * g.vs;
     double* w2 = w1 + (size_t)n * m;
     cx<T>* src = bufA;
     cx<T>* dst = bufB;
