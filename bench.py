@@ -90,6 +90,8 @@ def parse():
                     help="sine-transform kernels: 0 automatic, 1 register, 2 LDS-staged, 3 register with wide column tiles")
     ap.add_argument("--kkt-jchunk", type=int, default=0, help="KKT matvec time levels per thread (0 automatic)")
     ap.add_argument("--krylov-blocks", type=int, default=0, help="Krylov reduction blocks per member (0 automatic)")
+    ap.add_argument("--gs-update", type=int, default=0, choices=[0, 1, 2],
+                    help="Gram-Schmidt update kernel: 0 automatic, 1 doubles, 2 double2 pairs")
     ap.add_argument("--precond", choices=["eps", "ideal"], default="eps",
                     help="eps: the epsilon-circulant preconditioner; ideal: P of eq. matrix_P (sequential in time)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -233,7 +235,7 @@ def main():
                coeff=None if cfg.coeff == "one" else W.coeff_function(cfg.coeff),
                restart=30, maxit=300, rtol=1e-8, device=dev, stream=stream, tune=bool(args.tune),
                time_cols=args.time_cols, dst_kernel=args.dst_kernel, precond=args.precond,
-               kkt_jchunk=args.kkt_jchunk, krylov_blocks=args.krylov_blocks, **opts)
+               kkt_jchunk=args.kkt_jchunk, krylov_blocks=args.krylov_blocks, gs_update=args.gs_update, **opts)
     print(f"# bench: kernels {s.kernels}", file=sys.stderr, flush=True)
     tg = torch.tensor(g, device=dev)
     tf = torch.tensor(f, device=dev)

@@ -121,7 +121,7 @@ typedef struct {
  *              per block (512 threads).
  *   tune       1: pcop_setup times the candidates of every kernel choice
  *              left at 0 ("automatic": time_cols, dst_kernel, kkt_jchunk,
- *              krylov_blocks) on the context's stream and keeps the fastest; the choice is cached per device and
+ *              krylov_blocks, gs_update) on the context's stream and keeps the fastest; the choice is cached per device and
  *              shape for the process.  0: built-in choices.  All choices give
  *              the same iterates up to rounding (the reduction order follows
  *              the block count).
@@ -136,6 +136,8 @@ typedef struct {
  *   krylov_blocks  blocks per member of the Krylov reductions: 0 automatic,
  *              else 1..4096 (the reduction order, and so the rounding,
  *              follows it).
+ *   gs_update  Gram-Schmidt update kernel: 0 automatic, 1 one element per
+ *              thread and step, 2 double2 pairs.
  *   stream     hipStream_t on which all work is enqueued. */
 typedef struct {
   int precision;
@@ -153,6 +155,7 @@ typedef struct {
   int precond;
   int kkt_jchunk;
   int krylov_blocks;
+  int gs_update;
   void* stream;
 } pcop_options;
 
@@ -257,6 +260,7 @@ pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* ep
  *                  column tiles) or 0 (multigrid);
  *   kkt_jchunk     time levels per thread of the KKT matvec;
  *   krylov_blocks  blocks per member of the Krylov reductions;
+ *   gs_update      1 (one element per thread) or 2 (double2 pairs);
  *   tuned_precond_ms  the fastest preconditioner apply measured by the
  *                  tuner, 0 when no tuning ran. */
 typedef struct {
@@ -264,6 +268,7 @@ typedef struct {
   int dst_kernel;
   int kkt_jchunk;
   int krylov_blocks;
+  int gs_update;
   double tuned_precond_ms;
 } pcop_kernel_choice;
 pcop_status pcop_get_kernels(pcop_ctx ctx, pcop_kernel_choice* out);

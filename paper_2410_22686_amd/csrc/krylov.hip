@@ -113,6 +113,48 @@ __global__ void __launch_bounds__(kNT) update_kernel(KrylovArgs ka, int nv, doub
   block_reduce_store<MAXNV + 1>(out, nv + 1, partial + ((size_t)b * nblk + blockIdx.x) * kRedStride);
 }
 
+// the same update on double2 pairs (two elements per thread and step)
+template <int MAXNV>
+__global__ void __launch_bounds__(kNT) update2_kernel(KrylovArgs ka, int nv, double* __restrict__ w,
+                                                      const double* __restrict__ coef, int coef_ld,
+                                                      double* __restrict__ partial, int nblk,
+                                                      const int* __restrict__ skip) {
+  const int b = blockIdx.y;
+  if (ka.active && !ka.active[b]) return;
+  if (skip && skip[b]) return;
+  __shared__ double c[MAXNV];
+  for (int i = threadIdx.x; i < MAXNV; i += kNT) c[i] = (i < nv) ? coef[(size_t)b * coef_ld + i] : 0.0;
+  __syncthreads();
+  double acc[MAXNV + 1];
+#pragma unroll
+  for (int i = 0; i <= MAXNV; ++i) acc[i] = 0.0;
+  double2* wb = reinterpret_cast<double2*>(w + (size_t)b * ka.ms);
+  const double2* vb = reinterpret_cast<const double2*>(ka.basis + (size_t)b * ka.ms);
+  const long long n2 = ka.vl / 2;
+  const long long ss = ka.slot_stride / 2;
+  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < n2; e += (long long)nblk * kNT) {
+    double2 v[MAXNV];
+#pragma unroll
+    for (int i = 0; i < MAXNV; ++i) v[i] = (i < nv) ? vb[(size_t)i * ss + e] : double2{0.0, 0.0};
+    double2 wv = wb[e];
+#pragma unroll
+    for (int i = 0; i < MAXNV; ++i)
+      if (i < nv) {
+        wv.x -= c[i] * v[i].x;
+        wv.y -= c[i] * v[i].y;
+      }
+    wb[e] = wv;
+#pragma unroll
+    for (int i = 0; i < MAXNV; ++i)
+      if (i < nv) acc[i] += v[i].x * wv.x + v[i].y * wv.y;
+    acc[MAXNV] += wv.x * wv.x + wv.y * wv.y;
+  }
+  double out[MAXNV + 1];
+#pragma unroll
+  for (int i = 0; i <= MAXNV; ++i) out[i] = (i < nv) ? acc[i] : ((i == nv) ? acc[MAXNV] : 0.0);
+  block_reduce_store<MAXNV + 1>(out, nv + 1, partial + ((size_t)b * nblk + blockIdx.x) * kRedStride);
+}
+
 template <int MAXNV>
 __global__ void __launch_bounds__(kNT) combine_kernel(KrylovArgs ka, int nv, const double* __restrict__ coef,
                                                       int coef_ld, double* __restrict__ out, int accum) {
@@ -256,7 +298,11 @@ void launch_mdot(const KrylovArgs& ka, int nv, const double* w, double* partial,
 void launch_update(const KrylovArgs& ka, int nv, double* w, const double* coef, int coef_ld, double* partial,
                    int nblk, const int* skip, hipStream_t st) {
   dim3 grid(nblk, ka.B);
-  PCOP_DISPATCH_NV(update_kernel, nv, grid, st, ka, nv, w, coef, coef_ld, partial, nblk, skip);
+  if (ka.pairs) {
+    PCOP_DISPATCH_NV(update2_kernel, nv, grid, st, ka, nv, w, coef, coef_ld, partial, nblk, skip);
+  } else {
+    PCOP_DISPATCH_NV(update_kernel, nv, grid, st, ka, nv, w, coef, coef_ld, partial, nblk, skip);
+  }
 }
 
 void launch_combine(const KrylovArgs& ka, int nv, const double* coef, int coef_ld, double* out, int accum,

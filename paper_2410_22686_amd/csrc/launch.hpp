@@ -143,6 +143,7 @@ struct KrylovArgs {
   long long ms;           // doubles between members' vectors
   int B;
   const int* active;      // [B] or null
+  int pairs;              // Gram-Schmidt update on double2 pairs (1) or doubles (0)
 };
 constexpr int kMaxBasis = 41;   // restart <= 40
 constexpr int kRedStride = 48;  // doubles per (member, block) partial record

@@ -88,6 +88,7 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
   if (o->kkt_jchunk < 0 || o->kkt_jchunk > 64) return fail(PCOP_ERR_INVALID_ARG, "kkt_jchunk must be in 0..64");
   if (o->krylov_blocks < 0 || o->krylov_blocks > 4096)
     return fail(PCOP_ERR_INVALID_ARG, "krylov_blocks must be in 0..4096");
+  if (o->gs_update < 0 || o->gs_update > 2) return fail(PCOP_ERR_INVALID_ARG, "gs_update must be 0, 1 or 2");
   if (o->precision == PCOP_MIXED && o->side != PCOP_FLEXIBLE)
     return fail(PCOP_ERR_INVALID_ARG, "the mixed-precision preconditioner needs side = PCOP_FLEXIBLE");
   if (o->spatial == PCOP_DST) {
@@ -300,6 +301,7 @@ struct pcop_ctx_s {
   double tuned_ms = 0;
   int kkt_jchunk = 16;  // time levels per thread of the matvec
   int nblk = 1;         // blocks per member of the Krylov reductions
+  int upd_pairs = 0;    // Gram-Schmidt update on double2 pairs
   EventTimer timer;
   KTimer ktimer{&EventTimer::on_begin, &EventTimer::on_end, nullptr};
   // pinned host staging for every scalar transfer of the solver
@@ -327,7 +329,7 @@ struct pcop_ctx_s {
   double* basis(int slot) const { return at<double>(L.basis) + (size_t)slot * (size_t)g.vs * g.B; }
   double* zbasis(int slot) const { return at<double>(L.zbasis) + (size_t)slot * (size_t)g.vs * g.B; }
   KrylovArgs kargs(const double* base, const int* mask) const {
-    return KrylovArgs{base, (long long)g.vs * g.B, g.vl, g.vs, g.B, mask};
+    return KrylovArgs{base, (long long)g.vs * g.B, g.vl, g.vs, g.B, mask, upd_pairs};
   }
   // the geometry of the caller's unpadded vectors
   Geo user_geo() const {
@@ -399,18 +401,18 @@ void do_norm2(pcop_ctx c, const double* w, const int* mask, int nact) {
 struct TuneResult {
   int time_cols, dst_variant;
   double ms;  // fastest preconditioner apply
-  int jchunk, nblk;
+  int jchunk, nblk, pairs;
 };
 std::mutex g_tune_mu;
-std::map<std::array<int, 13>, TuneResult> g_tune_cache;
+std::map<std::array<int, 14>, TuneResult> g_tune_cache;
 
 pcop_status tune_kernels(pcop_ctx c) {
   const Geo& g = c->g;
   int dev = 0;
   PCOP_HIP(hipGetDevice(&dev));
-  const std::array<int, 13> key{dev, g.dim, g.nx, g.n, g.B, (int)c->fp32, c->opt.spatial, c->opt.time_cols,
+  const std::array<int, 14> key{dev, g.dim, g.nx, g.n, g.B, (int)c->fp32, c->opt.spatial, c->opt.time_cols,
                                 c->opt.dst_kernel, c->coeff_kind, c->opt.precond, c->opt.kkt_jchunk,
-                                c->opt.krylov_blocks};
+                                c->opt.krylov_blocks, c->opt.gs_update};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -420,6 +422,7 @@ pcop_status tune_kernels(pcop_ctx c) {
       c->tuned_ms = it->second.ms;
       c->kkt_jchunk = it->second.jchunk;
       c->nblk = it->second.nblk;
+      c->upd_pairs = it->second.pairs;
       return PCOP_OK;
     }
   }
@@ -452,7 +455,7 @@ pcop_status tune_kernels(pcop_ctx c) {
     return fail(PCOP_ERR_DEVICE, "tuner: event creation failed");
   }
   constexpr int kReps = 3;
-  TuneResult best{c->tb.time_cols, c->tb.dst_variant, 1e300, c->kkt_jchunk, c->nblk};
+  TuneResult best{c->tb.time_cols, c->tb.dst_variant, 1e300, c->kkt_jchunk, c->nblk, c->upd_pairs};
   hipError_t err = hipSuccess;
   // average milliseconds of kReps runs of f after one warm-up run
   auto time_it = [&](auto&& f, double& ms_out) -> bool {
@@ -511,22 +514,28 @@ pcop_status tune_kernels(pcop_ctx c) {
   double best_kr = 1e300;
   std::vector<int> tried;
   for (int f : {1, 2, 4, 8}) {
-    if (err != hipSuccess || c->opt.krylov_blocks != 0) break;
-    const int nb = std::max(1, c->L.nblk * f / 2);  // half .. four times the default
+    if (err != hipSuccess) break;
+    // half .. four times the default block count, unless fixed by the caller
+    const int nb = c->opt.krylov_blocks != 0 ? c->nblk : std::max(1, c->L.nblk * f / 2);
     if (nb > c->L.nblk_max || std::find(tried.begin(), tried.end(), nb) != tried.end()) continue;
     tried.push_back(nb);
-    KrylovArgs ka = c->kargs(c->basis(0), nullptr);
-    double* wv = c->basis(nv);
-    double* part = c->at<double>(c->L.partial);
-    double ms = 0;
-    if (!time_it([&] {
-          launch_mdot(ka, nv, wv, part, nb, st);
-          launch_update(ka, nv, wv, c->at<double>(c->L.coef), kMaxBasis, part, nb, c->at<int>(c->L.skip), st);
-        }, ms))
-      break;
-    if (ms < best_kr) {
-      best_kr = ms;
-      best.nblk = nb;
+    for (int pr : {0, 1}) {
+      if (c->opt.gs_update != 0 && pr != c->upd_pairs) continue;
+      KrylovArgs ka = c->kargs(c->basis(0), nullptr);
+      ka.pairs = pr;
+      double* wv = c->basis(nv);
+      double* part = c->at<double>(c->L.partial);
+      double ms = 0;
+      if (!time_it([&] {
+            launch_mdot(ka, nv, wv, part, nb, st);
+            launch_update(ka, nv, wv, c->at<double>(c->L.coef), kMaxBasis, part, nb, c->at<int>(c->L.skip), st);
+          }, ms))
+        break;
+      if (ms < best_kr) {
+        best_kr = ms;
+        best.nblk = nb;
+        best.pairs = pr;
+      }
     }
   }
   (void)hipEventDestroy(e0);
@@ -539,6 +548,7 @@ pcop_status tune_kernels(pcop_ctx c) {
   c->tuned_ms = best.ms;
   c->kkt_jchunk = best.jchunk;
   c->nblk = best.nblk;
+  c->upd_pairs = best.pairs;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune_cache[key] = best;
   return PCOP_OK;
@@ -870,6 +880,7 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   tb.dst_variant = (opts->dst_kernel >= 2) ? opts->dst_kernel - 1 : 0;
   c->nblk = opts->krylov_blocks > 0 ? opts->krylov_blocks : L.nblk;
   c->kkt_jchunk = opts->kkt_jchunk > 0 ? opts->kkt_jchunk : 16;
+  c->upd_pairs = opts->gs_update == 2 ? 1 : 0;
   {
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -926,6 +937,7 @@ pcop_status pcop_get_kernels(pcop_ctx c, pcop_kernel_choice* out) {
   out->dst_kernel = (c->opt.spatial == PCOP_DST) ? c->tb.dst_variant + 1 : 0;
   out->kkt_jchunk = c->kkt_jchunk;
   out->krylov_blocks = c->nblk;
+  out->gs_update = c->upd_pairs ? 2 : 1;
   out->tuned_precond_ms = c->tuned_ms;
   return PCOP_OK;
 }

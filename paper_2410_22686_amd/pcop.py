@@ -56,7 +56,7 @@ class c_options(ctypes.Structure):
                 ("graph", ctypes.c_int), ("graph_chunk", ctypes.c_int), ("reorth_tol", ctypes.c_double),
                 ("time_cols", ctypes.c_int), ("dst_kernel", ctypes.c_int), ("tune", ctypes.c_int),
                 ("precond", ctypes.c_int), ("kkt_jchunk", ctypes.c_int), ("krylov_blocks", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("gs_update", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
 class c_kernel_stat(ctypes.Structure):
@@ -66,7 +66,7 @@ class c_kernel_stat(ctypes.Structure):
 
 class c_kernel_choice(ctypes.Structure):
     _fields_ = [("time_cols", ctypes.c_int), ("dst_kernel", ctypes.c_int), ("kkt_jchunk", ctypes.c_int),
-                ("krylov_blocks", ctypes.c_int), ("tuned_precond_ms", ctypes.c_double)]
+                ("krylov_blocks", ctypes.c_int), ("gs_update", ctypes.c_int), ("tuned_precond_ms", ctypes.c_double)]
 
 
 class c_member_info(ctypes.Structure):
@@ -168,7 +168,7 @@ class Solver:
                  spatial: str = "dst", side: str = "right", restart: int = 30, maxit: int = 300,
                  rtol: float = 1e-8, graph: bool = False, graph_chunk: int = 4, reorth_tol: float = 1e-8,
                  time_cols: int = 0, dst_kernel: int = 0, tune: bool = False, precond: str = "eps",
-                 kkt_jchunk: int = 0, krylov_blocks: int = 0,
+                 kkt_jchunk: int = 0, krylov_blocks: int = 0, gs_update: int = 0,
                  device: Union[str, torch.device] = "cuda", stream: Optional[torch.cuda.Stream] = None):
         import numpy as np
         self.lib = load_library()
@@ -198,7 +198,7 @@ class Solver:
         opts.graph, opts.graph_chunk, opts.reorth_tol = int(bool(graph)), int(graph_chunk), float(reorth_tol)
         opts.time_cols, opts.dst_kernel, opts.tune = int(time_cols), int(dst_kernel), int(bool(tune))
         opts.precond = _PRECOND[precond]
-        opts.kkt_jchunk, opts.krylov_blocks = int(kkt_jchunk), int(krylov_blocks)
+        opts.kkt_jchunk, opts.krylov_blocks, opts.gs_update = int(kkt_jchunk), int(krylov_blocks), int(gs_update)
         self.stream = stream
         with torch.cuda.device(self.device):
             st = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -226,7 +226,7 @@ class Solver:
         # kernel choices in effect: time_cols -P two-buffer / +P in place / 0 chirp-z;
         # dst_kernel 1 register / 2 LDS-staged / 0 multigrid
         self.kernels = {"time_cols": kc.time_cols, "dst_kernel": kc.dst_kernel, "kkt_jchunk": kc.kkt_jchunk,
-                        "krylov_blocks": kc.krylov_blocks, "tuned_ms": kc.tuned_precond_ms}
+                        "krylov_blocks": kc.krylov_blocks, "gs_update": kc.gs_update, "tuned_ms": kc.tuned_precond_ms}
 
     # ------------------------------------------------------------------
     def __del__(self):

@@ -373,3 +373,20 @@ def test_autograd_matches_oracle_and_envelope():
     assert rel(tg.grad.cpu().numpy()[0], eg) < 1e-8
     assert rel(tf.grad.cpu().numpy()[0], ef) < 1e-8
     assert rel(ty0.grad.cpu().numpy()[0], ey0) < 1e-8
+
+
+@pytest.mark.parametrize("side", ["right", "flexible"])
+def test_gs_update_pairs_matches_scalar(side):
+    """The double2 Gram-Schmidt update and the one-element update give the
+    same iterates up to rounding (the dot products sum pairs first)."""
+    dim, nx, nt, gammas = 2, 15, 24, (1e-3, 1e-7)
+    fields = [W.random_fields(dim, nx, nt, seed=90 + b) for b in range(len(gammas))]
+    g, f, y0 = (to_dev(np.stack([fl[i] for fl in fields])) for i in range(3))
+    out = {}
+    for gs in (1, 2):
+        s = Solver(dim, nx, nt, list(gammas), side=side, gs_update=gs, device=DEV)
+        assert s.kernels["gs_update"] == gs
+        x, infos, _ = s.solve(s.rhs(g, f, y0))
+        out[gs] = (x.cpu().numpy(), [i.iters for i in infos])
+    assert out[1][1] == out[2][1]
+    assert rel(out[1][0], out[2][0]) < 1e-12
