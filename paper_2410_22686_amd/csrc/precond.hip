@@ -27,13 +27,16 @@ namespace pcop {
 // ---------------------------------------------------------------------------
 // points per block of the two-buffer time kernels: the largest power of two
 // in 4..want whose two [n][P] buffers fit 64 KiB and whose whole LDS (with
-// the tables) fits 80 KiB (two blocks per CU), else 0
-static int time_cols_sk(int n, int csz, int want) {
+// the tables) fits 80 KiB (two blocks per CU), else 0.  With wide = true,
+// 16 points may also use the wide kernels (512 threads, buffers up to
+// 128 KiB, one block per CU).
+static int time_cols_sk(int n, int csz, int want, bool wide = false) {
+  if (wide && want >= 16 && (size_t)2 * n * 16 * csz <= 131072 && sk_lds_bytes(n, 16, csz) <= 160 * 1024 - 1024)
+    return 16;
   for (int P = want; P >= 4; P /= 2)
     if ((size_t)2 * n * P * csz <= 65536 && sk_lds_bytes(n, P, csz) <= 81920) return P;
   return 0;
 }
-// columns per block of the chirp-z kernels: 16..4, or down to 1 for M >= 2048
 static int time_cols_bl(int M, int csz) {
   const int pmin = (M >= 2048) ? 1 : 4;
   for (int P = 16; P >= pmin; P /= 2)
@@ -91,7 +94,8 @@ static int time_cols_ip(const FftPlan& pl, int n, int csz, int want) {
 // buffers do not fit, and in-place requests fall back to two buffers.
 static int time_block(const FftPlan& pl, int n, int csz, int req) {
   if (req <= 0) {
-    const int P = time_cols_sk(n, csz, req < -1 ? -req : 16);
+    // an explicit -16 admits the wide kernels
+    const int P = time_cols_sk(n, csz, req < -1 ? -req : 16, req == -16);
     if (P > 0) return -P;
     return time_cols_ip(pl, n, csz, 16);
   }

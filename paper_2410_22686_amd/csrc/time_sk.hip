@@ -27,9 +27,9 @@ struct TileWalk {
   }
 };
 
-// Q = register slots per thread for one tile's inputs: n P <= Q * 256
-template <class T, int P, int Q>
-__global__ void __launch_bounds__(256) time_fwd_sk(Geo g, const double* __restrict__ v, cx<T>* __restrict__ spec,
+// Q = register slots per thread for one tile's inputs: n P <= Q * NT
+template <class T, int P, int Q, int NT>
+__global__ void __launch_bounds__(NT) time_fwd_sk(Geo g, const double* __restrict__ v, cx<T>* __restrict__ spec,
                                                    const double* __restrict__ dpow, const cx<T>* __restrict__ twn,
                                                    FftPlan plan, const double* __restrict__ vscale, int vs_stride,
                                                    TileWalk tw) {
@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(256) time_fwd_sk(Geo g, const double* __restri
   cx<T>* tw_l = bufB + nP;
   double* dp_l = reinterpret_cast<double*>(tw_l + n);  // d_j
   double* di_l = dp_l + n;                              // 1 / d_j
-  for (int t = threadIdx.x; t < n; t += 256) {
+  for (int t = threadIdx.x; t < n; t += NT) {
     tw_l[t] = twn[t];
     dp_l[t] = dpow[t];
     di_l[t] = 1.0 / dpow[t];
@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(256) time_fwd_sk(Geo g, const double* __restri
   __syncthreads();
   const int stride = gridDim.x;
   int tile = tw.next(xcd_remap(blockIdx.x, gridDim.x), stride);
-  double r1[Q], r2[Q];  // v_1, v_2 at element e = threadIdx.x + q * 256 of the tile
+  double r1[Q], r2[Q];  // v_1, v_2 at element e = threadIdx.x + q * NT of the tile
   auto fetch = [&](int t) {
     const int b = t / tw.tpm;
     const int i0 = (t - b * tw.tpm) * P;
@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(256) time_fwd_sk(Geo g, const double* __restri
     const double* v2 = v1 + (size_t)n * m;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int e = threadIdx.x + q * 256;
+      const int e = threadIdx.x + q * NT;
       const int j = e / P, i = i0 + (e % P);
       const bool in = e < nP && i < m;
       r1[q] = in ? v1[(size_t)j * m + i] : 0.0;
@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(256) time_fwd_sk(Geo g, const double* __restri
     // c_j = s (d_j v2_j + i v1_j / d_j), stored at [j][p] = element e
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int e = threadIdx.x + q * 256;
+      const int e = threadIdx.x + q * NT;
       if (e < nP) {
         const int j = e / P;
         bufA[e] = cx<T>{(T)(s * dp_l[j] * r2[q]), (T)(s * di_l[j] * r1[q])};
@@ -103,11 +103,11 @@ __global__ void __launch_bounds__(256) time_fwd_sk(Geo g, const double* __restri
   }
 }
 
-// Q = register slots per thread for one tile's spectrum: K P <= Q * 256.
+// Q = register slots per thread for one tile's spectrum: K P <= Q * NT.
 // ACC: add into w instead of overwriting it (a compile-time switch, so the
 // common kernel issues no global loads besides the prefetch)
-template <class T, int P, int Q, int ACC>
-__global__ void __launch_bounds__(256) time_inv_sk(Geo g, const cx<T>* __restrict__ spec, double* __restrict__ w,
+template <class T, int P, int Q, int ACC, int NT>
+__global__ void __launch_bounds__(NT) time_inv_sk(Geo g, const cx<T>* __restrict__ spec, double* __restrict__ w,
                                                    const double* __restrict__ dpow, const cx<T>* __restrict__ twn,
                                                    FftPlan plan, TileWalk tw) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(256) time_inv_sk(Geo g, const cx<T>* __restric
   cx<T>* tw_l = bufB + n * P;
   double* dn_l = reinterpret_cast<double*>(tw_l + n);  // d_j / n
   double* di_l = dn_l + n;                              // 1 / (n d_j)
-  for (int t = threadIdx.x; t < n; t += 256) {
+  for (int t = threadIdx.x; t < n; t += NT) {
     tw_l[t] = twn[t];
     dn_l[t] = dpow[t] / (double)n;
     di_l[t] = 1.0 / ((double)n * dpow[t]);
@@ -126,14 +126,14 @@ __global__ void __launch_bounds__(256) time_inv_sk(Geo g, const cx<T>* __restric
   __syncthreads();
   const int stride = gridDim.x;
   int tile = tw.next(xcd_remap(blockIdx.x, gridDim.x), stride);
-  cx<T> r2[Q], r1[Q];  // Z_2, Z_1 at element e = threadIdx.x + q * 256 = k P + p
+  cx<T> r2[Q], r1[Q];  // Z_2, Z_1 at element e = threadIdx.x + q * NT = k P + p
   auto fetch = [&](int t) {
     const int b = t / tw.tpm;
     const int i0 = (t - b * tw.tpm) * P;
     const cx<T>* in = spec + (size_t)b * (size_t)(2 * K) * m;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int e = threadIdx.x + q * 256;
+      const int e = threadIdx.x + q * NT;
       const int k = e / P, i = i0 + (e % P);
       const bool ok = e < KP && i < m;
       r2[q] = ok ? in[(size_t)(2 * k) * m + i] : cx<T>{0, 0};
@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(256) time_inv_sk(Geo g, const cx<T>* __restric
     const int i0 = (tile - b * tw.tpm) * P;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int e = threadIdx.x + q * 256;
+      const int e = threadIdx.x + q * NT;
       if (e < KP) {
         const int k = e / P, p = e % P;
         const cx<T> z2 = r2[q], z1 = r1[q];
@@ -197,8 +197,9 @@ __global__ void __launch_bounds__(256) time_inv_sk(Geo g, const cx<T>* __restric
   }
 }
 
-// register slots: the two [n][P] buffers fit 64 KiB, so n P <= 2048 (FP64)
-// or 4096 (FP32) and K P <= n P / 2 + P
+// register slots: with 256 threads the two [n][P] buffers fit 64 KiB, so
+// n P <= 2048 (FP64) or 4096 (FP32) and K P <= n P / 2 + P; the wide kernels
+// (512 threads, two buffers of up to 128 KiB) keep the same slots per thread
 template <class T>
 constexpr int sk_q_fwd() { return sizeof(T) == 8 ? 8 : 16; }
 template <class T>
@@ -211,23 +212,39 @@ void launch_time_sk(bool fwd, int P, const Geo& g, const double* v, cx<T>* spec,
   TileWalk tw{(g.m + P - 1) / P, 0, tb.active};
   tw.ntiles = tw.tpm * g.B;
   // persistent grid: as many blocks as stay resident on every CU
-#define PCOP_TIME_SK(PP)                                                                                      \
+#define PCOP_TIME_SK_NT(PP, NTT)                                                                              \
   if (fwd) {                                                                                                  \
-    auto kern = time_fwd_sk<T, PP, sk_q_fwd<T>()>;                                                            \
-    const int grid = std::min(tw.ntiles, resident_blocks(kern, 256, lds) * std::max(1, tb.ncu));              \
-    kern<<<grid, 256, lds, st>>>(g, v, spec, tb.dpow, twn, tb.plan, vscale, vs_stride, tw);                    \
+    auto kern = time_fwd_sk<T, PP, sk_q_fwd<T>(), NTT>;                                                       \
+    const int grid = std::min(tw.ntiles, resident_blocks(kern, NTT, lds) * std::max(1, tb.ncu));              \
+    kern<<<grid, NTT, lds, st>>>(g, v, spec, tb.dpow, twn, tb.plan, vscale, vs_stride, tw);                   \
   } else {                                                                                                    \
-    auto kern = accum ? time_inv_sk<T, PP, sk_q_inv<T>(), 1> : time_inv_sk<T, PP, sk_q_inv<T>(), 0>;          \
-    const int grid = std::min(tw.ntiles, resident_blocks(kern, 256, lds) * std::max(1, tb.ncu));              \
-    kern<<<grid, 256, lds, st>>>(g, spec, w, tb.dpow, twn, tb.plan, tw);                                      \
+    auto kern = accum ? time_inv_sk<T, PP, sk_q_inv<T>(), 1, NTT> : time_inv_sk<T, PP, sk_q_inv<T>(), 0, NTT>; \
+    const int grid = std::min(tw.ntiles, resident_blocks(kern, NTT, lds) * std::max(1, tb.ncu));              \
+    kern<<<grid, NTT, lds, st>>>(g, spec, w, tb.dpow, twn, tb.plan, tw);                                      \
   }
-  if (P == 16) {
+#define PCOP_TIME_SK(PP) PCOP_TIME_SK_NT(PP, 256)
+  if (P == 16 && (size_t)2 * g.n * P * sizeof(cx<T>) > 65536) {
+    // wide tiles: two buffers above 64 KiB, 512 threads, one block per CU
+    static bool attr_set = false;
+    if (!attr_set) {
+      attr_set = true;
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(time_fwd_sk<T, 16, sk_q_fwd<T>(), 512>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(time_inv_sk<T, 16, sk_q_inv<T>(), 0, 512>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(time_inv_sk<T, 16, sk_q_inv<T>(), 1, 512>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (void)hipGetLastError();
+    }
+    PCOP_TIME_SK_NT(16, 512)
+  } else if (P == 16) {
     PCOP_TIME_SK(16)
   } else if (P == 8) {
     PCOP_TIME_SK(8)
   } else {
     PCOP_TIME_SK(4)
   }
+#undef PCOP_TIME_SK_NT
 #undef PCOP_TIME_SK
 }
 
