@@ -7,6 +7,9 @@
 // Basis vectors are stored unnormalised: the Arnoldi vector v_i equals
 // sc[b][i] * basis_i, which lets the normalisation ride along in the
 // coefficients instead of costing a pass over the vector.
+#include <array>
+#include <utility>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -45,15 +48,16 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NACC], int ncol
 }
 
 // Vectors are read as double2 (the length 2 n m of a member vector is even
-// and every base address is 16-byte aligned).
-template <int MAXNV>
-__global__ void __launch_bounds__(kNT) mdot_kernel(KrylovArgs ka, int nv, const double* __restrict__ w,
+// and every base address is 16-byte aligned).  NV (the number of basis
+// vectors) is a compile-time constant: every load is issued without a guard.
+template <int NV>
+__global__ void __launch_bounds__(kNT) mdot_kernel(KrylovArgs ka, const double* __restrict__ w,
                                                    double* __restrict__ partial, int nblk) {
   const int b = blockIdx.y;
   if (ka.active && !ka.active[b]) return;
-  double acc[MAXNV + 1];
+  double acc[NV + 1];
 #pragma unroll
-  for (int i = 0; i <= MAXNV; ++i) acc[i] = 0.0;
+  for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
   const double2* wb = reinterpret_cast<const double2*>(w + (size_t)b * ka.ms);
   const double2* vb = reinterpret_cast<const double2*>(ka.basis + (size_t)b * ka.ms);
   const long long n2 = ka.vl / 2;
@@ -61,56 +65,47 @@ __global__ void __launch_bounds__(kNT) mdot_kernel(KrylovArgs ka, int nv, const 
   for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < n2; e += (long long)nblk * kNT) {
     const double2 wv = wb[e];
 #pragma unroll
-    for (int i = 0; i < MAXNV; ++i)
-      if (i < nv) {
-        const double2 v = vb[(size_t)i * ss + e];
-        acc[i] += v.x * wv.x + v.y * wv.y;
-      }
-    acc[MAXNV] += wv.x * wv.x + wv.y * wv.y;
+    for (int i = 0; i < NV; ++i) {
+      const double2 v = vb[(size_t)i * ss + e];
+      acc[i] += v.x * wv.x + v.y * wv.y;
+    }
+    acc[NV] += wv.x * wv.x + wv.y * wv.y;
   }
-  // columns 0..nv-1: dots, column nv: the squared norm
-  double out[MAXNV + 1];
-#pragma unroll
-  for (int i = 0; i <= MAXNV; ++i) out[i] = (i < nv) ? acc[i] : ((i == nv) ? acc[MAXNV] : 0.0);
-  block_reduce_store<MAXNV + 1>(out, nv + 1, partial + ((size_t)b * nblk + blockIdx.x) * kRedStride);
+  // columns 0..NV-1: dots, column NV: the squared norm
+  block_reduce_store<NV + 1>(acc, NV + 1, partial + ((size_t)b * nblk + blockIdx.x) * kRedStride);
 }
 
 // the update keeps the basis values of its element in registers for the
 // second product, so it works on one double per thread and iteration
-template <int MAXNV>
-__global__ void __launch_bounds__(kNT) update_kernel(KrylovArgs ka, int nv, double* __restrict__ w,
+template <int NV>
+__global__ void __launch_bounds__(kNT) update_kernel(KrylovArgs ka, double* __restrict__ w,
                                                      const double* __restrict__ coef, int coef_ld,
                                                      double* __restrict__ partial, int nblk,
                                                      const int* __restrict__ skip) {
   const int b = blockIdx.y;
   if (ka.active && !ka.active[b]) return;
   if (skip && skip[b]) return;
-  __shared__ double c[MAXNV];
-  for (int i = threadIdx.x; i < MAXNV; i += kNT) c[i] = (i < nv) ? coef[(size_t)b * coef_ld + i] : 0.0;
+  __shared__ double c[NV > 0 ? NV : 1];
+  for (int i = threadIdx.x; i < NV; i += kNT) c[i] = coef[(size_t)b * coef_ld + i];
   __syncthreads();
-  double acc[MAXNV + 1];
+  double acc[NV + 1];
 #pragma unroll
-  for (int i = 0; i <= MAXNV; ++i) acc[i] = 0.0;
+  for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
   double* wb = w + (size_t)b * ka.ms;
   const double* vb = ka.basis + (size_t)b * ka.ms;
   for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < ka.vl; e += (long long)nblk * kNT) {
-    double v[MAXNV];
+    double v[NV > 0 ? NV : 1];
 #pragma unroll
-    for (int i = 0; i < MAXNV; ++i) v[i] = (i < nv) ? vb[(size_t)i * ka.slot_stride + e] : 0.0;
+    for (int i = 0; i < NV; ++i) v[i] = vb[(size_t)i * ka.slot_stride + e];
     double wv = wb[e];
 #pragma unroll
-    for (int i = 0; i < MAXNV; ++i)
-      if (i < nv) wv -= c[i] * v[i];
+    for (int i = 0; i < NV; ++i) wv -= c[i] * v[i];
     wb[e] = wv;
 #pragma unroll
-    for (int i = 0; i < MAXNV; ++i)
-      if (i < nv) acc[i] += v[i] * wv;
-    acc[MAXNV] += wv * wv;
+    for (int i = 0; i < NV; ++i) acc[i] += v[i] * wv;
+    acc[NV] += wv * wv;
   }
-  double out[MAXNV + 1];
-#pragma unroll
-  for (int i = 0; i <= MAXNV; ++i) out[i] = (i < nv) ? acc[i] : ((i == nv) ? acc[MAXNV] : 0.0);
-  block_reduce_store<MAXNV + 1>(out, nv + 1, partial + ((size_t)b * nblk + blockIdx.x) * kRedStride);
+  block_reduce_store<NV + 1>(acc, NV + 1, partial + ((size_t)b * nblk + blockIdx.x) * kRedStride);
 }
 
 // the same update on double2 pairs (two elements per thread and step)
@@ -290,9 +285,24 @@ __global__ void set_scale_kernel(const double* __restrict__ red, int col, int B,
     else KERNEL<kMaxBasis><<<GRID, kNT, 0, ST>>>(__VA_ARGS__);                        \
   } while (0)
 
+// exact-size kernels for nv = 0 .. kMaxBasis - 1
+using MdotFn = void (*)(KrylovArgs, const double*, double*, int);
+using UpdateFn = void (*)(KrylovArgs, double*, const double*, int, double*, int, const int*);
+template <int... I>
+constexpr std::array<MdotFn, sizeof...(I)> mdot_table(std::integer_sequence<int, I...>) {
+  return {&mdot_kernel<I>...};
+}
+template <int... I>
+constexpr std::array<UpdateFn, sizeof...(I)> update_table(std::integer_sequence<int, I...>) {
+  return {&update_kernel<I>...};
+}
+static const auto kMdot = mdot_table(std::make_integer_sequence<int, kMaxBasis>{});
+static const auto kUpdate = update_table(std::make_integer_sequence<int, kMaxBasis>{});
+
 void launch_mdot(const KrylovArgs& ka, int nv, const double* w, double* partial, int nblk, hipStream_t st) {
   dim3 grid(nblk, ka.B);
-  PCOP_DISPATCH_NV(mdot_kernel, nv, grid, st, ka, nv, w, partial, nblk);
+  if (nv < 0 || nv >= kMaxBasis) return;
+  kMdot[nv]<<<grid, kNT, 0, st>>>(ka, w, partial, nblk);
 }
 
 void launch_update(const KrylovArgs& ka, int nv, double* w, const double* coef, int coef_ld, double* partial,
@@ -300,8 +310,8 @@ void launch_update(const KrylovArgs& ka, int nv, double* w, const double* coef, 
   dim3 grid(nblk, ka.B);
   if (ka.pairs) {
     PCOP_DISPATCH_NV(update2_kernel, nv, grid, st, ka, nv, w, coef, coef_ld, partial, nblk, skip);
-  } else {
-    PCOP_DISPATCH_NV(update_kernel, nv, grid, st, ka, nv, w, coef, coef_ld, partial, nblk, skip);
+  } else if (nv >= 0 && nv < kMaxBasis) {
+    kUpdate[nv]<<<grid, kNT, 0, st>>>(ka, w, coef, coef_ld, partial, nblk, skip);
   }
 }
 
