@@ -9,8 +9,10 @@ namespace pcop {
 
 // y = c - s A x  (c != nullptr)  or  y = s A x, with A or A^T (sgn = -1).
 // One thread per spatial point, marching over a chunk of time blocks so that
-// x1^{j-1} and x2^{j+1} are loaded once.
-template <int DIM, bool VAR>
+// x1^{j-1} and x2^{j+1} are loaded once.  JC > 0: the chunk is JC levels, a
+// compile-time count, so the loop unrolls and the loads of every level are
+// issued before the first result is formed; JC = 0: jchunk levels at run time.
+template <int DIM, bool VAR, int JC>
 __global__ void __launch_bounds__(256) kkt_apply_kernel(
     Geo g, const double* __restrict__ x, double* __restrict__ y, const double* __restrict__ c,
     const double* __restrict__ alpha, const double* __restrict__ xscale, int xs_stride,
@@ -43,13 +45,12 @@ __global__ void __launch_bounds__(256) kkt_apply_kernel(
   const StencilW sw = load_stencil<DIM, VAR>(i, m, ecoef, ediag, eoff);
   double x1prev = (j0 > 0) ? x1[(size_t)(j0 - 1) * m + i] : 0.0;
   double x2cur = x2[(size_t)j0 * m + i];
-  for (int j = j0; j < j1; ++j) {
+  // one time level: block row 1 alpha x1 + T^T x2, block row 2 -T x1 + alpha x2
+  auto level = [&](int j, double x2next) {
     const size_t o = (size_t)j * m;
     const double x1cur = x1[o + i];
-    const double x2next = (j + 1 < n) ? x2[o + m + i] : 0.0;
     const double ex2 = apply_E_w<DIM, VAR>(x2 + o, i, c1, c2, c3, nx, sw);
     const double ex1 = apply_E_w<DIM, VAR>(x1 + o, i, c1, c2, c3, nx, sw);
-    // block row 1: alpha x1 + T^T x2;  block row 2: -T x1 + alpha x2
     double r1 = a * x1cur + sgn * (ex2 - x2next);
     double r2 = a * x2cur - sgn * (ex1 - x1prev);
     r1 *= s;
@@ -62,6 +63,14 @@ __global__ void __launch_bounds__(256) kkt_apply_kernel(
     y2[o + i] = r2;
     x1prev = x1cur;
     x2cur = x2next;
+  };
+  if (JC > 0 && j0 + JC < n) {
+    // a full chunk followed by another level: no guards, so every load of
+    // the chunk can be issued up front
+#pragma unroll
+    for (int jj = 0; jj < (JC > 0 ? JC : 1); ++jj) level(j0 + jj, x2[(size_t)(j0 + jj + 1) * m + i]);
+  } else {
+    for (int j = j0; j < j1; ++j) level(j, (j + 1 < n) ? x2[(size_t)(j + 1) * m + i] : 0.0);
   }
 }
 
@@ -71,17 +80,31 @@ void launch_kkt_apply(const Geo& g, const double* x, double* y, const double* c,
   if (jchunk < 1) jchunk = 16;
   dim3 grid((g.m + 255) / 256, (g.n + jchunk - 1) / jchunk, g.B);
   const double sgn = transpose ? -1.0 : 1.0;
-  if (g.dim == 2) {
-    if (ecoef)
-      kkt_apply_kernel<2, true><<<grid, 256, 0, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn, ecoef, ediag, eoff, jchunk);
-    else
-      kkt_apply_kernel<2, false><<<grid, 256, 0, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn, ecoef, ediag, eoff, jchunk);
-  } else {
-    if (ecoef)
-      kkt_apply_kernel<3, true><<<grid, 256, 0, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn, ecoef, ediag, eoff, jchunk);
-    else
-      kkt_apply_kernel<3, false><<<grid, 256, 0, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn, ecoef, ediag, eoff, jchunk);
+#define PCOP_KKT(D, V, J) \
+  kkt_apply_kernel<D, V, J><<<grid, 256, 0, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn, ecoef, ediag, eoff, jchunk)
+#define PCOP_KKT_J(D, V)        \
+  switch (jchunk) {             \
+    case 1: PCOP_KKT(D, V, 1); break; \
+    case 2: PCOP_KKT(D, V, 2); break; \
+    case 4: PCOP_KKT(D, V, 4); break; \
+    case 8: PCOP_KKT(D, V, 8); break; \
+    default: PCOP_KKT(D, V, 0); break; \
   }
+  if (g.dim == 2) {
+    if (ecoef) {
+      PCOP_KKT_J(2, true)
+    } else {
+      PCOP_KKT_J(2, false)
+    }
+  } else {
+    if (ecoef) {
+      PCOP_KKT_J(3, true)
+    } else {
+      PCOP_KKT_J(3, false)
+    }
+  }
+#undef PCOP_KKT_J
+#undef PCOP_KKT
 }
 
 // ---------------------------------------------------------------------------
