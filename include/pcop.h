@@ -113,8 +113,11 @@ typedef struct {
  *              with at most that many points per block; 4 / 8 / 16 in-place
  *              Stockham (one LDS buffer) with at most that many points per
  *              block.  A kind of kernel that does not fit LDS falls back to
- *              the other.  Ignored when nt - 1 has a prime factor above 17
- *              (chirp-z kernels).
+ *              the other.  When nt - 1 has a prime factor above 17 the
+ *              chirp-z kernels run instead: 0 / -1 automatic, 4 / 8 / 16 at
+ *              most that many points per block with 256 threads, -4 / -8 /
+ *              -16 with 512 threads (a request that fits no kernel falls back
+ *              to the automatic choice).
  *   dst_kernel sine-transform kernels of step 2 (PCOP_DST): 0 automatic,
  *              1 register-resident lines, 2 lines staged through LDS,
  *              3 register-resident lines with twice as many strided lines
@@ -254,8 +257,10 @@ pcop_status pcop_error_eh(pcop_ctx ctx, const double* x, const double* yN, const
 pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* eps);
 
 /* Kernel choices in effect (after tuning):
- *   time_cols      -P (two LDS buffers, P points per block), +P (in place)
- *                  or 0 (chirp-z, or no time transform with PCOP_PRECOND_IDEAL);
+ *   time_cols      Stockham: -P (two LDS buffers, P points per block) or
+ *                  +P (in place); chirp-z (nt - 1 with a prime factor above
+ *                  17): +P (P points, 256 threads) or -P (512 threads);
+ *                  0 with PCOP_PRECOND_IDEAL (no time transform);
  *   dst_kernel     1 (register-resident), 2 (LDS-staged), 3 (register, wide
  *                  column tiles) or 0 (multigrid);
  *   kkt_jchunk     time levels per thread of the KKT matvec;

@@ -427,15 +427,21 @@ pcop_status tune_kernels(pcop_ctx c) {
     }
   }
   std::vector<int> tcs;
-  if (c->opt.time_cols != 0 || c->tb.plan.bluestein || c->opt.precond == PCOP_PRECOND_IDEAL) {
+  if (c->opt.time_cols != 0 || c->opt.precond == PCOP_PRECOND_IDEAL) {
     tcs.push_back(c->tb.time_cols);
   } else {
     std::vector<int> seen;
-    for (int want : {-8, -16, -4, 16, 8, 4}) {
+    // chirp-z: the automatic tile first, then every width with 256 and 512
+    // threads; Stockham: two buffers and in place with 16, 8, 4 points
+    const std::vector<int> wants = c->tb.plan.bluestein ? std::vector<int>{0, 16, 8, 4, -16, -8, -4}
+                                                        : std::vector<int>{-8, -16, -4, 16, 8, 4};
+    for (int want : wants) {
       PrecondTables t = c->tb;
       t.time_cols = want;
       const int eff = time_choice(g, t, c->fp32);
-      if (eff == 0 || (eff < 0) != (want < 0)) continue;  // this kind of kernel does not fit
+      if (eff == 0) continue;
+      // a Stockham request of one kind that falls back to the other
+      if (!c->tb.plan.bluestein && (eff < 0) != (want < 0)) continue;
       if (std::find(seen.begin(), seen.end(), eff) != seen.end()) continue;
       seen.push_back(eff);
       tcs.push_back(want);

@@ -37,12 +37,6 @@ static int time_cols_sk(int n, int csz, int want, bool wide = false) {
     if ((size_t)2 * n * P * csz <= 65536 && sk_lds_bytes(n, P, csz) <= 81920) return P;
   return 0;
 }
-static int time_cols_bl(int M, int csz) {
-  const int pmin = (M >= 2048) ? 1 : 4;
-  for (int P = 16; P >= pmin; P /= 2)
-    if ((size_t)(M + 1) * P * csz <= kBlueLds && M <= 4096) return P;
-  return 0;
-}
 
 
 FftPlan make_time_plan(int n) {
@@ -107,11 +101,11 @@ static int time_block(const FftPlan& pl, int n, int csz, int req) {
 bool time_lds_fits(int n, bool fp32) {
   const FftPlan pl = make_time_plan(n);
   const int csz = fp32 ? 8 : 16;
-  return pl.bluestein ? time_cols_bl(pl.M, csz) > 0 : time_block(pl, n, csz, 0) != 0;
+  return pl.bluestein ? bl_choice(pl.M, n, csz, 0) != 0 : time_block(pl, n, csz, 0) != 0;
 }
 
 int time_choice(const Geo& g, const PrecondTables& tb, bool fp32) {
-  if (tb.plan.bluestein) return 0;
+  if (tb.plan.bluestein) return bl_choice(tb.plan.M, g.n, fp32 ? 8 : 16, tb.time_cols);
   return time_block(tb.plan, g.n, fp32 ? 8 : 16, tb.time_cols);
 }
 
@@ -123,8 +117,8 @@ static bool time_pass(bool fwd, const Geo& g, const double* v, cx<T>* spec, doub
                 f32 ? (const void*)tb.chirp32 : (const void*)tb.chirp64, f32 ? (const void*)tb.bhat32 : (const void*)tb.bhat64};
   const int csz = (int)sizeof(cx<T>);
   if (tb.plan.bluestein) {
-    const int P = time_cols_bl(tb.plan.M, csz);
-    return P > 0 && launch_time_bl<T>(fwd, P, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st);
+    const int c = bl_choice(tb.plan.M, g.n, csz, tb.time_cols);
+    return c != 0 && launch_time_bl<T>(fwd, c, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st);
   }
   const cx<T>* twn = reinterpret_cast<const cx<T>*>(tt.twn);
   const int c = time_block(tb.plan, g.n, csz, tb.time_cols);

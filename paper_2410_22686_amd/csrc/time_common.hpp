@@ -70,6 +70,20 @@ __device__ __forceinline__ void combine_store(double* w1, double* w2, const doub
 }
 
 
+// Column tiles of the persistent time kernels: tile t covers member
+// t / tiles_per_member and spatial points i0 .. i0 + P - 1 with
+// i0 = (t mod tiles_per_member) P.
+struct TileWalk {
+  int tpm;     // tiles per member
+  int ntiles;  // B * tpm
+  const int* active;
+  // first tile at or after t (stepping by stride) whose member is active
+  __device__ __forceinline__ int next(int t, int stride) const {
+    while (t < ntiles && active && !active[t / tpm]) t += stride;
+    return t;
+  }
+};
+
 // per-variant launchers (one translation unit each)
 template <class T>
 void launch_time_sk(bool fwd, int P, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
@@ -78,10 +92,38 @@ template <class T, bool FWD>
 void launch_time_ip_dir(int P, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
                         const cx<T>* twn, const double* vscale, int vs_stride, int accum, hipStream_t st);
 template <class T>
-bool launch_time_bl(bool fwd, int P, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
+bool launch_time_bl(bool fwd, int c, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
                     const TimeTables& tt, const double* vscale, int vs_stride, int accum, hipStream_t st);
-// chirp-z tiles are static LDS; up to 80 KiB keeps two blocks per CU
-constexpr size_t kBlueLds = 81920;
+// chirp-z kernels for the request req (pcop_options::time_cols): +P for P
+// points per block with 256 threads, -P with 512 threads, 0 when no shape
+// fits.  0 and -1 pick automatically; an explicit request is honoured with
+// at most that many points, else the automatic choice is used.
+int bl_choice(int M, int n, int csz, int req);
+
+// Chirp-z tile shapes (M = convolution length, P points per block, NT
+// threads) that exist as kernels: one [P][M+1] buffer of at most 160 KiB,
+// M P <= 8192 (with n <= M/2 at most 16 prefetch slots per thread, and no
+// register spills), fewer than 4 points only for M >= 1024, and 512 threads
+// only for large tiles.
+constexpr size_t kLdsMax = 160 * 1024;
+constexpr bool bl_shape_ok(int M, int P, int NT, int csz) {
+  return M >= 64 && M <= 4096 && (NT == 256 || NT == 512) && M * P <= 8192 &&
+         (size_t)(M + 1) * P * csz <= kLdsMax && (P >= 4 || M >= 1024) &&
+         (NT == 256 || (P >= 4 && M * P >= 4096));
+}
+// The tables (twiddles, filter spectrum, chirp, D_eps factors) go to LDS too
+// when they fit beside the buffer for every n <= M/2: 8M bytes of twiddles
+// (FP64 stages read only the first half), the M/2 + 1 distinct filter
+// values (the filter is even), n chirp values and two tables of n doubles.
+constexpr bool bl_tables_in_lds(int M, int P, int csz) {
+  return (size_t)(M + 1) * P * csz + 8 * (size_t)M + (size_t)(M / 2 + 1) * csz + (size_t)(M / 2) * (csz + 16) <=
+         kLdsMax;
+}
+inline size_t bl_lds_bytes(int M, int P, int n, int csz) {
+  size_t b = (size_t)(M + 1) * P * csz;
+  if (bl_tables_in_lds(M, P, csz)) b += 8 * (size_t)M + (size_t)(M / 2 + 1) * csz + (size_t)n * (csz + 16);
+  return b;
+}
 // dynamic LDS of the two-buffer kernels: two [n][P] buffers, the n twiddles
 // and two tables of n scale factors (D_eps powers and their inverses)
 inline size_t sk_lds_bytes(int n, int P, size_t csz) { return (2 * (size_t)P + 1) * n * csz + 16 * (size_t)n; }

@@ -16,16 +16,6 @@ namespace pcop {
 //
 // Tile t covers member t / tiles_per_member and spatial points
 // i0 .. i0 + P - 1 with i0 = (t mod tiles_per_member) P.
-struct TileWalk {
-  int tpm;     // tiles per member
-  int ntiles;  // B * tpm
-  const int* active;
-  // first tile at or after t (stepping by stride) whose member is active
-  __device__ __forceinline__ int next(int t, int stride) const {
-    while (t < ntiles && active && !active[t / tpm]) t += stride;
-    return t;
-  }
-};
 
 // Q = register slots per thread for one tile's inputs: n P <= Q * NT
 template <class T, int P, int Q, int NT>

@@ -168,6 +168,55 @@ def test_precond_kernel_choices(dim, nx, nt, gammas, precision):
                 assert rel(w, ref) < (1e-5 if precision == "mixed" else 1e-14), (dk, tc, eff)
 
 
+CHIRP_CASES = [
+    # dim, nx, nt, gammas: lengths with a prime factor above 17 (chirp-z)
+    (2, 7, 20, (1e-4, 1e-8)),    # n = 19, M = 64, two members
+    (2, 15, 128, (1e-6,)),       # n = 127, M = 256 (the 127-point workloads)
+    (2, 3, 512, (1e-6,)),        # n = 511 = 7 * 73, M = 1024
+    (2, 3, 1024, (1e-4,)),       # n = 1023 = 3 * 11 * 31, M = 2048
+    (2, 3, 2048, (1e-4,)),       # n = 2047 = 23 * 89, M = 4096: FP64 tables stay in global memory
+]
+
+
+@pytest.mark.parametrize("dim,nx,nt,gammas", CHIRP_CASES)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_chirp_kernel_choices(dim, nx, nt, gammas, precision):
+    """Every chirp-z tile shape (points per block with 256 or 512 threads)
+    matches the oracle, and the shapes agree with each other to rounding (same
+    operations per element; FMA contraction may differ between instances, and
+    the two length-M FFTs of the convolution add about log2 M roundings of
+    the largest spectral values, hence 1e-13 in FP64).  In FP32 the two FFTs
+    give errors of about u log2 M (u = 6e-8), which D_eps^{-1} amplifies by up
+    to 1/eps = sqrt(n) in the last time levels: the bar is twice that product,
+    at least 1e-5."""
+    print(f"chirp-z choices {precision} dim={dim} nx={nx} nt={nt} B={len(gammas)}", flush=True)
+    side = "flexible" if precision == "mixed" else "right"
+    v = W.random_vector(dim, nx, nt, seed=23, batch=len(gammas))
+    wos = [P.EpsCirculantRBD(pb).apply(v[b].ravel()) for b, pb in enumerate(problems(dim, nx, nt, gammas))]
+    n = nt - 1
+    M = 1 << (2 * n - 2).bit_length()
+    tol32 = max(1e-5, 2 * 6e-8 * np.log2(M) * np.sqrt(n))
+    tol = tol32 if precision == "mixed" else 1e-11
+    ref, seen = None, set()
+    for tc in (0, 16, 8, 4, -16, -8, -4):
+        s = Solver(dim, nx, nt, list(gammas), precision=precision, side=side, time_cols=tc, device=DEV)
+        eff = s.kernels["time_cols"]
+        assert eff in (16, 8, 4, 2, 1, -16, -8, -4), eff
+        if tc != 0 and (eff < 0) == (tc < 0):
+            assert abs(eff) <= abs(tc)
+        if eff in seen:
+            continue
+        seen.add(eff)
+        w = s.precond_apply(to_dev(v)).cpu().numpy()
+        for b in range(len(gammas)):
+            assert rel(w[b], wos[b]) < tol, (tc, eff, b, rel(w[b], wos[b]))
+        if ref is None:
+            ref = w
+        else:
+            assert rel(w, ref) < (tol32 if precision == "mixed" else 1e-13), (tc, eff, rel(w, ref))
+    print(f"  shapes run: {sorted(seen)}", flush=True)
+
+
 def test_tuned_solve_matches_default():
     """tune = 1 picks kernels by timing; the solve gives the same iterate."""
     dim, nx, nt, gammas = 2, 31, 64, (1e-2, 1e-6)
