@@ -124,8 +124,10 @@ typedef struct {
  *              per block (512 threads).
  *   tune       1: pcop_setup times the candidates of every kernel choice
  *              left at 0 ("automatic": time_cols, dst_kernel, kkt_jchunk,
- *              krylov_blocks, gs_update) on the context's stream and keeps the fastest; the choice is cached per device and
- *              shape for the process.  0: built-in choices.  All choices give
+ *              krylov_blocks, gs_update) on the context's stream and keeps
+ *              the fastest (the Krylov choices per basis size); the choice
+ *              is cached per device and shape for the process.  0:
+ *              built-in choices.  All choices give
  *              the same iterates up to rounding (the reduction order follows
  *              the block count).
  *   precond    PCOP_PRECOND_EPS: the epsilon-circulant RBD preconditioner
@@ -136,8 +138,9 @@ typedef struct {
  *              comparison method of Tables 4 and 8).  time_cols is ignored.
  *   kkt_jchunk time levels per thread of the KKT matvec: 0 automatic (16, or
  *              the tuner's choice), else 1..64.
- *   krylov_blocks  blocks per member of the Krylov reductions: 0 automatic,
- *              else 1..4096 (the reduction order, and so the rounding,
+ *   krylov_blocks  blocks per member of the Krylov reductions: 0 automatic
+ *              (with tune = 1: chosen per basis size), else 1..4096 for
+ *              every size (the reduction order, and so the rounding,
  *              follows it).
  *   gs_update  Gram-Schmidt update kernel: 0 automatic, 1 one element per
  *              thread and step, 2 double2 pairs.
@@ -264,8 +267,11 @@ pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* ep
  *   dst_kernel     1 (register-resident), 2 (LDS-staged), 3 (register, wide
  *                  column tiles) or 0 (multigrid);
  *   kkt_jchunk     time levels per thread of the KKT matvec;
- *   krylov_blocks  blocks per member of the Krylov reductions;
- *   gs_update      1 (one element per thread) or 2 (double2 pairs);
+ *   krylov_blocks  blocks per member of the Krylov multi-dot over the full
+ *                  basis (the tuner picks counts per basis size: shorter
+ *                  bases may use others);
+ *   gs_update      1 (one element per thread) or 2 (double2 pairs), the
+ *                  update kernel over the full basis;
  *   tuned_precond_ms  the fastest preconditioner apply measured by the
  *                  tuner, 0 when no tuning ran. */
 typedef struct {

@@ -327,14 +327,25 @@ __device__ __forceinline__ void ip_stage_rt(int R, int n, int Ns, const cx<T>* _
   }
 }
 
+// identity output map of the FFT stages
+struct P2Keep {
+  template <class V>
+  __device__ __forceinline__ V operator()(int, V v) const { return v; }
+};
+
 // One in-place Stockham stage with radix R over LINES lines of length L held
 // in LDS ([LINES][ld]).  Each thread keeps its butterflies in registers
 // between the two barriers, which makes the stage safe in place.
-// twL[t] = exp(-2 pi i t / L).
-template <class T, int SG, int L, int R, int LINES, int NT>
-__device__ __forceinline__ void p2_stage(cx<T>* buf, int ld, int Ns, const cx<T>* __restrict__ twL) {
+// twL[t] = exp(-2 pi i t / L) (FP64 reads t < L/2 only).
+// HALF_IN (first stage): the inputs at L/2 and above are zero and not read.
+// HALF_OUT (last stage): only the outputs below L/2 are written.
+// post(k, value) maps each output k before it is written.
+template <class T, int SG, int L, int R, int LINES, int NT, bool HALF_IN, bool HALF_OUT, class POST>
+__device__ __forceinline__ void p2_stage_x(cx<T>* buf, int ld, int Ns, const cx<T>* __restrict__ twL, POST post) {
   constexpr int NB = LINES * (L / R);
   constexpr int PER = (NB + NT - 1) / NT;
+  constexpr int RIN = HALF_IN ? R / 2 : R;
+  constexpr int ROUT = HALF_OUT ? R / 2 : R;
   cx<T> v[PER][R];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
@@ -343,7 +354,7 @@ __device__ __forceinline__ void p2_stage(cx<T>* buf, int ld, int Ns, const cx<T>
       const int line = bf / (L / R);
       const int jb = bf - line * (L / R);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = buf[line * ld + jb + r * (L / R)];
+      for (int r = 0; r < R; ++r) v[q][r] = r < RIN ? buf[line * ld + jb + r * (L / R)] : cx<T>{0, 0};
     }
   }
   __syncthreads();
@@ -377,30 +388,47 @@ __device__ __forceinline__ void p2_stage(cx<T>* buf, int ld, int Ns, const cx<T>
       dftR<T, SG, R>(v[q]);
       const int base = (jb / Ns) * Ns * R + jl;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[line * ld + base + r * Ns] = v[q][r];
+      for (int r = 0; r < ROUT; ++r) buf[line * ld + base + r * Ns] = post(base + r * Ns, v[q][r]);
     }
   }
   __syncthreads();
 }
 
-template <class T, int SG, int L, int LINES, int NT, int NS>
+template <class T, int SG, int L, int R, int LINES, int NT>
+__device__ __forceinline__ void p2_stage(cx<T>* buf, int ld, int Ns, const cx<T>* __restrict__ twL) {
+  p2_stage_x<T, SG, L, R, LINES, NT, false, false>(buf, ld, Ns, twL, P2Keep{});
+}
+
+// the stages from size NS on; HALF_IN applies to the first stage, HALF_OUT
+// and post to the last
+template <class T, int SG, int L, int LINES, int NT, int NS, bool HALF_IN, bool HALF_OUT>
 struct P2Stages {
-  static __device__ __forceinline__ void run(cx<T>* buf, int ld, const cx<T>* __restrict__ twL) {
+  template <class POST>
+  static __device__ __forceinline__ void run(cx<T>* buf, int ld, const cx<T>* __restrict__ twL, POST post) {
     constexpr int R = (L / NS >= 8) ? 8 : (L / NS);
-    p2_stage<T, SG, L, R, LINES, NT>(buf, ld, NS, twL);
-    P2Stages<T, SG, L, LINES, NT, NS * R>::run(buf, ld, twL);
+    constexpr bool first = NS == 1;
+    if constexpr (NS * R == L) {
+      p2_stage_x<T, SG, L, R, LINES, NT, HALF_IN && first, HALF_OUT>(buf, ld, NS, twL, post);
+    } else {
+      p2_stage_x<T, SG, L, R, LINES, NT, HALF_IN && first, false>(buf, ld, NS, twL, P2Keep{});
+      P2Stages<T, SG, L, LINES, NT, NS * R, HALF_IN, HALF_OUT>::run(buf, ld, twL, post);
+    }
   }
-};
-template <class T, int SG, int L, int LINES, int NT>
-struct P2Stages<T, SG, L, LINES, NT, L> {
-  static __device__ __forceinline__ void run(cx<T>*, int, const cx<T>* __restrict__) {}
 };
 
 // In-place FFT of LINES lines of power-of-two length L; call with all
 // threads of the block after a barrier that publishes the data.
 template <class T, int SG, int L, int LINES, int NT>
 __device__ __forceinline__ void p2_fft(cx<T>* buf, int ld, const cx<T>* __restrict__ twL) {
-  P2Stages<T, SG, L, LINES, NT, 1>::run(buf, ld, twL);
+  P2Stages<T, SG, L, LINES, NT, 1, false, false>::run(buf, ld, twL, P2Keep{});
+}
+
+// The same FFT for zero-padded convolutions: with HALF_IN the inputs at L/2
+// and above are zero (and need not be in LDS), with HALF_OUT only outputs
+// below L/2 are produced; post(k, X_k) maps the outputs (a pointwise filter).
+template <class T, int SG, int L, int LINES, int NT, bool HALF_IN, bool HALF_OUT, class POST>
+__device__ __forceinline__ void p2_fft_x(cx<T>* buf, int ld, const cx<T>* __restrict__ twL, POST post) {
+  P2Stages<T, SG, L, LINES, NT, 1, HALF_IN, HALF_OUT>::run(buf, ld, twL, post);
 }
 
 }  // namespace pcop

@@ -300,8 +300,10 @@ struct pcop_ctx_s {
   bool fp32 = false;
   double tuned_ms = 0;
   int kkt_jchunk = 16;  // time levels per thread of the matvec
-  int nblk = 1;         // blocks per member of the Krylov reductions
-  int upd_pairs = 0;    // Gram-Schmidt update on double2 pairs
+  // per basis size nv: blocks per member of the multi-dot and of the
+  // Gram-Schmidt update, and the update kernel (double2 pairs or doubles);
+  // the best block count depends on how many vectors a kernel streams
+  std::array<int, kMaxBasis> nb_mdot{}, nb_upd{}, pairs_upd{};
   EventTimer timer;
   KTimer ktimer{&EventTimer::on_begin, &EventTimer::on_end, nullptr};
   // pinned host staging for every scalar transfer of the solver
@@ -329,7 +331,7 @@ struct pcop_ctx_s {
   double* basis(int slot) const { return at<double>(L.basis) + (size_t)slot * (size_t)g.vs * g.B; }
   double* zbasis(int slot) const { return at<double>(L.zbasis) + (size_t)slot * (size_t)g.vs * g.B; }
   KrylovArgs kargs(const double* base, const int* mask) const {
-    return KrylovArgs{base, (long long)g.vs * g.B, g.vl, g.vs, g.B, mask, upd_pairs};
+    return KrylovArgs{base, (long long)g.vs * g.B, g.vl, g.vs, g.B, mask, 0};
   }
   // the geometry of the caller's unpadded vectors
   Geo user_geo() const {
@@ -374,14 +376,22 @@ void do_kkt(pcop_ctx c, const double* x, double* y, const double* cvec, const do
 
 void do_mdot(pcop_ctx c, const KrylovArgs& ka, int nv, const double* w, int nact) {
   tbeg(c->kt(), KF_MDOT, 8.0 * (nv + 1) * c->g.vl * nact);
-  launch_mdot(ka, nv, w, c->at<double>(c->L.partial), c->nblk, c->st);
+  launch_mdot(ka, nv, w, c->at<double>(c->L.partial), c->nb_mdot[nv], c->st);
   tend(c->kt());
+}
+
+// the Gram-Schmidt update over nv basis vectors with the kernel and block
+// count chosen for that size (partials as launch_update writes them)
+void launch_update_nv(pcop_ctx c, const KrylovArgs& ka, int nv, double* w, const int* skip, hipStream_t st) {
+  KrylovArgs k2 = ka;
+  k2.pairs = c->pairs_upd[nv];
+  launch_update(k2, nv, w, c->at<double>(c->L.coef), kMaxBasis, c->at<double>(c->L.partial), c->nb_upd[nv], skip,
+                st);
 }
 
 void do_update(pcop_ctx c, const KrylovArgs& ka, int nv, double* w, const int* skip, int nact) {
   tbeg(c->kt(), KF_UPDATE, 8.0 * (nv + 2) * c->g.vl * nact);
-  launch_update(ka, nv, w, c->at<double>(c->L.coef), kMaxBasis, c->at<double>(c->L.partial), c->nblk, skip,
-                c->st);
+  launch_update_nv(c, ka, nv, w, skip, c->st);
   tend(c->kt());
 }
 
@@ -389,7 +399,7 @@ void do_update(pcop_ctx c, const KrylovArgs& ka, int nv, double* w, const int* s
 void do_norm2(pcop_ctx c, const double* w, const int* mask, int nact) {
   KrylovArgs ka = c->kargs(c->basis(0), mask);
   do_mdot(c, ka, 0, w, nact);
-  launch_reduce_partials(c->at<double>(c->L.partial), c->nblk, 1, c->g.B, c->at<double>(c->L.red), c->st);
+  launch_reduce_partials(c->at<double>(c->L.partial), c->nb_mdot[0], 1, c->g.B, c->at<double>(c->L.red), c->st);
 }
 
 // ---------------------------------------------------------------------------
@@ -401,7 +411,8 @@ void do_norm2(pcop_ctx c, const double* w, const int* mask, int nact) {
 struct TuneResult {
   int time_cols, dst_variant;
   double ms;  // fastest preconditioner apply
-  int jchunk, nblk, pairs;
+  int jchunk;
+  std::array<int, kMaxBasis> nb_mdot, nb_upd, pairs_upd;
 };
 std::mutex g_tune_mu;
 std::map<std::array<int, 14>, TuneResult> g_tune_cache;
@@ -421,8 +432,9 @@ pcop_status tune_kernels(pcop_ctx c) {
       c->tb.dst_variant = it->second.dst_variant;
       c->tuned_ms = it->second.ms;
       c->kkt_jchunk = it->second.jchunk;
-      c->nblk = it->second.nblk;
-      c->upd_pairs = it->second.pairs;
+      c->nb_mdot = it->second.nb_mdot;
+      c->nb_upd = it->second.nb_upd;
+      c->pairs_upd = it->second.pairs_upd;
       return PCOP_OK;
     }
   }
@@ -480,7 +492,7 @@ pcop_status tune_kernels(pcop_ctx c) {
   // a later candidate must beat the current best by 1% (the candidate lists
   // start with the built-in choices), so timing noise does not flip choices
   auto better = [](double ms, double best_ms) { return ms < 0.99 * best_ms; };
-  TuneResult best{c->tb.time_cols, c->tb.dst_variant, 1e300, c->kkt_jchunk, c->nblk, c->upd_pairs};
+  TuneResult best{c->tb.time_cols, c->tb.dst_variant, 1e300, c->kkt_jchunk, c->nb_mdot, c->nb_upd, c->pairs_upd};
   // preconditioner kernels
   for (int tc : tcs) {
     for (int dv : dvs) {
@@ -516,39 +528,68 @@ pcop_status tune_kernels(pcop_ctx c) {
       best.jchunk = jc;
     }
   }
-  // Krylov reductions: blocks per member, timed on a multi-dot and an update
-  // over nv basis vectors (zeroed first: the coefficients and skip flags too)
-  const int nv = std::min(10, c->opt.restart);
+  // Krylov reductions: blocks per member for the multi-dot and the update,
+  // and the update kernel, timed at sample basis sizes; every size takes the
+  // choice of the nearest sample.  A restart cycle runs every size from 1 to
+  // the restart length, and the best block count moves with the number of
+  // vectors streamed (more blocks hide more latency once the kernels hold
+  // many vectors in registers, fewer finish short sweeps sooner).  The
+  // vectors are zeroed first, the coefficients and skip flags too.
+  std::vector<int> nvs;
+  for (int nv : {1, 4, 8, 16, 24, 32, 40})
+    if (nv < c->opt.restart) nvs.push_back(nv);
+  nvs.push_back(c->opt.restart);
   if (err == hipSuccess)
-    err = hipMemsetAsync(c->basis(0), 0, sizeof(double) * (size_t)g.vs * g.B * (nv + 1), st);
+    err = hipMemsetAsync(c->basis(0), 0, sizeof(double) * (size_t)g.vs * g.B * (nvs.back() + 1), st);
   if (err == hipSuccess) err = hipMemsetAsync(c->at<double>(c->L.coef), 0, sizeof(double) * g.B * kMaxBasis, st);
   if (err == hipSuccess) err = hipMemsetAsync(c->at<int>(c->L.skip), 0, sizeof(int) * g.B, st);
-  double best_kr = 1e300;
-  std::vector<int> tried;
-  for (int f : {2, 1, 4, 8}) {  // the built-in count (f = 2) first
-    if (err != hipSuccess) break;
-    // half .. four times the default block count, unless fixed by the caller
-    const int nb = c->opt.krylov_blocks != 0 ? c->nblk : std::max(1, c->L.nblk * f / 2);
-    if (nb > c->L.nblk_max || std::find(tried.begin(), tried.end(), nb) != tried.end()) continue;
-    tried.push_back(nb);
-    for (int pr : {0, 1}) {
-      if (c->opt.gs_update != 0 && pr != c->upd_pairs) continue;
-      KrylovArgs ka = c->kargs(c->basis(0), nullptr);
-      ka.pairs = pr;
-      double* wv = c->basis(nv);
-      double* part = c->at<double>(c->L.partial);
+  // half .. four times the default block count (the default first), unless fixed by the caller
+  std::vector<int> nbs;
+  for (int f : {2, 1, 4, 8}) {
+    const int nb = c->opt.krylov_blocks != 0 ? c->nb_mdot[0] : std::max(1, c->L.nblk * f / 2);
+    if (nb <= c->L.nblk_max && std::find(nbs.begin(), nbs.end(), nb) == nbs.end()) nbs.push_back(nb);
+  }
+  std::vector<int> prs;
+  for (int pr : {0, 1})
+    if (c->opt.gs_update == 0 || pr == c->pairs_upd[0]) prs.push_back(pr);
+  std::vector<int> s_mdot(nvs.size(), c->nb_mdot[0]), s_upd(nvs.size(), c->nb_upd[0]),
+      s_pairs(nvs.size(), c->pairs_upd[0]);
+  KrylovArgs ka = c->kargs(c->basis(0), nullptr);
+  double* part = c->at<double>(c->L.partial);
+  for (size_t si = 0; si < nvs.size() && err == hipSuccess; ++si) {
+    const int nv = nvs[si];
+    double* wv = c->basis(nv);
+    double best_m = 1e300, best_u = 1e300;
+    for (int nb : nbs) {
       double ms = 0;
-      if (!time_it([&] {
-            launch_mdot(ka, nv, wv, part, nb, st);
-            launch_update(ka, nv, wv, c->at<double>(c->L.coef), kMaxBasis, part, nb, c->at<int>(c->L.skip), st);
-          }, ms))
-        break;
-      if (better(ms, best_kr)) {
-        best_kr = ms;
-        best.nblk = nb;
-        best.pairs = pr;
+      if (!time_it([&] { launch_mdot(ka, nv, wv, part, nb, st); }, ms)) break;
+      if (better(ms, best_m)) {
+        best_m = ms;
+        s_mdot[si] = nb;
       }
+      for (int pr : prs) {
+        KrylovArgs k2 = ka;
+        k2.pairs = pr;
+        if (!time_it([&] {
+              launch_update(k2, nv, wv, c->at<double>(c->L.coef), kMaxBasis, part, nb, c->at<int>(c->L.skip), st);
+            }, ms))
+          break;
+        if (better(ms, best_u)) {
+          best_u = ms;
+          s_upd[si] = nb;
+          s_pairs[si] = pr;
+        }
+      }
+      if (err != hipSuccess) break;
     }
+  }
+  for (int nv = 0; nv < kMaxBasis; ++nv) {
+    size_t k = 0;  // nearest sample (the larger one on a tie)
+    for (size_t si = 1; si < nvs.size(); ++si)
+      if (std::abs(nvs[si] - nv) <= std::abs(nvs[k] - nv)) k = si;
+    best.nb_mdot[nv] = s_mdot[k];
+    best.nb_upd[nv] = s_upd[k];
+    best.pairs_upd[nv] = s_pairs[k];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -559,8 +600,9 @@ pcop_status tune_kernels(pcop_ctx c) {
   c->tb.dst_variant = best.dst_variant;
   c->tuned_ms = best.ms;
   c->kkt_jchunk = best.jchunk;
-  c->nblk = best.nblk;
-  c->upd_pairs = best.pairs;
+  c->nb_mdot = best.nb_mdot;
+  c->nb_upd = best.nb_upd;
+  c->pairs_upd = best.pairs_upd;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune_cache[key] = best;
   return PCOP_OK;
@@ -890,9 +932,10 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   tb.bhat32 = c->at<float>(L.bhat32);
   tb.time_cols = opts->time_cols;
   tb.dst_variant = (opts->dst_kernel >= 2) ? opts->dst_kernel - 1 : 0;
-  c->nblk = opts->krylov_blocks > 0 ? opts->krylov_blocks : L.nblk;
+  c->nb_mdot.fill(opts->krylov_blocks > 0 ? opts->krylov_blocks : L.nblk);
+  c->nb_upd = c->nb_mdot;
   c->kkt_jchunk = opts->kkt_jchunk > 0 ? opts->kkt_jchunk : 16;
-  c->upd_pairs = opts->gs_update == 2 ? 1 : 0;
+  c->pairs_upd.fill(opts->gs_update == 2 ? 1 : 0);
   {
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -948,8 +991,8 @@ pcop_status pcop_get_kernels(pcop_ctx c, pcop_kernel_choice* out) {
   out->time_cols = (c->opt.precond == PCOP_PRECOND_EPS) ? time_choice(c->g, c->tb, c->fp32) : 0;
   out->dst_kernel = (c->opt.spatial == PCOP_DST) ? c->tb.dst_variant + 1 : 0;
   out->kkt_jchunk = c->kkt_jchunk;
-  out->krylov_blocks = c->nblk;
-  out->gs_update = c->upd_pairs ? 2 : 1;
+  out->krylov_blocks = c->nb_mdot[c->opt.restart];
+  out->gs_update = c->pairs_upd[c->opt.restart] ? 2 : 1;
   out->tuned_precond_ms = c->tuned_ms;
   return PCOP_OK;
 }
@@ -1140,7 +1183,6 @@ pcop_status enqueue_iteration(pcop_ctx c, int j, bool full, int n_active, hipStr
   double* wnorm2 = c->at<double>(L.wnorm2);
   int* skip = c->at<int>(L.skip);
   int* active = c->at<int>(L.active);
-  const int nblk = c->nblk;
   const int H_ld = kMaxBasis;
   double* vj = c->basis(j);
   double* w = c->basis(j + 1);
@@ -1161,14 +1203,14 @@ pcop_status enqueue_iteration(pcop_ctx c, int j, bool full, int n_active, hipStr
   // classical Gram-Schmidt; the update pass also measures the new vector
   KrylovArgs ka = c->kargs(c->basis(0), active);
   do_mdot(c, ka, j + 1, w, n_active);
-  launch_reduce_partials(partial, nblk, j + 2, B, red, st);
+  launch_reduce_partials(partial, c->nb_mdot[j + 1], j + 2, B, red, st);
   launch_gs_step1(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, active, st);
   do_update(c, ka, j + 1, w, nullptr, n_active);
-  launch_reduce_partials(partial, nblk, j + 2, B, red, st);
+  launch_reduce_partials(partial, c->nb_upd[j + 1], j + 2, B, red, st);
   launch_gs_step2(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, c->opt.reorth_tol, skip, sc, active, 0, st);
   if (full) {
-    launch_update(ka, j + 1, w, coef, kMaxBasis, partial, nblk, skip, st);
-    launch_reduce_partials(partial, nblk, j + 2, B, red, st);
+    launch_update_nv(c, ka, j + 1, w, skip, st);
+    launch_reduce_partials(partial, c->nb_upd[j + 1], j + 2, B, red, st);
     launch_gs_step2(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, c->opt.reorth_tol, skip, sc, active, 1, st);
   }
   return PCOP_OK;
@@ -1269,7 +1311,6 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
   int* skip = c->at<int>(L.skip);
   int* active = c->at<int>(L.active);
   int* finish = c->at<int>(L.finish);
-  const int nblk = c->nblk;
   const int H_ld = kMaxBasis;
 
   // the solve runs on padded copies of b and x (member stride g.vs);
@@ -1334,7 +1375,7 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
     }
     KrylovArgs kv = c->kargs(c->basis(0), active);
     do_mdot(c, kv, 0, c->basis(0), n_active);
-    launch_reduce_partials(partial, nblk, 1, B, red, st);
+    launch_reduce_partials(partial, c->nb_mdot[0], 1, B, red, st);
     launch_set_scale(red, 0, B, sc, norm, active, st);
     PCOP_HIP(download(h_norm.data(), norm, c->pin_norm, (size_t)B));
     for (int m = 0; m < B; ++m) {
@@ -1393,7 +1434,7 @@ extern "C" pcop_status pcop_solve(pcop_ctx c, const double* b, double* x, int tr
           // second classical Gram-Schmidt pass for the members that need it
           KrylovArgs ka = c->kargs(c->basis(0), active);
           do_update(c, ka, j + 1, c->basis(j + 1), skip, n_again);
-          launch_reduce_partials(partial, nblk, j + 2, B, red, st);
+          launch_reduce_partials(partial, c->nb_upd[j + 1], j + 2, B, red, st);
           launch_gs_step2(red, j, B, sc, H, H_ld, coef, kMaxBasis, wnorm2, c->opt.reorth_tol, skip, sc, active, 1,
                           st);
           launch_pack_hcol(H, H_ld, j, B, skip, hcol, st);

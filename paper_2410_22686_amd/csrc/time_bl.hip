@@ -82,17 +82,6 @@ struct BlTables {
   }
 };
 
-// the filter step between the two convolution FFTs: X_k <- X_k bhat_k
-template <class T, int P, int M, int NT, class TB>
-__device__ __forceinline__ void bl_filter(cx<T>* buf, const TB& tb) {
-  constexpr int LD = M + 1;
-  for (int t = threadIdx.x; t < M * P; t += NT) {
-    const int p = t / M, k = t - p * M;
-    buf[p * LD + k] = buf[p * LD + k] * tb.filter(k);
-  }
-  __syncthreads();
-}
-
 template <class T, int P, int M, int NT>
 __global__ void __launch_bounds__(NT) time_fwd_bl(Geo g, const double* __restrict__ v, cx<T>* __restrict__ spec,
                                                    const double* __restrict__ dpow, TimeTables tt,
@@ -139,16 +128,18 @@ __global__ void __launch_bounds__(NT) time_fwd_bl(Geo g, const double* __restric
         buf[p * LD + j] = x * tb.ch[j];
       }
     }
-    for (int t = threadIdx.x; t < (M - n) * P; t += NT) {
+    // zero padding up to M/2 (n <= M/2; the first stage takes the upper half as zero)
+    for (int t = threadIdx.x; t < (M / 2 - n) * P; t += NT) {
       const int j = n + t / P, p = t % P;
       buf[p * LD + j] = cx<T>{0, 0};
     }
     __syncthreads();
     const int nxt = tw.next(tile + stride, stride);
     if (nxt < tw.ntiles) fetch(nxt);
-    p2_fft<T, -1, M, P, NT>(buf, LD, tb.tw);
-    bl_filter<T, P, M, NT>(buf, tb);
-    p2_fft<T, 1, M, P, NT>(buf, LD, tb.tw);
+    // convolution with the chirp filter: FFT, filter spectrum (in the last
+    // stage), inverse FFT of which only the first n < M/2 outputs are used
+    p2_fft_x<T, -1, M, P, NT, true, false>(buf, LD, tb.tw, [&](int k, cx<T> x) { return x * tb.filter(k); });
+    p2_fft_x<T, 1, M, P, NT, false, true>(buf, LD, tb.tw, P2Keep{});
     // X_k = w_k (x w * conj w)_k: the chirp again and 1/M of the inverse FFT
     cx<T>* out = spec + (size_t)b * (size_t)(2 * K) * m;
     unpack_store<T>(out, n, K, P, i0, m, [&](int k, int p) { return scale(buf[p * LD + k] * tb.ch[k], invM); });
@@ -207,16 +198,18 @@ __global__ void __launch_bounds__(NT) time_inv_bl(Geo g, const cx<T>* __restrict
         }
       }
     }
-    for (int t = threadIdx.x; t < (M - n) * P; t += NT) {
+    // zero padding up to M/2 (n <= M/2; the first stage takes the upper half as zero)
+    for (int t = threadIdx.x; t < (M / 2 - n) * P; t += NT) {
       const int j = n + t / P, p = t % P;
       buf[p * LD + j] = cx<T>{0, 0};
     }
     __syncthreads();
     const int nxt = tw.next(tile + stride, stride);
     if (nxt < tw.ntiles) fetch(nxt);
-    p2_fft<T, -1, M, P, NT>(buf, LD, tb.tw);
-    bl_filter<T, P, M, NT>(buf, tb);
-    p2_fft<T, 1, M, P, NT>(buf, LD, tb.tw);
+    // convolution with the chirp filter: FFT, filter spectrum (in the last
+    // stage), inverse FFT of which only the first n < M/2 outputs are used
+    p2_fft_x<T, -1, M, P, NT, true, false>(buf, LD, tb.tw, [&](int k, cx<T> x) { return x * tb.filter(k); });
+    p2_fft_x<T, 1, M, P, NT, false, true>(buf, LD, tb.tw, P2Keep{});
     double* w1 = w + (size_t)b * g.vs;
     double* w2 = w1 + (size_t)n * m;
     for (int t = threadIdx.x; t < n * P; t += NT) {
