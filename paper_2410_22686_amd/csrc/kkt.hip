@@ -88,6 +88,7 @@ void launch_kkt_apply(const Geo& g, const double* x, double* y, const double* c,
     case 2: PCOP_KKT(D, V, 2); break; \
     case 4: PCOP_KKT(D, V, 4); break; \
     case 8: PCOP_KKT(D, V, 8); break; \
+    case 16: PCOP_KKT(D, V, 16); break; \
     default: PCOP_KKT(D, V, 0); break; \
   }
   if (g.dim == 2) {
