@@ -88,7 +88,7 @@ def parse():
                     help="time-pass kernels: 0 automatic, -P two LDS buffers, +P in place (P points per block)")
     ap.add_argument("--dst-kernel", type=int, default=0, choices=[0, 1, 2, 3],
                     help="sine-transform kernels: 0 automatic, 1 register, 2 LDS-staged, 3 register with wide column tiles")
-    ap.add_argument("--kkt-jchunk", type=int, default=0, help="KKT matvec time levels per thread (0 automatic)")
+    ap.add_argument("--kkt-jchunk", type=int, default=0, help="KKT matvec kernel: > 0 levels per thread, < 0 LDS tiles of that many levels (0 automatic)")
     ap.add_argument("--krylov-blocks", type=int, default=0, help="Krylov reduction blocks per member (0 automatic)")
     ap.add_argument("--gs-update", type=int, default=0, choices=[0, 1, 2],
                     help="Gram-Schmidt update kernel: 0 automatic, 1 doubles, 2 double2 pairs")

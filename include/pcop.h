@@ -136,8 +136,10 @@ typedef struct {
  *              eq. matrix_P, applied by sequential substitution in time
  *              (n dependent spatial solves with (1 + alpha) I + tau K; the
  *              comparison method of Tables 4 and 8).  time_cols is ignored.
- *   kkt_jchunk time levels per thread of the KKT matvec: 0 automatic (16, or
- *              the tuner's choice), else 1..64.
+ *   kkt_jchunk KKT matvec kernel: 0 automatic (-8, or the tuner's choice);
+ *              1..64 one thread per point marching that many time levels;
+ *              -64..-1 LDS-tiled blocks (1024 points and their in-plane
+ *              neighbours staged per level) marching -kkt_jchunk levels.
  *   krylov_blocks  blocks per member of the Krylov reductions: 0 automatic
  *              (with tune = 1: chosen per basis size), else 1..4096 for
  *              every size (the reduction order, and so the rounding,
@@ -266,7 +268,7 @@ pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* ep
  *                  0 with PCOP_PRECOND_IDEAL (no time transform);
  *   dst_kernel     1 (register-resident), 2 (LDS-staged), 3 (register, wide
  *                  column tiles) or 0 (multigrid);
- *   kkt_jchunk     time levels per thread of the KKT matvec;
+ *   kkt_jchunk     KKT matvec kernel (as in pcop_options);
  *   krylov_blocks  blocks per member of the Krylov multi-dot over the full
  *                  basis (the tuner picks counts per basis size: shorter
  *                  bases may use others);

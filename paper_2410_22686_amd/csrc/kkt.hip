@@ -74,12 +74,201 @@ __global__ void __launch_bounds__(256) kkt_apply_kernel(
   }
 }
 
+// E u at a staged point: the value and its in-plane neighbours from the LDS
+// tile s (local index li, row length nx), the neighbours across planes (3-D)
+// from the level's global values u.  Same selects and sums as apply_E_w.
+template <int DIM, bool VAR>
+__device__ __forceinline__ double apply_E_lds(const double* s, int li, const double* __restrict__ u, int i, int c1,
+                                              int c2, int c3, int nx, const StencilW& w) {
+  const bool h1 = c1 > 0, g1 = c1 < nx - 1, h2 = c2 > 0, g2 = c2 < nx - 1;
+  const bool h3 = DIM == 3 && c3 > 0, g3 = DIM == 3 && c3 < nx - 1;
+  const double uc = s[li];
+  const double m1 = s[li - 1], p1 = s[li + 1];
+  const double m2 = s[li - nx], p2 = s[li + nx];
+  double m3 = 0.0, p3 = 0.0;
+  if (DIM == 3) {
+    const int s3 = nx * nx;
+    m3 = u[h3 ? i - s3 : i];
+    p3 = u[g3 ? i + s3 : i];
+  }
+  if (!VAR) {
+    double nb = 0.0;
+    nb += h1 ? m1 : 0.0;
+    nb += g1 ? p1 : 0.0;
+    nb += h2 ? m2 : 0.0;
+    nb += g2 ? p2 : 0.0;
+    if (DIM == 3) {
+      nb += h3 ? m3 : 0.0;
+      nb += g3 ? p3 : 0.0;
+    }
+    return w.d * uc + w.lo[0] * nb;
+  } else {
+    double acc = w.d * uc;
+    acc += w.lo[0] * (h1 ? m1 : 0.0);
+    acc += w.hi[0] * (g1 ? p1 : 0.0);
+    acc += w.lo[1] * (h2 ? m2 : 0.0);
+    acc += w.hi[1] * (g2 ? p2 : 0.0);
+    if (DIM == 3) {
+      acc += w.lo[2] * (h3 ? m3 : 0.0);
+      acc += w.hi[2] * (g3 ? p3 : 0.0);
+    }
+    return acc;
+  }
+}
+
+// LDS-tiled matvec: a block owns TS = 256 PT consecutive spatial points and
+// a chunk of time levels.  Per level, x1 and x2 over the tile and nx points
+// on either side (every in-plane neighbour) are staged in LDS with
+// coalesced loads, the next level's being fetched into registers
+// meanwhile; the stencils then read LDS.  Block row 1 of level j needs
+// x2^{j+1}, so it is completed at level j + 1 from that level's staged
+// values.  The operations per element are those of kkt_apply_kernel.
+template <int DIM, bool VAR, int PT, int HQ>
+__global__ void __launch_bounds__(256) kkt_lds_kernel(
+    Geo g, const double* __restrict__ x, double* __restrict__ y, const double* __restrict__ c,
+    const double* __restrict__ alpha, const double* __restrict__ xscale, int xs_stride,
+    const int* __restrict__ active, double sgn, const double* __restrict__ ecoef, double ediag,
+    double eoff, int jchunk) {
+  constexpr int NT = 256, TS = NT * PT;
+  constexpr int QW = PT + HQ;  // staging slots per thread: TS + 2 nx <= QW NT (nx <= 128 HQ)
+  extern __shared__ double kkt_sm[];
+  const int total = gridDim.x * gridDim.y * gridDim.z;
+  const int hw = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int lg = xcd_remap(hw, total);
+  const int bx = lg % gridDim.x;
+  const int by = (lg / gridDim.x) % gridDim.y;
+  const int b = lg / (gridDim.x * gridDim.y);
+  if (active && !active[b]) return;
+  const int nx = g.nx, n = g.n, m = g.m, H = nx;
+  const int W = TS + 2 * H;
+  double* s1 = kkt_sm;
+  double* s2 = kkt_sm + W;
+  const int i0 = bx * TS;
+  const int j0 = by * jchunk;
+  const int j1 = min(n, j0 + jchunk);
+  const double a = alpha[b];
+  const double sc = xscale ? xscale[(size_t)b * xs_stride] : 1.0;
+  const size_t mb = (size_t)b * (size_t)g.vs;
+  const double* x1 = x + mb;
+  const double* x2 = x + mb + (size_t)n * m;
+  double* y1 = y + mb;
+  double* y2 = y + mb + (size_t)n * m;
+  const double* cc1 = c ? c + mb : nullptr;
+  const double* cc2 = c ? c + mb + (size_t)n * m : nullptr;
+
+  StencilW sw[PT];
+  double x1prev[PT], pex2[PT], px1[PT];
+  int cr1[PT], cr2[PT], cr3[PT];  // grid coordinates of the thread's points
+#pragma unroll
+  for (int r = 0; r < PT; ++r) {
+    const int i = i0 + threadIdx.x + NT * r;
+    const int ii = i < m ? i : 0;
+    cr1[r] = ii % nx;
+    cr2[r] = (ii / nx) % nx;
+    cr3[r] = (DIM == 3) ? ii / (nx * nx) : 0;
+    sw[r] = load_stencil<DIM, VAR>(ii, m, ecoef, ediag, eoff);
+    x1prev[r] = (j0 > 0 && i < m) ? x1[(size_t)(j0 - 1) * m + i] : 0.0;
+    pex2[r] = px1[r] = 0.0;
+  }
+  double p1[QW], p2[QW];
+  auto fetch = [&](int j) {
+    const size_t o = (size_t)j * m;
+#pragma unroll
+    for (int q = 0; q < QW; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int gi = i0 - H + e;
+      const bool ok = e < W && gi >= 0 && gi < m;
+      p1[q] = ok ? x1[o + gi] : 0.0;
+      p2[q] = ok ? x2[o + gi] : 0.0;
+    }
+  };
+  // block row 1 of level j: alpha x1 + T^T x2 with x2^{j+1} = x2n
+  auto finish_row1 = [&](int r, int j, int i, double x2n) {
+    double r1 = a * px1[r] + sgn * (pex2[r] - x2n);
+    r1 *= sc;
+    if (c) r1 = cc1[(size_t)j * m + i] - r1;
+    y1[(size_t)j * m + i] = r1;
+  };
+  if (j0 < j1) fetch(j0);
+  for (int j = j0; j < j1; ++j) {
+#pragma unroll
+    for (int q = 0; q < QW; ++q) {
+      const int e = threadIdx.x + NT * q;
+      if (e < W) {
+        s1[e] = p1[q];
+        s2[e] = p2[q];
+      }
+    }
+    __syncthreads();
+    if (j + 1 < j1) fetch(j + 1);
+    const size_t o = (size_t)j * m;
+#pragma unroll
+    for (int r = 0; r < PT; ++r) {
+      const int i = i0 + threadIdx.x + NT * r;
+      if (i < m) {
+        const int li = H + threadIdx.x + NT * r;
+        const int c1 = cr1[r], c2 = cr2[r], c3 = cr3[r];
+        const double x2c = s2[li];
+        if (j > j0) finish_row1(r, j - 1, i, x2c);
+        const double ex2 = apply_E_lds<DIM, VAR>(s2, li, x2 + o, i, c1, c2, c3, nx, sw[r]);
+        const double ex1 = apply_E_lds<DIM, VAR>(s1, li, x1 + o, i, c1, c2, c3, nx, sw[r]);
+        const double x1c = s1[li];
+        // block row 2: -T x1 + alpha x2
+        double r2 = a * x2c - sgn * (ex1 - x1prev[r]);
+        r2 *= sc;
+        if (c) r2 = cc2[o + i] - r2;
+        y2[o + i] = r2;
+        pex2[r] = ex2;
+        px1[r] = x1c;
+        x1prev[r] = x1c;
+      }
+    }
+    __syncthreads();
+  }
+  if (j0 < j1) {
+#pragma unroll
+    for (int r = 0; r < PT; ++r) {
+      const int i = i0 + threadIdx.x + NT * r;
+      if (i < m) finish_row1(r, j1 - 1, i, (j1 < n) ? x2[(size_t)j1 * m + i] : 0.0);
+    }
+  }
+}
+
 void launch_kkt_apply(const Geo& g, const double* x, double* y, const double* c, const double* alpha,
                       const double* xscale, int xs_stride, const int* active, bool transpose,
                       const double* ecoef, double ediag, double eoff, int jchunk, hipStream_t st) {
+  const double sgn = transpose ? -1.0 : 1.0;
+  if (jchunk < 0 && g.nx <= 1024) {
+    // LDS-tiled kernel, -jchunk levels per block
+    constexpr int PT = 4;
+    const int jc = -jchunk;
+    dim3 grid((g.m + 256 * PT - 1) / (256 * PT), (g.n + jc - 1) / jc, g.B);
+    const size_t lds = 2 * sizeof(double) * (256 * PT + 2 * (size_t)g.nx);
+#define PCOP_KKT_LDS_H(D, V, HQ) \
+  kkt_lds_kernel<D, V, PT, HQ><<<grid, 256, lds, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn, ecoef, ediag, eoff, jc)
+#define PCOP_KKT_LDS(D, V)                                        \
+  if (g.nx <= 256) PCOP_KKT_LDS_H(D, V, 2);                       \
+  else if (g.nx <= 512) PCOP_KKT_LDS_H(D, V, 4);                  \
+  else PCOP_KKT_LDS_H(D, V, 8);
+    if (g.dim == 2) {
+      if (ecoef) {
+        PCOP_KKT_LDS(2, true)
+      } else {
+        PCOP_KKT_LDS(2, false)
+      }
+    } else {
+      if (ecoef) {
+        PCOP_KKT_LDS(3, true)
+      } else {
+        PCOP_KKT_LDS(3, false)
+      }
+    }
+#undef PCOP_KKT_LDS
+#undef PCOP_KKT_LDS_H
+    return;
+  }
   if (jchunk < 1) jchunk = 16;
   dim3 grid((g.m + 255) / 256, (g.n + jchunk - 1) / jchunk, g.B);
-  const double sgn = transpose ? -1.0 : 1.0;
 #define PCOP_KKT(D, V, J) \
   kkt_apply_kernel<D, V, J><<<grid, 256, 0, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn, ecoef, ediag, eoff, jchunk)
 #define PCOP_KKT_J(D, V)        \

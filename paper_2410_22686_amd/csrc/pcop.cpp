@@ -85,7 +85,7 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
   if (o->tune != 0 && o->tune != 1) return fail(PCOP_ERR_INVALID_ARG, "tune must be 0 or 1");
   if (o->precond != PCOP_PRECOND_EPS && o->precond != PCOP_PRECOND_IDEAL)
     return fail(PCOP_ERR_INVALID_ARG, "unknown precond");
-  if (o->kkt_jchunk < 0 || o->kkt_jchunk > 64) return fail(PCOP_ERR_INVALID_ARG, "kkt_jchunk must be in 0..64");
+  if (o->kkt_jchunk < -64 || o->kkt_jchunk > 64) return fail(PCOP_ERR_INVALID_ARG, "kkt_jchunk must be in -64..64");
   if (o->krylov_blocks < 0 || o->krylov_blocks > 4096)
     return fail(PCOP_ERR_INVALID_ARG, "krylov_blocks must be in 0..4096");
   if (o->gs_update < 0 || o->gs_update > 2) return fail(PCOP_ERR_INVALID_ARG, "gs_update must be 0, 1 or 2");
@@ -299,7 +299,7 @@ struct pcop_ctx_s {
   const double* ecoef = nullptr;
   bool fp32 = false;
   double tuned_ms = 0;
-  int kkt_jchunk = 16;  // time levels per thread of the matvec
+  int kkt_jchunk = -8;  // matvec kernel: > 0 levels per thread, < 0 LDS tiles of -kkt_jchunk levels
   // per basis size nv: blocks per member of the multi-dot and of the
   // Gram-Schmidt update, and the update kernel (double2 pairs or doubles);
   // the best block count depends on how many vectors a kernel streams
@@ -515,7 +515,9 @@ pcop_status tune_kernels(pcop_ctx c) {
   }
   // matvec: time levels per thread
   double best_kkt = 1e300;
-  for (int jc : {16, 1, 2, 4, 8, 32}) {
+  // levels per block of the LDS-tiled kernel (the built-in -8 first), then
+  // levels per thread of the one-thread-per-point kernel
+  for (int jc : {-8, -16, -32, 16, 1, 2, 4, 8, 32}) {
     if (err != hipSuccess || c->opt.kkt_jchunk != 0) break;
     double ms = 0;
     if (!time_it([&] {
@@ -934,7 +936,7 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   tb.dst_variant = (opts->dst_kernel >= 2) ? opts->dst_kernel - 1 : 0;
   c->nb_mdot.fill(opts->krylov_blocks > 0 ? opts->krylov_blocks : L.nblk);
   c->nb_upd = c->nb_mdot;
-  c->kkt_jchunk = opts->kkt_jchunk > 0 ? opts->kkt_jchunk : 16;
+  c->kkt_jchunk = opts->kkt_jchunk != 0 ? opts->kkt_jchunk : -8;
   c->pairs_upd.fill(opts->gs_update == 2 ? 1 : 0);
   {
     int dev = 0, ncu = 0;

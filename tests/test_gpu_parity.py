@@ -40,15 +40,22 @@ KKT_CASES = [
     (3, 7, 9, (1e-3,), None),
     (2, 15, 6, (1e-3,), W.coeff_sines3d),
     (3, 7, 5, (1e-5, 1.0), W.coeff_sines3d),
+    (2, 63, 21, (1e-4,), None),               # m = 3969: several 1024-point LDS tiles and a ragged one
+    (3, 15, 11, (1e-3,), W.coeff_sines3d),    # m = 3375, variable coefficient across tiles
 ]
 
 
 @pytest.mark.parametrize("dim,nx,nt,gammas,coeff", KKT_CASES)
 @pytest.mark.parametrize("transpose", [False, True])
-def test_kkt_apply(dim, nx, nt, gammas, coeff, transpose):
-    print(f"kkt_apply dim={dim} nx={nx} nt={nt} B={len(gammas)} var={coeff is not None} T={transpose}", flush=True)
+@pytest.mark.parametrize("jchunk", [16, 3, -4, -16])
+def test_kkt_apply(dim, nx, nt, gammas, coeff, transpose, jchunk):
+    """Both matvec kernels (one thread per point marching jchunk levels; LDS
+    tiles marching -jchunk levels), chunks that do not divide n included."""
+    print(f"kkt_apply dim={dim} nx={nx} nt={nt} B={len(gammas)} var={coeff is not None} T={transpose} "
+          f"jchunk={jchunk}", flush=True)
     spatial = "dst" if coeff is None else "mg"
-    s = Solver(dim, nx, nt, list(gammas), coeff=coeff, spatial=spatial, device=DEV)
+    s = Solver(dim, nx, nt, list(gammas), coeff=coeff, spatial=spatial, kkt_jchunk=jchunk, device=DEV)
+    assert s.kernels["kkt_jchunk"] == jchunk
     x = W.random_vector(dim, nx, nt, seed=1, batch=len(gammas))
     y = s.kkt_apply(to_dev(x), transpose=transpose).cpu().numpy()
     for b, pb in enumerate(problems(dim, nx, nt, gammas, coeff=coeff)):
