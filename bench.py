@@ -86,7 +86,7 @@ def parse():
                     help="time the candidate preconditioner kernels at setup and keep the fastest")
     ap.add_argument("--time-cols", type=int, default=0, choices=[0, -1, -4, -8, -16, 4, 8, 16],
                     help="time-pass kernels: 0 automatic, -P two LDS buffers, +P in place (P points per block)")
-    ap.add_argument("--dst-kernel", type=int, default=0, choices=[0, 1, 2, 3],
+    ap.add_argument("--dst-kernel", type=int, default=0, choices=[0, 1, 2, 3, 4],
                     help="sine-transform kernels: 0 automatic, 1 register, 2 LDS-staged, 3 register with wide column tiles")
     ap.add_argument("--kkt-jchunk", type=int, default=0, help="KKT matvec kernel: > 0 levels per thread, < 0 LDS tiles of that many levels (0 automatic)")
     ap.add_argument("--krylov-blocks", type=int, default=0, help="Krylov reduction blocks per member (0 automatic)")

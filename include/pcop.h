@@ -121,7 +121,8 @@ typedef struct {
  *   dst_kernel sine-transform kernels of step 2 (PCOP_DST): 0 automatic,
  *              1 register-resident lines, 2 lines staged through LDS,
  *              3 register-resident lines with twice as many strided lines
- *              per block (512 threads).
+ *              per block (512 threads), 4 strided lines through a
+ *              half-length FFT (nx + 1 points; for nx >= 7, else as 1).
  *   tune       1: pcop_setup times the candidates of every kernel choice
  *              left at 0 ("automatic": time_cols, dst_kernel, kkt_jchunk,
  *              krylov_blocks, gs_update) on the context's stream and keeps
@@ -267,7 +268,8 @@ pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* ep
  *                  17): +P (P points, 256 threads) or -P (512 threads);
  *                  0 with PCOP_PRECOND_IDEAL (no time transform);
  *   dst_kernel     1 (register-resident), 2 (LDS-staged), 3 (register, wide
- *                  column tiles) or 0 (multigrid);
+ *                  column tiles), 4 (half-length strided transforms) or 0
+ *                  (multigrid);
  *   kkt_jchunk     KKT matvec kernel (as in pcop_options);
  *   krylov_blocks  blocks per member of the Krylov multi-dot over the full
  *                  basis (the tuner picks counts per basis size: shorter

@@ -398,6 +398,199 @@ __global__ void __launch_bounds__(NT) dst_col_kernel(Geo g, cx<T>* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Half-length variant for strided lines.  With M = L/2 = N + 1 and z_0 = 0,
+//   y_j = sin(pi j/M) (z_j + z_{M-j}) + (z_j - z_{M-j})/2,  U = FFT_M(y),
+// the stored values Y_k = -2i sum_j z_j sin(pi j k/M) of the odd-extension
+// transform follow as
+//   Y_{2k} = U_k - U_{M-k}   (k >= 1),
+//   Y_{2k+1} = -i P_k,  P_k = U_0 + sum_{q=1..k} (U_q + U_{M-q}),
+// (for a real z this is the classic sine transform through a real FFT of
+// length M: the symmetric part of y gives the odd outputs by a recurrence,
+// the antisymmetric part the even ones; the complex data carry two real
+// lines at once).  One length-M FFT per transform instead of length 2M:
+// M/8 threads per line, so a 256-thread tile holds twice the lines (whole
+// 128-byte rows of the strided axis in FP64 for nx = 255).
+// ---------------------------------------------------------------------------
+template <class T, int L>
+struct HalfDst {
+  static constexpr int M = L / 2, N = M - 1, TM = M / 8;
+  // y_j (j = t + TM s) from the line's values z_{e+1} at lbuf[pidx(e)]
+  static __device__ __forceinline__ void pre(cx<T> (&v)[8], int t, const cx<T>* lbuf, const T* sinl) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int j = t + TM * s;
+      if (j == 0) {
+        v[s] = cx<T>{0, 0};
+      } else {
+        const cx<T> a = lbuf[pidx(j - 1)], b = lbuf[pidx(M - j - 1)];
+        const T sj = sinl[j];
+        const cx<T> sum = a + b, dif = a - b;
+        v[s] = cx<T>{sj * sum.x + (T)0.5 * dif.x, sj * sum.y + (T)0.5 * dif.y};
+      }
+    }
+  }
+  // from U (natural order in v, positions t + TM s) to Y at positions
+  // 8t .. 8t + 7 (o[r] = Y_{8t + r}); the prefix sum runs over the TM
+  // threads of the line, which sit in one wavefront
+  static __device__ __forceinline__ void post(cx<T> (&v)[8], cx<T> (&o)[8], int t, cx<T>* lbuf) {
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) lbuf[pidx(t + TM * s)] = v[s];
+    __syncthreads();
+    cx<T> c[4], e[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = 4 * t + i;
+      const cx<T> uk = lbuf[pidx(k)];
+      const cx<T> um = lbuf[pidx(k == 0 ? 0 : M - k)];
+      c[i] = (k == 0) ? uk : uk + um;
+      e[i] = uk - um;
+    }
+    // inclusive prefix within the thread, then an exclusive scan of the
+    // thread totals over the line
+    cx<T> run = c[0];
+    c[0] = run;
+#pragma unroll
+    for (int i = 1; i < 4; ++i) {
+      run = run + c[i];
+      c[i] = run;
+    }
+    cx<T> incl = run;
+#pragma unroll
+    for (int d = 1; d < TM; d *= 2) {
+      const T px = __shfl_up(incl.x, d, TM);
+      const T py = __shfl_up(incl.y, d, TM);
+      if (t >= d) incl = incl + cx<T>{px, py};
+    }
+    const cx<T> excl = incl - run;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const cx<T> pk = excl + c[i];
+      o[2 * i] = e[i];                      // Y_{2k} (Y_0 unused)
+      o[2 * i + 1] = cx<T>{pk.y, -pk.x};    // -i P_k
+    }
+  }
+};
+
+template <class T, int L, int DIVIDE_, int NT>
+__global__ void __launch_bounds__(NT) dst_half_kernel(Geo g, cx<T>* __restrict__ data, LineGeom lg,
+                                                       const cx<T>* __restrict__ twL, DivideParams dp) {
+  using H = HalfDst<T, L>;
+  constexpr bool DIVIDE = DIVIDE_ != 0;
+  constexpr int M = H::M, N = H::N, TM = H::TM;
+  constexpr int LPB = NT / TM;
+  constexpr int LD = M + M / 8 + 1;
+  constexpr int QS = (N * LPB + NT - 1) / NT;  // tile elements per thread
+  __shared__ cx<T> buf[LPB * LD];
+  // length-M twiddles exp(-2 pi i t/M) = twL[2t], sines sin(pi j/M) = -Im twL[j],
+  // 1-D eigenvalues: in LDS, so that the prefetch is the only global load in the loop
+  __shared__ cx<T> twm[M];
+  __shared__ T sinl[M];
+  __shared__ double mul[DIVIDE ? N : 1];
+  for (int k = threadIdx.x; k < M; k += NT) {
+    twm[k] = twL[2 * k];
+    sinl[k] = -twL[k].y;
+  }
+  if (DIVIDE)
+    for (int k = threadIdx.x; k < N; k += NT) mul[k] = dp.mu1[k];
+  __syncthreads();
+  const long long tiles = (lg.lines + LPB - 1) / LPB;
+  const long long total = tiles * lg.nplanes;
+  const int lid = threadIdx.x / TM;
+  const int t = threadIdx.x - lid * TM;
+  cx<T>* lbuf = buf + lid * LD;
+  auto next = [&](long long blk) {
+    if (DIVIDE && dp.active)
+      while (blk < total && !dp.active[(int)((blk / tiles) / dp.spm)]) blk += gridDim.x;
+    return blk;
+  };
+  cx<T> pre[QS];
+  auto fetch = [&](long long blk) {
+    const long long plane = blk / tiles;
+    const int l0 = (int)(blk - plane * tiles) * LPB;
+    const long long pbase = plane * lg.plane_stride;
+#pragma unroll
+    for (int q = 0; q < QS; ++q) {
+      const int idx = threadIdx.x + NT * q;
+      const int e = idx / LPB, l = idx - (idx / LPB) * LPB;
+      const bool ok = idx < N * LPB && l0 + l < lg.lines;
+      pre[q] = ok ? data[pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride]
+                  : cx<T>{0, 0};
+    }
+  };
+  long long blk = next(xcd_remap(blockIdx.x, gridDim.x));
+  if (blk < total) fetch(blk);
+  while (blk < total) {
+    const long long plane = blk / tiles;
+    const int l0 = (int)(blk - plane * tiles) * LPB;
+    const long long pbase = plane * lg.plane_stride;
+    const int line = l0 + lid;
+    const bool valid = line < lg.lines;
+#pragma unroll
+    for (int q = 0; q < QS; ++q) {
+      const int idx = threadIdx.x + NT * q;
+      if (idx < N * LPB) {
+        const int e = idx / LPB, l = idx - (idx / LPB) * LPB;
+        buf[l * LD + pidx(e)] = pre[q];
+      }
+    }
+    __syncthreads();
+    const long long nxt = next(blk + gridDim.x);
+    if (nxt < total) fetch(nxt);
+    cx<T> v[8], o[8];
+    H::pre(v, t, lbuf, sinl);
+    RegStages<T, M, TM, -1, 1>::run(v, t, lbuf, twm);
+    H::post(v, o, t, lbuf);
+    if (DIVIDE) {
+      // the shift of plane p = (b, q): lambda_{q/2} + alpha_b, conjugated for odd q
+      const int b = (int)(plane / dp.spm);
+      const int q = (int)(plane - (long long)b * dp.spm);
+      const int k = q >> 1;
+      const double sre = dp.lam[2 * k] + dp.alpha[b];
+      const double sim = (q & 1) ? -dp.lam[2 * k + 1] : dp.lam[2 * k + 1];
+      double ml = mul[line % g.nx];
+      if (g.dim == 3) ml += mul[(line / g.nx) % g.nx];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int pos = 8 * t + r;
+        if (pos >= 1 && pos <= N && valid) {
+          const double dre = sre + g.tau * (ml + mul[pos - 1]);
+          const double den = dre * dre + sim * sim;
+          o[r] = o[r] * cx<T>{(T)(dp.cnorm * dre / den), (T)(-dp.cnorm * sim / den)};
+        }
+      }
+      // the divided values become the input of the inverse transform
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int pos = 8 * t + r;
+        if (pos >= 1 && pos <= N) lbuf[pidx(pos - 1)] = o[r];
+      }
+      __syncthreads();
+      H::pre(v, t, lbuf, sinl);
+      RegStages<T, M, TM, -1, 1>::run(v, t, lbuf, twm);
+      H::post(v, o, t, lbuf);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int pos = 8 * t + r;
+      if (pos >= 1 && pos <= N) lbuf[pidx(pos - 1)] = o[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QS; ++q) {
+      const int idx = threadIdx.x + NT * q;
+      const int e = idx / LPB, l = idx - (idx / LPB) * LPB;
+      if (idx < N * LPB && l0 + l < lg.lines)
+        data[pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride] = buf[l * LD + pidx(e)];
+    }
+    __syncthreads();
+    blk = nxt;
+  }
+}
+
 template <class T, int L>
 constexpr int dst_lines_per_block() {
   constexpr int bytes = (L + 1) * (int)sizeof(cx<T>);
@@ -434,6 +627,20 @@ static void dst_pass_L(const Geo& g, cx<T>* data, const LineGeom& lg, bool rows,
     // persistent grid: as many blocks as stay resident on every CU.  Variant
     // 2 doubles the lines per tile (512 threads) so that each element row of
     // a tile spans 128 bytes instead of 64
+    if constexpr (L >= 16) {
+      if (variant == 3) {
+        // half-length transforms: M/8 threads per line, 256-thread tiles
+        constexpr int LPBH = 256 / (L / 16);
+        const long long tilesh = (lg.lines + LPBH - 1) / LPBH;
+        static const int rh1 = resident_blocks(dst_half_kernel<T, L, 1, 256>, 256, 0);
+        static const int rh0 = resident_blocks(dst_half_kernel<T, L, 0, 256>, 256, 0);
+        const long long want = (long long)(divide ? rh1 : rh0) * std::max(1, ncu);
+        dim3 grid((unsigned)std::min(tilesh * lg.nplanes, want));
+        if (divide) dst_half_kernel<T, L, 1, 256><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
+        else dst_half_kernel<T, L, 0, 256><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
+        return;
+      }
+    }
     if constexpr (L >= 64) {
       if (variant == 2) {
       constexpr int LPB2 = 512 / (L / 8);

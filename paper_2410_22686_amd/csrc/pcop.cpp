@@ -81,7 +81,7 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
     if (tc != 0 && tc != 1 && tc != 4 && tc != 8 && tc != 16)
       return fail(PCOP_ERR_INVALID_ARG, "time_cols must be 0, -1, +-4, +-8 or +-16");
   }
-  if (o->dst_kernel < 0 || o->dst_kernel > 3) return fail(PCOP_ERR_INVALID_ARG, "dst_kernel must be in 0..3");
+  if (o->dst_kernel < 0 || o->dst_kernel > 4) return fail(PCOP_ERR_INVALID_ARG, "dst_kernel must be in 0..4");
   if (o->tune != 0 && o->tune != 1) return fail(PCOP_ERR_INVALID_ARG, "tune must be 0 or 1");
   if (o->precond != PCOP_PRECOND_EPS && o->precond != PCOP_PRECOND_IDEAL)
     return fail(PCOP_ERR_INVALID_ARG, "unknown precond");
@@ -460,7 +460,7 @@ pcop_status tune_kernels(pcop_ctx c) {
     }
   }
   std::vector<int> dvs;
-  if (c->opt.spatial == PCOP_DST && c->opt.dst_kernel == 0) dvs = {0, 1, 2};
+  if (c->opt.spatial == PCOP_DST && c->opt.dst_kernel == 0) dvs = {0, 1, 2, 3};
   else dvs = {c->tb.dst_variant};
   double* v = c->basis(0);
   double* w = c->basis(1);

@@ -156,7 +156,7 @@ def test_precond_kernel_choices(dim, nx, nt, gammas, precision):
     v = W.random_vector(dim, nx, nt, seed=17, batch=len(gammas))
     wos = [P.EpsCirculantRBD(pb).apply(v[b].ravel()) for b, pb in enumerate(problems(dim, nx, nt, gammas))]
     tol = 1e-5 if precision == "mixed" else 1e-11
-    for dk in (1, 2, 3):
+    for dk in (1, 2, 3, 4):
         ref = None
         for tc in (-1, -16, -8, -4, 4, 8, 16):
             s = Solver(dim, nx, nt, list(gammas), precision=precision, side=side, time_cols=tc, dst_kernel=dk,
@@ -173,6 +173,39 @@ def test_precond_kernel_choices(dim, nx, nt, gammas, precision):
                 ref = w
             else:
                 assert rel(w, ref) < (1e-5 if precision == "mixed" else 1e-14), (dk, tc, eff)
+
+
+HALF_DST_CASES = [
+    # dim, nx, nt, gammas: strided sine transforms through a half-length FFT
+    # (nx + 1 points, (nx + 1)/8 threads per line: 8, 16, 32 and 64, the
+    # prefix sum of the odd outputs spanning up to a whole wavefront)
+    (2, 63, 6, (1e-4, 1e-8)),
+    (2, 127, 5, (1e-3,)),
+    (2, 255, 4, (1e-6,)),
+    (2, 511, 3, (1e-5,)),
+    (3, 31, 5, (1e-3,)),       # both strided axes of 3-D
+]
+
+
+@pytest.mark.parametrize("dim,nx,nt,gammas", HALF_DST_CASES)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_half_length_dst(dim, nx, nt, gammas, precision):
+    """dst_kernel = 4 (strided lines through a half-length FFT and a prefix
+    sum) against the oracle and against the full-length register kernel
+    (different operations: agreement to rounding of the transforms)."""
+    print(f"half-length dst {precision} dim={dim} nx={nx} nt={nt} B={len(gammas)}", flush=True)
+    side = "flexible" if precision == "mixed" else "right"
+    v = W.random_vector(dim, nx, nt, seed=29, batch=len(gammas))
+    ws = {}
+    for dk in (1, 4):
+        s = Solver(dim, nx, nt, list(gammas), precision=precision, side=side, dst_kernel=dk, device=DEV)
+        assert s.kernels["dst_kernel"] == dk
+        ws[dk] = s.precond_apply(to_dev(v)).cpu().numpy()
+    tol = 1e-5 if precision == "mixed" else 1e-11
+    for b, pb in enumerate(problems(dim, nx, nt, gammas)):
+        wo = P.EpsCirculantRBD(pb).apply(v[b].ravel())
+        assert rel(ws[4][b], wo) < tol, (b, rel(ws[4][b], wo))
+    assert rel(ws[4], ws[1]) < (1e-5 if precision == "mixed" else 1e-12), rel(ws[4], ws[1])
 
 
 CHIRP_CASES = [
