@@ -25,6 +25,14 @@ int krylov_blocks(long long vl) {
   return (int)want;
 }
 
+// Basis vectors are streamed once per pass: their loads are nontemporal, so
+// they do not displace the vector being updated (or other live data) from
+// the caches.
+__device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  return double2{__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y)};
+}
+
 // block-level reduction of NACC accumulators; thread c < ncols writes column c
 template <int NACC>
 __device__ __forceinline__ void block_reduce_store(double (&acc)[NACC], int ncols, double* out) {
@@ -66,7 +74,7 @@ __global__ void __launch_bounds__(kNT) mdot_kernel(KrylovArgs ka, const double* 
     const double2 wv = wb[e];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      const double2 v = vb[(size_t)i * ss + e];
+      const double2 v = ld_stream(&vb[(size_t)i * ss + e]);
       acc[i] += v.x * wv.x + v.y * wv.y;
     }
     acc[NV] += wv.x * wv.x + wv.y * wv.y;
@@ -96,7 +104,7 @@ __global__ void __launch_bounds__(kNT) update_kernel(KrylovArgs ka, double* __re
   for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < ka.vl; e += (long long)nblk * kNT) {
     double v[NV > 0 ? NV : 1];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = vb[(size_t)i * ka.slot_stride + e];
+    for (int i = 0; i < NV; ++i) v[i] = ld_stream(&vb[(size_t)i * ka.slot_stride + e]);
     double wv = wb[e];
 #pragma unroll
     for (int i = 0; i < NV; ++i) wv -= c[i] * v[i];
@@ -130,7 +138,7 @@ __global__ void __launch_bounds__(kNT) update2_kernel(KrylovArgs ka, int nv, dou
   for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < n2; e += (long long)nblk * kNT) {
     double2 v[MAXNV];
 #pragma unroll
-    for (int i = 0; i < MAXNV; ++i) v[i] = (i < nv) ? vb[(size_t)i * ss + e] : double2{0.0, 0.0};
+    for (int i = 0; i < MAXNV; ++i) v[i] = (i < nv) ? ld_stream(&vb[(size_t)i * ss + e]) : double2{0.0, 0.0};
     double2 wv = wb[e];
 #pragma unroll
     for (int i = 0; i < MAXNV; ++i)
@@ -167,7 +175,7 @@ __global__ void __launch_bounds__(kNT) combine_kernel(KrylovArgs ka, int nv, con
 #pragma unroll
     for (int i = 0; i < MAXNV; ++i)
       if (i < nv && c[i] != 0.0) {
-        const double2 v = vb[(size_t)i * ss + e];
+        const double2 v = ld_stream(&vb[(size_t)i * ss + e]);
         acc.x += c[i] * v.x;
         acc.y += c[i] * v.y;
       }
