@@ -140,13 +140,15 @@ typedef struct {
  *   kkt_jchunk KKT matvec kernel: 0 automatic (-8, or the tuner's choice);
  *              1..64 one thread per point marching that many time levels;
  *              -64..-1 LDS-tiled blocks (1024 points and their in-plane
- *              neighbours staged per level) marching -kkt_jchunk levels.
+ *              neighbours staged per level) marching -kkt_jchunk levels
+ *              (for nx <= 1024, else as 16).
  *   krylov_blocks  blocks per member of the Krylov reductions: 0 automatic
  *              (with tune = 1: chosen per basis size), else 1..4096 for
  *              every size (the reduction order, and so the rounding,
  *              follows it).
- *   gs_update  Gram-Schmidt update kernel: 0 automatic, 1 one element per
- *              thread and step, 2 double2 pairs.
+ *   gs_update  Gram-Schmidt update kernel: 0 automatic (with tune = 1:
+ *              chosen per basis size), 1 one element per thread and step,
+ *              2 double2 pairs.
  *   stream     hipStream_t on which all work is enqueued. */
 typedef struct {
   int precision;

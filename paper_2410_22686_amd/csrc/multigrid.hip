@@ -47,73 +47,105 @@ __device__ __forceinline__ void coords(int i, int nx, int dim, int* c) {
   c[2] = (dim == 3) ? i / (nx * nx) : 0;
 }
 
-// one red-black sweep from z = 0
-template <class T, int DIM>
-__global__ void __launch_bounds__(256) mg_smooth_kernel(int nx, int m, const T* __restrict__ coef,
+// one red-black sweep from z = 0.  A thread owns one point for SB
+// consecutive slices: the point's stencil coefficients (and its neighbours'
+// diagonals) are loaded once for all of them, since the coefficient arrays
+// are shared by every slice and do not stay in the L2.
+template <class T, int DIM, int SB>
+__global__ void __launch_bounds__(256) mg_smooth_kernel(int nx, int m, int slices, const T* __restrict__ coef,
                                                         const cx<T>* __restrict__ r, cx<T>* __restrict__ z,
                                                         MgShift sh) {
-  const int s = blockIdx.y;
-  if (sh.active && !sh.active[s / sh.twoK]) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  const cx<T> sig = slice_sigma<T>(sh, s);
-  const cx<T>* rs = r + (size_t)s * m;
   int c[3];
   coords(i, nx, DIM, c);
-  const cx<T> di = cx<T>{sig.x + coef[i], sig.y};
   const bool red = ((c[0] + c[1] + c[2]) & 1) == 0;
-  cx<T> acc = rs[i];
-  if (!red) {
+  const T cdg = coef[i];
+  // neighbour n = 2a (minus) / 2a + 1 (plus): offset, its diagonal, the
+  // coupling weight; absent neighbours are skipped
+  int nbo[2 * DIM];
+  bool has[2 * DIM];
+  T nbd[2 * DIM], off[2 * DIM];
+  {
     int stride = 1;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-      if (c[a] > 0) {
-        const int nb = i - stride;
-        const cx<T> dn = cx<T>{sig.x + coef[nb], sig.y};
-        acc = acc - scale(cdiv(rs[nb], dn), coef[(size_t)(1 + 2 * a) * m + i]);
-      }
-      if (c[a] < nx - 1) {
-        const int nb = i + stride;
-        const cx<T> dn = cx<T>{sig.x + coef[nb], sig.y};
-        acc = acc - scale(cdiv(rs[nb], dn), coef[(size_t)(2 + 2 * a) * m + i]);
+      has[2 * a] = !red && c[a] > 0;
+      has[2 * a + 1] = !red && c[a] < nx - 1;
+      nbo[2 * a] = -stride;
+      nbo[2 * a + 1] = stride;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int n = 2 * a + u;
+        nbd[n] = has[n] ? coef[i + nbo[n]] : (T)0;
+        off[n] = has[n] ? coef[(size_t)(1 + n) * m + i] : (T)0;
       }
       stride *= nx;
     }
   }
-  z[(size_t)s * m + i] = cdiv(acc, di);
-}
-
-// residual at a fine point (nonzero only at red points)
-template <class T, int DIM>
-__device__ __forceinline__ cx<T> red_residual(const int* f, int nx, int m, const T* __restrict__ coef,
-                                              const cx<T>* __restrict__ zs) {
-  if (((f[0] + f[1] + f[2]) & 1) != 0) return cx<T>{0, 0};
-  const int i = f[0] + nx * (f[1] + nx * f[2]);
-  cx<T> acc{0, 0};
-  int stride = 1;
+  const int s0 = blockIdx.y * SB;
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) {
-    if (f[a] > 0) acc = acc - scale(zs[i - stride], coef[(size_t)(1 + 2 * a) * m + i]);
-    if (f[a] < nx - 1) acc = acc - scale(zs[i + stride], coef[(size_t)(2 + 2 * a) * m + i]);
-    stride *= nx;
+  for (int k = 0; k < SB; ++k) {
+    const int s = s0 + k;
+    if (s >= slices) break;
+    if (sh.active && !sh.active[s / sh.twoK]) continue;
+    const cx<T> sig = slice_sigma<T>(sh, s);
+    const cx<T>* rs = r + (size_t)s * m;
+    const cx<T> di = cx<T>{sig.x + cdg, sig.y};
+    cx<T> acc = rs[i];
+#pragma unroll
+    for (int n = 0; n < 2 * DIM; ++n) {
+      if (has[n]) {
+        const cx<T> dn = cx<T>{sig.x + nbd[n], sig.y};
+        acc = acc - scale(cdiv(rs[i + nbo[n]], dn), off[n]);
+      }
+    }
+    z[(size_t)s * m + i] = cdiv(acc, di);
   }
-  return acc;
 }
 
 // fine residual after the sweep, written at red points only (it is zero at
 // black points); res may alias the level's right-hand side, which the sweep
-// has consumed
-template <class T, int DIM>
-__global__ void __launch_bounds__(256) mg_residual_kernel(int nx, int m, const T* __restrict__ coef,
+// has consumed.  SB slices per thread, the coupling weights loaded once.
+template <class T, int DIM, int SB>
+__global__ void __launch_bounds__(256) mg_residual_kernel(int nx, int m, int slices, const T* __restrict__ coef,
                                                           const cx<T>* __restrict__ z, cx<T>* res, MgShift sh) {
-  const int s = blockIdx.y;
-  if (sh.active && !sh.active[s / sh.twoK]) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
   int f[3];
   coords(i, nx, DIM, f);
   if (((f[0] + f[1] + f[2]) & 1) != 0) return;
-  res[(size_t)s * m + i] = red_residual<T, DIM>(f, nx, m, coef, z + (size_t)s * m);
+  int nbo[2 * DIM];
+  bool has[2 * DIM];
+  T off[2 * DIM];
+  {
+    int stride = 1;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      has[2 * a] = f[a] > 0;
+      has[2 * a + 1] = f[a] < nx - 1;
+      nbo[2 * a] = -stride;
+      nbo[2 * a + 1] = stride;
+      off[2 * a] = has[2 * a] ? coef[(size_t)(1 + 2 * a) * m + i] : (T)0;
+      off[2 * a + 1] = has[2 * a + 1] ? coef[(size_t)(2 + 2 * a) * m + i] : (T)0;
+      stride *= nx;
+    }
+  }
+  const int s0 = blockIdx.y * SB;
+#pragma unroll
+  for (int k = 0; k < SB; ++k) {
+    const int s = s0 + k;
+    if (s >= slices) break;
+    if (sh.active && !sh.active[s / sh.twoK]) continue;
+    const cx<T>* zs = z + (size_t)s * m;
+    // r - A z at a red point after the sweep: -sum over the neighbours of off z_nb
+    // (minus then plus neighbour, axis by axis)
+    cx<T> acc{0, 0};
+#pragma unroll
+    for (int n = 0; n < 2 * DIM; ++n)
+      if (has[n]) acc = acc - scale(zs[i + nbo[n]], off[n]);
+    res[(size_t)s * m + i] = acc;
+  }
 }
 
 // coarse right-hand side by full weighting of the fine residual (red points
@@ -193,6 +225,9 @@ __global__ void __launch_bounds__(256) mg_prolong_kernel(int nxf, int mf, int nx
   out[(size_t)s * mf + i] = acc;
 }
 
+// slices per thread of the smoother and the residual
+constexpr int kMgSB = 8;
+
 template <class T, int DIM>
 static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, int spm, const double* lam,
                      hipStream_t st) {
@@ -212,8 +247,9 @@ static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, int spm
     const int nx = tb.mg[l].nx;
     const int m = (int)tb.mg[l].m;
     dim3 grid((m + 255) / 256, slices);
+    dim3 gridb((m + 255) / 256, (slices + kMgSB - 1) / kMgSB);
     tbeg(tb.timer, KF_MG_SMOOTH, 2.0 * cs * m);
-    mg_smooth_kernel<T, DIM><<<grid, 256, 0, st>>>(nx, m, coefp(l), rbuf(l), zbuf(l), sh);
+    mg_smooth_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), rbuf(l), zbuf(l), sh);
     tend(tb.timer);
     if (l + 1 < NL) {
       const int nxc = tb.mg[l + 1].nx;
@@ -222,7 +258,7 @@ static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, int spm
       // residual into the consumed right-hand side (half the points), then
       // full weighting
       tbeg(tb.timer, KF_MG_RESTRICT, cs * (m + 0.5 * m + 0.5 * m + mc));
-      mg_residual_kernel<T, DIM><<<grid, 256, 0, st>>>(nx, m, coefp(l), zbuf(l), rbuf(l), sh);
+      mg_residual_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), zbuf(l), rbuf(l), sh);
       mg_restrict_kernel<T, DIM><<<gc, 256, 0, st>>>(nx, m, nxc, mc, rbuf(l), rbuf(l + 1), sh);
       tend(tb.timer);
     }
