@@ -135,6 +135,45 @@ __device__ __forceinline__ void dft_odd(cx<T>* a, const cx<T>* __restrict__ twn,
   a[0] = x0;
 }
 
+// dft_odd with each output handed to out(r, X_r) as soon as it is formed
+// (same operations in the same order), so the outputs never occupy
+// registers together with the pair sums and differences
+template <class T, int SG, int R, class OUT>
+__device__ __forceinline__ void dft_odd_out(const cx<T>* a, const cx<T>* __restrict__ twn, int stride, OUT out) {
+  constexpr int H = (R - 1) / 2;
+  T c[H + 1], sn[H + 1];
+#pragma unroll
+  for (int t = 1; t <= H; ++t) {
+    const cx<T> w = twn[t * stride];
+    c[t] = w.x;
+    sn[t] = -w.y;
+  }
+  cx<T> sm[H + 1], df[H + 1];
+  cx<T> x0 = a[0];
+#pragma unroll
+  for (int r = 1; r <= H; ++r) {
+    sm[r] = a[r] + a[R - r];
+    df[r] = a[r] - a[R - r];
+    x0 = x0 + sm[r];
+  }
+  out(0, x0);
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    cx<T> p = a[0], q{0, 0};
+#pragma unroll
+    for (int r = 1; r <= H; ++r) {
+      const int t = (r * k) % R;
+      const T ct = (t <= H) ? c[t] : c[R - t];
+      const T st = (t <= H) ? sn[t] : -sn[R - t];
+      p = p + scale(sm[r], ct);
+      q = q + scale(df[r], st);
+    }
+    const cx<T> iq = mul_i<T, SG>(q);
+    out(k, p + iq);
+    out(R - k, p - iq);
+  }
+}
+
 template <class T, int SG, int R>
 __device__ __forceinline__ void dftR(cx<T>* a) {
   if constexpr (R == 2) dft2<T, SG>(a[0], a[1]);
@@ -199,10 +238,15 @@ __device__ __forceinline__ void sk_stage(int n, int Ns, const cx<T>* __restrict_
         }
       }
     }
-    dft_any<T, SG, R>(v, twn, nR);
     const int base = (jb - jl) * R + jl;
+    if constexpr (R >= 7 && R % 2 == 1) {
+      // long odd radices: outputs stored as they are formed
+      dft_odd_out<T, SG, R>(v, twn, nR, [&](int r, cx<T> val) { store(base + r * Ns, p, val); });
+    } else {
+      dft_any<T, SG, R>(v, twn, nR);
 #pragma unroll
-    for (int r = 0; r < R; ++r) store(base + r * Ns, p, v[r]);
+      for (int r = 0; r < R; ++r) store(base + r * Ns, p, v[r]);
+    }
   }
 }
 
