@@ -1,5 +1,5 @@
 """GPU checks at the full workload sizes, in the launch configurations the
-benchmark times.  The oracle cannot factor these systems in a test's time, so
+benchmark times (kernels chosen by the tuner, as in the benchmark).  The oracle cannot factor these systems in a test's time, so
 the checks use statements that hold at any size: the matvec against the
 oracle's block-wise A x, the preconditioner against the oracle's forward
 operator P_eps (P_eps w = v), and converged solves against the oracle's true
@@ -49,7 +49,8 @@ def test_config2_matvec_precond_and_solve():
     cfg = W.CONFIGS[2]
     print(f"full size {cfg.name}", flush=True)
     g, f, y0 = member_fields(cfg, range(3))
-    s = Solver(cfg.dim, cfg.nx, cfg.nt, list(cfg.gammas), device=DEV)
+    s = Solver(cfg.dim, cfg.nx, cfg.nt, list(cfg.gammas), tune=True, device=DEV)
+    print(f"  kernels {s.kernels}", flush=True)
     b = s.rhs(torch.tensor(g, device=DEV), torch.tensor(f, device=DEV), torch.tensor(y0, device=DEV))
     pbs = [D.make_problem(cfg.dim, cfg.nx, cfg.nt, gm) for gm in cfg.gammas]
     bh = b.cpu().numpy()
@@ -88,7 +89,8 @@ def test_config3_mixed_vs_fp64():
     pb = D.make_problem(cfg.dim, cfg.nx, cfg.nt, cfg.gammas[0])
     xs = {}
     for prec in ("mixed", "fp64"):
-        s = Solver(cfg.dim, cfg.nx, cfg.nt, cfg.gammas[0], precision=prec, side="flexible", device=DEV)
+        s = Solver(cfg.dim, cfg.nx, cfg.nt, cfg.gammas[0], precision=prec, side="flexible", tune=True, device=DEV)
+        print(f"  {prec} kernels {s.kernels}", flush=True)
         b = s.rhs(torch.tensor(g, device=DEV), torch.tensor(f, device=DEV), torch.tensor(y0, device=DEV))
         x, infos, _ = s.solve(b)
         bh = b.cpu().numpy().ravel()
@@ -114,7 +116,8 @@ def test_config4_batched_graph_and_adjoint():
     g, f, y0 = member_fields(cfg, range(B))
     stream = torch.cuda.Stream(device=DEV)
     s = Solver(cfg.dim, cfg.nx, cfg.nt, list(cfg.gammas), graph=True, graph_chunk=4, rtol=1e-11, maxit=600,
-               device=DEV, stream=stream)
+               tune=True, device=DEV, stream=stream)
+    print(f"  kernels {s.kernels}", flush=True)
     with torch.cuda.stream(stream):
         tg = torch.tensor(g, device=DEV)
         tf = torch.tensor(f, device=DEV)
@@ -129,13 +132,15 @@ def test_config4_batched_graph_and_adjoint():
         rr = true_relres(pb, bh[k].ravel(), xh[k].ravel())
         assert infos[k].converged and rr <= 1e-11 * 1.01, (k, rr)
     assert all(i.converged for i in infos)
-    # member 17 alone gives the same iterate (same kernels, same reductions)
+    # member 17 alone gives the same iterate to rounding (the tuner may pick
+    # other kernels and reduction orders for one member than for 64; the
+    # small-size batched test checks equality with identical kernels)
     k = 17
-    s1 = Solver(cfg.dim, cfg.nx, cfg.nt, cfg.gammas[k], rtol=1e-11, maxit=600, device=DEV)
+    s1 = Solver(cfg.dim, cfg.nx, cfg.nt, cfg.gammas[k], rtol=1e-11, maxit=600, tune=True, device=DEV)
     b1 = s1.rhs(tg[k:k + 1].clone(), tf[k:k + 1].clone(), ty0[k:k + 1].clone())
     x1, i1, _ = s1.solve(b1)
-    assert i1[0].iters == infos[k].iters
-    assert rel(x1.cpu().numpy()[0], xh[k]) < 1e-13
+    assert abs(i1[0].iters - infos[k].iters) <= 1
+    assert rel(x1.cpu().numpy()[0], xh[k]) < 1e-9
     del s1, b1, x1
     # adjoint: J = sum_b tau/2 ||y_b - g_b||^2 + gamma_b tau/2 ||p_b/gamma_b||^2
     gam = torch.tensor(cfg.gammas, device=DEV, dtype=torch.float64)[:, None, None]
@@ -170,7 +175,8 @@ def test_config5_multigrid_mixed():
     g, f, y0 = member_fields(cfg, [0])
     coeff = W.coeff_function(cfg.coeff)
     s = Solver(cfg.dim, cfg.nx, cfg.nt, cfg.gammas[0], coeff=coeff, spatial="mg", precision="mixed",
-               side="flexible", device=DEV)
+               side="flexible", tune=True, device=DEV)
+    print(f"  kernels {s.kernels}", flush=True)
     b = s.rhs(torch.tensor(g, device=DEV), torch.tensor(f, device=DEV), torch.tensor(y0, device=DEV))
     v = torch.tensor(W.random_vector(cfg.dim, cfg.nx, cfg.nt, seed=92), device=DEV)
     y = s.kkt_apply(v).cpu().numpy()
