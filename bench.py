@@ -75,7 +75,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
+                    help="workload: 1 2d-nx31-nt32, 2 2d-nx255-nt256 (default), 3 2d-nx511-nt512-mixed, "
+                         "4 2d-nx127-nt128-batch64, 5 3d-nx63-nt128-vara-mg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,

@@ -1,7 +1,8 @@
 // Host side of the C ABI declared in include/pcop.h: argument validation,
-// workspace layout, FP64 host tables, and the GMRES driver that sequences
-// the HIP kernels.  The driver keeps only O(restart^2) scalars per member on
-// the host (Givens rotations of the Hessenberg columns it reads back).
+// workspace layout, FP64 host tables, and the host-side GMRES loop that
+// sequences the HIP kernels.  The loop keeps only O(restart^2) scalars per
+// member on the host (Givens rotations of the Hessenberg columns it reads
+// back).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

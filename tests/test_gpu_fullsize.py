@@ -46,7 +46,7 @@ def true_relres(pb, b, x):
 def test_config2_matvec_precond_and_solve():
     """2-D nx = 255, nt = 256, gamma in {1e-2, 1e-6, 1e-10}: the benchmark's
     batched right-preconditioned GMRES(30) in FP64."""
-    cfg = W.CONFIGS[2]
+    cfg = W.WORKLOADS["2d-nx255-nt256"]
     print(f"full size {cfg.name}", flush=True)
     g, f, y0 = member_fields(cfg, range(3))
     s = Solver(cfg.dim, cfg.nx, cfg.nt, list(cfg.gammas), tune=True, device=DEV)
@@ -83,7 +83,7 @@ def test_config2_matvec_precond_and_solve():
 def test_config3_mixed_vs_fp64():
     """2-D nx = 511, nt = 512, gamma = 1e-6: the FP32-complex preconditioner
     inside FP64 flexible GMRES against the all-FP64 path, both to 1e-8."""
-    cfg = W.CONFIGS[3]
+    cfg = W.WORKLOADS["2d-nx511-nt512-mixed"]
     print(f"full size {cfg.name}", flush=True)
     g, f, y0 = member_fields(cfg, [0])
     pb = D.make_problem(cfg.dim, cfg.nx, cfg.nt, cfg.gammas[0])
@@ -110,7 +110,7 @@ def test_config4_batched_graph_and_adjoint():
     """2-D nx = 127, nt = 128, 64 members with their own gamma: one
     graph-captured batched solve, then the adjoint gradient dJ/dg checked by
     finite differences along a random direction."""
-    cfg = W.CONFIGS[4]
+    cfg = W.WORKLOADS["2d-nx127-nt128-batch64"]
     print(f"full size {cfg.name}", flush=True)
     B = cfg.batch
     g, f, y0 = member_fields(cfg, range(B))
@@ -170,7 +170,7 @@ def test_config4_batched_graph_and_adjoint():
 def test_config5_multigrid_mixed():
     """3-D nx = 63, nt = 128, a = 1 + sin sin sin / 2, gamma = 1e-5: one
     FP32 multigrid V-cycle per frequency inside FP64 flexible GMRES."""
-    cfg = W.CONFIGS[5]
+    cfg = W.WORKLOADS["3d-nx63-nt128-vara-mg"]
     print(f"full size {cfg.name}", flush=True)
     g, f, y0 = member_fields(cfg, [0])
     coeff = W.coeff_function(cfg.coeff)

@@ -346,7 +346,7 @@ def test_fixed_k_iterates_match_oracle(side):
 @pytest.mark.parametrize("side", ["right", "flexible"])
 def test_solve_converges_to_direct_solution(side):
     dim, nx, nt, gammas = 2, 31, 32, (1e-2, 1e-6, 1e-10)
-    fields = [W.fields(W.CONFIGS[1], member=b) for b in range(3)]
+    fields = [W.fields(W.WORKLOADS["2d-nx31-nt32"], member=b) for b in range(3)]
     s = Solver(dim, nx, nt, list(gammas), side=side, device=DEV)
     g = np.stack([fl[0] for fl in fields])
     f = np.stack([fl[1] for fl in fields])

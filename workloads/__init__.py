@@ -69,7 +69,7 @@ class Workload:
         return math.sqrt(self.tau) if self.eps is None else float(self.eps)
 
 
-def _config4_gammas(batch: int = 64) -> tuple:
+def _batch_gammas(batch: int = 64) -> tuple:
     rng = np.random.default_rng([4, 10 ** 6])
     return tuple(float(v) for v in 10.0 ** rng.uniform(-8.0, -2.0, size=batch))
 
@@ -78,10 +78,12 @@ CONFIGS = {
     1: Workload(1, "2d-nx31-nt32", 2, 31, 32, 1.0, (1e-4,)),
     2: Workload(2, "2d-nx255-nt256", 2, 255, 256, 1.0, (1e-2, 1e-6, 1e-10)),
     3: Workload(3, "2d-nx511-nt512-mixed", 2, 511, 512, 1.0, (1e-6,), precision="mixed"),
-    4: Workload(4, "2d-nx127-nt128-batch64", 2, 127, 128, 1.0, _config4_gammas(64), batch=64),
+    4: Workload(4, "2d-nx127-nt128-batch64", 2, 127, 128, 1.0, _batch_gammas(64), batch=64),
     5: Workload(5, "3d-nx63-nt128-vara-mg", 3, 63, 128, 1.0, (1e-5,), coeff="sines3d",
                 precision="mixed", spatial="mg"),
 }
+# the same workloads by name
+WORKLOADS = {w.name: w for w in CONFIGS.values()}
 
 
 def grid_points(nx: int) -> np.ndarray:
