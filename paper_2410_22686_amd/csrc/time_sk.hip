@@ -17,8 +17,66 @@ namespace pcop {
 // Tile t covers member t / tiles_per_member and spatial points
 // i0 .. i0 + P - 1 with i0 = (t mod tiles_per_member) P.
 
+// Stage sequences of the two-buffer kernels, ping-ponging between LDS
+// buffers src and dst; they return the buffer holding the result.  With
+// LASTOUT the last stage writes through `last` instead (the inverse pass
+// stores it to HBM).  PlanRT follows the host plan's radices at run time;
+// PlanCT<R...> is a fixed radix list (the plan of a common length), so each
+// stage is straight-line code with its sizes known at compile time.
+struct PlanRT {};
+template <int... R>
+struct PlanCT {
+  static constexpr int N = (R * ...);
+};
+
+template <class T, int P, int SG, bool LASTOUT, int NS, int R, int... RS>
+struct StagesCT {
+  template <class LAST>
+  static __device__ __forceinline__ cx<T>* run(const cx<T>* tw, cx<T>* src, cx<T>* dst, LAST last) {
+    constexpr int N = (R * ... * RS) * NS;
+    auto ld = [&](int j, int p) { return src[j * P + p]; };
+    if constexpr (sizeof...(RS) == 0 && LASTOUT) {
+      sk_stage<T, R, P, SG>(N, NS, tw, ld, last);
+      return src;
+    } else {
+      auto sto = [&](int j, int p, cx<T> val) { dst[j * P + p] = val; };
+      sk_stage<T, R, P, SG>(N, NS, tw, ld, sto);
+      __syncthreads();
+      if constexpr (sizeof...(RS) == 0) return dst;
+      else return StagesCT<T, P, SG, LASTOUT, NS * R, RS...>::run(tw, dst, src, last);
+    }
+  }
+};
+
+template <class T, int P, int SG, bool LASTOUT, class LAST>
+__device__ __forceinline__ cx<T>* run_stages(PlanRT, const FftPlan& plan, int n, const cx<T>* tw, cx<T>* src,
+                                             cx<T>* dst, LAST last) {
+  int Ns = 1;
+  for (int st = 0; st < plan.nrad; ++st) {
+    auto ld = [&](int j, int p) { return src[j * P + p]; };
+    if (LASTOUT && st + 1 == plan.nrad) {
+      sk_stage_rt<T, P, SG>(plan.rad[st], n, Ns, tw, ld, last);
+    } else {
+      auto sto = [&](int j, int p, cx<T> val) { dst[j * P + p] = val; };
+      sk_stage_rt<T, P, SG>(plan.rad[st], n, Ns, tw, ld, sto);
+      __syncthreads();
+      cx<T>* t = src;
+      src = dst;
+      dst = t;
+    }
+    Ns *= plan.rad[st];
+  }
+  return src;
+}
+
+template <class T, int P, int SG, bool LASTOUT, class LAST, int... R>
+__device__ __forceinline__ cx<T>* run_stages(PlanCT<R...>, const FftPlan&, int, const cx<T>* tw, cx<T>* src,
+                                             cx<T>* dst, LAST last) {
+  return StagesCT<T, P, SG, LASTOUT, 1, R...>::run(tw, src, dst, last);
+}
+
 // Q = register slots per thread for one tile's inputs: n P <= Q * NT
-template <class T, int P, int Q, int NT>
+template <class T, int P, int Q, int NT, class PL>
 __global__ void __launch_bounds__(NT) time_fwd_sk(Geo g, const double* __restrict__ v, cx<T>* __restrict__ spec,
                                                    const double* __restrict__ dpow, const cx<T>* __restrict__ twn,
                                                    FftPlan plan, const double* __restrict__ vscale, int vs_stride,
@@ -73,19 +131,8 @@ __global__ void __launch_bounds__(NT) time_fwd_sk(Geo g, const double* __restric
     __syncthreads();
     const int nxt = tw.next(tile + stride, stride);
     if (nxt < tw.ntiles) fetch(nxt);
-    cx<T>* src = bufA;
-    cx<T>* dst = bufB;
-    int Ns = 1;
-    for (int st = 0; st < plan.nrad; ++st) {
-      auto ld = [&](int j, int p) { return src[j * P + p]; };
-      auto sto = [&](int j, int p, cx<T> val) { dst[j * P + p] = val; };
-      sk_stage_rt<T, P, -1>(plan.rad[st], n, Ns, tw_l, ld, sto);
-      __syncthreads();
-      Ns *= plan.rad[st];
-      cx<T>* t = src;
-      src = dst;
-      dst = t;
-    }
+    auto none = [](int, int, cx<T>) {};
+    cx<T>* src = run_stages<T, P, -1, false>(PL{}, plan, n, tw_l, bufA, bufB, none);
     cx<T>* out = spec + (size_t)b * (size_t)(2 * K) * m;
     unpack_store<T>(out, n, K, P, i0, m, [&](int k, int p) { return src[k * P + p]; });
     __syncthreads();
@@ -96,7 +143,7 @@ __global__ void __launch_bounds__(NT) time_fwd_sk(Geo g, const double* __restric
 // Q = register slots per thread for one tile's spectrum: K P <= Q * NT.
 // ACC: add into w instead of overwriting it (a compile-time switch, so the
 // common kernel issues no global loads besides the prefetch)
-template <class T, int P, int Q, int ACC, int NT>
+template <class T, int P, int Q, int ACC, int NT, class PL>
 __global__ void __launch_bounds__(NT) time_inv_sk(Geo g, const cx<T>* __restrict__ spec, double* __restrict__ w,
                                                    const double* __restrict__ dpow, const cx<T>* __restrict__ twn,
                                                    FftPlan plan, TileWalk tw) {
@@ -150,38 +197,22 @@ __global__ void __launch_bounds__(NT) time_inv_sk(Geo g, const cx<T>* __restrict
     if (nxt < tw.ntiles) fetch(nxt);
     double* w1 = w + (size_t)b * g.vs;
     double* w2 = w1 + (size_t)n * m;
-    cx<T>* src = bufA;
-    cx<T>* dst = bufB;
-    int Ns = 1;
-    for (int st = 0; st < plan.nrad; ++st) {
-      auto ld = [&](int j, int p) { return src[j * P + p]; };
-      if (st + 1 < plan.nrad) {
-        auto sto = [&](int j, int p, cx<T> val) { dst[j * P + p] = val; };
-        sk_stage_rt<T, P, 1>(plan.rad[st], n, Ns, tw_l, ld, sto);
-        __syncthreads();
-        cx<T>* t = src;
-        src = dst;
-        dst = t;
-      } else {
-        auto sto = [&](int j, int p, cx<T> val) {
-          const int i = i0 + p;
-          if (i < m) {
-            // z_2 = Re(e) / (n d_j), z_1 = Im(e) d_j / n; w_1 = z_1 - z_2, w_2 = z_1 + z_2
-            const double z2 = (double)val.x * di_l[j], z1 = (double)val.y * dn_l[j];
-            const size_t o = (size_t)j * m + i;
-            if (ACC) {
-              w1[o] += z1 - z2;
-              w2[o] += z1 + z2;
-            } else {
-              w1[o] = z1 - z2;
-              w2[o] = z1 + z2;
-            }
-          }
-        };
-        sk_stage_rt<T, P, 1>(plan.rad[st], n, Ns, tw_l, ld, sto);
+    auto sto_out = [&](int j, int p, cx<T> val) {
+      const int i = i0 + p;
+      if (i < m) {
+        // z_2 = Re(e) / (n d_j), z_1 = Im(e) d_j / n; w_1 = z_1 - z_2, w_2 = z_1 + z_2
+        const double z2 = (double)val.x * di_l[j], z1 = (double)val.y * dn_l[j];
+        const size_t o = (size_t)j * m + i;
+        if (ACC) {
+          w1[o] += z1 - z2;
+          w2[o] += z1 + z2;
+        } else {
+          w1[o] = z1 - z2;
+          w2[o] = z1 + z2;
+        }
       }
-      Ns *= plan.rad[st];
-    }
+    };
+    run_stages<T, P, 1, true>(PL{}, plan, n, tw_l, bufA, bufB, sto_out);
     __syncthreads();
     tile = nxt;
   }
@@ -195,47 +226,68 @@ constexpr int sk_q_fwd() { return sizeof(T) == 8 ? 8 : 16; }
 template <class T>
 constexpr int sk_q_inv() { return sizeof(T) == 8 ? 5 : 9; }
 
+// launch one kernel pair with stage runner PL (persistent grid: as many
+// blocks as stay resident on every CU)
+template <class T, int P, int NT, class PL>
+static void sk_launch(bool fwd, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
+                      const cx<T>* twn, const double* vscale, int vs_stride, int accum, const TileWalk& tw,
+                      size_t lds, hipStream_t st) {
+  auto kf = time_fwd_sk<T, P, sk_q_fwd<T>(), NT, PL>;
+  auto ki0 = time_inv_sk<T, P, sk_q_inv<T>(), 0, NT, PL>;
+  auto ki1 = time_inv_sk<T, P, sk_q_inv<T>(), 1, NT, PL>;
+  if (lds > 65536) {
+    // above 64 KiB of dynamic LDS the kernels must opt in (once each)
+    static bool attr_set = false;
+    if (!attr_set) {
+      attr_set = true;
+      for (const void* k : {reinterpret_cast<const void*>(kf), reinterpret_cast<const void*>(ki0),
+                            reinterpret_cast<const void*>(ki1)})
+        (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (void)hipGetLastError();
+    }
+  }
+  if (fwd) {
+    const int grid = std::min(tw.ntiles, resident_blocks(kf, NT, lds) * std::max(1, tb.ncu));
+    kf<<<grid, NT, lds, st>>>(g, v, spec, tb.dpow, twn, tb.plan, vscale, vs_stride, tw);
+  } else {
+    auto ki = accum ? ki1 : ki0;
+    const int grid = std::min(tw.ntiles, resident_blocks(ki, NT, lds) * std::max(1, tb.ncu));
+    ki<<<grid, NT, lds, st>>>(g, spec, w, tb.dpow, twn, tb.plan, tw);
+  }
+}
+
+static bool plan_is(const FftPlan& pl, std::initializer_list<int> r) {
+  if (pl.nrad != (int)r.size()) return false;
+  int k = 0;
+  for (int x : r)
+    if (pl.rad[k++] != x) return false;
+  return true;
+}
+
 template <class T>
 void launch_time_sk(bool fwd, int P, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
                     const cx<T>* twn, const double* vscale, int vs_stride, int accum, hipStream_t st) {
   const size_t lds = sk_lds_bytes(g.n, P, sizeof(cx<T>));
   TileWalk tw{(g.m + P - 1) / P, 0, tb.active};
   tw.ntiles = tw.tpm * g.B;
-  // persistent grid: as many blocks as stay resident on every CU
-#define PCOP_TIME_SK_NT(PP, NTT)                                                                              \
-  if (fwd) {                                                                                                  \
-    auto kern = time_fwd_sk<T, PP, sk_q_fwd<T>(), NTT>;                                                       \
-    const int grid = std::min(tw.ntiles, resident_blocks(kern, NTT, lds) * std::max(1, tb.ncu));              \
-    kern<<<grid, NTT, lds, st>>>(g, v, spec, tb.dpow, twn, tb.plan, vscale, vs_stride, tw);                   \
-  } else {                                                                                                    \
-    auto kern = accum ? time_inv_sk<T, PP, sk_q_inv<T>(), 1, NTT> : time_inv_sk<T, PP, sk_q_inv<T>(), 0, NTT>; \
-    const int grid = std::min(tw.ntiles, resident_blocks(kern, NTT, lds) * std::max(1, tb.ncu));              \
-    kern<<<grid, NTT, lds, st>>>(g, spec, w, tb.dpow, twn, tb.plan, tw);                                      \
-  }
-#define PCOP_TIME_SK(PP) PCOP_TIME_SK_NT(PP, 256)
-  if (P == 16 && (size_t)2 * g.n * P * sizeof(cx<T>) > 65536) {
+  const bool wide = P == 16 && (size_t)2 * g.n * P * sizeof(cx<T>) > 65536;
+  // compile-time stage lists for common lengths (n = 255 = 3 * 5 * 17)
+  const bool ct255 = P == 16 && plan_is(tb.plan, {3, 5, 17});
+  using CT255 = PlanCT<3, 5, 17>;
+#define PCOP_SK(PP, NTT, PL) sk_launch<T, PP, NTT, PL>(fwd, g, v, spec, w, tb, twn, vscale, vs_stride, accum, tw, lds, st)
+  if (wide) {
     // wide tiles: two buffers above 64 KiB, 512 threads, one block per CU
-    static bool attr_set = false;
-    if (!attr_set) {
-      attr_set = true;
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(time_fwd_sk<T, 16, sk_q_fwd<T>(), 512>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(time_inv_sk<T, 16, sk_q_inv<T>(), 0, 512>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(time_inv_sk<T, 16, sk_q_inv<T>(), 1, 512>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      (void)hipGetLastError();
-    }
-    PCOP_TIME_SK_NT(16, 512)
+    if (ct255) PCOP_SK(16, 512, CT255);
+    else PCOP_SK(16, 512, PlanRT);
   } else if (P == 16) {
-    PCOP_TIME_SK(16)
+    if (ct255) PCOP_SK(16, 256, CT255);
+    else PCOP_SK(16, 256, PlanRT);
   } else if (P == 8) {
-    PCOP_TIME_SK(8)
+    PCOP_SK(8, 256, PlanRT);
   } else {
-    PCOP_TIME_SK(4)
+    PCOP_SK(4, 256, PlanRT);
   }
-#undef PCOP_TIME_SK_NT
-#undef PCOP_TIME_SK
+#undef PCOP_SK
 }
 
 template void launch_time_sk<double>(bool, int, const Geo&, const double*, cx<double>*, double*, const PrecondTables&,
