@@ -1,5 +1,6 @@
 // Time passes, Stockham kernels with two ping-pong LDS buffers.
 #include <algorithm>
+#include <initializer_list>
 
 #include "time_common.hpp"
 
@@ -25,9 +26,7 @@ namespace pcop {
 // stage is straight-line code with its sizes known at compile time.
 struct PlanRT {};
 template <int... R>
-struct PlanCT {
-  static constexpr int N = (R * ...);
-};
+struct PlanCT {};
 
 template <class T, int P, int SG, bool LASTOUT, int NS, int R, int... RS>
 struct StagesCT {
