@@ -213,7 +213,7 @@ class Solver:
         base = self.workspace.data_ptr()
         aligned = (base + 255) & ~255
         ctx = ctypes.c_void_p()
-        _check(self.lib.pcop_setup(ctypes.byref(ctx), ctypes.byref(prob), ctypes.byref(opts),
+        _check(self._call(self.lib.pcop_setup, ctypes.byref(ctx), ctypes.byref(prob), ctypes.byref(opts),
                                    ctypes.c_void_p(aligned), ctypes.c_size_t(self.workspace_bytes)))
         self.ctx = ctx
         tau, eps_out = ctypes.c_double(), ctypes.c_double()
@@ -268,19 +268,36 @@ class Solver:
     def new_vector(self) -> torch.Tensor:
         return torch.zeros(self.vec_shape, dtype=torch.float64, device=self.device)
 
+    def _call(self, fn, *args):
+        """Run one enqueuing library call on the solver's stream in order with
+        the caller's current stream.  Tensors are allocated (and zero-filled)
+        on the current stream, so the solver's stream first waits for it; the
+        current stream then waits for the solver's stream, so results are
+        visible there and torch's allocator never recycles memory the library
+        still uses."""
+        cur = torch.cuda.current_stream(self.device)
+        st = self._torch_stream
+        if st != cur:
+            st.wait_stream(cur)
+        try:
+            return fn(*args)
+        finally:
+            if st != cur:
+                cur.wait_stream(st)
+
     # ------------------------------------------------------------------
     def rhs(self, g: torch.Tensor, f: torch.Tensor, y0: torch.Tensor, out: Optional[torch.Tensor] = None):
         self._vec(g, "g", self.field_shape)
         self._vec(f, "f", self.field_shape)
         self._vec(y0, "y0", (self.batch, self.m))
         b = self.new_vector() if out is None else self._vec(out, "out")
-        _check(self.lib.pcop_rhs(self.ctx, _ptr(g), _ptr(f), _ptr(y0), _ptr(b)))
+        _check(self._call(self.lib.pcop_rhs, self.ctx, _ptr(g), _ptr(f), _ptr(y0), _ptr(b)))
         return b
 
     def kkt_apply(self, x: torch.Tensor, transpose: bool = False, out: Optional[torch.Tensor] = None):
         self._vec(x, "x")
         y = self.new_vector() if out is None else self._vec(out, "out")
-        _check(self.lib.pcop_kkt_apply(self.ctx, _ptr(x), _ptr(y), int(bool(transpose))))
+        _check(self._call(self.lib.pcop_kkt_apply, self.ctx, _ptr(x), _ptr(y), int(bool(transpose))))
         return y
 
     def post_solve(self, x: torch.Tensor, fN: torch.Tensor, g0: torch.Tensor, y0: torch.Tensor):
@@ -292,7 +309,7 @@ class Solver:
         yN = torch.empty((self.batch, self.m), dtype=torch.float64, device=self.device)
         p0 = torch.empty_like(yN)
         rel = (ctypes.c_double * self.batch)()
-        _check(self.lib.pcop_post_solve(self.ctx, _ptr(x), _ptr(fN), _ptr(g0), _ptr(y0), _ptr(yN), _ptr(p0), rel))
+        _check(self._call(self.lib.pcop_post_solve, self.ctx, _ptr(x), _ptr(fN), _ptr(g0), _ptr(y0), _ptr(yN), _ptr(p0), rel))
         return yN, p0, list(rel)
 
     def error_eh(self, x: torch.Tensor, yN: torch.Tensor, p0: torch.Tensor, y_exact: torch.Tensor,
@@ -305,13 +322,13 @@ class Solver:
         self._vec(y_exact, "y_exact", (self.batch, self.nt + 1, self.m))
         self._vec(p_exact, "p_exact", (self.batch, self.nt + 1, self.m))
         eh = (ctypes.c_double * self.batch)()
-        _check(self.lib.pcop_error_eh(self.ctx, _ptr(x), _ptr(yN), _ptr(p0), _ptr(y_exact), _ptr(p_exact), eh))
+        _check(self._call(self.lib.pcop_error_eh, self.ctx, _ptr(x), _ptr(yN), _ptr(p0), _ptr(y_exact), _ptr(p_exact), eh))
         return list(eh)
 
     def precond_apply(self, v: torch.Tensor, out: Optional[torch.Tensor] = None):
         self._vec(v, "v")
         w = self.new_vector() if out is None else self._vec(out, "out")
-        _check(self.lib.pcop_precond_apply(self.ctx, _ptr(v), _ptr(w)))
+        _check(self._call(self.lib.pcop_precond_apply, self.ctx, _ptr(v), _ptr(w)))
         return w
 
     def solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, transpose: bool = False,
@@ -326,7 +343,7 @@ class Solver:
             import numpy as np
             hist = np.full((self.batch, self.maxit + 1), np.nan)
             hist_ptr = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        st = self.lib.pcop_solve(self.ctx, _ptr(b), _ptr(x), int(bool(transpose)), info, hist_ptr)
+        st = self._call(self.lib.pcop_solve, self.ctx, _ptr(b), _ptr(x), int(bool(transpose)), info, hist_ptr)
         if st not in (PCOP_OK, PCOP_NOT_CONVERGED) or (raise_on_fail and st != PCOP_OK):
             _check(st)
         infos = [SolveInfo(i.iters, bool(i.converged), i.relres_est, i.relres_true) for i in info]
@@ -336,7 +353,7 @@ class Solver:
         self._vec(x, "x")
         y = torch.empty(self.field_shape, dtype=torch.float64, device=self.device)
         p = torch.empty_like(y)
-        _check(self.lib.pcop_unpack(self.ctx, _ptr(x), _ptr(y), _ptr(p)))
+        _check(self._call(self.lib.pcop_unpack, self.ctx, _ptr(x), _ptr(y), _ptr(p)))
         return y, p
 
     def pack_cotangent(self, ybar: Optional[torch.Tensor], pbar: Optional[torch.Tensor]):
@@ -345,7 +362,7 @@ class Solver:
         if pbar is not None:
             self._vec(pbar, "pbar", self.field_shape)
         r = self.new_vector()
-        _check(self.lib.pcop_pack_cotangent(self.ctx, _ptr(ybar), _ptr(pbar), _ptr(r)))
+        _check(self._call(self.lib.pcop_pack_cotangent, self.ctx, _ptr(ybar), _ptr(pbar), _ptr(r)))
         return r
 
     def timing_enable(self, enable: bool = True):
@@ -366,7 +383,7 @@ class Solver:
         dg = torch.empty(self.field_shape, dtype=torch.float64, device=self.device)
         df = torch.empty_like(dg)
         dy0 = torch.empty((self.batch, self.m), dtype=torch.float64, device=self.device)
-        _check(self.lib.pcop_data_grad(self.ctx, _ptr(lam), _ptr(dg), _ptr(df), _ptr(dy0)))
+        _check(self._call(self.lib.pcop_data_grad, self.ctx, _ptr(lam), _ptr(dg), _ptr(df), _ptr(dy0)))
         return dg, df, dy0
 
 

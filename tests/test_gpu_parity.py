@@ -421,6 +421,31 @@ def test_graph_solve_matches_eager(chunk):
         torch.cuda.synchronize()
 
 
+def test_side_stream_solve_starts_from_zero():
+    """A solver on its own stream (as graph mode requires) orders its work
+    after the caller's stream: x0 = 0 is zero-filled on the caller's stream,
+    so without that order a solve could read recycled memory as its initial
+    guess.  Before each solve a freed block full of ones is left in torch's
+    caching allocator; every solve must still match the eager solve."""
+    dim, nx, nt, gammas = 2, 15, 16, (1e-2, 1e-7, 1e-4)
+    fields = [W.random_fields(dim, nx, nt, seed=85 + b) for b in range(3)]
+    g = np.stack([fl[0] for fl in fields])
+    f = np.stack([fl[1] for fl in fields])
+    y0 = np.stack([fl[2] for fl in fields])
+    se = Solver(dim, nx, nt, list(gammas), device=DEV)
+    xe, ie, _ = se.solve(se.rhs(to_dev(g), to_dev(f), to_dev(y0)))
+    side = torch.cuda.Stream(device=DEV)
+    sg = Solver(dim, nx, nt, list(gammas), graph=True, graph_chunk=3, device=DEV, stream=side)
+    b = sg.rhs(to_dev(g), to_dev(f), to_dev(y0))
+    for rep in range(4):
+        junk = torch.ones(sg.vec_shape, dtype=torch.float64, device=DEV)
+        del junk  # the next vector of this size may reuse the block
+        xg, ig, _ = sg.solve(b)
+        for k in range(3):
+            assert ig[k].converged and ig[k].iters == ie[k].iters, (rep, k, ig[k].iters, ie[k].iters)
+        assert rel(xg.cpu().numpy(), xe.cpu().numpy()) < 1e-13, rep
+
+
 def test_transpose_solve():
     dim, nx, nt, gamma = 2, 15, 16, 1e-3
     pb = D.make_problem(dim, nx, nt, gamma)
