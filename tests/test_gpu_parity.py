@@ -421,6 +421,28 @@ def test_graph_solve_matches_eager(chunk):
         torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("dim,nx,nt", [(2, 1, 4), (2, 3, 5), (3, 3, 6), (2, 7, 33), (2, 15, 20)])
+def test_tuned_solve_tiny_shapes(dim, nx, nt):
+    """With tune = 1 every kernel candidate runs on tiny shapes (a one-point
+    grid through multigrid, tiles mostly empty, a chirp-z length); the tuned
+    solve converges to the untuned one."""
+    gammas = (1e-3, 1e-7)
+    fields = [W.random_fields(dim, nx, nt, seed=95 + b) for b in range(2)]
+    g = np.stack([fl[0] for fl in fields])
+    f = np.stack([fl[1] for fl in fields])
+    y0 = np.stack([fl[2] for fl in fields])
+    spatial = "dst" if nx >= 3 else "mg"  # sine transforms need nx + 1 >= 4
+    xs = {}
+    for tune in (False, True):
+        s = Solver(dim, nx, nt, list(gammas), spatial=spatial, side="flexible" if spatial == "mg" else "right",
+                   tune=tune, device=DEV)
+        print(f"tiny dim={dim} nx={nx} nt={nt} tune={tune} kernels {s.kernels}", flush=True)
+        x, infos, _ = s.solve(s.rhs(to_dev(g), to_dev(f), to_dev(y0)))
+        assert all(i.converged and i.relres_true <= 1e-8 * 1.001 for i in infos), infos
+        xs[tune] = x.cpu().numpy()
+    assert rel(xs[True], xs[False]) < 1e-6
+
+
 def test_side_stream_solve_starts_from_zero():
     """A solver on its own stream (as graph mode requires) orders its work
     after the caller's stream: x0 = 0 is zero-filled on the caller's stream,
