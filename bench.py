@@ -89,7 +89,8 @@ def parse():
     ap.add_argument("--time-cols", type=int, default=0, choices=[0, -1, -4, -8, -16, 4, 8, 16],
                     help="time-pass kernels: 0 automatic, -P two LDS buffers, +P in place (P points per block)")
     ap.add_argument("--dst-kernel", type=int, default=0, choices=[0, 1, 2, 3, 4],
-                    help="sine-transform kernels: 0 automatic, 1 register, 2 LDS-staged, 3 register with wide column tiles")
+                    help="sine-transform kernels: 0 automatic, 1 register, 2 LDS-staged, 3 register with wide column "
+                         "tiles, 4 half-length strided transforms")
     ap.add_argument("--kkt-jchunk", type=int, default=0, help="KKT matvec kernel: > 0 levels per thread, < 0 LDS tiles of that many levels (0 automatic)")
     ap.add_argument("--krylov-blocks", type=int, default=0, help="Krylov reduction blocks per member (0 automatic)")
     ap.add_argument("--gs-update", type=int, default=0, choices=[0, 1, 2],

@@ -91,11 +91,9 @@ __global__ void __launch_bounds__(NT) dst_lines_kernel(Geo g, cx<T>* __restrict_
         double mu = dp.mu1[e] + dp.mu1[line % g.nx];
         if (g.dim == 3) mu += dp.mu1[line / g.nx];
         const double dre = sre + g.tau * mu;
-        const double den = dre * dre + sim * sim;
-        // cnorm / (dre + i sim) = cnorm (dre - i sim) / den
-        const double fre = dp.cnorm * dre / den;
-        const double fim = -dp.cnorm * sim / den;
-        y = y * cx<T>{(T)fre, (T)fim};
+        // cnorm / (dre + i sim) = cnorm (dre - i sim) / (dre^2 + sim^2)
+        const double f = dp.cnorm / (dre * dre + sim * sim);
+        y = y * cx<T>{(T)(f * dre), (T)(-f * sim)};
       }
       buf[l * LD + e + 1] = y;
       buf[l * LD + L - 1 - e] = cx<T>{-y.x, -y.y};
@@ -208,8 +206,8 @@ __device__ __forceinline__ void divide_line(cx<T> (&v)[8], int t, const Geo& g, 
     const int pos = t + TL * s;
     if (pos >= 1 && pos <= N && valid) {
       const double dre = sre + g.tau * (mul + dp.mu1[pos - 1]);
-      const double den = dre * dre + sim * sim;
-      v[s] = v[s] * cx<T>{(T)(dp.cnorm * dre / den), (T)(-dp.cnorm * sim / den)};
+      const double f = dp.cnorm / (dre * dre + sim * sim);
+      v[s] = v[s] * cx<T>{(T)(f * dre), (T)(-f * sim)};
     }
   }
 }
@@ -482,6 +480,7 @@ __global__ void __launch_bounds__(NT) dst_half_kernel(Geo g, cx<T>* __restrict__
   constexpr int LPB = NT / TM;
   constexpr int LD = M + M / 8 + 1;
   constexpr int QS = (N * LPB + NT - 1) / NT;  // tile elements per thread
+  static_assert(LPB * TM == NT, "a tile is a whole number of lines");
   __shared__ cx<T> buf[LPB * LD];
   // length-M twiddles exp(-2 pi i t/M) = twL[2t], sines sin(pi j/M) = -Im twL[j],
   // 1-D eigenvalues: in LDS, so that the prefetch is the only global load in the loop
@@ -506,17 +505,20 @@ __global__ void __launch_bounds__(NT) dst_half_kernel(Geo g, cx<T>* __restrict__
     return blk;
   };
   cx<T> pre[QS];
+  // element e of line l0 + l sits at (l0 + l) line_stride + e elem_stride
+  // inside its plane (an in-plane offset, below 2^31); a thread always
+  // handles line l = threadIdx.x mod LPB of the tile
+  const int tl = threadIdx.x % LPB, te = threadIdx.x / LPB;
   auto fetch = [&](long long blk) {
     const long long plane = blk / tiles;
     const int l0 = (int)(blk - plane * tiles) * LPB;
-    const long long pbase = plane * lg.plane_stride;
+    const cx<T>* src = data + plane * lg.plane_stride;
+    const bool lok = l0 + tl < lg.lines;
+    const int off = (l0 + tl) * lg.line_stride + te * lg.elem_stride;
 #pragma unroll
     for (int q = 0; q < QS; ++q) {
-      const int idx = threadIdx.x + NT * q;
-      const int e = idx / LPB, l = idx - (idx / LPB) * LPB;
-      const bool ok = idx < N * LPB && l0 + l < lg.lines;
-      pre[q] = ok ? data[pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride]
-                  : cx<T>{0, 0};
+      const bool ok = threadIdx.x + NT * q < N * LPB && lok;
+      pre[q] = ok ? src[off + q * (NT / LPB) * lg.elem_stride] : cx<T>{0, 0};
     }
   };
   long long blk = next(xcd_remap(blockIdx.x, gridDim.x));
@@ -528,13 +530,8 @@ __global__ void __launch_bounds__(NT) dst_half_kernel(Geo g, cx<T>* __restrict__
     const int line = l0 + lid;
     const bool valid = line < lg.lines;
 #pragma unroll
-    for (int q = 0; q < QS; ++q) {
-      const int idx = threadIdx.x + NT * q;
-      if (idx < N * LPB) {
-        const int e = idx / LPB, l = idx - (idx / LPB) * LPB;
-        buf[l * LD + pidx(e)] = pre[q];
-      }
-    }
+    for (int q = 0; q < QS; ++q)
+      if (threadIdx.x + NT * q < N * LPB) buf[tl * LD + pidx(te + q * (NT / LPB))] = pre[q];
     __syncthreads();
     const long long nxt = next(blk + gridDim.x);
     if (nxt < total) fetch(nxt);
@@ -556,8 +553,8 @@ __global__ void __launch_bounds__(NT) dst_half_kernel(Geo g, cx<T>* __restrict__
         const int pos = 8 * t + r;
         if (pos >= 1 && pos <= N && valid) {
           const double dre = sre + g.tau * (ml + mul[pos - 1]);
-          const double den = dre * dre + sim * sim;
-          o[r] = o[r] * cx<T>{(T)(dp.cnorm * dre / den), (T)(-dp.cnorm * sim / den)};
+          const double f = dp.cnorm / (dre * dre + sim * sim);
+          o[r] = o[r] * cx<T>{(T)(f * dre), (T)(-f * sim)};
         }
       }
       // the divided values become the input of the inverse transform
@@ -579,12 +576,14 @@ __global__ void __launch_bounds__(NT) dst_half_kernel(Geo g, cx<T>* __restrict__
       if (pos >= 1 && pos <= N) lbuf[pidx(pos - 1)] = o[r];
     }
     __syncthreads();
+    if (l0 + tl < lg.lines) {
+      cx<T>* dstp = data + pbase;
+      const int off = (l0 + tl) * lg.line_stride + te * lg.elem_stride;
 #pragma unroll
-    for (int q = 0; q < QS; ++q) {
-      const int idx = threadIdx.x + NT * q;
-      const int e = idx / LPB, l = idx - (idx / LPB) * LPB;
-      if (idx < N * LPB && l0 + l < lg.lines)
-        data[pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride] = buf[l * LD + pidx(e)];
+      for (int q = 0; q < QS; ++q) {
+        const int e = te + q * (NT / LPB);
+        if (threadIdx.x + NT * q < N * LPB) dstp[off + q * (NT / LPB) * lg.elem_stride] = buf[tl * LD + pidx(e)];
+      }
     }
     __syncthreads();
     blk = nxt;
