@@ -63,6 +63,8 @@ enum { PCOP_PRECOND_EPS = 0, PCOP_PRECOND_IDEAL = 1 };      /* preconditioner */
  *   dim      2 or 3.
  *   nx       interior points per dimension (>= 1; 2^p - 1 for PCOP_MG).
  *   nt       number of backward-Euler steps N (>= 2); n = nt - 1 blocks.
+ *            With PCOP_PRECOND_EPS, n <= 2048 (the time FFT runs in LDS;
+ *            longer lengths return PCOP_ERR_UNSUPPORTED).
  *   T        final time (> 0).
  *   batch    number of independent systems solved together (>= 1).
  *   gamma    host array [batch] of regularisation parameters (> 0).
@@ -113,8 +115,9 @@ typedef struct {
  *              with at most that many points per block; 4 / 8 / 16 in-place
  *              Stockham (one LDS buffer) with at most that many points per
  *              block.  A kind of kernel that does not fit LDS falls back to
- *              the other.  When nt - 1 has a prime factor above 17 the
- *              chirp-z kernels run instead: 0 / -1 automatic, 4 / 8 / 16 at
+ *              the other.  When nt - 1 has a prime factor above 17, or no
+ *              Stockham tile of it fits LDS (long smooth lengths, e.g.
+ *              FP64 n = 1152 or 2048), the chirp-z kernels run instead: 0 / -1 automatic, 4 / 8 / 16 at
  *              most that many points per block with 256 threads, -4 / -8 /
  *              -16 with 512 threads (a request that fits no kernel falls back
  *              to the automatic choice).
@@ -267,7 +270,8 @@ pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* ep
 /* Kernel choices in effect (after tuning):
  *   time_cols      Stockham: -P (two LDS buffers, P points per block) or
  *                  +P (in place); chirp-z (nt - 1 with a prime factor above
- *                  17): +P (P points, 256 threads) or -P (512 threads);
+ *                  17, or no Stockham tile fits LDS): +P (P points, 256
+ *                  threads) or -P (512 threads);
  *                  0 with PCOP_PRECOND_IDEAL (no time transform);
  *   dst_kernel     1 (register-resident), 2 (LDS-staged), 3 (register, wide
  *                  column tiles), 4 (half-length strided transforms) or 0

@@ -17,7 +17,8 @@
 namespace pcop {
 
 // Time-axis FFT plan: Stockham radices (each <= 17) or, when n has a larger
-// prime factor, Bluestein's chirp-z transform with a power-of-two length M.
+// prime factor or no Stockham tile of it fits LDS, Bluestein's chirp-z
+// transform with a power-of-two length M.
 struct FftPlan {
   int nrad;
   int rad[16];

@@ -96,7 +96,7 @@ bool time_lds_fits(int n, bool fp32);
 // time-pass kernels that launch_precond runs for tb.time_cols: 0 chirp-z,
 // -P two LDS buffers, +P in place, with P points per block
 int time_choice(const Geo& g, const PrecondTables& tb, bool fp32);
-FftPlan make_time_plan(int n);
+FftPlan make_time_plan(int n, bool fp32);
 bool launch_precond(const Geo& g, const double* v, double* w, void* spec, bool fp32, int spatial,
                     const PrecondTables& tb, const double* vscale, int vs_stride, int accum,
                     hipStream_t st);

@@ -151,7 +151,7 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
   L.post = take(L, sizeof(double) * ((size_t)B * ((m + 255) / 256) + B + 2 * (size_t)B * (n + 1) + B));
   L.twn64 = take(L, 16 * (size_t)n);
   L.twn32 = take(L, 8 * (size_t)n);
-  const FftPlan tp = make_time_plan(n);
+  const FftPlan tp = make_time_plan(n, o->precision == PCOP_MIXED);
   L.M = tp.bluestein ? tp.M : 1;
   L.twM64 = take(L, 16 * (size_t)L.M);
   L.twM32 = take(L, 8 * (size_t)L.M);
@@ -927,7 +927,7 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   tb.lam = c->at<double>(L.lam);
   tb.alpha = c->at<double>(L.alpha);
   tb.active = nullptr;
-  tb.plan = make_time_plan(n);
+  tb.plan = make_time_plan(n, opts->precision == PCOP_MIXED);
   tb.twM64 = c->at<double>(L.twM64);
   tb.twM32 = c->at<float>(L.twM32);
   tb.chirp64 = c->at<double>(L.chirp64);

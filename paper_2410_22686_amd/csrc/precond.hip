@@ -39,33 +39,6 @@ static int time_cols_sk(int n, int csz, int want, bool wide = false) {
 }
 
 
-FftPlan make_time_plan(int n) {
-  FftPlan pl{};
-  int r = n;
-  int big = 0;
-  for (int f = 2; f * f <= r; ++f)
-    while (r % f == 0) {
-      if (f > 17) big = 1;
-      r /= f;
-    }
-  if (r > 17) big = 1;
-  if (big) {
-    pl.bluestein = 1;
-    pl.M = 1;
-    while (pl.M < 2 * n - 1) pl.M *= 2;
-    pl.nrad = 0;
-    return pl;
-  }
-  r = n;
-  while (r % 8 == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = 8; r /= 8; }
-  while (r % 4 == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = 4; r /= 4; }
-  while (r % 2 == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = 2; r /= 2; }
-  for (int f = 3; f <= 17 && pl.nrad < 16; f += 2)
-    while (r % f == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = f; r /= f; }
-  if (pl.nrad == 0) pl.rad[pl.nrad++] = 1;  // n = 1
-  return pl;
-}
-
 // points per block of the in-place time kernels: the largest power of two in
 // 4..want that fits 64 KiB with every stage within the supported butterflies
 // per thread, else 0
@@ -98,8 +71,49 @@ static int time_block(const FftPlan& pl, int n, int csz, int req) {
   return -time_cols_sk(n, csz, 16);
 }
 
+static FftPlan chirp_plan(int n) {
+  FftPlan pl{};
+  pl.bluestein = 1;
+  pl.M = 1;
+  while (pl.M < 2 * n - 1) pl.M *= 2;
+  pl.nrad = 0;
+  return pl;
+}
+
+// radix plan of length n (radices 2..17), or the chirp-z plan when n has a
+// prime factor above 17
+static FftPlan radix_plan(int n) {
+  FftPlan pl{};
+  int r = n;
+  int big = 0;
+  for (int f = 2; f * f <= r; ++f)
+    while (r % f == 0) {
+      if (f > 17) big = 1;
+      r /= f;
+    }
+  if (r > 17) big = 1;
+  if (big) return chirp_plan(n);
+  r = n;
+  while (r % 8 == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = 8; r /= 8; }
+  while (r % 4 == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = 4; r /= 4; }
+  while (r % 2 == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = 2; r /= 2; }
+  for (int f = 3; f <= 17 && pl.nrad < 16; f += 2)
+    while (r % f == 0 && pl.nrad < 16) { pl.rad[pl.nrad++] = f; r /= f; }
+  if (pl.nrad == 0) pl.rad[pl.nrad++] = 1;  // n = 1
+  return pl;
+}
+
+// The time plan: the radix plan when a Stockham kernel holds its tiles in
+// LDS, else the chirp-z transform (lengths with a prime factor above 17, and
+// long smooth lengths whose tiles exceed LDS: FP64 n > 1024 among others)
+FftPlan make_time_plan(int n, bool fp32) {
+  const FftPlan pl = radix_plan(n);
+  if (pl.bluestein || time_block(pl, n, fp32 ? 8 : 16, 0) != 0) return pl;
+  return chirp_plan(n);
+}
+
 bool time_lds_fits(int n, bool fp32) {
-  const FftPlan pl = make_time_plan(n);
+  const FftPlan pl = make_time_plan(n, fp32);
   const int csz = fp32 ? 8 : 16;
   return pl.bluestein ? bl_choice(pl.M, n, csz, 0) != 0 : time_block(pl, n, csz, 0) != 0;
 }

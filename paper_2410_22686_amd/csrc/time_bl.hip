@@ -1,5 +1,6 @@
-// Time passes for lengths with a prime factor above 17: chirp-z (Bluestein)
-// transform with power-of-two convolutions in LDS.
+// Time passes for lengths with a prime factor above 17 (and long smooth
+// lengths whose Stockham tiles exceed LDS): chirp-z (Bluestein) transform
+// with power-of-two convolutions in LDS.
 //
 // Persistent blocks walk column tiles lb, lb + G, ... (round robin, so that
 // neighbouring tiles, which share 128-byte lines, run at the same time on one

@@ -13,8 +13,9 @@ namespace pcop {
 // A block owns P consecutive spatial points and all n time levels.
 // Stockham mode: LDS holds two [n][P] buffers; the first stage of the forward
 // pass reads HBM directly and the last stage of the inverse pass writes HBM
-// directly.  Bluestein mode (n has a prime factor > 17): a length-M
-// power-of-two convolution in one in-place [P][M+1] LDS buffer,
+// directly.  Bluestein mode (n has a prime factor > 17, or no Stockham tile
+// fits LDS): a length-M power-of-two convolution in one in-place [P][M+1]
+// LDS buffer,
 //   X_k = w_k sum_j (x_j w_j) conj(w_{k-j}),  w_j = exp(-i pi j^2/n),
 // with the FFT of the chirp filter precomputed (bhat).
 // ---------------------------------------------------------------------------

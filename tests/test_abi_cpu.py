@@ -100,6 +100,21 @@ def test_kernel_choice_options_validate(lib):
         assert lib.pcop_validate(ctypes.byref(p), ctypes.byref(_opts(lib, **kw))) == 0, kw
 
 
+def test_every_time_length_up_to_2048_validates(lib):
+    """Every n = nt - 1 in 1..2048 has a time-pass kernel in both precisions:
+    radix plans whose tiles fit LDS, otherwise the chirp-z transform (M up to
+    4096), which also takes long smooth lengths such as n = 1152 or 2048.
+    Beyond that the chirp-z length exceeds 4096 and setup refuses."""
+    from paper_2410_22686_amd import pcop
+    for precision, side in ((pcop.PCOP_FP64, pcop.PCOP_RIGHT), (pcop.PCOP_MIXED, pcop.PCOP_FLEXIBLE)):
+        o = _opts(lib, precision=precision, side=side)
+        bad = [n for n in range(1, 2049)
+               if lib.pcop_validate(ctypes.byref(_prob(nx=3, nt=n + 1)), ctypes.byref(o)) != pcop.PCOP_OK]
+        assert bad == [], (precision, bad[:10])
+        for n in (2049, 2050, 4096):
+            assert lib.pcop_validate(ctypes.byref(_prob(nx=3, nt=n + 1)), ctypes.byref(o)) == 2, (precision, n)
+
+
 def test_gamma_must_be_positive(lib):
     assert lib.pcop_validate(ctypes.byref(_prob(gammas=(1e-4, -1.0))), ctypes.byref(_opts(lib))) == 1
     assert lib.pcop_validate(ctypes.byref(_prob(gammas=(float("nan"),))), ctypes.byref(_opts(lib))) == 1

@@ -215,7 +215,18 @@ CHIRP_CASES = [
     (2, 3, 512, (1e-6,)),        # n = 511 = 7 * 73, M = 1024
     (2, 3, 1024, (1e-4,)),       # n = 1023 = 3 * 11 * 31, M = 2048
     (2, 3, 2048, (1e-4,)),       # n = 2047 = 23 * 89, M = 4096: FP64 tables stay in global memory
+    (2, 3, 1153, (1e-4,)),       # n = 1152 = 2^7 3^2: smooth, but no radix tile fits LDS (M = 4096)
+    (2, 3, 2049, (1e-4,)),       # n = 2048: chirp-z in FP64 (M = 4096), radix kernels in FP32
 ]
+
+
+@pytest.mark.parametrize("nt,precision", [(1153, "fp64"), (1153, "mixed"), (2049, "fp64"), (1537, "fp64")])
+def test_long_smooth_lengths_use_chirp(nt, precision):
+    """Smooth lengths whose radix tiles do not fit LDS run the chirp-z kernels
+    (M = 4096 allows at most 2 points per block) instead of being refused."""
+    side = "flexible" if precision == "mixed" else "right"
+    s = Solver(2, 3, nt, [1e-4], precision=precision, side=side, device=DEV)
+    assert s.kernels["time_cols"] in (1, 2), s.kernels
 
 
 @pytest.mark.parametrize("dim,nx,nt,gammas", CHIRP_CASES)
