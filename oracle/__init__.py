@@ -7,7 +7,8 @@ function here is written from the paper with plain NumPy/SciPy (sparse
 matrices, dense Fourier matrices, sparse LU), in float64.
 
 Modules:
-  discretize -- grid, K = -L_h, B_n, C_eps, the KKT matrices and the RHS
+  discretize -- grid, K = -L_h (or the Q1 finite-element M and K), B_n,
+                C_eps, the KKT matrices and the RHS
                 (Section 1: eq. main_system_before, eq. matrix_A_before,
                 eq. main_system, eq. matrix_A, eq. matrix_T)
   precond    -- P_eps^{-1} by the four steps of Section 2.1, the dense

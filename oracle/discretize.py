@@ -86,6 +86,43 @@ def stiffness(dim: int, nx: int, coeff: Optional[Callable] = None) -> sp.csr_mat
     return K.tocsr()
 
 
+# ---------------------------------------------------------------------------
+# bilinear (d = 2) or trilinear (d = 3) finite elements on the uniform grid:
+# the mass and stiffness matrices M_m, K_m of Section 1 for a = 1
+# ---------------------------------------------------------------------------
+
+def fem_q1_1d(nx: int):
+    """1-D piecewise-linear mass and stiffness matrices with zero Dirichlet
+    data: M1 = (h/6) tridiag(1, 4, 1), K1 = (1/h) tridiag(-1, 2, -1)."""
+    h = 1.0 / (nx + 1)
+    M1 = sp.diags([np.ones(nx - 1), 4.0 * np.ones(nx), np.ones(nx - 1)], [-1, 0, 1], format="csr") * (h / 6.0)
+    K1 = sp.diags([-np.ones(nx - 1), 2.0 * np.ones(nx), -np.ones(nx - 1)], [-1, 0, 1], format="csr") / h
+    return M1, K1
+
+
+def fem_q1(dim: int, nx: int):
+    """Tensor-product (Q1) mass and stiffness matrices on the interior nodes:
+    M = M1 (x) .. (x) M1 and K = sum over axes of the product with K1 on that
+    axis and M1 on the others (the element integrals of phi_a phi_b and
+    grad phi_a . grad phi_b factor by axis for tensor-product shape
+    functions)."""
+    M1, K1 = fem_q1_1d(nx)
+
+    def prod(factors):
+        out = factors[dim - 1]
+        for a in range(dim - 2, -1, -1):      # axis 0 = x1 fastest: rightmost factor
+            out = sp.kron(out, factors[a], format="csr")
+        return out
+
+    M = prod([M1] * dim)
+    K = None
+    for axis in range(dim):
+        fs = [M1] * dim
+        fs[axis] = K1
+        K = prod(fs) if K is None else K + prod(fs)
+    return M.tocsr(), K.tocsr()
+
+
 def dst_eigenvalues(dim: int, nx: int) -> np.ndarray:
     """Eigenvalues mu of the constant-coefficient K, one per DST-I mode in
     lexicographic order (x1 fastest): mu = (4/h^2) sum_d sin^2(pi j_d h / 2)."""
@@ -132,6 +169,11 @@ class Problem:
     gamma: float
     eps: float
     K: sp.csr_matrix
+    M: Optional[sp.csr_matrix] = None   # mass matrix; None means M_m = I (finite differences)
+
+    @property
+    def Mm(self) -> sp.csr_matrix:
+        return sp.identity(self.m, format="csr") if self.M is None else self.M
 
     @property
     def n(self) -> int:
@@ -155,9 +197,19 @@ class Problem:
 
 
 def make_problem(dim: int, nx: int, nt: int, gamma: float, T: float = 1.0,
-                 eps: Optional[float] = None, coeff: Optional[Callable] = None) -> Problem:
+                 eps: Optional[float] = None, coeff: Optional[Callable] = None,
+                 mass: str = "identity") -> Problem:
+    """mass = "identity": finite differences (M_m = I, K_m = -L_h);
+    mass = "q1": bilinear/trilinear finite elements (a = 1 only)."""
     tau = T / nt
     e = math.sqrt(tau) if eps is None else float(eps)
+    if mass == "q1":
+        if coeff is not None:
+            raise ValueError("the finite-element matrices are built for a = 1")
+        M, K = fem_q1(dim, nx)
+        return Problem(dim, nx, nt, T, gamma, e, K, M)
+    if mass != "identity":
+        raise ValueError(mass)
     return Problem(dim, nx, nt, T, gamma, e, stiffness(dim, nx, coeff))
 
 
@@ -166,18 +218,18 @@ def make_problem(dim: int, nx: int, nt: int, gamma: float, T: float = 1.0,
 # ---------------------------------------------------------------------------
 
 def kkt_unscaled(pb: Problem) -> sp.csr_matrix:
-    """The matrix of eq. matrix_A_before (M = I):
-        [[tau I,          B^T (x) I + tau I (x) K],
-         [B (x) I + tau I (x) K,       -tau/gamma I]]
+    """The matrix of eq. matrix_A_before:
+        [[tau I (x) M,          B^T (x) M + tau I (x) K],
+         [B (x) M + tau I (x) K,       -tau/gamma I (x) M]]
     acting on [y; p] with y = (y^1..y^n), p = (p^1..p^n)."""
-    n, m, tau = pb.n, pb.m, pb.tau
-    Im = sp.identity(m, format="csr")
+    n, tau = pb.n, pb.tau
+    Mm = pb.Mm
     In = sp.identity(n, format="csr")
     B = toeplitz_B(n)
-    Tm = sp.kron(B, Im) + tau * sp.kron(In, pb.K)
-    Tt = sp.kron(B.T, Im) + tau * sp.kron(In, pb.K)
-    Inm = sp.identity(n * m, format="csr")
-    return sp.bmat([[tau * Inm, Tt], [Tm, -(tau / pb.gamma) * Inm]], format="csr")
+    Tm = sp.kron(B, Mm) + tau * sp.kron(In, pb.K)
+    Tt = sp.kron(B.T, Mm) + tau * sp.kron(In, pb.K)
+    InM = sp.kron(In, Mm, format="csr")
+    return sp.bmat([[tau * InM, Tt], [Tm, -(tau / pb.gamma) * InM]], format="csr")
 
 
 def kkt_scaled(pb: Problem) -> sp.csr_matrix:
@@ -194,13 +246,14 @@ def kkt_scaled(pb: Problem) -> sp.csr_matrix:
 
 def rhs_unscaled(pb: Problem, g: np.ndarray, f: np.ndarray, y0: np.ndarray,
                  pN: Optional[np.ndarray] = None) -> np.ndarray:
-    """Right-hand side [g; f] of eq. main_system_before (M = I):
-    g-block tau g^j (+ p^N at j = n), f-block tau f^j (+ y^0 at j = 1)."""
-    gb = pb.tau * np.array(g, dtype=np.float64).reshape(pb.n, pb.m).copy()
-    fb = pb.tau * np.array(f, dtype=np.float64).reshape(pb.n, pb.m).copy()
+    """Right-hand side [g; f] of eq. main_system_before:
+    g-block tau M g^j (+ M p^N at j = n), f-block tau M f^j (+ M y^0 at j = 1)."""
+    Mm = pb.Mm
+    gb = pb.tau * (Mm @ np.array(g, dtype=np.float64).reshape(pb.n, pb.m).T).T
+    fb = pb.tau * (Mm @ np.array(f, dtype=np.float64).reshape(pb.n, pb.m).T).T
     if pN is not None:
-        gb[-1] += pN
-    fb[0] += y0
+        gb[-1] += Mm @ np.asarray(pN, dtype=np.float64)
+    fb[0] += Mm @ np.asarray(y0, dtype=np.float64)
     return np.concatenate([gb.ravel(), fb.ravel()])
 
 
@@ -227,20 +280,23 @@ def kkt_apply(pb: Problem, x: np.ndarray, transpose: bool = False) -> np.ndarray
 
 def kkt_apply_blocks(pb: Problem, x: np.ndarray, transpose: bool = False) -> np.ndarray:
     """y = A x (or A^T x) written out block by block from eq. matrix_A without
-    assembling A:  with E = I + tau K,
-        y_1^j = alpha x_1^j + E x_2^j - x_2^{j+1},
-        y_2^j = -(E x_1^j - x_1^{j-1}) + alpha x_2^j,
+    assembling A:  with E = M + tau K,
+        y_1^j = alpha M x_1^j + E x_2^j - M x_2^{j+1},
+        y_2^j = -(E x_1^j - M x_1^{j-1}) + alpha M x_2^j,
     x^0 = x^{n+1} = 0 (B_n has ones on the diagonal and -1 below it); A^T flips
-    the sign of both off-diagonal blocks (M = I).  Used where the assembled
-    matrix is too large to build."""
+    the sign of both off-diagonal blocks (M and K are symmetric).  Used where
+    the assembled matrix is too large to build."""
     n, m = pb.n, pb.m
     X = np.asarray(x, dtype=np.float64).reshape(2, n, m)
     x1, x2 = X[0], X[1]
-    Ex1 = x1 + pb.tau * (pb.K @ x1.T).T
-    Ex2 = x2 + pb.tau * (pb.K @ x2.T).T
-    x2next = np.vstack([x2[1:], np.zeros((1, m))])
-    x1prev = np.vstack([np.zeros((1, m)), x1[:-1]])
+    Mm = pb.Mm
+    Mx1 = (Mm @ x1.T).T
+    Mx2 = (Mm @ x2.T).T
+    Ex1 = Mx1 + pb.tau * (pb.K @ x1.T).T
+    Ex2 = Mx2 + pb.tau * (pb.K @ x2.T).T
+    x2next = np.vstack([Mx2[1:], np.zeros((1, m))])
+    x1prev = np.vstack([np.zeros((1, m)), Mx1[:-1]])
     sgn = -1.0 if transpose else 1.0
-    y1 = pb.alpha * x1 + sgn * (Ex2 - x2next)
-    y2 = -sgn * (Ex1 - x1prev) + pb.alpha * x2
+    y1 = pb.alpha * Mx1 + sgn * (Ex2 - x2next)
+    y2 = -sgn * (Ex1 - x1prev) + pb.alpha * Mx2
     return np.concatenate([y1.ravel(), y2.ravel()])

@@ -38,7 +38,7 @@ def lambda_eps(n: int, eps: float) -> np.ndarray:
 
 
 class EpsCirculantRBD:
-    """w = P_eps^{-1} v by the four steps of Section 2.1 (M = I).
+    """w = P_eps^{-1} v by the four steps of Section 2.1.
 
     ``spatial="lu"`` solves the shifted systems of Step 2 exactly (sparse
     LU per frequency); ``spatial="mg"`` replaces each solve by one V-cycle of
@@ -54,10 +54,10 @@ class EpsCirculantRBD:
         self.spatial = spatial
         if spatial == "lu":
             Kc = pb.K.tocsc().astype(np.complex128)
-            I = sp.identity(m, format="csc", dtype=np.complex128)
-            # one factorisation per frequency of (lambda_k + alpha) I + tau K;
+            Mc = pb.Mm.tocsc().astype(np.complex128)
+            # one factorisation per frequency of (lambda_k + alpha) M + tau K;
             # block 1 needs conj(lambda_k) = lambda_{(n-k) mod n}
-            self.lu = [spla.splu((self.lam[k] + pb.alpha) * I + pb.tau * Kc) for k in range(n)]
+            self.lu = [spla.splu(((self.lam[k] + pb.alpha) * Mc + pb.tau * Kc).tocsc()) for k in range(n)]
         elif spatial == "mg":
             from .multigrid import ShiftedVCycle
             self.mg = ShiftedVCycle(pb.dim, pb.nx, pb.tau, coeff)
@@ -97,8 +97,9 @@ class EpsCirculantRBD:
 def eps_circulant_dense(pb: Problem) -> np.ndarray:
     """P_eps of eq. matrix_P_eps assembled densely (tiny grids only)."""
     n, m = pb.n, pb.m
-    C = np.kron(eps_circulant(n, pb.eps), np.eye(m)) + pb.tau * np.kron(np.eye(n), pb.K.toarray())
-    A = pb.alpha * np.eye(n * m)
+    Md = pb.Mm.toarray()
+    C = np.kron(eps_circulant(n, pb.eps), Md) + pb.tau * np.kron(np.eye(n), pb.K.toarray())
+    A = pb.alpha * np.kron(np.eye(n), Md)
     H = np.block([[C.T + A, np.zeros_like(C)], [np.zeros_like(C), C + A]])
     I = np.eye(n * m)
     G = np.block([[I, I], [-I, I]])
@@ -108,8 +109,9 @@ def eps_circulant_dense(pb: Problem) -> np.ndarray:
 def ideal_rbd_dense(pb: Problem) -> np.ndarray:
     """P of eq. matrix_P assembled densely (tiny grids only)."""
     n, m = pb.n, pb.m
-    Tm = np.kron(toeplitz_B(n).toarray(), np.eye(m)) + pb.tau * np.kron(np.eye(n), pb.K.toarray())
-    A = pb.alpha * np.eye(n * m)
+    Md = pb.Mm.toarray()
+    Tm = np.kron(toeplitz_B(n).toarray(), Md) + pb.tau * np.kron(np.eye(n), pb.K.toarray())
+    A = pb.alpha * np.kron(np.eye(n), Md)
     H = np.block([[Tm.T + A, np.zeros_like(Tm)], [np.zeros_like(Tm), Tm + A]])
     I = np.eye(n * m)
     G = np.block([[I, I], [-I, I]])
@@ -122,8 +124,9 @@ class IdealRBD:
     P^{-1} = G^{-1} blockdiag(T^T + alpha I, T + alpha I)^{-1}: the two block
     bidiagonal systems are solved by sequential substitution in time
     (T + alpha I forward from level 1, T^T + alpha I backward from level n),
-    each step a solve with T_0 = (1 + alpha) I + tau K (Section 2, the
-    block lower-triangular Toeplitz structure of (T + alpha I)^{-1}).
+    each step a solve with T_0 = (1 + alpha) M + tau K and the coupling
+    -M to the neighbouring level (Section 2, the block lower-triangular
+    Toeplitz structure of (T + alpha I (x) M)^{-1}).
 
     ``spatial="lu"`` solves with T_0 exactly (sparse LU); ``spatial="mg"``
     takes one V-cycle of :mod:`oracle.multigrid` with the real shift
@@ -135,7 +138,7 @@ class IdealRBD:
         m = pb.m
         self.spatial = spatial
         if spatial == "lu":
-            T0 = (1.0 + pb.alpha) * sp.identity(m, format="csc") + pb.tau * pb.K.tocsc()
+            T0 = (1.0 + pb.alpha) * pb.Mm.tocsc() + pb.tau * pb.K.tocsc()
             self.lu = spla.splu(T0.tocsc())
         elif spatial == "mg":
             from .multigrid import ShiftedVCycle
@@ -154,11 +157,12 @@ class IdealRBD:
         v = np.asarray(v, dtype=np.float64).reshape(2, n, m)
         z1 = np.zeros((n, m))
         z2 = np.zeros((n, m))
-        for j in range(n):                       # (T + alpha I) z2 = v2
-            r = v[1, j] + (z2[j - 1] if j > 0 else 0.0)
+        Mm = pb.Mm
+        for j in range(n):                       # (T + alpha I (x) M) z2 = v2
+            r = v[1, j] + (Mm @ z2[j - 1] if j > 0 else 0.0)
             z2[j] = self._solve(r)
-        for j in range(n - 1, -1, -1):           # (T^T + alpha I) z1 = v1
-            r = v[0, j] + (z1[j + 1] if j < n - 1 else 0.0)
+        for j in range(n - 1, -1, -1):           # (T^T + alpha I (x) M) z1 = v1
+            r = v[0, j] + (Mm @ z1[j + 1] if j < n - 1 else 0.0)
             z1[j] = self._solve(r)
         return np.concatenate([(z1 - z2).ravel(), (z1 + z2).ravel()])
 
@@ -166,23 +170,25 @@ class IdealRBD:
 def eps_circulant_apply(pb: Problem, w: np.ndarray) -> np.ndarray:
     """v = P_eps w for P_eps of eq. matrix_P_eps without assembling it:
     with [u_1; u_2] = [[I, I], [-I, I]] w,
-        v_1 = (C_eps^T + alpha I) u_1 / 2,  v_2 = (C_eps + alpha I) u_2 / 2,
-    C_eps = C_{eps,n} (x) I + tau I (x) K, and C_{eps,n} = B_n with -eps in the
+        v_1 = (C_eps^T + alpha I (x) M) u_1 / 2,  v_2 = (C_eps + alpha I (x) M) u_2 / 2,
+    C_eps = C_{eps,n} (x) M + tau I (x) K, and C_{eps,n} = B_n with -eps in the
     top-right corner.  Checks a computed P_eps^{-1} v at any size."""
     n, m = pb.n, pb.m
     W = np.asarray(w, dtype=np.float64).reshape(2, n, m)
     u1 = W[0] + W[1]
     u2 = -W[0] + W[1]
+    Mm = pb.Mm
 
     def c_apply(u, transpose):
         tK = pb.tau * (pb.K @ u.T).T
-        out = u + tK + pb.alpha * u
-        if not transpose:   # (C u)_j = u_j - u_{j-1}, j = 0 wraps with -eps
-            out[1:] -= u[:-1]
-            out[0] -= pb.eps * u[-1]
-        else:               # (C^T u)_j = u_j - u_{j+1}, j = n-1 wraps with -eps
-            out[:-1] -= u[1:]
-            out[-1] -= pb.eps * u[0]
+        Mu = (Mm @ u.T).T
+        out = Mu + tK + pb.alpha * Mu
+        if not transpose:   # (C u)_j = M u_j - M u_{j-1}, j = 0 wraps with -eps
+            out[1:] -= Mu[:-1]
+            out[0] -= pb.eps * Mu[-1]
+        else:               # (C^T u)_j = M u_j - M u_{j+1}, j = n-1 wraps with -eps
+            out[:-1] -= Mu[1:]
+            out[-1] -= pb.eps * Mu[0]
         return out
 
     v1 = 0.5 * c_apply(u1, True)
