@@ -58,6 +58,7 @@ enum { PCOP_DST = 0, PCOP_MG = 1 };              /* spatial solver of Step 2 */
 enum { PCOP_RIGHT = 0, PCOP_LEFT = 1, PCOP_FLEXIBLE = 2 };  /* GMRES variant */
 enum { PCOP_COEFF_ONE = 0, PCOP_COEFF_HALFGRID = 1 };        /* a(x) */
 enum { PCOP_PRECOND_EPS = 0, PCOP_PRECOND_IDEAL = 1 };      /* preconditioner */
+enum { PCOP_MASS_IDENTITY = 0, PCOP_MASS_Q1 = 1 };           /* M_m of Section 1 */
 
 /* Problem statement (Section 1; Section 3 for the discretisation).
  *   dim      2 or 3.
@@ -76,7 +77,17 @@ enum { PCOP_PRECOND_EPS = 0, PCOP_PRECOND_IDEAL = 1 };      /* preconditioner */
  *            values of a(x) sampled at x = k h/2, k = 1..2nx+1 in every
  *            dimension (lexicographic, x1 fastest); these samples contain
  *            a at every face midpoint of every multigrid level.  The values
- *            are copied at pcop_setup. */
+ *            are copied at pcop_setup.
+ *   mass     PCOP_MASS_IDENTITY: finite differences, M_m = I and K_m = -L_h
+ *            (5-point / 7-point stencil).  PCOP_MASS_Q1: bilinear (2-D) or
+ *            trilinear (3-D) finite elements on the same grid, M_m and K_m
+ *            the element mass and stiffness matrices (Section 1 with
+ *            M_m != I: eq. matrix_A_before, eq. matrix_A, eq. matrix_P_eps
+ *            carry I (x) M_m and C_eps (x) M_m); requires PCOP_COEFF_ONE,
+ *            PCOP_DST and PCOP_PRECOND_EPS, and pcop_post_solve /
+ *            pcop_error_eh return PCOP_ERR_UNSUPPORTED.  The right-hand side
+ *            of pcop_rhs and the maps of pcop_data_grad include M_m.
+ *            Appended last: zero-initialised callers get finite differences. */
 typedef struct {
   int dim;
   int nx;
@@ -87,6 +98,7 @@ typedef struct {
   double eps;
   int coeff_kind;
   const double* coeff;
+  int mass;
 } pcop_problem;
 
 /* Solver options.

@@ -53,6 +53,7 @@ struct Geo {
   long long vs;  // doubles between consecutive members' vectors (>= vl; padded to 256 bytes inside the solver)
   double tau;
   double h2inv;  // 1/h^2
+  int fem;       // 1: Q1 finite-element mass and stiffness matrices (M != I), 0: finite differences (M = I)
 };
 
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).

@@ -35,6 +35,9 @@ struct DivideParams {
   const int* active;     // [B] or null
   double cnorm;
   int spm;               // slices per member: plane p belongs to member p / spm, slice p mod spm
+  const double* im1;     // [nx] 1/m_k of the Q1 mass matrix, or null (M = I): the shifted
+                         // operator sigma M + tau K has the sine-basis eigenvalues
+                         // prod_d m_{k_d} (sigma + tau sum_d k_{k_d}/m_{k_d}), mu1 holding k/m
 };
 
 template <class T, int L, int LINES, int NT, bool ROWS, bool DIVIDE>
@@ -91,8 +94,13 @@ __global__ void __launch_bounds__(NT) dst_lines_kernel(Geo g, cx<T>* __restrict_
         double mu = dp.mu1[e] + dp.mu1[line % g.nx];
         if (g.dim == 3) mu += dp.mu1[line / g.nx];
         const double dre = sre + g.tau * mu;
+        double psi = 1.0;
+        if (dp.im1) {
+          psi = dp.im1[e] * dp.im1[line % g.nx];
+          if (g.dim == 3) psi *= dp.im1[line / g.nx];
+        }
         // cnorm / (dre + i sim) = cnorm (dre - i sim) / (dre^2 + sim^2)
-        const double f = dp.cnorm / (dre * dre + sim * sim);
+        const double f = psi * dp.cnorm / (dre * dre + sim * sim);
         y = y * cx<T>{(T)(f * dre), (T)(-f * sim)};
       }
       buf[l * LD + e + 1] = y;
@@ -201,12 +209,18 @@ __device__ __forceinline__ void divide_line(cx<T> (&v)[8], int t, const Geo& g, 
   const double sim = (q & 1) ? -dp.lam[2 * k + 1] : dp.lam[2 * k + 1];
   double mul = dp.mu1[line % g.nx];
   if (g.dim == 3) mul += dp.mu1[(line / g.nx) % g.nx];
+  double psl = 1.0;
+  if (dp.im1) {
+    psl = dp.im1[line % g.nx];
+    if (g.dim == 3) psl *= dp.im1[(line / g.nx) % g.nx];
+  }
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     const int pos = t + TL * s;
     if (pos >= 1 && pos <= N && valid) {
       const double dre = sre + g.tau * (mul + dp.mu1[pos - 1]);
-      const double f = dp.cnorm / (dre * dre + sim * sim);
+      const double psi = dp.im1 ? psl * dp.im1[pos - 1] : 1.0;
+      const double f = psi * dp.cnorm / (dre * dre + sim * sim);
       v[s] = v[s] * cx<T>{(T)(f * dre), (T)(-f * sim)};
     }
   }
@@ -548,12 +562,18 @@ __global__ void __launch_bounds__(NT) dst_half_kernel(Geo g, cx<T>* __restrict__
       const double sim = (q & 1) ? -dp.lam[2 * k + 1] : dp.lam[2 * k + 1];
       double ml = mul[line % g.nx];
       if (g.dim == 3) ml += mul[(line / g.nx) % g.nx];
+      double psl = 1.0;
+      if (dp.im1) {
+        psl = dp.im1[line % g.nx];
+        if (g.dim == 3) psl *= dp.im1[(line / g.nx) % g.nx];
+      }
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int pos = 8 * t + r;
         if (pos >= 1 && pos <= N && valid) {
           const double dre = sre + g.tau * (ml + mul[pos - 1]);
-          const double f = dp.cnorm / (dre * dre + sim * sim);
+          const double psi = dp.im1 ? psl * dp.im1[pos - 1] : 1.0;
+          const double f = psi * dp.cnorm / (dre * dre + sim * sim);
           o[r] = o[r] * cx<T>{(T)(f * dre), (T)(-f * sim)};
         }
       }
@@ -687,7 +707,7 @@ static bool dst_solve(const Geo& g, cx<T>* spec, const PrecondTables& tb, int sp
                       hipStream_t st) {
   const int nx = g.nx;
   const long long slices = (long long)g.B * spm;
-  DivideParams dp{tb.mu1, lam, tb.alpha, tb.active, 0.0, spm};
+  DivideParams dp{tb.mu1, lam, tb.alpha, tb.active, 0.0, spm, tb.im1};
   dp.cnorm = (g.dim == 2) ? 1.0 / (4.0 * (nx + 1.0) * (nx + 1.0))
                           : -1.0 / (8.0 * (nx + 1.0) * (nx + 1.0) * (nx + 1.0));
   const cx<T>* twL = reinterpret_cast<const cx<T>*>(sizeof(T) == 8 ? (const void*)tb.twL64 : (const void*)tb.twL32);

@@ -1,0 +1,162 @@
+// Finite-element form of the KKT system (Section 1 with M_m != I): bilinear
+// (2-D) or trilinear (3-D) elements on the uniform grid, a = 1, zero
+// Dirichlet data.  The mass and stiffness matrices are tensor products of
+// the 1-D matrices M1 = (h/6) tridiag(1, 4, 1) and K1 = (1/h) tridiag(-1, 2, -1):
+//   M = M1 (x) M1 (x) M1,  K = K1 (x) M1 (x) M1 + M1 (x) K1 (x) M1 + M1 (x) M1 (x) K1
+// (2-D: drop one factor), so both act as 9-point (27-point) stencils.
+#include <algorithm>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace pcop {
+
+struct Q1W {
+  double m0, m1;  // M1 diagonal and off-diagonal: 4h/6, h/6
+  double k0, k1;  // K1 diagonal and off-diagonal: 2/h, -1/h
+};
+
+__host__ __device__ inline Q1W q1_weights(int nx) {
+  const double h = 1.0 / (nx + 1);
+  return Q1W{4.0 * h / 6.0, h / 6.0, 2.0 / h, -1.0 / h};
+}
+
+// (M u)_i and (K u)_i at grid point (c1, c2, c3) of one spatial slice u:
+// sums along x1 first, then folded along x2 (and x3) with the mass weight on
+// the axes that are not differentiated
+template <int DIM>
+__device__ __forceinline__ void q1_apply(const double* __restrict__ u, int c1, int c2, int c3, int nx,
+                                         const Q1W& w, double& Mu, double& Ku) {
+  double Pm = 0.0, Pk = 0.0;
+#pragma unroll
+  for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
+    const int z = c3 + dz;
+    if (DIM == 3 && (z < 0 || z >= nx)) continue;
+    double Qm = 0.0, Qk = 0.0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int yy = c2 + dy;
+      if (yy < 0 || yy >= nx) continue;
+      const double* row = u + ((size_t)z * nx + yy) * nx;
+      const double ul = c1 > 0 ? row[c1 - 1] : 0.0;
+      const double uc = row[c1];
+      const double ur = c1 + 1 < nx ? row[c1 + 1] : 0.0;
+      const double rm = w.m0 * uc + w.m1 * (ul + ur);
+      const double rk = w.k0 * uc + w.k1 * (ul + ur);
+      const double my = dy == 0 ? w.m0 : w.m1, ky = dy == 0 ? w.k0 : w.k1;
+      Qm += my * rm;
+      Qk += my * rk + ky * rm;
+    }
+    if (DIM == 3) {
+      const double mz = dz == 0 ? w.m0 : w.m1, kz = dz == 0 ? w.k0 : w.k1;
+      Pm += mz * Qm;
+      Pk += mz * Qk + kz * Qm;
+    } else {
+      Pm = Qm;
+      Pk = Qk;
+    }
+  }
+  Mu = Pm;
+  Ku = Pk;
+}
+
+// y = c - s A x (c != nullptr) or y = s A x with A of eq. matrix_A (sgn = 1)
+// or A^T (sgn = -1), E = M + tau K:
+//   y_1^j = alpha M x_1^j + sgn (E x_2^j - M x_2^{j+1}),
+//   y_2^j = alpha M x_2^j - sgn (E x_1^j - M x_1^{j-1}),  x^0 = x^{n+1} = 0.
+// One thread per spatial point and chunk of time levels; the products with
+// M x_2^{j+1} and M x_1^j are carried to the next level.
+template <int DIM>
+__global__ void __launch_bounds__(256) kkt_fem_kernel(Geo g, const double* __restrict__ x, double* __restrict__ y,
+                                                      const double* __restrict__ c, const double* __restrict__ alpha,
+                                                      const double* __restrict__ xscale, int xs_stride,
+                                                      const int* __restrict__ active, double sgn, int jchunk) {
+  const int b = blockIdx.z;
+  if (active && !active[b]) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.m) return;
+  const int nx = g.nx, n = g.n, m = g.m;
+  const int c1 = i % nx, c2 = (i / nx) % nx, c3 = (DIM == 3) ? i / (nx * nx) : 0;
+  const int j0 = blockIdx.y * jchunk;
+  const int j1 = min(n, j0 + jchunk);
+  const Q1W w = q1_weights(nx);
+  const double a = alpha[b];
+  const double s = xscale ? xscale[(size_t)b * xs_stride] : 1.0;
+  const size_t mb = (size_t)b * (size_t)g.vs;
+  const double* x1 = x + mb;
+  const double* x2 = x + mb + (size_t)n * m;
+  double* y1 = y + mb;
+  double* y2 = y + mb + (size_t)n * m;
+  const double* cc1 = c ? c + mb : nullptr;
+  const double* cc2 = c ? c + mb + (size_t)n * m : nullptr;
+  // slices are addressed from their first point; q1_apply adds the row offset
+  auto slice = [&](const double* base, int j) { return base + (size_t)j * m; };
+  double Mx1prev = 0.0, dummy = 0.0;
+  if (j0 > 0) q1_apply<DIM>(slice(x1, j0 - 1), c1, c2, c3, nx, w, Mx1prev, dummy);
+  double Mx2c, Kx2c;
+  q1_apply<DIM>(slice(x2, j0), c1, c2, c3, nx, w, Mx2c, Kx2c);
+  for (int j = j0; j < j1; ++j) {
+    double Mx1, Kx1;
+    q1_apply<DIM>(slice(x1, j), c1, c2, c3, nx, w, Mx1, Kx1);
+    double Mx2n = 0.0, Kx2n = 0.0;
+    if (j + 1 < n) q1_apply<DIM>(slice(x2, j + 1), c1, c2, c3, nx, w, Mx2n, Kx2n);
+    double r1 = a * Mx1 + sgn * (Mx2c + g.tau * Kx2c - Mx2n);
+    double r2 = a * Mx2c - sgn * (Mx1 + g.tau * Kx1 - Mx1prev);
+    r1 *= s;
+    r2 *= s;
+    const size_t o = (size_t)j * m + i;
+    if (c) {
+      r1 = cc1[o] - r1;
+      r2 = cc2[o] - r2;
+    }
+    y1[o] = r1;
+    y2[o] = r2;
+    Mx1prev = Mx1;
+    Mx2c = Mx2n;
+    Kx2c = Kx2n;
+  }
+}
+
+// y = M x on spatial slices: slice q of group k = q / spg starts at
+// x + k sgs + (q mod spg) m and y + k dgs + (q mod spg) m
+template <int DIM>
+__global__ void __launch_bounds__(256) mass_apply_kernel(Geo g, const double* __restrict__ x, long long sgs,
+                                                         double* __restrict__ y, long long dgs, int spg,
+                                                         long long nslices) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.m) return;
+  const int nx = g.nx, m = g.m;
+  const int c1 = i % nx, c2 = (i / nx) % nx, c3 = (DIM == 3) ? i / (nx * nx) : 0;
+  const Q1W w = q1_weights(nx);
+  for (long long q = blockIdx.y; q < nslices; q += gridDim.y) {
+    const long long k = q / spg, r = q - k * spg;
+    const double* u = x + k * sgs + r * (long long)m;
+    double Mu, Ku;
+    q1_apply<DIM>(u, c1, c2, c3, nx, w, Mu, Ku);
+    y[k * dgs + r * (long long)m + i] = Mu;
+  }
+}
+
+void launch_kkt_fem(const Geo& g, const double* x, double* y, const double* c, const double* alpha,
+                    const double* xscale, int xs_stride, const int* active, bool transpose, hipStream_t st) {
+  constexpr int JC = 16;
+  const dim3 grid((g.m + 255) / 256, (g.n + JC - 1) / JC, g.B);
+  const double sgn = transpose ? -1.0 : 1.0;
+  if (g.dim == 2)
+    kkt_fem_kernel<2><<<grid, 256, 0, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn, JC);
+  else
+    kkt_fem_kernel<3><<<grid, 256, 0, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn, JC);
+}
+
+void launch_mass_apply(const Geo& g, const double* x, long long sgs, double* y, long long dgs, int spg,
+                       int ngroups, hipStream_t st) {
+  const long long ns = (long long)spg * ngroups;
+  if (ns <= 0) return;
+  const dim3 grid((g.m + 255) / 256, (unsigned)std::min<long long>(ns, 65535));
+  if (g.dim == 2)
+    mass_apply_kernel<2><<<grid, 256, 0, st>>>(g, x, sgs, y, dgs, spg, ns);
+  else
+    mass_apply_kernel<3><<<grid, 256, 0, st>>>(g, x, sgs, y, dgs, spg, ns);
+}
+
+}  // namespace pcop

@@ -237,6 +237,10 @@ __global__ void __launch_bounds__(256) kkt_lds_kernel(
 void launch_kkt_apply(const Geo& g, const double* x, double* y, const double* c, const double* alpha,
                       const double* xscale, int xs_stride, const int* active, bool transpose,
                       const double* ecoef, double ediag, double eoff, int jchunk, hipStream_t st) {
+  if (g.fem) {
+    launch_kkt_fem(g, x, y, c, alpha, xscale, xs_stride, active, transpose, st);
+    return;
+  }
   const double sgn = transpose ? -1.0 : 1.0;
   if (jchunk < 0 && g.nx <= 1024) {
     // LDS-tiled kernel, -jchunk levels per block

@@ -63,7 +63,9 @@ struct PrecondTables {
   const float* bhat32;
   const double* twL64;   // [L]  exp(-2 pi i t/L), L = 2(nx+1)
   const float* twL32;
-  const double* mu1;     // [nx] (4/h^2) sin^2(pi k h/2), k = 1..nx
+  const double* mu1;     // [nx] 1-D eigenvalue of K per sine mode k = 1..nx: (4/h^2) sin^2(pi k h/2)
+                         // (finite differences) or k_k / m_k (Q1 elements, see im1)
+  const double* im1;     // [nx] 1 / m_k, m_k = (h/3)(2 + cos(pi k h)) the 1-D Q1 mass eigenvalue; null when M = I
   const double* lam;     // [K] lambda_k as (re, im)
   const double* alpha;   // [B]
   const int* active;     // [B] or null
@@ -81,6 +83,14 @@ struct PrecondTables {
 void launch_kkt_apply(const Geo& g, const double* x, double* y, const double* c, const double* alpha,
                       const double* xscale, int xs_stride, const int* active, bool transpose,
                       const double* ecoef, double ediag, double eoff, int jchunk, hipStream_t st);
+// Q1 finite elements (fem.hip): the KKT matvec with M != I (same arguments
+// as launch_kkt_apply, which forwards to it when g.fem), and y = M x on
+// ngroups groups of spg consecutive spatial slices (group k of x at
+// k * sgs doubles, of y at k * dgs)
+void launch_kkt_fem(const Geo& g, const double* x, double* y, const double* c, const double* alpha,
+                    const double* xscale, int xs_stride, const int* active, bool transpose, hipStream_t st);
+void launch_mass_apply(const Geo& g, const double* x, long long sgs, double* y, long long dgs, int spg,
+                       int ngroups, hipStream_t st);
 // dst = src or J src (flip), members at b * dvs / b * svs
 void launch_restride(const Geo& g, const double* src, long long svs, double* dst, long long dvs, bool flip,
                      hipStream_t st);

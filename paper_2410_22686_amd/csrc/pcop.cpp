@@ -67,6 +67,13 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
   } else {
     return fail(PCOP_ERR_INVALID_ARG, "unknown coeff_kind");
   }
+  if (p->mass != PCOP_MASS_IDENTITY && p->mass != PCOP_MASS_Q1) return fail(PCOP_ERR_INVALID_ARG, "unknown mass");
+  if (p->mass == PCOP_MASS_Q1) {
+    if (p->coeff_kind != PCOP_COEFF_ONE)
+      return fail(PCOP_ERR_UNSUPPORTED, "finite elements are built for a = 1 (PCOP_COEFF_ONE)");
+    if (o->spatial != PCOP_DST) return fail(PCOP_ERR_UNSUPPORTED, "finite elements need PCOP_DST");
+    if (o->precond != PCOP_PRECOND_EPS) return fail(PCOP_ERR_UNSUPPORTED, "finite elements need PCOP_PRECOND_EPS");
+  }
   if (o->precision != PCOP_FP64 && o->precision != PCOP_MIXED)
     return fail(PCOP_ERR_INVALID_ARG, "unknown precision");
   if (o->spatial != PCOP_DST && o->spatial != PCOP_MG) return fail(PCOP_ERR_INVALID_ARG, "unknown spatial");
@@ -114,7 +121,7 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t total = 0;
-  size_t dpow, twn64, twn32, twL64, twL32, mu1, lam, alpha, sg, ecoef, unit, zero, post;
+  size_t dpow, twn64, twn32, twL64, twL32, mu1, im1, lam, alpha, sg, ecoef, unit, zero, post;
   size_t twM64, twM32, chirp64, chirp32, bhat64, bhat32;
   int M = 1;
   size_t sc, H, coef, red, partial, wnorm2, norm, skip, active, finish, hcol;
@@ -162,6 +169,7 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
   L.twL64 = take(L, 16 * (size_t)Lf);
   L.twL32 = take(L, 8 * (size_t)Lf);
   L.mu1 = take(L, sizeof(double) * nx);
+  L.im1 = take(L, sizeof(double) * nx);
   L.lam = take(L, 16 * (size_t)K);
   L.alpha = take(L, sizeof(double) * B);
   L.sg = take(L, sizeof(double) * B);
@@ -291,6 +299,7 @@ struct pcop_ctx_s {
   Geo g{};
   pcop_options opt{};
   int coeff_kind = PCOP_COEFF_ONE;
+  int mass = PCOP_MASS_IDENTITY;
   double eps = 0, T = 0;
   std::vector<double> gamma, alpha, sgam;
   hipStream_t st = nullptr;
@@ -424,7 +433,7 @@ pcop_status tune_kernels(pcop_ctx c) {
   int dev = 0;
   PCOP_HIP(hipGetDevice(&dev));
   const std::array<int, 14> key{dev, g.dim, g.nx, g.n, g.B, (int)c->fp32, c->opt.spatial, c->opt.time_cols,
-                                c->opt.dst_kernel, c->coeff_kind, c->opt.precond, c->opt.kkt_jchunk,
+                                c->opt.dst_kernel, c->coeff_kind + 2 * c->mass, c->opt.precond, c->opt.kkt_jchunk,
                                 c->opt.krylov_blocks, c->opt.gs_update};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -664,6 +673,7 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   c->ws = reinterpret_cast<char*>(workspace);
   c->fp32 = opts->precision == PCOP_MIXED;
   c->coeff_kind = prob->coeff_kind;
+  c->mass = prob->mass;
   const int d = prob->dim, nx = prob->nx, n = prob->nt - 1, B = prob->batch;
   const long long m = (long long)std::llround(std::pow((double)nx, d));
   Geo& g = c->g;
@@ -679,6 +689,7 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   g.tau = prob->T / prob->nt;
   const double h = 1.0 / (nx + 1);
   g.h2inv = 1.0 / (h * h);
+  g.fem = prob->mass == PCOP_MASS_Q1 ? 1 : 0;
   c->eps = prob->eps > 0.0 ? prob->eps : std::sqrt(g.tau);
   c->gamma.assign(prob->gamma, prob->gamma + B);
   c->alpha.resize(B);
@@ -690,7 +701,7 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
 
   // host tables in long double, rounded once
   const long double PI = 3.141592653589793238462643383279502884L;
-  std::vector<double> dpow(n), twn64(2 * n), mu1(nx), lam(2 * g.K), twL64(2 * (2 * (nx + 1)));
+  std::vector<double> dpow(n), twn64(2 * n), mu1(nx), im1(nx, 1.0), lam(2 * g.K), twL64(2 * (2 * (nx + 1)));
   std::vector<float> twn32(2 * n), twL32(2 * (2 * (nx + 1)));
   const long double le = std::log((long double)c->eps);
   for (int j = 0; j < n; ++j) dpow[j] = (double)std::exp(le * j / n);
@@ -762,7 +773,16 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   }
   for (int k = 1; k <= nx; ++k) {
     long double sv = std::sin(PI * k * (long double)h / 2.0L);
-    mu1[k - 1] = (double)(4.0L / ((long double)h * h) * sv * sv);
+    if (g.fem) {
+      // Q1 elements: sine-mode eigenvalues m_k = (h/3)(2 + cos(pi k h)) of
+      // M1 and k_k = (4/h) sin^2(pi k h/2) of K1; the divide uses k_k/m_k and 1/m_k
+      const long double mk = (long double)h / 3.0L * (2.0L + std::cos(PI * k * (long double)h));
+      const long double kk = 4.0L / (long double)h * sv * sv;
+      mu1[k - 1] = (double)(kk / mk);
+      im1[k - 1] = (double)(1.0L / mk);
+    } else {
+      mu1[k - 1] = (double)(4.0L / ((long double)h * h) * sv * sv);
+    }
   }
   const long double e1n = std::exp(le / n);
   for (int k = 0; k < g.K; ++k) {
@@ -788,6 +808,7 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   if (e == hipSuccess) e = up(L.twL64, twL64.data(), sizeof(double) * 2 * Lf);
   if (e == hipSuccess) e = up(L.twL32, twL32.data(), sizeof(float) * 2 * Lf);
   if (e == hipSuccess) e = up(L.mu1, mu1.data(), sizeof(double) * nx);
+  if (e == hipSuccess) e = up(L.im1, im1.data(), sizeof(double) * nx);
   if (e == hipSuccess) e = up(L.lam, lam.data(), sizeof(double) * 2 * g.K);
   if (e == hipSuccess) e = up(L.alpha, c->alpha.data(), sizeof(double) * B);
   if (e == hipSuccess) e = up(L.sg, c->sgam.data(), sizeof(double) * B);
@@ -924,6 +945,7 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   tb.twL64 = c->at<double>(L.twL64);
   tb.twL32 = c->at<float>(L.twL32);
   tb.mu1 = c->at<double>(L.mu1);
+  tb.im1 = g.fem ? c->at<double>(L.im1) : nullptr;
   tb.lam = c->at<double>(L.lam);
   tb.alpha = c->at<double>(L.alpha);
   tb.active = nullptr;
@@ -1004,6 +1026,7 @@ pcop_status pcop_get_kernels(pcop_ctx c, pcop_kernel_choice* out) {
 pcop_status pcop_post_solve(pcop_ctx c, const double* x, const double* fN, const double* g0, const double* y0,
                             double* yN, double* p0, double* relres) {
   if (!c || !x || !fN || !g0 || !y0 || !yN || !p0) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  if (c->g.fem) return fail(PCOP_ERR_UNSUPPORTED, "post-solve is built for M = I");
   const Geo& g = c->g;
   const int B = g.B;
   hipStream_t st = c->st;
@@ -1060,6 +1083,7 @@ pcop_status pcop_post_solve(pcop_ctx c, const double* x, const double* fN, const
 pcop_status pcop_error_eh(pcop_ctx c, const double* x, const double* yN, const double* p0, const double* y_exact,
                           const double* p_exact, double* eh) {
   if (!c || !x || !yN || !p0 || !y_exact || !p_exact || !eh) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  if (c->g.fem) return fail(PCOP_ERR_UNSUPPORTED, "e_h is built for M = I");
   const Geo& g = c->g;
   const int B = g.B;
   hipStream_t st = c->st;
@@ -1076,6 +1100,16 @@ pcop_status pcop_error_eh(pcop_ctx c, const double* x, const double* yN, const d
 
 pcop_status pcop_rhs(pcop_ctx c, const double* g, const double* f, const double* y0, double* b) {
   if (!c || !g || !f || !y0 || !b) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  if (c->g.fem) {
+    // b = (I (x) M) b_fd: the finite-difference right-hand side into scratch,
+    // then the mass matrix on every spatial slice
+    const Geo gu = c->user_geo();
+    double* t = c->at<double>(c->L.tmp1);
+    launch_rhs(gu, g, f, y0, c->at<double>(c->L.sg), t, c->st);
+    launch_mass_apply(gu, t, 0, b, 0, 2 * gu.n * gu.B, 1, c->st);
+    PCOP_HIP(hipGetLastError());
+    return PCOP_OK;
+  }
   launch_rhs(c->user_geo(), g, f, y0, c->at<double>(c->L.sg), b, c->st);
   PCOP_HIP(hipGetLastError());
   return PCOP_OK;
@@ -1117,6 +1151,21 @@ pcop_status pcop_pack_cotangent(pcop_ctx c, const double* ybar, const double* pb
 
 pcop_status pcop_data_grad(pcop_ctx c, const double* lam, double* dg, double* df, double* dy0) {
   if (!c || !lam) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  if (c->g.fem) {
+    // the finite-difference maps into scratch, then M on every slice
+    // (b depends on the data through I (x) M, and M is symmetric)
+    const Geo gu = c->user_geo();
+    const long long nm = (long long)gu.n * gu.m * gu.B;
+    double* t1 = c->at<double>(c->L.tmp1);
+    double* t2 = c->at<double>(c->L.tmp2);
+    launch_data_grad(gu, lam, c->at<double>(c->L.sg), dg ? t1 : nullptr, df ? t1 + nm : nullptr, dy0 ? t2 : nullptr,
+                     c->st);
+    if (dg) launch_mass_apply(gu, t1, 0, dg, 0, gu.n * gu.B, 1, c->st);
+    if (df) launch_mass_apply(gu, t1 + nm, 0, df, 0, gu.n * gu.B, 1, c->st);
+    if (dy0) launch_mass_apply(gu, t2, 0, dy0, 0, gu.B, 1, c->st);
+    PCOP_HIP(hipGetLastError());
+    return PCOP_OK;
+  }
   launch_data_grad(c->user_geo(), lam, c->at<double>(c->L.sg), dg, df, dy0, c->st);
   PCOP_HIP(hipGetLastError());
   return PCOP_OK;

@@ -25,6 +25,7 @@ PCOP_DST, PCOP_MG = 0, 1
 PCOP_RIGHT, PCOP_LEFT, PCOP_FLEXIBLE = 0, 1, 2
 PCOP_COEFF_ONE, PCOP_COEFF_HALFGRID = 0, 1
 PCOP_PRECOND_EPS, PCOP_PRECOND_IDEAL = 0, 1
+PCOP_MASS_IDENTITY, PCOP_MASS_Q1 = 0, 1
 
 EXPORTED = [
     "pcop_validate", "pcop_default_options", "pcop_workspace_size", "pcop_setup", "pcop_rhs",
@@ -47,7 +48,7 @@ class NotConverged(PcopError):
 class c_problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_int), ("nt", ctypes.c_int), ("T", ctypes.c_double),
                 ("batch", ctypes.c_int), ("gamma", ctypes.POINTER(ctypes.c_double)), ("eps", ctypes.c_double),
-                ("coeff_kind", ctypes.c_int), ("coeff", ctypes.POINTER(ctypes.c_double))]
+                ("coeff_kind", ctypes.c_int), ("coeff", ctypes.POINTER(ctypes.c_double)), ("mass", ctypes.c_int)]
 
 
 class c_options(ctypes.Structure):
@@ -142,6 +143,7 @@ _PREC = {"fp64": PCOP_FP64, "mixed": PCOP_MIXED}
 _SPAT = {"dst": PCOP_DST, "mg": PCOP_MG}
 _SIDE = {"right": PCOP_RIGHT, "left": PCOP_LEFT, "flexible": PCOP_FLEXIBLE}
 _PRECOND = {"eps": PCOP_PRECOND_EPS, "ideal": PCOP_PRECOND_IDEAL}
+_MASS = {"identity": PCOP_MASS_IDENTITY, "q1": PCOP_MASS_Q1}
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -168,7 +170,7 @@ class Solver:
                  spatial: str = "dst", side: str = "right", restart: int = 30, maxit: int = 300,
                  rtol: float = 1e-8, graph: bool = False, graph_chunk: int = 4, reorth_tol: float = 1e-8,
                  time_cols: int = 0, dst_kernel: int = 0, tune: bool = False, precond: str = "eps",
-                 kkt_jchunk: int = 0, krylov_blocks: int = 0, gs_update: int = 0,
+                 kkt_jchunk: int = 0, krylov_blocks: int = 0, gs_update: int = 0, mass: str = "identity",
                  device: Union[str, torch.device] = "cuda", stream: Optional[torch.cuda.Stream] = None):
         import numpy as np
         self.lib = load_library()
@@ -185,6 +187,8 @@ class Solver:
         prob.dim, prob.nx, prob.nt, prob.T, prob.batch = self.dim, self.nx, self.nt, self.T, self.batch
         prob.gamma = ctypes.cast(self._gamma, ctypes.POINTER(ctypes.c_double))
         prob.eps = -1.0 if eps is None else float(eps)
+        prob.mass = _MASS[mass]
+        self.mass = mass
         if coeff is None:
             prob.coeff_kind, prob.coeff = PCOP_COEFF_ONE, None
         else:

@@ -115,6 +115,21 @@ def test_every_time_length_up_to_2048_validates(lib):
             assert lib.pcop_validate(ctypes.byref(_prob(nx=3, nt=n + 1)), ctypes.byref(o)) == 2, (precision, n)
 
 
+def test_finite_element_mass_rules(lib):
+    """PCOP_MASS_Q1 (Section 1 with M_m != I) runs with a = 1, sine
+    transforms and the epsilon-circulant preconditioner; other combinations
+    are refused before any launch, and unknown values are invalid."""
+    from paper_2410_22686_amd import pcop
+    p = _prob(dim=2, nx=7, nt=8)
+    p.mass = pcop.PCOP_MASS_Q1
+    assert lib.pcop_validate(ctypes.byref(p), ctypes.byref(_opts(lib))) == 0
+    assert lib.pcop_validate(ctypes.byref(p), ctypes.byref(_opts(lib, precision=1, side=2))) == 0
+    assert lib.pcop_validate(ctypes.byref(p), ctypes.byref(_opts(lib, spatial=1, side=2))) == 2
+    assert lib.pcop_validate(ctypes.byref(p), ctypes.byref(_opts(lib, precond=1))) == 2
+    p.mass = 2
+    assert lib.pcop_validate(ctypes.byref(p), ctypes.byref(_opts(lib))) == 1
+
+
 def test_gamma_must_be_positive(lib):
     assert lib.pcop_validate(ctypes.byref(_prob(gammas=(1e-4, -1.0))), ctypes.byref(_opts(lib))) == 1
     assert lib.pcop_validate(ctypes.byref(_prob(gammas=(float("nan"),))), ctypes.byref(_opts(lib))) == 1
