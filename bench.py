@@ -41,7 +41,7 @@ _TIME_SOURCES = ["precond.hip", "time_common.hpp", "time_sk.hip", "time_ip.hpp",
                  "time_ip_inv_f64.hip", "time_ip_fwd_f32.hip", "time_ip_inv_f32.hip", "time_bl.hip", "fft_lds.hpp"]
 FAMILY_SOURCES = {
     "gs_update": ["krylov.hip"], "mdot": ["krylov.hip"], "combine": ["krylov.hip"],
-    "kkt_apply": ["kkt.hip", "stencil.hpp"], "time_fwd": _TIME_SOURCES, "time_inv": _TIME_SOURCES,
+    "kkt_apply": ["kkt.hip", "stencil.hpp", "fem.hip"], "time_fwd": _TIME_SOURCES, "time_inv": _TIME_SOURCES,
     "dst_rows": ["dst.hip", "fft_lds.hpp"], "dst_last_solve": ["dst.hip", "fft_lds.hpp"],
     "dst_ax2": ["dst.hip", "fft_lds.hpp"], "mg_smooth": ["multigrid.hip"], "mg_restrict": ["multigrid.hip"],
     "mg_prolong": ["multigrid.hip"], "ideal_step": ["ideal.hip"],
@@ -95,6 +95,9 @@ def parse():
     ap.add_argument("--krylov-blocks", type=int, default=0, help="Krylov reduction blocks per member (0 automatic)")
     ap.add_argument("--gs-update", type=int, default=0, choices=[0, 1, 2],
                     help="Gram-Schmidt update kernel: 0 automatic, 1 doubles, 2 double2 pairs")
+    ap.add_argument("--mass", choices=["identity", "q1"], default="identity",
+                    help="identity: finite differences (M = I); q1: bilinear/trilinear finite elements "
+                         "(M != I, a = 1, sine transforms)")
     ap.add_argument("--precond", choices=["eps", "ideal"], default="eps",
                     help="eps: the epsilon-circulant preconditioner; ideal: P of eq. matrix_P (sequential in time)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -112,7 +115,7 @@ def solver_options(cfg, precision=None, graph=None):
     return opts
 
 
-def cpu_baseline(cfg, iters, budget_s):
+def cpu_baseline(cfg, iters, budget_s, mass="identity"):
     """Time the FP64 oracle on this host on a bounded sample of the workload
     and scale it to solves/s.
 
@@ -137,12 +140,12 @@ def cpu_baseline(cfg, iters, budget_s):
         threads = 1
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     gamma = cfg.gammas[0]
-    pb = D.make_problem(cfg.dim, cfg.nx, cfg.nt, gamma, T=cfg.T, eps=cfg.eps)
+    pb = D.make_problem(cfg.dim, cfg.nx, cfg.nt, gamma, T=cfg.T, eps=cfg.eps, mass=mass)
     n, m = pb.n, pb.m
     # the sparse KKT matvec costs O(n m): time it on the same grid with 8 time
     # blocks (the oracle's assembly of the full matrix alone takes minutes)
     n_mv = min(8, n)
-    pb_mv = D.make_problem(cfg.dim, cfg.nx, n_mv + 1, gamma, T=cfg.T * (n_mv + 1) / cfg.nt, eps=pb.eps)
+    pb_mv = D.make_problem(cfg.dim, cfg.nx, n_mv + 1, gamma, T=cfg.T * (n_mv + 1) / cfg.nt, eps=pb.eps, mass=mass)
     A = D.kkt_scaled(pb_mv)
     rng = np.random.default_rng(0)
     x = rng.standard_normal(A.shape[0])
@@ -162,12 +165,12 @@ def cpu_baseline(cfg, iters, budget_s):
     t_dft = time.perf_counter() - t0
     lam = P.lambda_eps(n, pb.eps)
     Kc = pb.K.tocsc().astype(np.complex128)
-    I = sp.identity(m, format="csc", dtype=np.complex128)
+    I = pb.Mm.tocsc().astype(np.complex128)  # M (the identity for finite differences)
     nfac, t_fac, t_lu, nlu = 0, 0.0, 0.0, 0
     rhs = rng.standard_normal(m) + 1j * rng.standard_normal(m)
     while nfac < min(64, n):  # as many as fit about 60% of the time budget
         t0 = time.perf_counter()
-        lu = spla.splu((lam[nfac] + pb.alpha) * I + pb.tau * Kc)
+        lu = spla.splu(((lam[nfac] + pb.alpha) * I + pb.tau * Kc).tocsc())
         t_fac += time.perf_counter() - t0
         t0 = time.perf_counter()
         for _ in range(3):
@@ -195,7 +198,7 @@ def cpu_baseline(cfg, iters, budget_s):
     return {
         "value": solves_per_s, "unit": "solves/s", "cores": int(threads), "host_cores_visible": int(cores),
         "kind": "oracle",
-        "sample": (f"FP64 NumPy/SciPy oracle pieces at full size ({cfg.name}, one member): {nfac} of {n} "
+        "sample": (f"FP64 NumPy/SciPy oracle pieces at full size ({cfg.name}, {mass} mass matrix, one member): {nfac} of {n} "
                    f"per-frequency splu factorisations and {nlu} LU solves, one dense time-DFT product, "
                    f"sparse KKT matvecs on {n_mv} of {n} time blocks (scaled by {n}/{n_mv}), one MGS step; scaled to {len(iters)} right-preconditioned solves "
                    f"with the GPU iteration counts {list(iters)}; factorisation (setup, "
@@ -218,6 +221,10 @@ def main():
     from paper_2410_22686_amd import Solver
 
     cfg = W.CONFIGS[args.config]
+    if args.mass == "q1" and cfg.spatial != "dst":
+        print(json.dumps({"error": "--mass q1 needs a workload with sine transforms (a = 1)"}))
+        sys.exit(2)
+    workload = cfg.name + ("-q1" if args.mass == "q1" else "")
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
@@ -238,7 +245,8 @@ def main():
                coeff=None if cfg.coeff == "one" else W.coeff_function(cfg.coeff),
                restart=30, maxit=300, rtol=1e-8, device=dev, stream=stream, tune=bool(args.tune),
                time_cols=args.time_cols, dst_kernel=args.dst_kernel, precond=args.precond,
-               kkt_jchunk=args.kkt_jchunk, krylov_blocks=args.krylov_blocks, gs_update=args.gs_update, **opts)
+               kkt_jchunk=args.kkt_jchunk, krylov_blocks=args.krylov_blocks, gs_update=args.gs_update,
+               mass=args.mass, **opts)
     print(f"# bench: kernels {s.kernels}", file=sys.stderr, flush=True)
     tg = torch.tensor(g, device=dev)
     tf = torch.tensor(f, device=dev)
@@ -278,7 +286,7 @@ def main():
     dom_ms_per_launch = dom["ms"] / dom["launches"]
     dom_bytes_per_launch = dom["bytes"] / dom["launches"]
     achieved = dom_bytes_per_launch / (dom_ms_per_launch * 1e-3) / 1e9
-    traffic = recorded_traffic(cfg.name, dom_name)
+    traffic = recorded_traffic(workload, dom_name)
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_unit": "bytes/launch",
@@ -309,7 +317,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if opts["precision"] == "fp64" else "f64+f32",
         "data": "synthetic (seeded smooth sine products + N(0,1e-2) noise)",
-        "config": {"workload": cfg.name, "dim": cfg.dim, "nx": cfg.nx, "nt": cfg.nt, "T": cfg.T,
+        "config": {"workload": workload, "mass": args.mass, "dim": cfg.dim, "nx": cfg.nx, "nt": cfg.nt, "T": cfg.T,
                    "gammas": list(cfg.gammas), "eps": "sqrt(tau)" if cfg.eps is None else cfg.eps,
                    "precision": opts["precision"], "spatial": opts["spatial"], "krylov": f"{opts['side']} GMRES(30)",
                    "graph": opts["graph"], "preconditioner": args.precond,
@@ -323,7 +331,7 @@ def main():
     elif not args.no_cpu_baseline:
         print("# bench: cpu baseline", file=sys.stderr, flush=True)
         try:
-            out["cpu_baseline"] = cpu_baseline(cfg, iters, args.cpu_sample_seconds)
+            out["cpu_baseline"] = cpu_baseline(cfg, iters, args.cpu_sample_seconds, args.mass)
         except Exception as e:  # pragma: no cover
             out["cpu_baseline"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)

@@ -65,19 +65,27 @@ __device__ __forceinline__ void q1_apply(const double* __restrict__ u, int c1, i
 //   y_1^j = alpha M x_1^j + sgn (E x_2^j - M x_2^{j+1}),
 //   y_2^j = alpha M x_2^j - sgn (E x_1^j - M x_1^{j-1}),  x^0 = x^{n+1} = 0.
 // One thread per spatial point and chunk of time levels; the products with
-// M x_2^{j+1} and M x_1^j are carried to the next level.
-template <int DIM>
+// M x_2^{j+1} and M x_1^j are carried to the next level.  JC > 0: chunks of
+// JC levels (compile time, unrolled); JC = 0: jchunk levels at run time.
+template <int DIM, int JC>
 __global__ void __launch_bounds__(256) kkt_fem_kernel(Geo g, const double* __restrict__ x, double* __restrict__ y,
                                                       const double* __restrict__ c, const double* __restrict__ alpha,
                                                       const double* __restrict__ xscale, int xs_stride,
                                                       const int* __restrict__ active, double sgn, int jchunk) {
-  const int b = blockIdx.z;
+  // logical block (x: spatial tile, y: time chunk, z: member) in XCD-aware
+  // order, so that tiles sharing neighbour rows run on one XCD's L2
+  const int total = gridDim.x * gridDim.y * gridDim.z;
+  const int hw = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int lg = xcd_remap(hw, total);
+  const int bx = lg % gridDim.x;
+  const int by = (lg / gridDim.x) % gridDim.y;
+  const int b = lg / (gridDim.x * gridDim.y);
   if (active && !active[b]) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = bx * blockDim.x + threadIdx.x;
   if (i >= g.m) return;
   const int nx = g.nx, n = g.n, m = g.m;
   const int c1 = i % nx, c2 = (i / nx) % nx, c3 = (DIM == 3) ? i / (nx * nx) : 0;
-  const int j0 = blockIdx.y * jchunk;
+  const int j0 = by * jchunk;
   const int j1 = min(n, j0 + jchunk);
   const Q1W w = q1_weights(nx);
   const double a = alpha[b];
@@ -95,11 +103,11 @@ __global__ void __launch_bounds__(256) kkt_fem_kernel(Geo g, const double* __res
   if (j0 > 0) q1_apply<DIM>(slice(x1, j0 - 1), c1, c2, c3, nx, w, Mx1prev, dummy);
   double Mx2c, Kx2c;
   q1_apply<DIM>(slice(x2, j0), c1, c2, c3, nx, w, Mx2c, Kx2c);
-  for (int j = j0; j < j1; ++j) {
+  auto level = [&](int j, bool has_next) {
     double Mx1, Kx1;
     q1_apply<DIM>(slice(x1, j), c1, c2, c3, nx, w, Mx1, Kx1);
     double Mx2n = 0.0, Kx2n = 0.0;
-    if (j + 1 < n) q1_apply<DIM>(slice(x2, j + 1), c1, c2, c3, nx, w, Mx2n, Kx2n);
+    if (has_next) q1_apply<DIM>(slice(x2, j + 1), c1, c2, c3, nx, w, Mx2n, Kx2n);
     double r1 = a * Mx1 + sgn * (Mx2c + g.tau * Kx2c - Mx2n);
     double r2 = a * Mx2c - sgn * (Mx1 + g.tau * Kx1 - Mx1prev);
     r1 *= s;
@@ -114,6 +122,14 @@ __global__ void __launch_bounds__(256) kkt_fem_kernel(Geo g, const double* __res
     Mx1prev = Mx1;
     Mx2c = Mx2n;
     Kx2c = Kx2n;
+  };
+  if (JC > 0 && j0 + JC < n) {
+    // a full chunk followed by another level: straight-line code, so the
+    // stencil loads of every level can be issued up front
+#pragma unroll
+    for (int jj = 0; jj < (JC > 0 ? JC : 1); ++jj) level(j0 + jj, true);
+  } else {
+    for (int j = j0; j < j1; ++j) level(j, j + 1 < n);
   }
 }
 
@@ -139,13 +155,15 @@ __global__ void __launch_bounds__(256) mass_apply_kernel(Geo g, const double* __
 
 void launch_kkt_fem(const Geo& g, const double* x, double* y, const double* c, const double* alpha,
                     const double* xscale, int xs_stride, const int* active, bool transpose, hipStream_t st) {
-  constexpr int JC = 16;
-  const dim3 grid((g.m + 255) / 256, (g.n + JC - 1) / JC, g.B);
+  // 16 levels per thread with a run-time loop: unrolled 8-level chunks
+  // (JC = 8) measured slower on the 2-D nx = 255, n = 255 workload
+  constexpr int jc = 16;
+  const dim3 grid((g.m + 255) / 256, (g.n + jc - 1) / jc, g.B);
   const double sgn = transpose ? -1.0 : 1.0;
   if (g.dim == 2)
-    kkt_fem_kernel<2><<<grid, 256, 0, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn, JC);
+    kkt_fem_kernel<2, 0><<<grid, 256, 0, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn, jc);
   else
-    kkt_fem_kernel<3><<<grid, 256, 0, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn, JC);
+    kkt_fem_kernel<3, 0><<<grid, 256, 0, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn, jc);
 }
 
 void launch_mass_apply(const Geo& g, const double* x, long long sgs, double* y, long long dgs, int spg,
