@@ -80,6 +80,42 @@ def test_config2_matvec_precond_and_solve():
         assert abs(rr - infos[k].relres_true) <= 1e-3 * rr
 
 
+def test_config2_finite_elements():
+    """The same workload with Q1 finite elements (Section 1 with M != I), as
+    `bench.py --mass q1` runs it: b, the Q1 matvec and P_eps against the
+    oracle's block-wise operators at full size, and the converged solve's
+    true residual recomputed by the oracle."""
+    cfg = W.WORKLOADS["2d-nx255-nt256"]
+    print(f"full size {cfg.name} q1", flush=True)
+    g, f, y0 = member_fields(cfg, range(3))
+    s = Solver(cfg.dim, cfg.nx, cfg.nt, list(cfg.gammas), mass="q1", tune=True, device=DEV)
+    print(f"  kernels {s.kernels}", flush=True)
+    b = s.rhs(torch.tensor(g, device=DEV), torch.tensor(f, device=DEV), torch.tensor(y0, device=DEV))
+    pbs = [D.make_problem(cfg.dim, cfg.nx, cfg.nt, gm, mass="q1") for gm in cfg.gammas]
+    bh = b.cpu().numpy()
+    for k, pb in enumerate(pbs):
+        assert rel(bh[k], D.rhs_scaled(pb, g[k], f[k], y0[k])) < 1e-14
+    v = torch.tensor(W.random_vector(cfg.dim, cfg.nx, cfg.nt, seed=92, batch=3), device=DEV)
+    vh = v.cpu().numpy()
+    for transpose in (False, True):
+        y = s.kkt_apply(v, transpose=transpose).cpu().numpy()
+        for k, pb in enumerate(pbs):
+            assert rel(y[k], D.kkt_apply_blocks(pb, vh[k].ravel(), transpose)) < 1e-14
+    w = s.precond_apply(v).cpu().numpy()
+    for k, pb in enumerate(pbs):
+        res = rel(P.eps_circulant_apply(pb, w[k].ravel()), vh[k].ravel())
+        print(f"  member {k}: ||P w - v|| / ||v|| = {res:.2e}")
+        assert res < 1e-9
+    del v, w
+    x, infos, _ = s.solve(b)
+    xh = x.cpu().numpy()
+    for k, pb in enumerate(pbs):
+        rr = true_relres(pb, bh[k].ravel(), xh[k].ravel())
+        print(f"  member {k}: iters {infos[k].iters} relres gpu {infos[k].relres_true:.3e} oracle {rr:.3e}")
+        assert infos[k].converged and rr <= 1e-8 * 1.001
+        assert abs(rr - infos[k].relres_true) <= 1e-3 * rr
+
+
 def test_config3_mixed_vs_fp64():
     """2-D nx = 511, nt = 512, gamma = 1e-6: the FP32-complex preconditioner
     inside FP64 flexible GMRES against the all-FP64 path, both to 1e-8."""
