@@ -214,8 +214,10 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
                        void* workspace, size_t bytes);
 
 /* b = [g-block; -sqrt(gamma) f-block] of eq. main_system from device g, f
- * [batch][n][m] and y0 [batch][m]: b_1^j = tau g^j, b_2^j = -sqrt(gamma)
- * (tau f^j + [j = 1] y0) (eq. main_system_before with M = I, p^N = 0). */
+ * [batch][n][m] and y0 [batch][m]: b_1^j = tau M g^j, b_2^j = -sqrt(gamma)
+ * M (tau f^j + [j = 1] y0) (eq. main_system_before with p^N = 0; M = I for
+ * PCOP_MASS_IDENTITY; with PCOP_MASS_Q1 the intermediate without M is
+ * staged in the workspace, on the context's stream). */
 pcop_status pcop_rhs(pcop_ctx ctx, const double* g, const double* f, const double* y0,
                      double* b);
 
@@ -246,8 +248,9 @@ pcop_status pcop_pack_cotangent(pcop_ctx ctx, const double* ybar, const double* 
                                 double* r);
 
 /* Gradients of a loss with respect to the data from lam = A^{-T} dL/dx:
- * dg = tau lam_1, df = -sqrt(gamma) tau lam_2, dy0 = -sqrt(gamma) lam_2^1
- * (the transpose of the map in pcop_rhs).  Any output may be NULL. */
+ * dg = tau M lam_1, df = -sqrt(gamma) tau M lam_2, dy0 = -sqrt(gamma) M lam_2^1
+ * (the transpose of the map in pcop_rhs; M = I for PCOP_MASS_IDENTITY).
+ * Any output may be NULL. */
 pcop_status pcop_data_grad(pcop_ctx ctx, const double* lam, double* dg, double* df,
                            double* dy0);
 
