@@ -17,14 +17,15 @@ from .discretize import Problem
 
 def post_solve(pb: Problem, y: np.ndarray, p: np.ndarray, fN: np.ndarray, g0: np.ndarray,
                y0: np.ndarray, pN=None):
-    """y^N and p^0 from (I + tau K) y^N = y^{N-1} + tau f^N + (tau/gamma) p^N and
-    (I + tau K) p^0 = p^1 + tau g^0 - tau y^0 (M = I)."""
+    """y^N and p^0 from (M + tau K) y^N = M y^{N-1} + tau M f^N + (tau/gamma) M p^N
+    and (M + tau K) p^0 = M p^1 + tau M g^0 - tau M y^0 (M = I for finite
+    differences)."""
     if pN is None:
         pN = np.zeros(pb.m)
-    E = (sp.identity(pb.m, format="csc") + pb.tau * pb.K.tocsc()).tocsc()
-    lu = spla.splu(E)
-    yN = lu.solve(y[-1] + pb.tau * fN + (pb.tau / pb.gamma) * pN)
-    p0 = lu.solve(p[0] + pb.tau * g0 - pb.tau * y0)
+    Mm = pb.Mm.tocsc()
+    lu = spla.splu((Mm + pb.tau * pb.K.tocsc()).tocsc())
+    yN = lu.solve(Mm @ (y[-1] + pb.tau * fN + (pb.tau / pb.gamma) * pN))
+    p0 = lu.solve(Mm @ (p[0] + pb.tau * g0 - pb.tau * y0))
     return yN, p0
 
 

@@ -11,6 +11,7 @@ import scipy.linalg
 import scipy.sparse.linalg as spla
 
 from oracle import adjoint as ADJ
+from oracle import examples as EX
 from oracle import discretize as D
 from oracle import precond as P
 
@@ -191,3 +192,21 @@ def test_fem_envelope_gradients_match_finite_differences():
         args_m[k] = args_m[k] - h * dirn
         fd = (optimum(*args_p)[2] - optimum(*args_m)[2]) / (2 * h)
         assert abs(fd - np.sum(grad * dirn)) <= 1e-6 * (abs(fd) + 1e-12), which
+
+
+def test_fem_post_solve_completes_the_recursions():
+    """The end levels y^N and p^0 of the post-solve satisfy the two discrete
+    recursions of Section 1 at k1 = N - 1 and k2 = 0 with M != I."""
+    dim, nx, nt, gamma = 2, 3, 6, 1e-3
+    pb = D.make_problem(dim, nx, nt, gamma, mass="q1")
+    g, f, y0 = W.random_fields(dim, nx, nt, seed=21)
+    rng = np.random.default_rng(4)
+    fN, g0 = rng.standard_normal(pb.m), rng.standard_normal(pb.m)
+    x = spla.spsolve(D.kkt_scaled(pb).tocsc(), D.rhs_scaled(pb, g, f, y0))
+    y, p = D.unpack_solution(pb, x)
+    yN, p0 = EX.post_solve(pb, y, p, fN, g0, y0)
+    M, K, tau = pb.Mm.toarray(), pb.K.toarray(), pb.tau
+    r = M @ (yN - y[-1]) / tau + K @ yN - M @ fN              # p^N = 0
+    assert np.abs(r).max() < 1e-10 * (1 + np.abs(M @ fN).max())
+    r = -M @ (p[0] - p0) / tau + K @ p0 - M @ (g0 - y0)
+    assert np.abs(r).max() < 1e-10 * (1 + np.abs(M @ g0).max() / tau)
