@@ -84,9 +84,9 @@ enum { PCOP_MASS_IDENTITY = 0, PCOP_MASS_Q1 = 1 };           /* M_m of Section 1
  *            the element mass and stiffness matrices (Section 1 with
  *            M_m != I: eq. matrix_A_before, eq. matrix_A, eq. matrix_P_eps
  *            carry I (x) M_m and C_eps (x) M_m); requires PCOP_COEFF_ONE,
- *            PCOP_DST and PCOP_PRECOND_EPS, and pcop_post_solve /
- *            pcop_error_eh return PCOP_ERR_UNSUPPORTED.  The right-hand side
- *            of pcop_rhs and the maps of pcop_data_grad include M_m.
+ *            PCOP_DST and PCOP_PRECOND_EPS.  The right-hand side of
+ *            pcop_rhs, the maps of pcop_data_grad and the end-level solves
+ *            of pcop_post_solve include M_m.
  *            Appended last: zero-initialised callers get finite differences. */
 typedef struct {
   int dim;
@@ -255,8 +255,9 @@ pcop_status pcop_data_grad(pcop_ctx ctx, const double* lam, double* dg, double* 
                            double* dy0);
 
 /* End levels of the discrete solution from a solved x (Section 1, the two
- * formulas after eq. Toeplitz_Mat_B, M = I, p^N = 0):
- *   (I + tau K) y^N = y^{N-1} + tau f^N,   (I + tau K) p^0 = p^1 + tau (g^0 - y^0).
+ * formulas after eq. Toeplitz_Mat_B, p^N = 0):
+ *   (M + tau K) y^N = M (y^{N-1} + tau f^N),   (M + tau K) p^0 = M (p^1 + tau (g^0 - y^0)),
+ * M = I for PCOP_MASS_IDENTITY.
  * x: [batch][2][n][m] solution of pcop_solve; fN, g0, y0: [batch][m] data at
  * t = T, t = 0 and the initial state; outputs yN, p0: [batch][m].  All device
  * FP64 pointers.  Solved by iterative refinement with an FP64 residual and

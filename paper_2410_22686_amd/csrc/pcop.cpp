@@ -1026,7 +1026,6 @@ pcop_status pcop_get_kernels(pcop_ctx c, pcop_kernel_choice* out) {
 pcop_status pcop_post_solve(pcop_ctx c, const double* x, const double* fN, const double* g0, const double* y0,
                             double* yN, double* p0, double* relres) {
   if (!c || !x || !fN || !g0 || !y0 || !yN || !p0) return fail(PCOP_ERR_INVALID_ARG, "null argument");
-  if (c->g.fem) return fail(PCOP_ERR_UNSUPPORTED, "post-solve is built for M = I");
   const Geo& g = c->g;
   const int B = g.B;
   hipStream_t st = c->st;
@@ -1040,7 +1039,16 @@ pcop_status pcop_post_solve(pcop_ctx c, const double* x, const double* fN, const
   tb.nact = B;
   tb.timer = nullptr;
   const double* unit = c->at<double>(c->L.unit);
-  launch_post_rhs(c->user_geo(), x, fN, g0, y0, c->at<double>(c->L.sg), a, st);
+  if (g.fem) {
+    // Q1 elements: the right-hand sides without M into the (still unused)
+    // correction slice, then M on both planes of every member
+    PostArgs a0 = a;
+    a0.rhs = c->at<double>(c->L.spec);
+    launch_post_rhs(c->user_geo(), x, fN, g0, y0, c->at<double>(c->L.sg), a0, st);
+    launch_mass_apply(g, a0.rhs, 0, a.rhs, 0, 2 * B, 1, st);
+  } else {
+    launch_post_rhs(c->user_geo(), x, fN, g0, y0, c->at<double>(c->L.sg), a, st);
+  }
   PCOP_HIP(hipGetLastError());
   auto read_norms = [&](std::vector<double>& out) -> hipError_t {
     hipError_t e = hipMemcpyAsync(c->pin_norm, a.norm2, sizeof(double) * B, hipMemcpyDeviceToHost, st);
@@ -1083,7 +1091,6 @@ pcop_status pcop_post_solve(pcop_ctx c, const double* x, const double* fN, const
 pcop_status pcop_error_eh(pcop_ctx c, const double* x, const double* yN, const double* p0, const double* y_exact,
                           const double* p_exact, double* eh) {
   if (!c || !x || !yN || !p0 || !y_exact || !p_exact || !eh) return fail(PCOP_ERR_INVALID_ARG, "null argument");
-  if (c->g.fem) return fail(PCOP_ERR_UNSUPPORTED, "e_h is built for M = I");
   const Geo& g = c->g;
   const int B = g.B;
   hipStream_t st = c->st;

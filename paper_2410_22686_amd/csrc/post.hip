@@ -1,7 +1,9 @@
 // End levels of the discrete solution and the error e_h (Section 1, the two
-// formulas after eq. Toeplitz_Mat_B; Section 3 for e_h), with M = I:
-//   (I + tau K) y^N = y^{N-1} + tau f^N + (tau/gamma) p^N,   p^N = 0,
-//   (I + tau K) p^0 = p^1 + tau (g^0 - y^0).
+// formulas after eq. Toeplitz_Mat_B; Section 3 for e_h):
+//   (M + tau K) y^N = M (y^{N-1} + tau f^N + (tau/gamma) p^N),   p^N = 0,
+//   (M + tau K) p^0 = M (p^1 + tau (g^0 - y^0)),
+// with M = I for finite differences (E = I + tau K below; with Q1 elements
+// E = M + tau K and the caller applies M to the right-hand sides).
 // E = I + tau K is real, so both right-hand sides ride in one complex slice
 // per member, r = r_y + i r_p, solved by iterative refinement
 //   z <- z + S (rhs - E z),
@@ -12,6 +14,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "fem.hpp"
 #include "launch.hpp"
 #include "stencil.hpp"
 
@@ -74,6 +77,32 @@ __global__ void __launch_bounds__(256) post_resid_kernel(Geo g, const double* __
   if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = tot;
 }
 
+// the same residual with E = M + tau K of Q1 finite elements
+template <class T, int DIM>
+__global__ void __launch_bounds__(256) post_resid_fem_kernel(Geo g, const double* __restrict__ rhs,
+                                                             const double* __restrict__ z, cx<T>* __restrict__ s,
+                                                             double* __restrict__ part) {
+  const int b = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nx = g.nx, m = g.m;
+  double r2 = 0.0;
+  if (i < m) {
+    const int c1 = i % nx, c2 = (i / nx) % nx, c3 = (DIM == 3) ? i / (nx * nx) : 0;
+    const Q1W w = q1_weights(nx);
+    const double* rb = rhs + (size_t)b * 2 * m;
+    const double* zb = z + (size_t)b * 2 * m;
+    double Mr, Kr, Mi, Ki;
+    q1_apply<DIM>(zb, c1, c2, c3, nx, w, Mr, Kr);
+    q1_apply<DIM>(zb + m, c1, c2, c3, nx, w, Mi, Ki);
+    const double re = rb[i] - (Mr + g.tau * Kr);
+    const double im = rb[m + i] - (Mi + g.tau * Ki);
+    s[(size_t)b * m + i] = cx<T>{(T)re, (T)im};
+    r2 = re * re + im * im;
+  }
+  const double tot = block_sum256(r2);
+  if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = tot;
+}
+
 // z += s
 template <class T>
 __global__ void __launch_bounds__(256) post_correct_kernel(Geo g, const cx<T>* __restrict__ s, double* __restrict__ z) {
@@ -112,6 +141,11 @@ __global__ void __launch_bounds__(256) post_store_kernel(Geo g, const double* __
 template <class T>
 static void resid_launch(const Geo& g, const PostArgs& a, cx<T>* s, int nblk, hipStream_t st) {
   dim3 grid(nblk, g.B);
+  if (g.fem) {
+    if (g.dim == 2) post_resid_fem_kernel<T, 2><<<grid, 256, 0, st>>>(g, a.rhs, a.z, s, a.part);
+    else post_resid_fem_kernel<T, 3><<<grid, 256, 0, st>>>(g, a.rhs, a.z, s, a.part);
+    return;
+  }
   const bool var = a.ecoef != nullptr;
   if (g.dim == 2) {
     if (var) post_resid_kernel<T, 2, true><<<grid, 256, 0, st>>>(g, a.rhs, a.z, s, a.part, a.ecoef, a.ediag, a.eoff);

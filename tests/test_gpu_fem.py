@@ -5,7 +5,7 @@ import pytest
 import scipy.sparse.linalg as spla
 
 import workloads as W
-from oracle import adjoint as ADJ, discretize as D, precond as P
+from oracle import adjoint as ADJ, discretize as D, examples as E, precond as P
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 if not torch.cuda.is_available():  # pragma: no cover - CPU containers
     pytest.skip("needs a GPU", allow_module_level=True)
 
-from paper_2410_22686_amd import PcopError, Solver  # noqa: E402
+from paper_2410_22686_amd import Solver  # noqa: E402
 
 DEV = torch.device("cuda:0")
 
@@ -124,9 +124,25 @@ def test_fem_data_grad_and_transposed_solve():
         assert rel(dy0[b].cpu().numpy(), ey0) < 1e-14
 
 
-def test_fem_post_solve_is_refused():
-    s = Solver(2, 7, 8, [1e-3], mass="q1", device=DEV)
-    x = s.new_vector()
-    z = torch.zeros(s.field_shape[0], s.m, dtype=torch.float64, device=DEV)
-    with pytest.raises(PcopError):
-        s.post_solve(x, z, z, z)
+@pytest.mark.parametrize("dim,nx,nt,gammas", [(2, 15, 12, (1e-3, 1e-6)), (3, 7, 8, (1e-4,))])
+def test_fem_post_solve_matches_oracle(dim, nx, nt, gammas):
+    """End levels with M != I: (M + tau K) y^N = M (y^{N-1} + tau f^N) and
+    (M + tau K) p^0 = M (p^1 + tau (g^0 - y^0)), by refinement with the Q1
+    residual and the sine-transform solve with shift 1."""
+    print(f"fem post-solve dim={dim} nx={nx} nt={nt}", flush=True)
+    s = Solver(dim, nx, nt, list(gammas), mass="q1", rtol=1e-12, device=DEV)
+    B = len(gammas)
+    fields = [W.random_fields(dim, nx, nt, seed=70 + b) for b in range(B)]
+    g, f, y0 = (np.stack([fl[i] for fl in fields]) for i in range(3))
+    x, infos, _ = s.solve(s.rhs(to_dev(g), to_dev(f), to_dev(y0)))
+    assert all(i.converged for i in infos)
+    rng = np.random.default_rng(12)
+    fN, g0 = rng.standard_normal((B, s.m)), rng.standard_normal((B, s.m))
+    yN, p0, relres = s.post_solve(x, to_dev(fN), to_dev(g0), to_dev(y0))
+    assert max(relres) < 1e-10, relres
+    xh = x.cpu().numpy()
+    for b, pb in enumerate(problems(dim, nx, nt, gammas)):
+        y, p = D.unpack_solution(pb, xh[b].ravel())
+        yo, po = E.post_solve(pb, y, p, fN[b], g0[b], y0[b])
+        assert rel(yN[b].cpu().numpy(), yo) < 1e-12
+        assert rel(p0[b].cpu().numpy(), po) < 1e-12
