@@ -41,7 +41,7 @@ _TIME_SOURCES = ["precond.hip", "time_common.hpp", "time_sk.hip", "time_ip.hpp",
                  "time_ip_inv_f64.hip", "time_ip_fwd_f32.hip", "time_ip_inv_f32.hip", "time_bl.hip", "fft_lds.hpp"]
 FAMILY_SOURCES = {
     "gs_update": ["krylov.hip"], "mdot": ["krylov.hip"], "combine": ["krylov.hip"],
-    "kkt_apply": ["kkt.hip", "stencil.hpp", "fem.hip"], "time_fwd": _TIME_SOURCES, "time_inv": _TIME_SOURCES,
+    "kkt_apply": ["kkt.hip", "stencil.hpp", "fem.hip", "fem.hpp"], "time_fwd": _TIME_SOURCES, "time_inv": _TIME_SOURCES,
     "dst_rows": ["dst.hip", "fft_lds.hpp"], "dst_last_solve": ["dst.hip", "fft_lds.hpp"],
     "dst_ax2": ["dst.hip", "fft_lds.hpp"], "mg_smooth": ["multigrid.hip"], "mg_restrict": ["multigrid.hip"],
     "mg_prolong": ["multigrid.hip"], "ideal_step": ["ideal.hip"],
