@@ -210,3 +210,14 @@ def test_fem_post_solve_completes_the_recursions():
     assert np.abs(r).max() < 1e-10 * (1 + np.abs(M @ fN).max())
     r = -M @ (p[0] - p0) / tau + K @ p0 - M @ (g0 - y0)
     assert np.abs(r).max() < 1e-10 * (1 + np.abs(M @ g0).max() / tau)
+
+
+@pytest.mark.parametrize("dim,nx,nt", [(2, 3, 6), (3, 2, 5)])
+def test_fem_ideal_rbd_apply_equals_dense_inverse(dim, nx, nt):
+    """P^{-1} v by the two sequential substitutions with T_0 = (1 + alpha) M +
+    tau K and the coupling M to the neighbouring level equals the inverse of
+    eq. matrix_P assembled densely with M != I."""
+    pb = D.make_problem(dim, nx, nt, 1e-3, mass="q1")
+    v = np.random.default_rng(9).standard_normal(2 * pb.n * pb.m)
+    w = P.IdealRBD(pb).apply(v)
+    assert rel(w, np.linalg.solve(P.ideal_rbd_dense(pb), v)) < 1e-12
