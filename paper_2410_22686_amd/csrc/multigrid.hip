@@ -41,6 +41,15 @@ __device__ __forceinline__ cx<T> slice_sigma(const MgShift& sh, int slice) {
   return cx<T>{(T)re, (T)im};
 }
 
+// (point chunk, slice group) of this block in XCD-friendly order: the blocks
+// one XCD runs take consecutive point chunks of a slice group, so the
+// neighbour planes a block reads were brought into that XCD's L2 by the
+// blocks next to it
+__device__ __forceinline__ int2 mg_block() {
+  const int lg = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  return make_int2(lg % gridDim.x, lg / gridDim.x);
+}
+
 __device__ __forceinline__ void coords(int i, int nx, int dim, int* c) {
   c[0] = i % nx;
   c[1] = (i / nx) % nx;
@@ -55,7 +64,8 @@ template <class T, int DIM, int SB>
 __global__ void __launch_bounds__(256) mg_smooth_kernel(int nx, int m, int slices, const T* __restrict__ coef,
                                                         const cx<T>* __restrict__ r, cx<T>* __restrict__ z,
                                                         MgShift sh) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int2 bk = mg_block();
+  const int i = bk.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
   int c[3];
   coords(i, nx, DIM, c);
@@ -83,7 +93,7 @@ __global__ void __launch_bounds__(256) mg_smooth_kernel(int nx, int m, int slice
       stride *= nx;
     }
   }
-  const int s0 = blockIdx.y * SB;
+  const int s0 = bk.y * SB;
 #pragma unroll
   for (int k = 0; k < SB; ++k) {
     const int s = s0 + k;
@@ -110,7 +120,8 @@ __global__ void __launch_bounds__(256) mg_smooth_kernel(int nx, int m, int slice
 template <class T, int DIM, int SB>
 __global__ void __launch_bounds__(256) mg_residual_kernel(int nx, int m, int slices, const T* __restrict__ coef,
                                                           const cx<T>* __restrict__ z, cx<T>* res, MgShift sh) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int2 bk = mg_block();
+  const int i = bk.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
   int f[3];
   coords(i, nx, DIM, f);
@@ -131,7 +142,7 @@ __global__ void __launch_bounds__(256) mg_residual_kernel(int nx, int m, int sli
       stride *= nx;
     }
   }
-  const int s0 = blockIdx.y * SB;
+  const int s0 = bk.y * SB;
 #pragma unroll
   for (int k = 0; k < SB; ++k) {
     const int s = s0 + k;
@@ -154,9 +165,10 @@ template <class T, int DIM>
 __global__ void __launch_bounds__(256) mg_restrict_kernel(int nxf, int mf, int nxc, int mc,
                                                           const cx<T>* __restrict__ res, cx<T>* __restrict__ rc,
                                                           MgShift sh) {
-  const int s = blockIdx.y;
+  const int2 bk = mg_block();
+  const int s = bk.y;
   if (sh.active && !sh.active[s / sh.twoK]) return;
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  const int I = bk.x * blockDim.x + threadIdx.x;
   if (I >= mc) return;
   int C[3];
   coords(I, nxc, DIM, C);
@@ -180,9 +192,10 @@ template <class T, int DIM>
 __global__ void __launch_bounds__(256) mg_prolong_kernel(int nxf, int mf, int nxc, int mc,
                                                          const cx<T>* __restrict__ zf, const cx<T>* __restrict__ zc,
                                                          cx<T>* out, MgShift sh) {
-  const int s = blockIdx.y;
+  const int2 bk = mg_block();
+  const int s = bk.y;
   if (sh.active && !sh.active[s / sh.twoK]) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = bk.x * blockDim.x + threadIdx.x;
   if (i >= mf) return;
   int f[3];
   coords(i, nxf, DIM, f);
