@@ -187,14 +187,14 @@ __global__ void __launch_bounds__(256) mg_restrict_kernel(int nxf, int mf, int n
   rc[(size_t)s * mc + I] = scale(acc, inv);
 }
 
-// out = z_fine + P z_coarse (out may alias z_fine)
-template <class T, int DIM>
-__global__ void __launch_bounds__(256) mg_prolong_kernel(int nxf, int mf, int nxc, int mc,
+// out = z_fine + P z_coarse (out may alias z_fine).  A thread owns one fine
+// point for SB consecutive slices: its coarse indices and weights are formed
+// once for all of them.
+template <class T, int DIM, int SB>
+__global__ void __launch_bounds__(256) mg_prolong_kernel(int nxf, int mf, int nxc, int mc, int slices,
                                                          const cx<T>* __restrict__ zf, const cx<T>* __restrict__ zc,
                                                          cx<T>* out, MgShift sh) {
   const int2 bk = mg_block();
-  const int s = bk.y;
-  if (sh.active && !sh.active[s / sh.twoK]) return;
   const int i = bk.x * blockDim.x + threadIdx.x;
   if (i >= mf) return;
   int f[3];
@@ -227,15 +227,22 @@ __global__ void __launch_bounds__(256) mg_prolong_kernel(int nxf, int mf, int nx
       }
     }
   }
-  const cx<T>* zcs = zc + (size_t)s * mc;
-  cx<T> acc = zf[(size_t)s * mf + i];
-  for (int u2 = 0; u2 < cn[2]; ++u2)
-    for (int u1 = 0; u1 < cn[1]; ++u1)
-      for (int u0 = 0; u0 < cn[0]; ++u0) {
-        const int I = ci[0][u0] + nxc * (ci[1][u1] + nxc * ci[2][u2]);
-        acc = acc + scale(zcs[I], cw[0][u0] * cw[1][u1] * cw[2][u2]);
-      }
-  out[(size_t)s * mf + i] = acc;
+  const int s0 = bk.y * SB;
+#pragma unroll
+  for (int k = 0; k < SB; ++k) {
+    const int s = s0 + k;
+    if (s >= slices) break;
+    if (sh.active && !sh.active[s / sh.twoK]) continue;
+    const cx<T>* zcs = zc + (size_t)s * mc;
+    cx<T> acc = zf[(size_t)s * mf + i];
+    for (int u2 = 0; u2 < cn[2]; ++u2)
+      for (int u1 = 0; u1 < cn[1]; ++u1)
+        for (int u0 = 0; u0 < cn[0]; ++u0) {
+          const int I = ci[0][u0] + nxc * (ci[1][u1] + nxc * ci[2][u2]);
+          acc = acc + scale(zcs[I], cw[0][u0] * cw[1][u1] * cw[2][u2]);
+        }
+    out[(size_t)s * mf + i] = acc;
+  }
 }
 
 // slices per thread of the smoother and the residual
@@ -259,7 +266,6 @@ static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, int spm
   for (int l = 0; l < NL; ++l) {
     const int nx = tb.mg[l].nx;
     const int m = (int)tb.mg[l].m;
-    dim3 grid((m + 255) / 256, slices);
     dim3 gridb((m + 255) / 256, (slices + kMgSB - 1) / kMgSB);
     tbeg(tb.timer, KF_MG_SMOOTH, 2.0 * cs * m);
     mg_smooth_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), rbuf(l), zbuf(l), sh);
@@ -281,17 +287,17 @@ static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, int spm
     const int m = (int)tb.mg[l].m;
     const int nxc = tb.mg[l + 1].nx;
     const int mc = (int)tb.mg[l + 1].m;
-    dim3 grid((m + 255) / 256, slices);
+    dim3 gridb((m + 255) / 256, (slices + kMgSB - 1) / kMgSB);
     cx<T>* out = (l == 0) ? spec : zbuf(l);
     tbeg(tb.timer, KF_MG_PROLONG, cs * (2.0 * m + mc));
-    mg_prolong_kernel<T, DIM><<<grid, 256, 0, st>>>(nx, m, nxc, mc, zbuf(l), zbuf(l + 1), out, sh);
+    mg_prolong_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(nx, m, nxc, mc, slices, zbuf(l), zbuf(l + 1), out, sh);
     tend(tb.timer);
   }
   if (NL == 1) {
     // single-point grid: the smoothed value is the exact solve; copy it back
     const int m = (int)tb.mg[0].m;
-    dim3 grid((m + 255) / 256, slices);
-    mg_prolong_kernel<T, DIM><<<grid, 256, 0, st>>>(1, m, 0, 0, zbuf(0), zbuf(0), spec, sh);
+    dim3 gridb((m + 255) / 256, (slices + kMgSB - 1) / kMgSB);
+    mg_prolong_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(1, m, 0, 0, slices, zbuf(0), zbuf(0), spec, sh);
   }
 }
 
