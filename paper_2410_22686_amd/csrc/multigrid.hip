@@ -245,8 +245,11 @@ __global__ void __launch_bounds__(256) mg_prolong_kernel(int nxf, int mf, int nx
   }
 }
 
-// slices per thread of the smoother and the residual
+// slices per thread of the smoother, the residual and the prolongation on
+// levels where that still gives at least kMgMinBlocks blocks (one slice per
+// thread below)
 constexpr int kMgSB = 8;
+constexpr long long kMgMinBlocks = 1024;
 
 template <class T, int DIM>
 static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, int spm, const double* lam,
@@ -263,12 +266,20 @@ static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, int spm
   auto rbuf = [&](int l) -> cx<T>* { return l == 0 ? spec : reinterpret_cast<cx<T>*>(tb.mg[l].r); };
   // pass bytes (algorithmic): complex data in and out of every kernel
   const double cs = sizeof(cx<T>) * (double)slices * tb.nact / g.B;
+  // kMgSB slices per thread where that still leaves kMgMinBlocks blocks to
+  // fill the chip, one slice per thread on the small (coarse) levels
+  auto wide = [&](int m) { return (long long)((m + 255) / 256) * ((slices + kMgSB - 1) / kMgSB) >= kMgMinBlocks; };
+  auto grid_sb = [&](int m) {
+    const int sb = wide(m) ? kMgSB : 1;
+    return dim3((m + 255) / 256, (slices + sb - 1) / sb);
+  };
   for (int l = 0; l < NL; ++l) {
     const int nx = tb.mg[l].nx;
     const int m = (int)tb.mg[l].m;
-    dim3 gridb((m + 255) / 256, (slices + kMgSB - 1) / kMgSB);
+    const dim3 gridb = grid_sb(m);
     tbeg(tb.timer, KF_MG_SMOOTH, 2.0 * cs * m);
-    mg_smooth_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), rbuf(l), zbuf(l), sh);
+    if (wide(m)) mg_smooth_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), rbuf(l), zbuf(l), sh);
+    else mg_smooth_kernel<T, DIM, 1><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), rbuf(l), zbuf(l), sh);
     tend(tb.timer);
     if (l + 1 < NL) {
       const int nxc = tb.mg[l + 1].nx;
@@ -277,7 +288,8 @@ static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, int spm
       // residual into the consumed right-hand side (half the points), then
       // full weighting
       tbeg(tb.timer, KF_MG_RESTRICT, cs * (m + 0.5 * m + 0.5 * m + mc));
-      mg_residual_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), zbuf(l), rbuf(l), sh);
+      if (wide(m)) mg_residual_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), zbuf(l), rbuf(l), sh);
+      else mg_residual_kernel<T, DIM, 1><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), zbuf(l), rbuf(l), sh);
       mg_restrict_kernel<T, DIM><<<gc, 256, 0, st>>>(nx, m, nxc, mc, rbuf(l), rbuf(l + 1), sh);
       tend(tb.timer);
     }
@@ -287,17 +299,20 @@ static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, int spm
     const int m = (int)tb.mg[l].m;
     const int nxc = tb.mg[l + 1].nx;
     const int mc = (int)tb.mg[l + 1].m;
-    dim3 gridb((m + 255) / 256, (slices + kMgSB - 1) / kMgSB);
+    const dim3 gridb = grid_sb(m);
     cx<T>* out = (l == 0) ? spec : zbuf(l);
     tbeg(tb.timer, KF_MG_PROLONG, cs * (2.0 * m + mc));
-    mg_prolong_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(nx, m, nxc, mc, slices, zbuf(l), zbuf(l + 1), out, sh);
+    if (wide(m))
+      mg_prolong_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(nx, m, nxc, mc, slices, zbuf(l), zbuf(l + 1), out, sh);
+    else
+      mg_prolong_kernel<T, DIM, 1><<<gridb, 256, 0, st>>>(nx, m, nxc, mc, slices, zbuf(l), zbuf(l + 1), out, sh);
     tend(tb.timer);
   }
   if (NL == 1) {
     // single-point grid: the smoothed value is the exact solve; copy it back
     const int m = (int)tb.mg[0].m;
-    dim3 gridb((m + 255) / 256, (slices + kMgSB - 1) / kMgSB);
-    mg_prolong_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(1, m, 0, 0, slices, zbuf(0), zbuf(0), spec, sh);
+    dim3 grid1((m + 255) / 256, slices);
+    mg_prolong_kernel<T, DIM, 1><<<grid1, 256, 0, st>>>(1, m, 0, 0, slices, zbuf(0), zbuf(0), spec, sh);
   }
 }
 
