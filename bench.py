@@ -1,21 +1,35 @@
-"""Benchmark: KKT solves per second to 1e-8 relative residual on one MI355X.
+"""Benchmark: KKT solves per second to 1e-8 relative residual on one MI355X,
+FP64 against mixed precision.
 
-Workload (default): 2-D, a = 1, nx = 255 interior points per dimension
-(m = 65 025), N = nt = 256 backward-Euler steps (n = 255 time blocks),
-T = 1, gamma in {1e-2, 1e-6, 1e-10}, eps = sqrt(tau), smooth-plus-noise
-g, f, y0 (seeded), FP64 right-preconditioned GMRES(30) with the
-epsilon-circulant RBD preconditioner (time FFT + sine transforms), stopped at
-||b - A x|| <= 1e-8 ||b||.  One step solves the three systems (one batched
-solve with one member per gamma); inputs are resident in HBM before timing.
+Workload (default): 2-D, a = 1, nx = 511 interior points per dimension
+(m = 261 121), N = nt = 512 backward-Euler steps (n = 511 time blocks),
+T = 1, gamma = 1e-6, eps = sqrt(tau), smooth-plus-noise g, f, y0 (seeded),
+the epsilon-circulant RBD preconditioner (time FFT + sine transforms).  One
+step solves the system twice from x0 = 0 to ||b - A x|| <= 1e-8 ||b||:
+  * FP64 leg:  preconditioner in FP64, right-preconditioned GMRES(30);
+  * mixed leg: preconditioner in complex FP32 inside FP64 flexible
+               GMRES(30) (matvec, Arnoldi and residuals in FP64).
+``value`` is solves per second over the whole step (both legs); each leg's
+own rate, iteration count and true residual, and the relative difference
+between the two solutions, are reported beside it.  Inputs are resident in
+HBM before timing; setup (tables, tuning) is outside the timed region.
 
 Prints one JSON line.  Fields beyond the common contract:
+  legs          -- per leg: solves/s, ms per solve, iterations, residual,
+                   kernel choice, per-family kernel table;
+  mixed_vs_fp64 -- ||x_mixed - x_fp64|| / ||x_fp64|| per member;
   roofline      -- the kernel family with the largest summed event time in
-                   the timed region, its algorithmic bytes per launch over
-                   its mean launch duration, against 8 TB/s HBM;
-  precond_apply -- the same for the whole preconditioner apply (5 kernels);
+                   the timed region (both legs), its algorithmic bytes per
+                   launch over its mean launch duration, against 8 TB/s HBM;
+  precond_apply -- per leg, the same for the whole preconditioner apply;
   cpu_baseline  -- the FP64 oracle timed on this host on a bounded sample.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Kernel choices come from the tuner; its choices are cached in the text file
+named by PCOP_TUNE_CACHE (default: the committed cache of this package), so
+repeated runs and profiler runs time the same kernels.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C]
+                       [--precision fp64|mixed] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -48,10 +62,16 @@ FAMILY_SOURCES = {
 }
 
 
-def recorded_traffic(workload, family):
+CHOICE_KEYS = ("time_cols", "dst_kernel", "kkt_jchunk", "krylov_blocks", "gs_update")
+DEFAULT_TUNE_CACHE = os.path.join(ROOT, "paper_2410_22686_amd", "tune_cache_mi355x.txt")
+
+
+def recorded_traffic(workload, family, choices):
     """HBM bytes per launch recorded by rocprofv3 FETCH_SIZE/WRITE_SIZE runs in
-    profiles/kernels_<workload>.md, or None when absent or when the kernel
-    sources changed since the counters were taken."""
+    profiles/kernels_<workload>.md, or None when absent, when the kernel
+    sources changed since the counters were taken, or when the kernel choice
+    of a leg (choices: {leg: kernel choice}) differs from the one the
+    counters were taken with."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"kernels_{workload}.md")
     if not os.path.exists(path) or family not in FAMILY_SOURCES:
@@ -62,6 +82,10 @@ def recorded_traffic(workload, family):
             rec = json.loads(line[len("traffic: "):])
     if not rec or rec.get("workload") != workload or family not in rec.get("families", {}):
         return None
+    kern = rec.get("kernels", {})
+    for leg, ch in choices.items():
+        if leg not in kern or any(kern[leg].get(k) != ch.get(k) for k in CHOICE_KEYS):
+            return None
     h = hashlib.sha256()
     for fn in FAMILY_SOURCES[family]:
         with open(os.path.join(ROOT, "paper_2410_22686_amd", "csrc", fn), "rb") as fh:
@@ -75,17 +99,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
-                    help="workload: 1 2d-nx31-nt32, 2 2d-nx255-nt256 (default), 3 2d-nx511-nt512-mixed, "
-                         "4 2d-nx127-nt128-batch64, 5 3d-nx63-nt128-vara-mg")
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4, 5],
+                    help="workload: 1 2d-nx31-nt32, 2 2d-nx255-nt256, 3 2d-nx511-nt512 (default; FP64 and mixed "
+                         "legs), 4 2d-nx127-nt128-batch64, 5 3d-nx63-nt128-vara-mg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
-                    help="override the workload's preconditioner precision")
+                    help="run one leg in this precision (default: both legs on workload 3, the workload's own "
+                         "precision elsewhere)")
     ap.add_argument("--graph", type=int, default=None, choices=[0, 1],
                     help="capture Arnoldi chunks as HIP graphs (default: on for the batched and smallest workloads)")
     ap.add_argument("--tune", type=int, default=1, choices=[0, 1],
-                    help="time the candidate preconditioner kernels at setup and keep the fastest")
+                    help="time the candidate kernels at setup and keep the fastest (or take the cached choice)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tuner cache file (default: $PCOP_TUNE_CACHE, else the committed cache); '' for none")
     ap.add_argument("--time-cols", type=int, default=0, choices=[0, -1, -4, -8, -16, 4, 8, 16],
                     help="time-pass kernels: 0 automatic, -P two LDS buffers, +P in place (P points per block)")
     ap.add_argument("--dst-kernel", type=int, default=0, choices=[0, 1, 2, 3, 4],
@@ -105,14 +132,28 @@ def parse():
     return ap.parse_args()
 
 
-def solver_options(cfg, precision=None, graph=None):
-    prec = precision or cfg.precision
-    if prec == "mixed" or cfg.spatial == "mg":
-        opts = dict(precision=prec, spatial=cfg.spatial, side="flexible")
+def solver_options(cfg, precision, graph=None):
+    if precision == "mixed" or cfg.spatial == "mg":
+        opts = dict(precision=precision, spatial=cfg.spatial, side="flexible")
     else:
         opts = dict(precision="fp64", spatial="dst", side="right")
     opts["graph"] = bool(graph) if graph is not None else cfg.config_id in (1, 4)
     return opts
+
+
+def legs_of(cfg, precision):
+    if precision is not None:
+        return [precision]
+    return ["fp64", "mixed"] if cfg.config_id == 3 else [cfg.precision]
+
+
+def workload_name(cfg, legs, mass):
+    if legs == [cfg.precision]:
+        name = cfg.name
+    else:
+        base = cfg.name[: -len("-mixed")] if cfg.name.endswith("-mixed") else cfg.name
+        name = base + "-" + "-and-".join(legs)
+    return name + ("-q1" if mass == "q1" else "")
 
 
 def cpu_baseline(cfg, iters, budget_s, mass="identity"):
@@ -121,16 +162,17 @@ def cpu_baseline(cfg, iters, budget_s, mass="identity"):
 
     Sample: the oracle's own pieces at full size for one member -- a few of
     the n per-frequency sparse LU factorisations of (lambda_k + alpha) I +
-    tau K and their solves, one dense Fourier-matrix product along time, one
-    sparse KKT matvec and one modified Gram-Schmidt step.  A right-
-    preconditioned solve of k iterations costs k (apply + matvec) +
-    sum_{j<k} (j+1) MGS steps + one final apply, with
+    tau K and their solves, the dense Fourier-matrix product along time (on
+    a subset of the m spatial columns when n^2 m is large, scaled by the
+    column count), a sparse KKT matvec (on 8 of the n time blocks, scaled)
+    and one modified Gram-Schmidt step (on a slice of the vector when it is
+    large, scaled).  A right-preconditioned solve of k iterations costs
+    k (apply + matvec) + sum_{j<k} (j+1) MGS steps + one final apply, with
     apply = 4 dense DFTs + 2n LU solves (the four steps of Section 2.1);
     factorisations are setup and excluded, as on the GPU."""
     import numpy as np
-    import scipy.sparse as sp
-    import scipy.sparse.linalg as spla
     from oracle import discretize as D, precond as P
+    import scipy.sparse.linalg as spla
 
     t_start = time.perf_counter()
     try:
@@ -157,12 +199,15 @@ def cpu_baseline(cfg, iters, budget_s, mass="identity"):
         if time.perf_counter() - t0 > 0.5:
             break
     t_mv = (time.perf_counter() - t0) / reps * (n / n_mv)
+    # dense time DFT (n x n) on m_dft of the m columns: O(n^2 m), scaled by m/m_dft
     F = P.fourier_matrix(n)
-    V = rng.standard_normal((n, m)) + 0j
+    m_dft = min(m, max(64, int(4e9 / (8.0 * n * n))))
+    V = rng.standard_normal((n, m_dft)) + 0j
     F.conj().T @ V  # first call pays page faults and thread start-up
     t0 = time.perf_counter()
     F.conj().T @ V
-    t_dft = time.perf_counter() - t0
+    t_dft = (time.perf_counter() - t0) * (m / m_dft)
+    del V
     lam = P.lambda_eps(n, pb.eps)
     Kc = pb.K.tocsc().astype(np.complex128)
     I = pb.Mm.tocsc().astype(np.complex128)  # M (the identity for finite differences)
@@ -181,15 +226,19 @@ def cpu_baseline(cfg, iters, budget_s, mass="identity"):
         if time.perf_counter() - t_start > 0.6 * budget_s:
             break
     t_lu /= nlu
-    w = rng.standard_normal(2 * n * m)
-    v = rng.standard_normal(2 * n * m)
+    # one MGS step (a dot product and an axpy over a member vector): O(n m),
+    # on at most 2^25 of the 2 n m values, scaled
+    vlen = 2 * n * m
+    vsub = min(vlen, 1 << 25)
+    w = rng.standard_normal(vsub)
+    v = rng.standard_normal(vsub)
     times = []
     for _ in range(3):  # the first pass pays page faults
         t0 = time.perf_counter()
         h = np.dot(v, w)
         w = w - h * v
         times.append(time.perf_counter() - t0)
-    t_mgs = min(times[1:])
+    t_mgs = min(times[1:]) * (vlen / vsub)
     apply_s = 4 * t_dft + 2 * n * t_lu
     total = 0.0
     for k in iters:
@@ -199,13 +248,39 @@ def cpu_baseline(cfg, iters, budget_s, mass="identity"):
         "value": solves_per_s, "unit": "solves/s", "cores": int(threads), "host_cores_visible": int(cores),
         "kind": "oracle",
         "sample": (f"FP64 NumPy/SciPy oracle pieces at full size ({cfg.name}, {mass} mass matrix, one member): {nfac} of {n} "
-                   f"per-frequency splu factorisations and {nlu} LU solves, one dense time-DFT product, "
-                   f"sparse KKT matvecs on {n_mv} of {n} time blocks (scaled by {n}/{n_mv}), one MGS step; scaled to {len(iters)} right-preconditioned solves "
-                   f"with the GPU iteration counts {list(iters)}; factorisation (setup, "
+                   f"per-frequency splu factorisations and {nlu} LU solves, the dense time-DFT product on {m_dft} of "
+                   f"{m} columns (scaled), sparse KKT matvecs on {n_mv} of {n} time blocks (scaled by {n}/{n_mv}), "
+                   f"one MGS step on {vsub} of {vlen} values (scaled); composed into {len(iters)} right-preconditioned "
+                   f"FP64 solves with the GPU's FP64 iteration counts {list(iters)}; factorisation (setup, "
                    f"{t_fac / max(nfac, 1):.2f} s each, {n} needed) excluded"),
         "sample_wall_s": round(time.perf_counter() - t_start, 2),
         "per_apply_s": apply_s, "per_matvec_s": t_mv,
     }
+
+
+def precond_stats(stats, precision, cfg):
+    """The preconditioner's passes (time forward, spatial solves, time
+    inverse) of one leg: their algorithmic bytes over their summed time."""
+    pre = {k: v for k, v in stats.items() if k in PRECOND_FAMILIES}
+    pre_ms = sum(v["ms"] for v in pre.values())
+    pre_bytes = sum(v["bytes"] for v in pre.values())
+    if pre_ms <= 0 or "time_fwd" not in pre:
+        return None
+    csz = 16.0 if precision == "fp64" else 8.0
+    per_member = 8.0 * 2 * cfg.n * cfg.m + csz * 2 * (cfg.n // 2 + 1) * cfg.m
+    member_applies = pre["time_fwd"]["bytes"] / per_member
+    return {"achieved_pass_bytes_GBs": round(pre_bytes / (pre_ms * 1e-3) / 1e9, 1),
+            "frac": round(pre_bytes / (pre_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "member_applies": round(member_applies, 2),
+            "ms_per_member_apply": pre_ms / member_applies,
+            "compulsory_GBs": round(32.0 * cfg.n * cfg.m * member_applies / (pre_ms * 1e-3) / 1e9, 1),
+            "pass_bytes_per_member_apply": pre_bytes / member_applies}
+
+
+def kernel_table(stats):
+    return {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                "GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
+            for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])}
 
 
 def main():
@@ -214,6 +289,11 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus_requested": args.gpus}))
         sys.exit(2)
+    cache = args.tune_cache if args.tune_cache is not None else os.environ.get("PCOP_TUNE_CACHE", DEFAULT_TUNE_CACHE)
+    if cache:
+        os.environ["PCOP_TUNE_CACHE"] = cache
+    else:
+        os.environ.pop("PCOP_TUNE_CACHE", None)
     import numpy as np
     import torch
 
@@ -224,7 +304,8 @@ def main():
     if args.mass == "q1" and cfg.spatial != "dst":
         print(json.dumps({"error": "--mass q1 needs a workload with sine transforms (a = 1)"}))
         sys.exit(2)
-    workload = cfg.name + ("-q1" if args.mass == "q1" else "")
+    legs = legs_of(cfg, args.precision)
+    workload = workload_name(cfg, legs, args.mass)
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
@@ -233,103 +314,128 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     members = list(range(len(cfg.gammas)))
-    print(f"# bench: {cfg.name} members={len(members)} generating inputs", file=sys.stderr, flush=True)
+    print(f"# bench: {workload} members={len(members)} legs={legs} generating inputs", file=sys.stderr, flush=True)
     g = np.empty((len(members), cfg.n, cfg.m))
     f = np.empty_like(g)
     y0 = np.empty((len(members), cfg.m))
     for b in members:
         g[b], f[b], y0[b] = W.fields(cfg, member=b)
-    opts = solver_options(cfg, args.precision, args.graph)
-    stream = torch.cuda.Stream(device=dev) if opts["graph"] else None
-    s = Solver(cfg.dim, cfg.nx, cfg.nt, list(cfg.gammas), T=cfg.T, eps=cfg.eps,
-               coeff=None if cfg.coeff == "one" else W.coeff_function(cfg.coeff),
-               restart=30, maxit=300, rtol=1e-8, device=dev, stream=stream, tune=bool(args.tune),
-               time_cols=args.time_cols, dst_kernel=args.dst_kernel, precond=args.precond,
-               kkt_jchunk=args.kkt_jchunk, krylov_blocks=args.krylov_blocks, gs_update=args.gs_update,
-               mass=args.mass, **opts)
-    print(f"# bench: kernels {s.kernels}", file=sys.stderr, flush=True)
+    solvers, opts_of = {}, {}
+    for leg in legs:
+        opts = solver_options(cfg, leg, args.graph)
+        stream = torch.cuda.Stream(device=dev) if opts["graph"] else None
+        solvers[leg] = Solver(cfg.dim, cfg.nx, cfg.nt, list(cfg.gammas), T=cfg.T, eps=cfg.eps,
+                              coeff=None if cfg.coeff == "one" else W.coeff_function(cfg.coeff),
+                              restart=30, maxit=300, rtol=1e-8, device=dev, stream=stream, tune=bool(args.tune),
+                              time_cols=args.time_cols, dst_kernel=args.dst_kernel, precond=args.precond,
+                              kkt_jchunk=args.kkt_jchunk, krylov_blocks=args.krylov_blocks,
+                              gs_update=args.gs_update, mass=args.mass, **opts)
+        opts_of[leg] = opts
+        print(f"# bench: {leg} kernels {solvers[leg].kernels}", file=sys.stderr, flush=True)
     tg = torch.tensor(g, device=dev)
     tf = torch.tensor(f, device=dev)
     ty0 = torch.tensor(y0, device=dev)
     del g, f
     torch.cuda.synchronize()
-    b = s.rhs(tg, tf, ty0)
+    b = solvers[legs[0]].rhs(tg, tf, ty0)
+    del tg, tf, ty0
     torch.cuda.synchronize()
     print("# bench: warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        x, infos, _ = s.solve(b)
-    torch.cuda.synchronize()
+        for leg in legs:
+            solvers[leg].solve(b)
+            torch.cuda.synchronize()
     print("# bench: timed steps", file=sys.stderr, flush=True)
     # with graphs the timed region runs the captured chunks untouched and the
     # per-kernel table comes from one extra eager solve afterwards
-    if not opts["graph"]:
-        s.timing_enable(True)
+    for leg in legs:
+        if not opts_of[leg]["graph"]:
+            solvers[leg].timing_enable(True)
+    leg_s = {leg: 0.0 for leg in legs}
+    xs, infos = {}, {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        x, infos, _ = s.solve(b)
+        for leg in legs:
+            tl = time.perf_counter()
+            xs[leg], infos[leg], _ = solvers[leg].solve(b)
+            torch.cuda.synchronize()
+            leg_s[leg] += time.perf_counter() - tl
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    if opts["graph"]:
-        s.timing_enable(True)
-        s.solve(b)
-        torch.cuda.synchronize()
-    stats = s.timing_read()
-    s.timing_enable(False)
+    stats_of = {}
+    for leg in legs:
+        s = solvers[leg]
+        if opts_of[leg]["graph"]:
+            s.timing_enable(True)
+            s.solve(b)
+            torch.cuda.synchronize()
+        stats_of[leg] = s.timing_read()
+        s.timing_enable(False)
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
-    solves = len(members) * args.steps
+    solves = len(members) * len(legs) * args.steps
     value = solves / elapsed
-    ok = all(i.converged and i.relres_true <= 1e-8 * 1.0001 for i in infos)
+    ok = all(i.converged and i.relres_true <= 1e-8 * 1.0001 for leg in legs for i in infos[leg])
 
-    dom_name, dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
+    # the dominant kernel family over the whole step (both legs)
+    total = {}
+    for st in stats_of.values():
+        for k, v in st.items():
+            t = total.setdefault(k, {"launches": 0, "ms": 0.0, "bytes": 0.0})
+            for q in ("launches", "ms", "bytes"):
+                t[q] += v[q]
+    dom_name, dom = max(total.items(), key=lambda kv: kv[1]["ms"])
     dom_ms_per_launch = dom["ms"] / dom["launches"]
     dom_bytes_per_launch = dom["bytes"] / dom["launches"]
     achieved = dom_bytes_per_launch / (dom_ms_per_launch * 1e-3) / 1e9
-    traffic = recorded_traffic(workload, dom_name)
+    choices = {leg: {k: solvers[leg].kernels[k] for k in CHOICE_KEYS} for leg in legs}
+    traffic = recorded_traffic(workload, dom_name, choices)
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_unit": "bytes/launch",
                 "bytes_per_launch": dom_bytes_per_launch, "ms_per_launch": dom_ms_per_launch,
                 "launches": dom["launches"]}
-    pre = {k: v for k, v in stats.items() if k in PRECOND_FAMILIES}
-    pre_ms = sum(v["ms"] for v in pre.values())
-    pre_bytes = sum(v["bytes"] for v in pre.values())
-    applies = max(v["launches"] for k, v in pre.items() if k == "time_fwd") if "time_fwd" in pre else 0
-    precond = None
-    if pre_ms > 0 and "time_fwd" in pre:
-        csz = 16.0 if opts["precision"] == "fp64" else 8.0
-        per_member = 8.0 * 2 * cfg.n * cfg.m + csz * 2 * (cfg.n // 2 + 1) * cfg.m
-        member_applies = pre["time_fwd"]["bytes"] / per_member
-        precond = {"achieved_pass_bytes_GBs": round(pre_bytes / (pre_ms * 1e-3) / 1e9, 1),
-                   "frac": round(pre_bytes / (pre_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                   "member_applies": round(member_applies, 2),
-                   "ms_per_member_apply": pre_ms / member_applies,
-                   "compulsory_GBs": round(32.0 * cfg.n * cfg.m * member_applies / (pre_ms * 1e-3) / 1e9, 1),
-                   "pass_bytes_per_member_apply": pre_bytes / member_applies}
-    kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
-                   "GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
-               for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])}
-    iters = [i.iters for i in infos]
+    leg_out = {}
+    for leg in legs:
+        n_solves = len(members) * args.steps
+        leg_out[leg] = {
+            "solves_per_s": round(n_solves / leg_s[leg], 4), "ms_per_solve": round(1e3 * leg_s[leg] / n_solves, 3),
+            "precision": opts_of[leg]["precision"], "krylov": f"{opts_of[leg]['side']} GMRES(30)",
+            "iters": [i.iters for i in infos[leg]], "relres_true": [i.relres_true for i in infos[leg]],
+            "kernel_choice": solvers[leg].kernels, "kernels": kernel_table(stats_of[leg]),
+            "kernel_table_source": "eager solve after the timed region" if opts_of[leg]["graph"] else "timed region",
+        }
+    mixed_vs_fp64 = None
+    if "fp64" in xs and "mixed" in xs:
+        d = (xs["mixed"] - xs["fp64"]).reshape(len(members), -1).norm(dim=1)
+        r = xs["fp64"].reshape(len(members), -1).norm(dim=1)
+        mixed_vs_fp64 = [float(v) for v in (d / r).cpu()]
+    both = len(legs) == 2
+    metric = ("KKT solves/s to 1e-8 rel. residual, FP64 vs mixed; preconditioner HBM GB/s" if both else
+              f"KKT solves/s to 1e-8 rel. residual ({'FP64' if legs[0] == 'fp64' else 'mixed FP32-preconditioner / FP64 FGMRES'}, "
+              f"eps-circulant RBD-preconditioned GMRES)")
     out = {
-        "metric": "KKT solves/s to 1e-8 rel. residual (FP64, eps-circulant RBD-preconditioned GMRES)",
-        "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "metric": metric, "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if opts["precision"] == "fp64" else "f64+f32",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if legs == ["fp64"] else ("f64+f32" if both or legs == ["mixed"] else "f64"),
         "data": "synthetic (seeded smooth sine products + N(0,1e-2) noise)",
         "config": {"workload": workload, "mass": args.mass, "dim": cfg.dim, "nx": cfg.nx, "nt": cfg.nt, "T": cfg.T,
                    "gammas": list(cfg.gammas), "eps": "sqrt(tau)" if cfg.eps is None else cfg.eps,
-                   "precision": opts["precision"], "spatial": opts["spatial"], "krylov": f"{opts['side']} GMRES(30)",
-                   "graph": opts["graph"], "preconditioner": args.precond,
-                   "rtol": 1e-8, "batch": len(members), "global_batch": len(members)},
-        "iters": iters, "relres_true": [i.relres_true for i in infos], "converged": ok,
-        "kernel_table_source": "eager solve after the timed region" if opts["graph"] else "timed region",
-        "roofline": roofline, "precond_apply": precond, "kernel_choice": s.kernels, "kernels": kernels,
+                   "legs": legs, "spatial": cfg.spatial, "preconditioner": args.precond,
+                   "rtol": 1e-8, "batch": len(members), "global_batch": len(members),
+                   "step": f"{len(members)} member(s) solved once per leg"},
+        "converged": ok, "mixed_vs_fp64": mixed_vs_fp64, "legs": leg_out,
+        "roofline": roofline,
+        "precond_apply": {leg: precond_stats(stats_of[leg], opts_of[leg]["precision"], cfg) for leg in legs},
+        "tune_cache": os.environ.get("PCOP_TUNE_CACHE"),
     }
     if not args.no_cpu_baseline and cfg.spatial == "mg":
         out["cpu_baseline"] = {"value": None, "note": "the oracle's multigrid path is timed only for the DST workloads"}
     elif not args.no_cpu_baseline:
         print("# bench: cpu baseline", file=sys.stderr, flush=True)
+        iters = leg_out["fp64"]["iters"] if "fp64" in leg_out else leg_out[legs[0]]["iters"]
         try:
             out["cpu_baseline"] = cpu_baseline(cfg, iters, args.cpu_sample_seconds, args.mass)
         except Exception as e:  # pragma: no cover

@@ -51,6 +51,11 @@ struct MgLevel {
   void* r;             // [B][2K][m] complex right-hand side on this level (levels >= 1)
 };
 
+// multigrid levels a hierarchy can hold: vertex-centred coarsening of
+// nx = 2^p - 1 reaches one point after p levels, and the largest accepted
+// grid (m <= 2^28, so nx <= 16383 in 2-D) needs 14
+constexpr int kMaxMgLevels = 16;
+
 struct PrecondTables {
   const double* dpow;    // [n]  eps^{j/n}
   const double* twn64;   // [n]  exp(-2 pi i t/n) as (re, im)
@@ -76,7 +81,7 @@ struct PrecondTables {
   const KTimer* timer;   // or null
   FftPlan plan;          // radices of n
   int mg_levels;
-  MgLevel mg[12];
+  MgLevel mg[kMaxMgLevels];
   const void* mg_res;    // finest-level residual scratch [B][2K][m] complex
 };
 

@@ -11,8 +11,11 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <mutex>
+#include <set>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -107,6 +110,9 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
       return fail(PCOP_ERR_UNSUPPORTED, "sine transforms need nx + 1 a power of two in 4..512");
   } else {
     if (!is_pow2(p->nx + 1)) return fail(PCOP_ERR_INVALID_ARG, "multigrid needs nx = 2^p - 1");
+    int levels = 0;
+    for (long long v = p->nx + 1; v > 1; v >>= 1) ++levels;
+    if (levels > kMaxMgLevels) return fail(PCOP_ERR_UNSUPPORTED, "multigrid hierarchy deeper than 16 levels");
   }
   const int n = p->nt - 1;
   if (o->precond == PCOP_PRECOND_EPS && !time_lds_fits(n, o->precision == PCOP_MIXED))
@@ -126,9 +132,9 @@ struct Layout {
   int M = 1;
   size_t sc, H, coef, red, partial, wnorm2, norm, skip, active, finish, hcol;
   size_t basis, zbasis, tmp1, tmp2, xpad, spec;
-  size_t mgcoef[12], mgz[12], mgr[12];
+  size_t mgcoef[kMaxMgLevels], mgz[kMaxMgLevels], mgr[kMaxMgLevels];
   int mg_levels = 0;
-  int mg_nx[12];
+  int mg_nx[kMaxMgLevels];
   int nblk = 1;      // default blocks per member of the Krylov reductions
   int nblk_max = 1;  // the most the partial-sum buffer holds (tuner candidates)
   long long vl = 0;
@@ -211,7 +217,7 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
       L.mgr[l] = take(L, csz * (size_t)B * 2 * K * lm);
       L.mgz[l] = (l > 0) ? take(L, csz * (size_t)B * 2 * K * lm) : 0;
       ++l;
-      if (lnx == 1 || l >= 12) break;
+      if (lnx == 1) break;  // validate() bounds the depth by kMaxMgLevels
       lnx = (lnx - 1) / 2;
     }
     L.mg_levels = l;
@@ -425,27 +431,115 @@ struct TuneResult {
   int jchunk;
   std::array<int, kMaxBasis> nb_mdot, nb_upd, pairs_upd;
 };
+// The choice is cached per device model (architecture and compute-unit
+// count) and shape for the process, and, when the environment variable
+// PCOP_TUNE_CACHE names a file, in that file: one text line per tuned shape
+//   pcop-tune <version> <device> <14 key ints> <time_cols> <dst_variant>
+//             <jchunk> <ms> <nb_mdot x 41> <nb_upd x 41> <pairs_upd x 41>
+// read once per process before the first tuning and appended after each
+// new one, so separate processes (a benchmark and a profiler run) run the
+// same kernels.  Lines of another version, malformed lines and entries that
+// do not fit the context are ignored (the shape is then tuned afresh).
+constexpr int kTuneVersion = 1;  // bump when the meaning of a kernel choice changes
+using TuneKey = std::pair<std::string, std::array<int, 14>>;
 std::mutex g_tune_mu;
-std::map<std::array<int, 14>, TuneResult> g_tune_cache;
+std::map<TuneKey, TuneResult> g_tune_cache;
+std::set<std::string> g_tune_files_read;
+
+std::string device_id(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string arch(prop.gcnArchName);
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch.resize(colon);
+  return arch + ":" + std::to_string(prop.multiProcessorCount);
+}
+
+// caller holds g_tune_mu
+void read_tune_file(const std::string& path) {
+  if (!g_tune_files_read.insert(path).second) return;
+  std::ifstream in(path);
+  std::string line;
+  while (in && std::getline(in, line)) {
+    std::istringstream ss(line);
+    std::string tag, dev;
+    int ver = 0;
+    if (!(ss >> tag >> ver >> dev) || tag != "pcop-tune" || ver != kTuneVersion) continue;
+    std::array<int, 14> k{};
+    TuneResult r{};
+    bool ok = true;
+    for (int& v : k) ok = ok && static_cast<bool>(ss >> v);
+    ok = ok && static_cast<bool>(ss >> r.time_cols >> r.dst_variant >> r.jchunk >> r.ms);
+    for (auto* arr : {&r.nb_mdot, &r.nb_upd, &r.pairs_upd})
+      for (int& v : *arr) ok = ok && static_cast<bool>(ss >> v);
+    if (ok) g_tune_cache[{dev, k}] = r;  // a later line for the same key wins
+  }
+}
+
+void append_tune_file(const std::string& path, const TuneKey& key, const TuneResult& r) {
+  std::ostringstream ss;
+  ss << "pcop-tune " << kTuneVersion << " " << key.first;
+  for (int v : key.second) ss << " " << v;
+  char ms[32];
+  std::snprintf(ms, sizeof(ms), "%.6g", r.ms);
+  ss << " " << r.time_cols << " " << r.dst_variant << " " << r.jchunk << " " << ms;
+  for (const auto* arr : {&r.nb_mdot, &r.nb_upd, &r.pairs_upd})
+    for (int v : *arr) ss << " " << v;
+  ss << "\n";
+  const std::string text = ss.str();
+  // one append of the whole line
+  if (FILE* fh = std::fopen(path.c_str(), "a")) {
+    (void)std::fwrite(text.data(), 1, text.size(), fh);
+    (void)std::fclose(fh);
+  }
+}
+
+// a cached choice this context can run (the partial-sum buffer holds
+// nblk_max blocks per member; a file may hold anything)
+bool tune_entry_fits(pcop_ctx c, const TuneResult& r) {
+  if (r.dst_variant < 0 || r.dst_variant > 3) return false;
+  if (r.jchunk == 0 || r.jchunk < -64 || r.jchunk > 64) return false;
+  for (int nv = 0; nv < kMaxBasis; ++nv) {
+    if (r.nb_mdot[nv] < 1 || r.nb_mdot[nv] > c->L.nblk_max) return false;
+    if (r.nb_upd[nv] < 1 || r.nb_upd[nv] > c->L.nblk_max) return false;
+    if (r.pairs_upd[nv] != 0 && r.pairs_upd[nv] != 1) return false;
+  }
+  if (c->opt.precond == PCOP_PRECOND_EPS) {
+    const int tc = r.time_cols < 0 ? -r.time_cols : r.time_cols;
+    if (tc != 0 && tc != 1 && tc != 4 && tc != 8 && tc != 16) return false;
+    PrecondTables t = c->tb;
+    t.time_cols = r.time_cols;
+    if (time_choice(c->g, t, c->fp32) == 0) return false;
+  }
+  return true;
+}
+
+void apply_tune_result(pcop_ctx c, const TuneResult& r) {
+  c->tb.time_cols = r.time_cols;
+  c->tb.dst_variant = r.dst_variant;
+  c->tuned_ms = r.ms;
+  c->kkt_jchunk = r.jchunk;
+  c->nb_mdot = r.nb_mdot;
+  c->nb_upd = r.nb_upd;
+  c->pairs_upd = r.pairs_upd;
+}
 
 pcop_status tune_kernels(pcop_ctx c) {
   const Geo& g = c->g;
   int dev = 0;
   PCOP_HIP(hipGetDevice(&dev));
-  const std::array<int, 14> key{dev, g.dim, g.nx, g.n, g.B, (int)c->fp32, c->opt.spatial, c->opt.time_cols,
-                                c->opt.dst_kernel, c->coeff_kind + 2 * c->mass, c->opt.precond, c->opt.kkt_jchunk,
-                                c->opt.krylov_blocks, c->opt.gs_update};
+  const TuneKey key{device_id(dev),
+                    {g.dim, g.nx, g.n, g.B, (int)c->fp32, c->opt.spatial, c->opt.time_cols, c->opt.dst_kernel,
+                     c->coeff_kind + 2 * c->mass, c->opt.precond, c->opt.kkt_jchunk, c->opt.krylov_blocks,
+                     c->opt.gs_update, c->opt.restart}};
+  const char* env = std::getenv("PCOP_TUNE_CACHE");
+  const std::string cache_file = (env && *env) ? env : "";
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!cache_file.empty()) read_tune_file(cache_file);
     auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) {
-      c->tb.time_cols = it->second.time_cols;
-      c->tb.dst_variant = it->second.dst_variant;
-      c->tuned_ms = it->second.ms;
-      c->kkt_jchunk = it->second.jchunk;
-      c->nb_mdot = it->second.nb_mdot;
-      c->nb_upd = it->second.nb_upd;
-      c->pairs_upd = it->second.pairs_upd;
+    if (it != g_tune_cache.end() && tune_entry_fits(c, it->second)) {
+      apply_tune_result(c, it->second);
       return PCOP_OK;
     }
   }
@@ -609,15 +703,10 @@ pcop_status tune_kernels(pcop_ctx c) {
   if (err == hipSuccess) err = hipGetLastError();
   if (err != hipSuccess) return fail(PCOP_ERR_DEVICE, std::string("tuner: ") + hipGetErrorString(err));
   if (best.ms >= 1e300) return fail(PCOP_ERR_UNSUPPORTED, "tuner: no preconditioner variant runs for this shape");
-  c->tb.time_cols = best.time_cols;
-  c->tb.dst_variant = best.dst_variant;
-  c->tuned_ms = best.ms;
-  c->kkt_jchunk = best.jchunk;
-  c->nb_mdot = best.nb_mdot;
-  c->nb_upd = best.nb_upd;
-  c->pairs_upd = best.pairs_upd;
+  apply_tune_result(c, best);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune_cache[key] = best;
+  if (!cache_file.empty()) append_tune_file(cache_file, key, best);
   return PCOP_OK;
 }
 

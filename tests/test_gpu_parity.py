@@ -16,14 +16,9 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU containers
     pytest.skip("needs a GPU", allow_module_level=True)
 
 from paper_2410_22686_amd import Solver, kkt_solve  # noqa: E402
+from parity import check, rel  # noqa: E402
 
 DEV = torch.device("cuda:0")
-
-
-def rel(a, b):
-    a = np.asarray(a).ravel()
-    b = np.asarray(b).ravel()
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def to_dev(a):
@@ -111,9 +106,10 @@ def test_precond_apply_fp64(dim, nx, nt, gammas, eps):
     s = Solver(dim, nx, nt, list(gammas), eps=eps, device=DEV)
     v = W.random_vector(dim, nx, nt, seed=7, batch=len(gammas))
     w = s.precond_apply(to_dev(v)).cpu().numpy()
-    for b, pb in enumerate(problems(dim, nx, nt, gammas, eps=eps)):
-        wo = P.EpsCirculantRBD(pb).apply(v[b].ravel())
-        assert rel(w[b], wo) < 1e-11, rel(w[b], wo)
+    wo = np.stack([P.EpsCirculantRBD(pb).apply(v[b].ravel()) for b, pb in enumerate(problems(dim, nx, nt, gammas, eps=eps))])
+    for b in range(len(gammas)):
+        assert rel(w[b], wo[b]) < 1e-11, rel(w[b], wo[b])
+    check(w, wo, 1e-11, len(gammas), nt - 1, nx ** dim, label="fp64 apply")
 
 
 @pytest.mark.parametrize("dim,nx,nt,gammas,eps", PRECOND_CASES[:3] + PRECOND_CASES[8:11])
@@ -121,10 +117,12 @@ def test_precond_apply_mixed(dim, nx, nt, gammas, eps):
     s = Solver(dim, nx, nt, list(gammas), eps=eps, precision="mixed", side="flexible", device=DEV)
     v = W.random_vector(dim, nx, nt, seed=8, batch=len(gammas))
     w = s.precond_apply(to_dev(v)).cpu().numpy()
-    for b, pb in enumerate(problems(dim, nx, nt, gammas, eps=eps)):
-        err = rel(w[b], P.EpsCirculantRBD(pb).apply(v[b].ravel()))
+    wo = np.stack([P.EpsCirculantRBD(pb).apply(v[b].ravel()) for b, pb in enumerate(problems(dim, nx, nt, gammas, eps=eps))])
+    for b in range(len(gammas)):
+        err = rel(w[b], wo[b])
         print(f"mixed precond rel err {err:.2e}")
         assert err < 1e-5
+    check(w, wo, 1e-5, len(gammas), nt - 1, nx ** dim, label="mixed apply")
 
 
 KERNEL_CASES = [
@@ -169,6 +167,7 @@ def test_precond_kernel_choices(dim, nx, nt, gammas, precision):
             w = s.precond_apply(to_dev(v)).cpu().numpy()
             for b in range(len(gammas)):
                 assert rel(w[b], wos[b]) < tol, (dk, tc, eff, b, rel(w[b], wos[b]))
+            check(w, np.stack(wos), tol, len(gammas), nt - 1, nx ** dim, label=f"dst {dk} time {eff}")
             if ref is None:
                 ref = w
             else:
@@ -202,9 +201,10 @@ def test_half_length_dst(dim, nx, nt, gammas, precision):
         assert s.kernels["dst_kernel"] == dk
         ws[dk] = s.precond_apply(to_dev(v)).cpu().numpy()
     tol = 1e-5 if precision == "mixed" else 1e-11
-    for b, pb in enumerate(problems(dim, nx, nt, gammas)):
-        wo = P.EpsCirculantRBD(pb).apply(v[b].ravel())
-        assert rel(ws[4][b], wo) < tol, (b, rel(ws[4][b], wo))
+    wo = np.stack([P.EpsCirculantRBD(pb).apply(v[b].ravel()) for b, pb in enumerate(problems(dim, nx, nt, gammas))])
+    for b in range(len(gammas)):
+        assert rel(ws[4][b], wo[b]) < tol, (b, rel(ws[4][b], wo[b]))
+    check(ws[4], wo, tol, len(gammas), nt - 1, nx ** dim, label="half-length dst")
     assert rel(ws[4], ws[1]) < (1e-5 if precision == "mixed" else 1e-12), rel(ws[4], ws[1])
 
 
@@ -261,6 +261,7 @@ def test_chirp_kernel_choices(dim, nx, nt, gammas, precision):
         w = s.precond_apply(to_dev(v)).cpu().numpy()
         for b in range(len(gammas)):
             assert rel(w[b], wos[b]) < tol, (tc, eff, b, rel(w[b], wos[b]))
+        check(w, np.stack(wos), tol, len(gammas), nt - 1, nx ** dim, label=f"chirp-z {eff}")
         if ref is None:
             ref = w
         else:
@@ -293,22 +294,40 @@ MG_CASES = [
     (3, 15, 8, (1e-2,), W.coeff_sines3d),
     (2, 1, 5, (1e-3,), W.coeff_sines3d),      # single-point grid: the cycle is an exact solve
     (2, 31, 20, (1e-6,), W.coeff_example2),   # Example 2 coefficient, chirp-z time transform
+    # shapes whose finest level runs the smoother, residual and prolongation
+    # with eight slices per thread (at least 1024 blocks of 256 points x 8
+    # slices); coarser levels fall back to one slice per thread
+    (2, 127, 128, (1e-5,), W.coeff_sines3d),  # 64 point blocks x 16 slice groups
+    (2, 127, 130, (1e-4,), W.coeff_example2), # 130 slices: the last group holds 2
+    (3, 31, 72, (1e-5,), W.coeff_sines3d),    # 117 x 9 groups (72 slices)
+    (3, 31, 38, (1e-3, 1e-7), W.coeff_sines3d),  # 76 slices: member boundary inside a group, tail of 4
 ]
+
+
+def mg_wide_levels(dim, nx, nt, batch):
+    """Levels that take the eight-slices-per-thread kernels (the launch rule
+    of the multigrid cycle: ceil(m/256) * ceil(slices/8) >= 1024)."""
+    slices = batch * 2 * ((nt - 1) // 2 + 1)
+    out = []
+    while True:
+        out.append(((nx ** dim + 255) // 256) * ((slices + 7) // 8) >= 1024)
+        if nx == 1:
+            return out
+        nx = (nx - 1) // 2
 
 
 @pytest.mark.parametrize("dim,nx,nt,gammas,coeff", MG_CASES)
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_precond_apply_multigrid(dim, nx, nt, gammas, coeff, precision):
-    print(f"precond mg {precision} dim={dim} nx={nx} nt={nt} B={len(gammas)}", flush=True)
+    wide = mg_wide_levels(dim, nx, nt, len(gammas))
+    print(f"precond mg {precision} dim={dim} nx={nx} nt={nt} B={len(gammas)} eight-slice levels {wide}", flush=True)
     side = "flexible" if precision == "mixed" else "right"
     s = Solver(dim, nx, nt, list(gammas), coeff=coeff, spatial="mg", precision=precision, side=side, device=DEV)
     v = W.random_vector(dim, nx, nt, seed=17, batch=len(gammas))
     w = s.precond_apply(to_dev(v)).cpu().numpy()
-    for b, pb in enumerate(problems(dim, nx, nt, gammas, coeff=coeff)):
-        wo = P.EpsCirculantRBD(pb, spatial="mg", coeff=coeff).apply(v[b].ravel())
-        err = rel(w[b], wo)
-        print(f"  member {b}: rel err {err:.2e}")
-        assert err < (1e-11 if precision == "fp64" else 1e-5)
+    wo = np.stack([P.EpsCirculantRBD(pb, spatial="mg", coeff=coeff).apply(v[b].ravel())
+                   for b, pb in enumerate(problems(dim, nx, nt, gammas, coeff=coeff))])
+    check(w, wo, 1e-11 if precision == "fp64" else 1e-5, len(gammas), nt - 1, nx ** dim, label="mg apply")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -352,6 +371,100 @@ def test_fixed_k_iterates_match_oracle(side):
         assert infos[0].iters == k
         assert rel(x.cpu().numpy(), res.x) < 1e-10
         np.testing.assert_allclose(hist[0, : k + 1], res.history[: k + 1], rtol=1e-8)
+
+
+@pytest.mark.parametrize("side", ["right", "left", "flexible"])
+def test_long_iterates_across_restart_match_oracle(side):
+    """k = 8, 20, 30 and 35 Arnoldi steps of GMRES(30) (35 crosses the
+    restart) on a slowly converging problem (eps near 1 and a short horizon,
+    so the preconditioned spectrum spreads and the residual is still about
+    1e-6 at step 35): every basis size up to 31 and the restarted cycle are
+    compared with the oracle's iterate and residual history."""
+    dim, nx, nt, gamma, eps, T = 2, 15, 24, 1e-3, 0.99, 0.005
+    g, f, y0 = W.random_fields(dim, nx, nt, seed=21)
+    pb = D.make_problem(dim, nx, nt, gamma, eps=eps, T=T)
+    A = D.kkt_scaled(pb)
+    bo = D.rhs_scaled(pb, g, f, y0)
+    pc = P.EpsCirculantRBD(pb)
+    for k in (8, 20, 30, 35):
+        s = Solver(dim, nx, nt, gamma, T=T, eps=eps, side=side, restart=30, maxit=k, rtol=1e-30, device=DEV)
+        b = s.rhs(to_dev(g[None]), to_dev(f[None]), to_dev(y0[None]))
+        x, infos, hist = s.solve(b, history=True)
+        res = KR.gmres(lambda v: A @ v, bo, pc.apply, side=side, restart=30, maxit=k, rtol=1e-30)
+        assert infos[0].iters == k == res.iters
+        err = rel(x.cpu().numpy(), res.x)
+        hd = np.abs(hist[0, : k + 1] - np.asarray(res.history[: k + 1]))
+        print(f"  {side} k={k}: x rel err {err:.2e}, residual {res.history[k]:.2e}, "
+              f"history max rel diff {np.max(hd / np.asarray(res.history[: k + 1])):.2e}", flush=True)
+        assert err < 1e-10
+        # the estimates are |g_{k+1}| / beta0 with g rotated from beta0 e_1, so
+        # their rounding is absolute (a few hundred ulps of 1), not relative
+        np.testing.assert_allclose(hist[0, : k + 1], res.history[: k + 1], rtol=1e-8, atol=1e-13)
+
+
+MIXED_SOLVE_CASES = [
+    # dim, nx, nt, gamma: FP32 preconditioner in FP64 flexible GMRES at 1e-8
+    (2, 31, 32, 1e-2),
+    (2, 31, 32, 1e-4),
+    (2, 31, 32, 1e-6),
+    (2, 31, 32, 1e-10),
+    (2, 63, 64, 1e-6),
+    (2, 15, 128, 1e-2),   # n = 127: chirp-z time transform in FP32
+]
+
+
+@pytest.mark.parametrize("dim,nx,nt,gamma", MIXED_SOLVE_CASES)
+def test_mixed_solve_matches_fp64_oracle(dim, nx, nt, gamma):
+    """The mixed path (complex-FP32 P_eps^{-1}; matvec, Arnoldi and residuals
+    in FP64) stopped at the true relative residual 1e-8 against the oracle's
+    all-FP64 flexible GMRES stopped at the same residual: relative error at
+    most 1e-7.  The error against the exact solution x* = A^{-1} b is printed
+    for each result."""
+    g, f, y0 = W.random_fields(dim, nx, nt, seed=101)
+    pb = D.make_problem(dim, nx, nt, gamma)
+    A = D.kkt_scaled(pb)
+    bo = D.rhs_scaled(pb, g, f, y0)
+    res = KR.gmres(lambda v: A @ v, bo, P.EpsCirculantRBD(pb).apply, side="flexible", rtol=1e-8, restart=30,
+                   maxit=300)
+    assert res.converged
+    s = Solver(dim, nx, nt, gamma, precision="mixed", side="flexible", rtol=1e-8, device=DEV)
+    x, infos, _ = s.solve(s.rhs(to_dev(g[None]), to_dev(f[None]), to_dev(y0[None])))
+    assert infos[0].converged and infos[0].relres_true <= 1e-8 * 1.0001, infos[0]
+    xg = x.cpu().numpy().ravel()
+    e_orc = rel(xg, res.x)
+    msg = (f"  mixed dim={dim} nx={nx} nt={nt} gamma={gamma:g}: iters gpu {infos[0].iters} oracle {res.iters}; "
+           f"rel err vs FP64 oracle iterate {e_orc:.2e}")
+    if A.shape[0] <= 100000:  # a sparse direct solve of the whole system stays quick
+        xstar = spla.spsolve(A.tocsc(), bo)
+        msg += f", vs x* {rel(xg, xstar):.2e} (oracle iterate vs x* {rel(res.x, xstar):.2e})"
+    print(msg, flush=True)
+    assert e_orc <= 1e-7
+
+
+def test_resume_from_nonzero_initial_guess():
+    """GMRES(5) stopped after 5 steps and called again from the returned x
+    continues exactly as one 10-step call (the second call starts the second
+    restart cycle from the same residual)."""
+    dim, nx, nt, gamma = 2, 15, 24, 1e-3
+    g, f, y0 = W.random_fields(dim, nx, nt, seed=21)
+    kw = dict(T=0.005, eps=0.99, restart=5, rtol=1e-30, device=DEV)
+    s10 = Solver(dim, nx, nt, gamma, maxit=10, **kw)
+    b = s10.rhs(to_dev(g[None]), to_dev(f[None]), to_dev(y0[None]))
+    x10, i10, _ = s10.solve(b)
+    s5 = Solver(dim, nx, nt, gamma, maxit=5, **kw)
+    x5, i5, _ = s5.solve(b)
+    xr, ir, _ = s5.solve(b, x0=x5)
+    assert i10[0].iters == 10 and i5[0].iters == 5 and ir[0].iters == 5
+    err = rel(xr.cpu().numpy(), x10.cpu().numpy())
+    print(f"  resumed vs uninterrupted: {err:.2e}; true residuals {ir[0].relres_true:.3e} {i10[0].relres_true:.3e}")
+    assert err < 1e-12
+    assert abs(ir[0].relres_true - i10[0].relres_true) <= 1e-8 * i10[0].relres_true + 1e-15
+    # and the oracle's restarted GMRES(5) from the same initial guess
+    pb = D.make_problem(dim, nx, nt, gamma, eps=0.99, T=0.005)
+    A = D.kkt_scaled(pb)
+    res = KR.gmres(lambda v: A @ v, b.cpu().numpy().ravel(), P.EpsCirculantRBD(pb).apply, side="right",
+                   x0=x5.cpu().numpy().ravel(), restart=5, maxit=5, rtol=1e-30)
+    assert rel(xr.cpu().numpy(), res.x) < 1e-10
 
 
 @pytest.mark.parametrize("side", ["right", "flexible"])
