@@ -230,6 +230,26 @@ pcop_status pcop_kkt_apply(pcop_ctx ctx, const double* x, double* y, int transpo
  * v, w: device vectors; they may alias. */
 pcop_status pcop_precond_apply(pcop_ctx ctx, const double* v, double* w);
 
+/* w = P_eps^{-1} v exactly as pcop_precond_apply (same kernels, same
+ * results), for callers that cannot allocate device memory at call time or
+ * hand the library scratch per call: code under HIP graph capture, tight
+ * serving loops.  The spectrum scratch is not the context's workspace but a
+ * file-scope device array of the library, one per device, held until the
+ * process ends; the call itself allocates nothing and does no per-kernel
+ * timing.
+ *   Limit: the spectrum, 2 (n/2 + 1) m complex values per member (16 bytes
+ *   each in FP64, 8 with PCOP_MIXED), must fit 64 MiB; larger contexts get
+ *   PCOP_ERR_UNSUPPORTED, as do contexts with PCOP_MG or
+ *   PCOP_PRECOND_IDEAL.  The current device must be the one current at
+ *   pcop_setup (PCOP_ERR_INVALID_ARG otherwise).
+ *   Sharing: every call on a device uses that device's one array (the
+ *   forward time pass writes all of it before it is read, so nothing needs
+ *   clearing); calls that overlap in time on one device -- from different
+ *   streams, contexts or threads -- race and must be serialised by the
+ *   caller.
+ * v, w: device vectors as in pcop_precond_apply; they may alias. */
+pcop_status pcop_precond_apply_noalloc(pcop_ctx ctx, const double* v, double* w);
+
 /* Solve A x = b (transpose = 0) or A^T x = b (transpose = 1) with
  * preconditioned GMRES.  x: device vector, initial guess on entry, solution
  * on exit.  b and x must be 16-byte aligned (PCOP_ERR_INVALID_ARG otherwise).  info: host array [batch] (may be NULL).  res_hist: host array

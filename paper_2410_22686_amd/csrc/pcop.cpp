@@ -24,9 +24,37 @@
 
 using namespace pcop;
 
+// Spectrum scratch of pcop_precond_apply_noalloc: one copy per device, held
+// from the library's first use on that device until the process ends.  In
+// host code `scratch` is only a stand-in for the symbol: its device address
+// is taken per device with hipGetSymbolAddress (in pcop_setup) and only that
+// address is ever handed to kernels.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
 
 thread_local std::string g_last_error;
+
+// device -> address of that device's copy of `scratch` (filled once per
+// device, with the device current)
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;
+
+hipError_t static_scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_addr[dev] = p;
+  *out = p;
+  return hipSuccess;
+}
 
 pcop_status fail(pcop_status s, const std::string& msg) {
   g_last_error = msg;
@@ -322,6 +350,8 @@ struct pcop_ctx_s {
   // the best block count depends on how many vectors a kernel streams
   std::array<int, kMaxBasis> nb_mdot{}, nb_upd{}, pairs_upd{};
   EventTimer timer;
+  int device = 0;                  // the device current at pcop_setup
+  void* static_scratch = nullptr;  // this device's copy of `scratch`
   KTimer ktimer{&EventTimer::on_begin, &EventTimer::on_end, nullptr};
   // pinned host staging for every scalar transfer of the solver
   double* pin = nullptr;
@@ -362,8 +392,8 @@ namespace {
 
 // the configured preconditioner with tables tb (epsilon-circulant or ideal)
 bool run_precond(pcop_ctx c, const Geo& g, const PrecondTables& tb, const double* v, double* w,
-                 const double* vscale, int vs_stride, int accum) {
-  void* spec = c->at<void>(c->L.spec);
+                 const double* vscale, int vs_stride, int accum, void* spec_override = nullptr) {
+  void* spec = spec_override ? spec_override : c->at<void>(c->L.spec);
   if (c->opt.precond == PCOP_PRECOND_IDEAL)
     return launch_ideal_precond(g, v, w, spec, c->fp32, c->opt.spatial, tb, c->at<double>(c->L.unit), vscale,
                                 vs_stride, accum, c->st);
@@ -1059,6 +1089,12 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
       return fail(PCOP_ERR_DEVICE, "cannot query the number of compute units");
     }
     tb.ncu = ncu;
+    c->device = dev;
+    const hipError_t se = static_scratch_address(dev, &c->static_scratch);
+    if (se != hipSuccess) {
+      delete c;
+      return fail(PCOP_ERR_DEVICE, std::string("static scratch address: ") + hipGetErrorString(se));
+    }
   }
   tb.mg_levels = L.mg_levels;
   for (int l = 0; l < L.mg_levels; ++l) {
@@ -1227,6 +1263,34 @@ pcop_status pcop_precond_apply(pcop_ctx c, const double* v, double* w) {
   const Geo gu = c->user_geo();
   pcop_status s = do_precond(c, v, w, nullptr, 0, 0, nullptr, c->g.B, &gu);
   if (s != PCOP_OK) return s;
+  PCOP_HIP(hipGetLastError());
+  return PCOP_OK;
+}
+
+pcop_status pcop_precond_apply_noalloc(pcop_ctx c, const double* v, double* w) {
+  if (!c || !v || !w) return fail(PCOP_ERR_INVALID_ARG, "null argument");
+  if (c->opt.precond != PCOP_PRECOND_EPS || c->opt.spatial != PCOP_DST)
+    return fail(PCOP_ERR_UNSUPPORTED,
+                "pcop_precond_apply_noalloc needs the epsilon-circulant preconditioner with sine transforms");
+  const Geo gu = c->user_geo();
+  const size_t need = (c->fp32 ? 8 : 16) * (size_t)gu.B * 2 * gu.K * (size_t)gu.m;
+  if (need > kStaticScratchBytes)
+    return fail(PCOP_ERR_UNSUPPORTED, "pcop_precond_apply_noalloc: the spectrum needs " + std::to_string(need) +
+                                          " bytes, more than the " + std::to_string(kStaticScratchBytes) +
+                                          "-byte static scratch");
+  if (!c->static_scratch) return fail(PCOP_ERR_DEVICE, "static scratch address unavailable");
+  int dev = 0;
+  PCOP_HIP(hipGetDevice(&dev));
+  if (dev != c->device) return fail(PCOP_ERR_INVALID_ARG, "the current device is not the context's device");
+  // the forward time pass writes every spectrum value before any is read,
+  // so the scratch needs no clearing; no per-kernel timing (its events
+  // would be created on demand)
+  PrecondTables tb = c->tb;
+  tb.active = nullptr;
+  tb.nact = gu.B;
+  tb.timer = nullptr;
+  if (!run_precond(c, gu, tb, v, w, nullptr, 0, 0, c->static_scratch))
+    return fail(PCOP_ERR_UNSUPPORTED, "preconditioner variant not available for this shape");
   PCOP_HIP(hipGetLastError());
   return PCOP_OK;
 }

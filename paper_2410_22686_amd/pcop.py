@@ -32,6 +32,7 @@ EXPORTED = [
     "pcop_kkt_apply", "pcop_precond_apply", "pcop_solve", "pcop_unpack", "pcop_pack_cotangent",
     "pcop_data_grad", "pcop_get_params", "pcop_destroy", "pcop_status_string", "pcop_last_error",
     "pcop_timing_enable", "pcop_timing_read", "pcop_get_kernels", "pcop_post_solve", "pcop_error_eh",
+    "pcop_precond_apply_noalloc",
 ]
 
 
@@ -96,6 +97,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "pcop_rhs": (ip, [vp, vp, vp, vp, vp]),
         "pcop_kkt_apply": (ip, [vp, vp, vp, ip]),
         "pcop_precond_apply": (ip, [vp, vp, vp]),
+        "pcop_precond_apply_noalloc": (ip, [vp, vp, vp]),
         "pcop_solve": (ip, [vp, vp, vp, ip, ctypes.POINTER(c_member_info), dp]),
         "pcop_unpack": (ip, [vp, vp, vp, vp]),
         "pcop_pack_cotangent": (ip, [vp, vp, vp, vp]),
@@ -334,6 +336,14 @@ class Solver:
         w = self.new_vector() if out is None else self._vec(out, "out")
         _check(self._call(self.lib.pcop_precond_apply, self.ctx, _ptr(v), _ptr(w)))
         return w
+
+    def precond_apply_noalloc(self, v: torch.Tensor, out: torch.Tensor):
+        """pcop_precond_apply_noalloc: the same apply with the library's static
+        spectrum scratch; the output tensor is the caller's."""
+        self._vec(v, "v")
+        self._vec(out, "out")
+        _check(self._call(self.lib.pcop_precond_apply_noalloc, self.ctx, _ptr(v), _ptr(out)))
+        return out
 
     def solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, transpose: bool = False,
               history: bool = False, raise_on_fail: bool = False):
