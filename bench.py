@@ -52,7 +52,8 @@ PRECOND_FAMILIES = ("time_fwd", "dst_rows", "dst_ax2", "dst_last_solve", "time_i
 # kernel sources behind each timed family (to tell whether recorded counters
 # still describe the code that runs)
 _TIME_SOURCES = ["precond.hip", "time_common.hpp", "time_sk.hip", "time_ip.hpp", "time_ip_fwd_f64.hip",
-                 "time_ip_inv_f64.hip", "time_ip_fwd_f32.hip", "time_ip_inv_f32.hip", "time_bl.hip", "fft_lds.hpp"]
+                 "time_ip_inv_f64.hip", "time_ip_fwd_f32.hip", "time_ip_inv_f32.hip", "time_bl.hip", "time_cz.hip",
+                 "fft_lds.hpp", "fft_reg.hpp"]
 FAMILY_SOURCES = {
     "gs_update": ["krylov.hip"], "mdot": ["krylov.hip"], "combine": ["krylov.hip"],
     "kkt_apply": ["kkt.hip", "stencil.hpp", "fem.hip", "fem.hpp"], "time_fwd": _TIME_SOURCES, "time_inv": _TIME_SOURCES,

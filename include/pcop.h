@@ -127,10 +127,14 @@ typedef struct {
  *              with at most that many points per block; 4 / 8 / 16 in-place
  *              Stockham (one LDS buffer) with at most that many points per
  *              block.  A kind of kernel that does not fit LDS falls back to
- *              the other.  When nt - 1 has a prime factor above 17, or no
- *              Stockham tile of it fits LDS (long smooth lengths, e.g.
- *              FP64 n = 1152 or 2048), the chirp-z kernels run instead: 0 / -1 automatic, 4 / 8 / 16 at
- *              most that many points per block with 256 threads, -4 / -8 /
+ *              the other; +-32 as +-16 with up to 32 points.  When nt - 1
+ *              has a prime factor above 17, or no Stockham tile of it fits
+ *              LDS (long smooth lengths, e.g. FP64 n = 1152 or 2048), the
+ *              chirp-z kernels run instead: 0 / -1 automatic (the
+ *              three-stage kernels where they exist, convolution lengths up
+ *              to 1024, i.e. n <= 512); 32 / -32 the three-stage kernels
+ *              with 256 / 512 threads; 4 / 8 / 16 the two-FFT kernels with at
+ *              most that many points per block and 256 threads, -4 / -8 /
  *              -16 with 512 threads (a request that fits no kernel falls back
  *              to the automatic choice).
  *   dst_kernel sine-transform kernels of step 2 (PCOP_DST): 0 automatic,
@@ -207,9 +211,15 @@ pcop_status pcop_workspace_size(const pcop_problem* prob, const pcop_options* op
 
 /* Create a context.  workspace: caller-owned device memory of at least
  * pcop_workspace_size bytes, 256-byte aligned, that stays valid and unused
- * by the caller until pcop_destroy.  Host tables (D_eps, lambda_k, DST
- * eigenvalues, twiddles, per-member alpha) are computed in FP64 and copied
- * into the workspace on the stream. */
+ * by the caller until pcop_destroy.  Host tables are computed in FP64 (long
+ * double where the host has it, rounded once) and copied into the workspace
+ * on the stream: the factors of eq. decomposition_eps -- D_eps =
+ * diag(eps^{(j-1)/n}) and the eigenvalues lambda_k = 1 - eps^{1/n}
+ * theta^{-k} of C_{eps,n} -- the sine-mode eigenvalues of K (Section 3,
+ * Example 1), the time and sine-transform twiddles, the chirp-z tables,
+ * per-member alpha = tau / sqrt(gamma) (eq. matrix_A), and for PCOP_MG the
+ * re-discretised tau K_a of every multigrid level.  With tune = 1 the kernel
+ * candidates are timed here (see pcop_options). */
 pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_options* opts,
                        void* workspace, size_t bytes);
 
@@ -250,8 +260,13 @@ pcop_status pcop_precond_apply(pcop_ctx ctx, const double* v, double* w);
  * v, w: device vectors as in pcop_precond_apply; they may alias. */
 pcop_status pcop_precond_apply_noalloc(pcop_ctx ctx, const double* v, double* w);
 
-/* Solve A x = b (transpose = 0) or A^T x = b (transpose = 1) with
- * preconditioned GMRES.  x: device vector, initial guess on entry, solution
+/* Solve A x = b (transpose = 0) or A^T x = b (transpose = 1) with GMRES
+ * preconditioned by P_eps (eq. preconditioned_system: the preconditioned
+ * system P_eps^{-1} A x = P_eps^{-1} b for PCOP_LEFT, as in Section 3's
+ * experiments with zero initial guess and relative tolerance; A P_eps^{-1}
+ * for PCOP_RIGHT and PCOP_FLEXIBLE), or by P of eq. matrix_P with
+ * PCOP_PRECOND_IDEAL.  A^T = J A J with J = diag(I, -I), so the transposed
+ * solve runs the same iteration on J b and returns J times its solution.  x: device vector, initial guess on entry, solution
  * on exit.  b and x must be 16-byte aligned (PCOP_ERR_INVALID_ARG otherwise).  info: host array [batch] (may be NULL).  res_hist: host array
  * [batch][maxit + 1] of monitored relative residuals (may be NULL; entries
  * after a member's last step are left untouched).  Returns

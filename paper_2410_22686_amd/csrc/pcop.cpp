@@ -118,8 +118,8 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
   if (o->graph && o->graph_chunk < 1) return fail(PCOP_ERR_INVALID_ARG, "graph_chunk must be >= 1");
   {
     const int tc = o->time_cols < 0 ? -o->time_cols : o->time_cols;
-    if (tc != 0 && tc != 1 && tc != 4 && tc != 8 && tc != 16)
-      return fail(PCOP_ERR_INVALID_ARG, "time_cols must be 0, -1, +-4, +-8 or +-16");
+    if (tc != 0 && tc != 1 && tc != 4 && tc != 8 && tc != 16 && tc != 32)
+      return fail(PCOP_ERR_INVALID_ARG, "time_cols must be 0, -1, +-4, +-8, +-16 or +-32");
   }
   if (o->dst_kernel < 0 || o->dst_kernel > 4) return fail(PCOP_ERR_INVALID_ARG, "dst_kernel must be in 0..4");
   if (o->tune != 0 && o->tune != 1) return fail(PCOP_ERR_INVALID_ARG, "tune must be 0 or 1");
@@ -470,7 +470,7 @@ struct TuneResult {
 // new one, so separate processes (a benchmark and a profiler run) run the
 // same kernels.  Lines of another version, malformed lines and entries that
 // do not fit the context are ignored (the shape is then tuned afresh).
-constexpr int kTuneVersion = 1;  // bump when the meaning of a kernel choice changes
+constexpr int kTuneVersion = 2;  // bump when the meaning of a kernel choice changes
 using TuneKey = std::pair<std::string, std::array<int, 14>>;
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneResult> g_tune_cache;
@@ -536,7 +536,7 @@ bool tune_entry_fits(pcop_ctx c, const TuneResult& r) {
   }
   if (c->opt.precond == PCOP_PRECOND_EPS) {
     const int tc = r.time_cols < 0 ? -r.time_cols : r.time_cols;
-    if (tc != 0 && tc != 1 && tc != 4 && tc != 8 && tc != 16) return false;
+    if (tc != 0 && tc != 1 && tc != 4 && tc != 8 && tc != 16 && tc != 32) return false;
     PrecondTables t = c->tb;
     t.time_cols = r.time_cols;
     if (time_choice(c->g, t, c->fp32) == 0) return false;
@@ -578,9 +578,10 @@ pcop_status tune_kernels(pcop_ctx c) {
     tcs.push_back(c->tb.time_cols);
   } else {
     std::vector<int> seen;
-    // chirp-z: the automatic tile first, then every width with 256 and 512
-    // threads; Stockham: two buffers and in place with 16, 8, 4 points
-    const std::vector<int> wants = c->tb.plan.bluestein ? std::vector<int>{0, 16, 8, 4, -16, -8, -4}
+    // chirp-z: the automatic choice first, then the three-stage kernels with
+    // 256 and 512 threads and the two-FFT kernels with every width; Stockham:
+    // two buffers and in place with 16, 8, 4 points
+    const std::vector<int> wants = c->tb.plan.bluestein ? std::vector<int>{0, 32, -32, 16, 8, 4, -16, -8, -4}
                                                         : std::vector<int>{-8, -16, -4, 16, 8, 4};
     for (int want : wants) {
       PrecondTables t = c->tb;

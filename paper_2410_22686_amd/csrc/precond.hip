@@ -14,6 +14,8 @@
 // (eq. decomposition_eps; C_eps^T = D F conj(Lambda) F^* D^{-1}).  The
 // spectrum buffer is laid out [batch][2K][m], slice q = 2k + s with s = 0
 // for V2 and s = 1 for V1, K = n/2 + 1.
+#include <algorithm>
+
 #include "common.hpp"
 #include "fft_lds.hpp"
 #include "launch.hpp"
@@ -23,7 +25,8 @@ namespace pcop {
 
 // ---------------------------------------------------------------------------
 // launchers; the time-pass kernels are in time_sk.hip (two LDS buffers),
-// time_ip_*.hip (one in-place buffer) and time_bl.hip (chirp-z)
+// time_ip_*.hip (one in-place buffer), time_cz.hip (chirp-z in three LDS
+// stages) and time_bl.hip (chirp-z with two LDS FFTs)
 // ---------------------------------------------------------------------------
 // points per block of the two-buffer time kernels: the largest power of two
 // in 4..want whose two [n][P] buffers fit 64 KiB and whose whole LDS (with
@@ -60,6 +63,8 @@ static int time_cols_ip(const FftPlan& pl, int n, int csz, int want) {
 // Automatic (0) and two-buffer requests fall back to in place when the two
 // buffers do not fit, and in-place requests fall back to two buffers.
 static int time_block(const FftPlan& pl, int n, int csz, int req) {
+  // the Stockham kernels exist for 4, 8 and 16 points: +-32 asks for +-16
+  req = std::max(-16, std::min(16, req));
   if (req <= 0) {
     // an explicit -16 admits the wide kernels
     const int P = time_cols_sk(n, csz, req < -1 ? -req : 16, req == -16);
@@ -132,6 +137,7 @@ static bool time_pass(bool fwd, const Geo& g, const double* v, cx<T>* spec, doub
   const int csz = (int)sizeof(cx<T>);
   if (tb.plan.bluestein) {
     const int c = bl_choice(tb.plan.M, g.n, csz, tb.time_cols);
+    if (c == 32 || c == -32) return launch_time_cz<T>(fwd, c, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st);
     return c != 0 && launch_time_bl<T>(fwd, c, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st);
   }
   const cx<T>* twn = reinterpret_cast<const cx<T>*>(tt.twn);

@@ -296,6 +296,10 @@ static bool bl_exists(int M, int csz, int c) {
 }
 
 int bl_choice(int M, int n, int csz, int req) {
+  if (req == 32 || req == -32) {
+    if (cz_exists(M, csz, req)) return req;
+    req = 0;
+  }
   if (req > 0 || req < -1) {
     // at most |req| points, with the requested thread count
     for (int P = req > 0 ? req : -req; P >= 1; P /= 2) {
@@ -303,8 +307,11 @@ int bl_choice(int M, int n, int csz, int req) {
       if (bl_exists(M, csz, c)) return c;
     }
   }
-  // automatic: 256 threads and the widest tile that keeps two blocks per CU,
-  // else the widest that fits at all
+  // automatic: the three-stage kernels (256 threads, else 512), else the
+  // two-FFT kernels with 256 threads and the widest tile that keeps two
+  // blocks per CU, else the widest that fits at all
+  if (cz_exists(M, csz, 32)) return 32;
+  if (cz_exists(M, csz, -32)) return -32;
   for (int P = 16; P >= 1; P /= 2)
     if (bl_exists(M, csz, P) && bl_lds_bytes(M, P, n, csz) <= kLdsMax / 2) return P;
   for (int P = 16; P >= 1; P /= 2)

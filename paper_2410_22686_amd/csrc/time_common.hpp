@@ -95,10 +95,18 @@ void launch_time_ip_dir(int P, const Geo& g, const double* v, cx<T>* spec, doubl
 template <class T>
 bool launch_time_bl(bool fwd, int c, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
                     const TimeTables& tt, const double* vscale, int vs_stride, int accum, hipStream_t st);
-// chirp-z kernels for the request req (pcop_options::time_cols): +P for P
-// points per block with 256 threads, -P with 512 threads, 0 when no shape
-// fits.  0 and -1 pick automatically; an explicit request is honoured with
-// at most that many points, else the automatic choice is used.
+// chirp-z with the convolution in three LDS stages (time_cz.hip), for
+// M <= 1024: c = 32 (256 threads) or -32 (512 threads)
+template <class T>
+bool launch_time_cz(bool fwd, int c, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
+                    const TimeTables& tt, const double* vscale, int vs_stride, int accum, hipStream_t st);
+bool cz_exists(int M, int csz, int c);
+// chirp-z kernels for the request req (pcop_options::time_cols): +-32 the
+// three-stage kernels with 256 / 512 threads; +P for P points per block of
+// the two-FFT kernels with 256 threads, -P with 512 threads; 0 when no shape
+// fits.  0 and -1 pick automatically (the three-stage kernels where they
+// exist); an explicit request is honoured with at most that many points,
+// else the automatic choice is used.
 int bl_choice(int M, int n, int csz, int req);
 
 // Chirp-z tile shapes (M = convolution length, P points per block, NT

@@ -232,8 +232,9 @@ def test_long_smooth_lengths_use_chirp(nt, precision):
 @pytest.mark.parametrize("dim,nx,nt,gammas", CHIRP_CASES)
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_chirp_kernel_choices(dim, nx, nt, gammas, precision):
-    """Every chirp-z tile shape (points per block with 256 or 512 threads)
-    matches the oracle, and the shapes agree with each other to rounding (same
+    """Every chirp-z kernel -- the three-stage convolution (+-32: 256 or 512
+    threads) and the two-FFT kernels (points per block with 256 or 512
+    threads) -- matches the oracle, and the shapes agree with each other to rounding (same
     operations per element; FMA contraction may differ between instances, and
     the two length-M FFTs of the convolution add about log2 M roundings of
     the largest spectral values, hence 1e-13 in FP64).  In FP32 the two FFTs
@@ -249,10 +250,10 @@ def test_chirp_kernel_choices(dim, nx, nt, gammas, precision):
     tol32 = max(1e-5, 2 * 6e-8 * np.log2(M) * np.sqrt(n))
     tol = tol32 if precision == "mixed" else 1e-11
     ref, seen = None, set()
-    for tc in (0, 16, 8, 4, -16, -8, -4):
+    for tc in (0, 32, -32, 16, 8, 4, -16, -8, -4):
         s = Solver(dim, nx, nt, list(gammas), precision=precision, side=side, time_cols=tc, device=DEV)
         eff = s.kernels["time_cols"]
-        assert eff in (16, 8, 4, 2, 1, -16, -8, -4), eff
+        assert eff in (32, -32, 16, 8, 4, 2, 1, -16, -8, -4), eff
         if tc != 0 and (eff < 0) == (tc < 0):
             assert abs(eff) <= abs(tc)
         if eff in seen:
