@@ -310,8 +310,7 @@ int bl_choice(int M, int n, int csz, int req) {
   // automatic: the three-stage kernels (256 threads, else 512), else the
   // two-FFT kernels with 256 threads and the widest tile that keeps two
   // blocks per CU, else the widest that fits at all
-  if (cz_exists(M, csz, 32)) return 32;
-  if (cz_exists(M, csz, -32)) return -32;
+  if (const int c = cz_auto(M, csz)) return c;
   for (int P = 16; P >= 1; P /= 2)
     if (bl_exists(M, csz, P) && bl_lds_bytes(M, P, n, csz) <= kLdsMax / 2) return P;
   for (int P = 16; P >= 1; P /= 2)
