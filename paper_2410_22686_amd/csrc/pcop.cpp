@@ -86,7 +86,12 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
       return fail(PCOP_ERR_INVALID_ARG, "gamma must be finite and > 0");
   if (!std::isfinite(p->eps) || p->eps > 1.0)
     return fail(PCOP_ERR_INVALID_ARG, "eps must lie in (0, 1] (or <= 0 for sqrt(tau))");
-  const long long m = (long long)std::pow((double)p->nx, p->dim) + 0.5;
+  // sizes first, in floating point, so that no integer arithmetic below
+  // (here, in the workspace layout or in the kernel plans) can overflow
+  const double md = std::pow((double)p->nx, p->dim);
+  if (p->nx > (1 << 20) || md > (double)((1LL << 31) / 8)) return fail(PCOP_ERR_UNSUPPORTED, "spatial grid too large");
+  if (p->nt > (1 << 24) || 2.0 * (p->nt - 1) * md > (double)(1LL << 40))
+    return fail(PCOP_ERR_UNSUPPORTED, "problem too large");
   if (p->coeff_kind == PCOP_COEFF_ONE) {
     if (p->coeff) return fail(PCOP_ERR_INVALID_ARG, "coeff must be null for PCOP_COEFF_ONE");
   } else if (p->coeff_kind == PCOP_COEFF_HALFGRID) {
@@ -145,8 +150,6 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
   const int n = p->nt - 1;
   if (o->precond == PCOP_PRECOND_EPS && !time_lds_fits(n, o->precision == PCOP_MIXED))
     return fail(PCOP_ERR_UNSUPPORTED, "nt too large for the LDS time FFT");
-  if (m > (1LL << 31) / 8) return fail(PCOP_ERR_UNSUPPORTED, "spatial grid too large");
-  if ((long long)n * m * 2 > (1LL << 40)) return fail(PCOP_ERR_UNSUPPORTED, "problem too large");
   return PCOP_OK;
 }
 
@@ -1333,7 +1336,10 @@ pcop_status pcop_data_grad(pcop_ctx c, const double* lam, double* dg, double* df
 }
 
 const char* pcop_status_string(pcop_status s) {
-  switch (s) {
+  // a C caller may pass any int: read the bits as one, not as the enum
+  int v = 0;
+  std::memcpy(&v, &s, sizeof(v));
+  switch (v) {
     case PCOP_OK: return "ok";
     case PCOP_ERR_INVALID_ARG: return "invalid argument";
     case PCOP_ERR_UNSUPPORTED: return "unsupported";
