@@ -114,8 +114,9 @@ def parse():
                     help="time the candidate kernels at setup and keep the fastest (or take the cached choice)")
     ap.add_argument("--tune-cache", default=None,
                     help="tuner cache file (default: $PCOP_TUNE_CACHE, else the committed cache); '' for none")
-    ap.add_argument("--time-cols", type=int, default=0, choices=[0, -1, -4, -8, -16, 4, 8, 16],
-                    help="time-pass kernels: 0 automatic, -P two LDS buffers, +P in place (P points per block)")
+    ap.add_argument("--time-cols", type=int, default=0, choices=[0, -1, -4, -8, -16, -32, 4, 8, 16, 32],
+                    help="time-pass kernels: 0 automatic, -P two LDS buffers, +P in place (P points per block); "
+                         "+32 / -32 chirp-z whole-group / lane-pair kernels")
     ap.add_argument("--dst-kernel", type=int, default=0, choices=[0, 1, 2, 3, 4],
                     help="sine-transform kernels: 0 automatic, 1 register, 2 LDS-staged, 3 register with wide column "
                          "tiles, 4 half-length strided transforms")
