@@ -117,7 +117,7 @@ def parse():
     ap.add_argument("--time-cols", type=int, default=0, choices=[0, -1, -4, -8, -16, -32, 4, 8, 16, 32],
                     help="time-pass kernels: 0 automatic, -P two LDS buffers, +P in place (P points per block); "
                          "+32 / -32 chirp-z whole-group / lane-pair kernels")
-    ap.add_argument("--dst-kernel", type=int, default=0, choices=[0, 1, 2, 3, 4],
+    ap.add_argument("--dst-kernel", type=int, default=0, choices=[0, 1, 2, 3, 4, 5],
                     help="sine-transform kernels: 0 automatic, 1 register, 2 LDS-staged, 3 register with wide column "
                          "tiles, 4 half-length strided transforms")
     ap.add_argument("--kkt-jchunk", type=int, default=0, help="KKT matvec kernel: > 0 levels per thread, < 0 LDS tiles of that many levels (0 automatic)")

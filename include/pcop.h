@@ -141,7 +141,8 @@ typedef struct {
  *              1 register-resident lines, 2 lines staged through LDS,
  *              3 register-resident lines with twice as many strided lines
  *              per block (512 threads), 4 strided lines through a
- *              half-length FFT (nx + 1 points; for nx >= 7, else as 1).
+ *              half-length FFT (nx + 1 points; for nx >= 7, else as 1),
+ *              5 the half-length FFT for the contiguous lines as well.
  *   tune       1: pcop_setup times the candidates of every kernel choice
  *              left at 0 ("automatic": time_cols, dst_kernel, kkt_jchunk,
  *              krylov_blocks, gs_update) on the context's stream and keeps
@@ -325,8 +326,8 @@ pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* ep
  *                  threads) or -P (512 threads);
  *                  0 with PCOP_PRECOND_IDEAL (no time transform);
  *   dst_kernel     1 (register-resident), 2 (LDS-staged), 3 (register, wide
- *                  column tiles), 4 (half-length strided transforms) or 0
- *                  (multigrid);
+ *                  column tiles), 4 (half-length strided transforms), 5
+ *                  (half-length transforms on every axis) or 0 (multigrid);
  *   kkt_jchunk     KKT matvec kernel (as in pcop_options);
  *   krylov_blocks  blocks per member of the Krylov multi-dot over the full
  *                  basis (the tuner picks counts per basis size: shorter

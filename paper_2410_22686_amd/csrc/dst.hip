@@ -610,11 +610,107 @@ __global__ void __launch_bounds__(NT) dst_half_kernel(Geo g, cx<T>* __restrict__
   }
 }
 
+// Half-length transforms of contiguous lines (x1).  A tile is LPB whole
+// lines; its elements are loaded and stored in flattened order (element f
+// of the tile is element f mod N of line f / N), so consecutive threads
+// touch consecutive addresses when the lines follow each other (line
+// stride N), and each line's values are staged in LDS for HalfDst::pre.
+// Persistent blocks prefetch the next tile into registers.
+template <class T, int L, int NT>
+__global__ void __launch_bounds__(NT) dst_half_rows_kernel(Geo g, cx<T>* __restrict__ data, LineGeom lg,
+                                                            const cx<T>* __restrict__ twL) {
+  using H = HalfDst<T, L>;
+  constexpr int M = H::M, N = H::N, TM = H::TM;
+  constexpr int LPB = NT / TM;
+  constexpr int LD = M + M / 8 + 1;
+  constexpr int QS = (N * LPB + NT - 1) / NT;
+  static_assert(LPB * TM == NT, "a tile is a whole number of lines");
+  __shared__ cx<T> buf[LPB * LD];
+  __shared__ cx<T> twm[M];
+  __shared__ T sinl[M];
+  for (int k = threadIdx.x; k < M; k += NT) {
+    twm[k] = twL[2 * k];
+    sinl[k] = -twL[k].y;
+  }
+  __syncthreads();
+  const long long tiles = (lg.lines + LPB - 1) / LPB;
+  const long long total = tiles * lg.nplanes;
+  const int lid = threadIdx.x / TM;
+  const int t = threadIdx.x - lid * TM;
+  cx<T>* lbuf = buf + lid * LD;
+  // the (line, element) of each of this thread's tile slots
+  int sl[QS], se[QS];
+#pragma unroll
+  for (int q = 0; q < QS; ++q) {
+    const int f = threadIdx.x + NT * q;
+    sl[q] = f / N;
+    se[q] = f - sl[q] * N;
+  }
+  cx<T> pre[QS];
+  auto fetch = [&](long long blk) {
+    const long long plane = blk / tiles;
+    const int l0 = (int)(blk - plane * tiles) * LPB;
+    const cx<T>* src = data + plane * lg.plane_stride;
+    // unconditional loads from a clamped line: slots past the tile or the
+    // last line hold copies of real values, which are never stored
+#pragma unroll
+    for (int q = 0; q < QS; ++q) {
+      const int ln = min(l0 + sl[q], lg.lines - 1);
+      pre[q] = src[ln * lg.line_stride + se[q] * lg.elem_stride];
+    }
+  };
+  long long blk = xcd_remap(blockIdx.x, gridDim.x);
+  if (blk < total) fetch(blk);
+  while (blk < total) {
+    const long long plane = blk / tiles;
+    const int l0 = (int)(blk - plane * tiles) * LPB;
+#pragma unroll
+    for (int q = 0; q < QS; ++q)
+      if (threadIdx.x + NT * q < N * LPB) buf[sl[q] * LD + pidx(se[q])] = pre[q];
+    __syncthreads();
+    const long long nxt = blk + gridDim.x;
+    if (nxt < total) fetch(nxt);
+    cx<T> v[8], o[8];
+    H::pre(v, t, lbuf, sinl);
+    RegStages<T, M, TM, -1, 1>::run(v, t, lbuf, twm);
+    H::post(v, o, t, lbuf);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int pos = 8 * t + r;
+      if (pos >= 1 && pos <= N) lbuf[pidx(pos - 1)] = o[r];
+    }
+    __syncthreads();
+    cx<T>* dstp = data + plane * lg.plane_stride;
+#pragma unroll
+    for (int q = 0; q < QS; ++q)
+      if (threadIdx.x + NT * q < N * LPB && l0 + sl[q] < lg.lines)
+        dstp[(l0 + sl[q]) * lg.line_stride + se[q] * lg.elem_stride] = buf[sl[q] * LD + pidx(se[q])];
+    __syncthreads();
+    blk = nxt;
+  }
+}
+
 template <class T, int L>
 constexpr int dst_lines_per_block() {
   constexpr int bytes = (L + 1) * (int)sizeof(cx<T>);
   constexpr int fit = 49152 / bytes;
   return fit < 1 ? 1 : (fit > 64 ? 64 : fit);
+}
+
+// persistent grid of half-length strided kernels: as many blocks as stay
+// resident on every CU
+template <class T, int L, int NT>
+static void launch_half_strided(const Geo& g, cx<T>* data, const LineGeom& lg, bool divide, const cx<T>* twL,
+                                const DivideParams& dp, int ncu, hipStream_t st) {
+  constexpr int LPBH = NT / (L / 16);
+  const long long tilesh = (lg.lines + LPBH - 1) / LPBH;
+  static const int rh1 = resident_blocks(dst_half_kernel<T, L, 1, NT>, NT, 0);
+  static const int rh0 = resident_blocks(dst_half_kernel<T, L, 0, NT>, NT, 0);
+  const long long want = (long long)(divide ? rh1 : rh0) * std::max(1, ncu);
+  dim3 grid((unsigned)std::min(tilesh * lg.nplanes, want));
+  if (divide) dst_half_kernel<T, L, 1, NT><<<grid, NT, 0, st>>>(g, data, lg, twL, dp);
+  else dst_half_kernel<T, L, 0, NT><<<grid, NT, 0, st>>>(g, data, lg, twL, dp);
 }
 
 template <class T, int L>
@@ -638,6 +734,18 @@ static void dst_pass_L(const Geo& g, cx<T>* data, const LineGeom& lg, bool rows,
   // register variants: L/8 threads per line
   constexpr int LPB = 256 / (L / 8);
   const long long tiles = (lg.lines + LPB - 1) / LPB;
+  if constexpr (L >= 16) {
+    if (variant == 4 && rows && !divide) {
+      // half-length rows: M/8 threads per line, persistent 256-thread tiles
+      constexpr int LPBH = 256 / (L / 16);
+      const long long tilesh = (lg.lines + LPBH - 1) / LPBH;
+      static const int rr = resident_blocks(dst_half_rows_kernel<T, L, 256>, 256, 0);
+      const long long want = (long long)rr * std::max(1, ncu);
+      dim3 grid((unsigned)std::min(tilesh * lg.nplanes, want));
+      dst_half_rows_kernel<T, L, 256><<<grid, 256, 0, st>>>(g, data, lg, twL);
+      return;
+    }
+  }
   if (rows) {
     dim3 grid((unsigned)(tiles * lg.nplanes));
     if (divide) dst_reg_kernel<T, L, 1><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
@@ -647,16 +755,11 @@ static void dst_pass_L(const Geo& g, cx<T>* data, const LineGeom& lg, bool rows,
     // 2 doubles the lines per tile (512 threads) so that each element row of
     // a tile spans 128 bytes instead of 64
     if constexpr (L >= 16) {
-      if (variant == 3) {
+      if (variant == 3 || variant == 4) {
         // half-length transforms: M/8 threads per line, 256-thread tiles
-        constexpr int LPBH = 256 / (L / 16);
-        const long long tilesh = (lg.lines + LPBH - 1) / LPBH;
-        static const int rh1 = resident_blocks(dst_half_kernel<T, L, 1, 256>, 256, 0);
-        static const int rh0 = resident_blocks(dst_half_kernel<T, L, 0, 256>, 256, 0);
-        const long long want = (long long)(divide ? rh1 : rh0) * std::max(1, ncu);
-        dim3 grid((unsigned)std::min(tilesh * lg.nplanes, want));
-        if (divide) dst_half_kernel<T, L, 1, 256><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
-        else dst_half_kernel<T, L, 0, 256><<<grid, 256, 0, st>>>(g, data, lg, twL, dp);
+        // (512-thread tiles, whose element rows span twice the bytes, were
+        // measured slower: their registers allow one block per CU)
+        launch_half_strided<T, L, 256>(g, data, lg, divide, twL, dp, ncu, st);
         return;
       }
     }

@@ -126,7 +126,7 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
     if (tc != 0 && tc != 1 && tc != 4 && tc != 8 && tc != 16 && tc != 32)
       return fail(PCOP_ERR_INVALID_ARG, "time_cols must be 0, -1, +-4, +-8, +-16 or +-32");
   }
-  if (o->dst_kernel < 0 || o->dst_kernel > 4) return fail(PCOP_ERR_INVALID_ARG, "dst_kernel must be in 0..4");
+  if (o->dst_kernel < 0 || o->dst_kernel > 5) return fail(PCOP_ERR_INVALID_ARG, "dst_kernel must be in 0..5");
   if (o->tune != 0 && o->tune != 1) return fail(PCOP_ERR_INVALID_ARG, "tune must be 0 or 1");
   if (o->precond != PCOP_PRECOND_EPS && o->precond != PCOP_PRECOND_IDEAL)
     return fail(PCOP_ERR_INVALID_ARG, "unknown precond");
@@ -530,7 +530,7 @@ void append_tune_file(const std::string& path, const TuneKey& key, const TuneRes
 // a cached choice this context can run (the partial-sum buffer holds
 // nblk_max blocks per member; a file may hold anything)
 bool tune_entry_fits(pcop_ctx c, const TuneResult& r) {
-  if (r.dst_variant < 0 || r.dst_variant > 3) return false;
+  if (r.dst_variant < 0 || r.dst_variant > 4) return false;
   if (r.jchunk == 0 || r.jchunk < -64 || r.jchunk > 64) return false;
   for (int nv = 0; nv < kMaxBasis; ++nv) {
     if (r.nb_mdot[nv] < 1 || r.nb_mdot[nv] > c->L.nblk_max) return false;
@@ -599,7 +599,7 @@ pcop_status tune_kernels(pcop_ctx c) {
     }
   }
   std::vector<int> dvs;
-  if (c->opt.spatial == PCOP_DST && c->opt.dst_kernel == 0) dvs = {0, 1, 2, 3};
+  if (c->opt.spatial == PCOP_DST && c->opt.dst_kernel == 0) dvs = {0, 1, 2, 3, 4};
   else dvs = {c->tb.dst_variant};
   double* v = c->basis(0);
   double* w = c->basis(1);

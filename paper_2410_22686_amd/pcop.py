@@ -231,7 +231,8 @@ class Solver:
         _check(self.lib.pcop_get_kernels(ctx, ctypes.byref(kc)))
         # kernel choices in effect: time_cols -P two-buffer / +P in place (Stockham),
         # +P 256 threads / -P 512 threads (chirp-z), 0 ideal preconditioner;
-        # dst_kernel 1 register / 2 LDS-staged / 3 wide columns / 4 half-length strided / 0 multigrid
+        # dst_kernel 1 register / 2 LDS-staged / 3 wide columns / 4 half-length strided / 5 half-length on
+        # every axis / 0 multigrid
         self.kernels = {"time_cols": kc.time_cols, "dst_kernel": kc.dst_kernel, "kkt_jchunk": kc.kkt_jchunk,
                         "krylov_blocks": kc.krylov_blocks, "gs_update": kc.gs_update, "tuned_ms": kc.tuned_precond_ms}
 

@@ -57,7 +57,7 @@ static void random_options(pcop_options* o) {
   if (pick(4) == 0) o->graph = pick(3);
   if (pick(4) == 0) o->graph_chunk = pick(6) - 1;
   if (pick(3) == 0) o->time_cols = pick(70) - 35;
-  if (pick(4) == 0) o->dst_kernel = pick(7) - 1;
+  if (pick(4) == 0) o->dst_kernel = pick(8) - 1;
   if (pick(6) == 0) o->tune = pick(3);
   if (pick(4) == 0) o->precond = pick(4) - 1;
   if (pick(4) == 0) o->kkt_jchunk = pick(140) - 70;

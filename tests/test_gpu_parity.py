@@ -154,7 +154,7 @@ def test_precond_kernel_choices(dim, nx, nt, gammas, precision):
     v = W.random_vector(dim, nx, nt, seed=17, batch=len(gammas))
     wos = [P.EpsCirculantRBD(pb).apply(v[b].ravel()) for b, pb in enumerate(problems(dim, nx, nt, gammas))]
     tol = 1e-5 if precision == "mixed" else 1e-11
-    for dk in (1, 2, 3, 4):
+    for dk in (1, 2, 3, 4, 5):
         ref = None
         for tc in (-1, -16, -8, -4, 4, 8, 16):
             s = Solver(dim, nx, nt, list(gammas), precision=precision, side=side, time_cols=tc, dst_kernel=dk,
@@ -190,22 +190,24 @@ HALF_DST_CASES = [
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_half_length_dst(dim, nx, nt, gammas, precision):
     """dst_kernel = 4 (strided lines through a half-length FFT and a prefix
-    sum) against the oracle and against the full-length register kernel
-    (different operations: agreement to rounding of the transforms)."""
+    sum) and 5 (the same for the contiguous lines too) against the oracle
+    and against the full-length register kernel (different operations:
+    agreement to rounding of the transforms)."""
     print(f"half-length dst {precision} dim={dim} nx={nx} nt={nt} B={len(gammas)}", flush=True)
     side = "flexible" if precision == "mixed" else "right"
     v = W.random_vector(dim, nx, nt, seed=29, batch=len(gammas))
     ws = {}
-    for dk in (1, 4):
+    for dk in (1, 4, 5):
         s = Solver(dim, nx, nt, list(gammas), precision=precision, side=side, dst_kernel=dk, device=DEV)
         assert s.kernels["dst_kernel"] == dk
         ws[dk] = s.precond_apply(to_dev(v)).cpu().numpy()
     tol = 1e-5 if precision == "mixed" else 1e-11
     wo = np.stack([P.EpsCirculantRBD(pb).apply(v[b].ravel()) for b, pb in enumerate(problems(dim, nx, nt, gammas))])
-    for b in range(len(gammas)):
-        assert rel(ws[4][b], wo[b]) < tol, (b, rel(ws[4][b], wo[b]))
-    check(ws[4], wo, tol, len(gammas), nt - 1, nx ** dim, label="half-length dst")
-    assert rel(ws[4], ws[1]) < (1e-5 if precision == "mixed" else 1e-12), rel(ws[4], ws[1])
+    for dk in (4, 5):
+        for b in range(len(gammas)):
+            assert rel(ws[dk][b], wo[b]) < tol, (dk, b, rel(ws[dk][b], wo[b]))
+        check(ws[dk], wo, tol, len(gammas), nt - 1, nx ** dim, label=f"half-length dst {dk}")
+        assert rel(ws[dk], ws[1]) < (1e-5 if precision == "mixed" else 1e-12), (dk, rel(ws[dk], ws[1]))
 
 
 CHIRP_CASES = [
