@@ -53,7 +53,7 @@ PRECOND_FAMILIES = ("time_fwd", "dst_rows", "dst_ax2", "dst_last_solve", "time_i
 # still describe the code that runs)
 _TIME_SOURCES = ["precond.hip", "time_common.hpp", "time_sk.hip", "time_ip.hpp", "time_ip_fwd_f64.hip",
                  "time_ip_inv_f64.hip", "time_ip_fwd_f32.hip", "time_ip_inv_f32.hip", "time_bl.hip", "time_cz.hip",
-                 "fft_lds.hpp", "fft_reg.hpp"]
+                 "time_pr.hip", "fft_lds.hpp", "fft_reg.hpp"]
 FAMILY_SOURCES = {
     "gs_update": ["krylov.hip"], "mdot": ["krylov.hip"], "combine": ["krylov.hip"],
     "kkt_apply": ["kkt.hip", "stencil.hpp", "fem.hip", "fem.hpp"], "time_fwd": _TIME_SOURCES, "time_inv": _TIME_SOURCES,
@@ -114,9 +114,10 @@ def parse():
                     help="time the candidate kernels at setup and keep the fastest (or take the cached choice)")
     ap.add_argument("--tune-cache", default=None,
                     help="tuner cache file (default: $PCOP_TUNE_CACHE, else the committed cache); '' for none")
-    ap.add_argument("--time-cols", type=int, default=0, choices=[0, -1, -4, -8, -16, -32, 4, 8, 16, 32],
+    ap.add_argument("--time-cols", type=int, default=0, choices=[0, -1, -4, -8, -16, -32, -64, 4, 8, 16, 32, 64],
                     help="time-pass kernels: 0 automatic, -P two LDS buffers, +P in place (P points per block); "
-                         "+32 / -32 chirp-z whole-group / lane-pair kernels")
+                         "+32 / -32 chirp-z whole-group / lane-pair kernels, +64 / -64 prime-factor kernels (n = 511) "
+                         "with 8 / 16 columns per block")
     ap.add_argument("--dst-kernel", type=int, default=0, choices=[0, 1, 2, 3, 4, 5],
                     help="sine-transform kernels: 0 automatic, 1 register, 2 LDS-staged, 3 register with wide column "
                          "tiles, 4 half-length strided transforms")

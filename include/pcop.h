@@ -131,12 +131,16 @@ typedef struct {
  *              has a prime factor above 17, or no Stockham tile of it fits
  *              LDS (long smooth lengths, e.g. FP64 n = 1152 or 2048), the
  *              chirp-z kernels run instead: 0 / -1 automatic (the
+ *              prime-factor kernels below where they exist, else the
  *              three-stage kernels where they exist, convolution lengths up
  *              to 1024, i.e. n <= 512); 32 / -32 the three-stage kernels
  *              with 256 / 512 threads; 4 / 8 / 16 the two-FFT kernels with at
  *              most that many points per block and 256 threads, -4 / -8 /
  *              -16 with 512 threads (a request that fits no kernel falls back
- *              to the automatic choice).
+ *              to the automatic choice); 64 / -64 the prime-factor kernels
+ *              with 8 / 16 spatial points per block and 256 / 512 threads
+ *              (n = 511 = 7 x 73 by the Good-Thomas split with a Rader
+ *              transform of 73 points; other n fall back to automatic).
  *   dst_kernel sine-transform kernels of step 2 (PCOP_DST): 0 automatic,
  *              1 register-resident lines, 2 lines staged through LDS,
  *              3 register-resident lines with twice as many strided lines
@@ -323,7 +327,7 @@ pcop_status pcop_get_params(pcop_ctx ctx, double* tau, double* alpha, double* ep
  *   time_cols      Stockham: -P (two LDS buffers, P points per block) or
  *                  +P (in place); chirp-z (nt - 1 with a prime factor above
  *                  17, or no Stockham tile fits LDS): +P (P points, 256
- *                  threads) or -P (512 threads);
+ *                  threads) or -P (512 threads), +-64 (prime-factor);
  *                  0 with PCOP_PRECOND_IDEAL (no time transform);
  *   dst_kernel     1 (register-resident), 2 (LDS-staged), 3 (register, wide
  *                  column tiles), 4 (half-length strided transforms), 5

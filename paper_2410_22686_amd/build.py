@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpcop.so")
 # slowest translation units first, so the parallel build finishes sooner
 SOURCES = ["time_ip_fwd_f64.hip", "time_ip_inv_f64.hip", "time_ip_fwd_f32.hip", "time_ip_inv_f32.hip",
-           "time_sk.hip", "time_cz.hip", "time_bl.hip", "dst.hip", "kkt.hip", "fem.hip", "krylov.hip", "multigrid.hip", "precond.hip", "ideal.hip", "post.hip",
+           "time_sk.hip", "time_cz.hip", "time_pr.hip", "time_bl.hip", "dst.hip", "kkt.hip", "fem.hip", "krylov.hip", "multigrid.hip", "precond.hip", "ideal.hip", "post.hip",
            "pcop.cpp"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

@@ -66,6 +66,8 @@ struct PrecondTables {
   const float* chirp32;
   const double* bhat64;  // [M]  FFT_M of the chirp filter
   const float* bhat32;
+  const double* pr64;    // prime-factor plans (n = N1 PR): [RC] exp(-2 pi i t/RC), then [RC]
+  const float* pr32;     //   the Rader filter DFT_RC(b)/RC, RC = PR - 1; null for other n
   const double* twL64;   // [L]  exp(-2 pi i t/L), L = 2(nx+1)
   const float* twL32;
   const double* mu1;     // [nx] 1-D eigenvalue of K per sine mode k = 1..nx: (4/h^2) sin^2(pi k h/2)
@@ -112,6 +114,9 @@ bool time_lds_fits(int n, bool fp32);
 // -P two LDS buffers, +P in place, with P points per block
 int time_choice(const Geo& g, const PrecondTables& tb, bool fp32);
 FftPlan make_time_plan(int n, bool fp32);
+// lengths with a prime-factor plan (time_pr.hip): the prime PR of the Rader
+// transform and the generator g of the group mod PR used by its filter table
+bool pr_params(int n, int* pr, int* gen);
 bool launch_precond(const Geo& g, const double* v, double* w, void* spec, bool fp32, int spatial,
                     const PrecondTables& tb, const double* vscale, int vs_stride, int accum,
                     hipStream_t st);

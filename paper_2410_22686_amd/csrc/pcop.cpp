@@ -123,8 +123,8 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
   if (o->graph && o->graph_chunk < 1) return fail(PCOP_ERR_INVALID_ARG, "graph_chunk must be >= 1");
   {
     const int tc = o->time_cols < 0 ? -o->time_cols : o->time_cols;
-    if (tc != 0 && tc != 1 && tc != 4 && tc != 8 && tc != 16 && tc != 32)
-      return fail(PCOP_ERR_INVALID_ARG, "time_cols must be 0, -1, +-4, +-8, +-16 or +-32");
+    if (tc != 0 && tc != 1 && tc != 4 && tc != 8 && tc != 16 && tc != 32 && tc != 64)
+      return fail(PCOP_ERR_INVALID_ARG, "time_cols must be 0, -1, +-4, +-8, +-16, +-32 or +-64");
   }
   if (o->dst_kernel < 0 || o->dst_kernel > 5) return fail(PCOP_ERR_INVALID_ARG, "dst_kernel must be in 0..5");
   if (o->tune != 0 && o->tune != 1) return fail(PCOP_ERR_INVALID_ARG, "tune must be 0 or 1");
@@ -160,7 +160,9 @@ struct Layout {
   size_t total = 0;
   size_t dpow, twn64, twn32, twL64, twL32, mu1, im1, lam, alpha, sg, ecoef, unit, zero, post;
   size_t twM64, twM32, chirp64, chirp32, bhat64, bhat32;
+  size_t pr64 = 0, pr32 = 0;
   int M = 1;
+  int RC = 0;  // Rader convolution length of a prime-factor plan, or 0
   size_t sc, H, coef, red, partial, wnorm2, norm, skip, active, finish, hcol;
   size_t basis, zbasis, tmp1, tmp2, xpad, spec;
   size_t mgcoef[kMaxMgLevels], mgz[kMaxMgLevels], mgr[kMaxMgLevels];
@@ -203,6 +205,14 @@ void plan_layout(const pcop_problem* p, const pcop_options* o, Layout& L) {
   L.chirp32 = take(L, 8 * (size_t)n);
   L.bhat64 = take(L, 16 * (size_t)L.M);
   L.bhat32 = take(L, 8 * (size_t)L.M);
+  {
+    int pr = 0, gen = 0;
+    L.RC = pr_params(n, &pr, &gen) ? pr - 1 : 0;
+    if (L.RC > 0) {
+      L.pr64 = take(L, 16 * 2 * (size_t)L.RC);
+      L.pr32 = take(L, 8 * 2 * (size_t)L.RC);
+    }
+  }
   L.twL64 = take(L, 16 * (size_t)Lf);
   L.twL32 = take(L, 8 * (size_t)Lf);
   L.mu1 = take(L, sizeof(double) * nx);
@@ -539,7 +549,7 @@ bool tune_entry_fits(pcop_ctx c, const TuneResult& r) {
   }
   if (c->opt.precond == PCOP_PRECOND_EPS) {
     const int tc = r.time_cols < 0 ? -r.time_cols : r.time_cols;
-    if (tc != 0 && tc != 1 && tc != 4 && tc != 8 && tc != 16 && tc != 32) return false;
+    if (tc != 0 && tc != 1 && tc != 4 && tc != 8 && tc != 16 && tc != 32 && tc != 64) return false;
     PrecondTables t = c->tb;
     t.time_cols = r.time_cols;
     if (time_choice(c->g, t, c->fp32) == 0) return false;
@@ -581,10 +591,11 @@ pcop_status tune_kernels(pcop_ctx c) {
     tcs.push_back(c->tb.time_cols);
   } else {
     std::vector<int> seen;
-    // chirp-z: the automatic choice first, then the three-stage kernels with
-    // 256 and 512 threads and the two-FFT kernels with every width; Stockham:
-    // two buffers and in place with 16, 8, 4 points
-    const std::vector<int> wants = c->tb.plan.bluestein ? std::vector<int>{0, 32, -32, 16, 8, 4, -16, -8, -4}
+    // chirp-z: the automatic choice first, then the prime-factor kernels,
+    // the three-stage kernels with 256 and 512 threads and the two-FFT
+    // kernels with every width; Stockham: two buffers and in place with 16,
+    // 8, 4 points
+    const std::vector<int> wants = c->tb.plan.bluestein ? std::vector<int>{0, 64, -64, 32, -32, 16, 8, 4, -16, -8, -4}
                                                         : std::vector<int>{-8, -16, -4, 16, 8, 4};
     for (int want : wants) {
       PrecondTables t = c->tb;
@@ -886,6 +897,46 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
       }
     }
   }
+  // prime-factor plans: W_RC^t and the Rader filter B[k] = DFT_RC(b)[k] / RC,
+  // b_m = exp(-2 pi i (g^m mod PR)/PR)
+  const int RC = L.RC;
+  std::vector<double> pr64(4 * (size_t)RC);
+  std::vector<float> pr32(4 * (size_t)RC);
+  if (RC > 0) {
+    int pr = 0, gen = 0;
+    (void)pr_params(n, &pr, &gen);
+    std::vector<long double> cR(RC), sR(RC), br(RC), bi(RC);
+    for (int t = 0; t < RC; ++t) {
+      const long double a = -2.0L * PI * t / RC;
+      cR[t] = std::cos(a);
+      sR[t] = std::sin(a);
+    }
+    long long gm = 1;
+    for (int t = 0; t < RC; ++t) {
+      const long double a = -2.0L * PI * (long double)gm / pr;
+      br[t] = std::cos(a);
+      bi[t] = std::sin(a);
+      gm = gm * gen % pr;
+    }
+    for (int k = 0; k < RC; ++k) {
+      long double re = 0.0L, im = 0.0L;
+      for (int t = 0; t < RC; ++t) {
+        const int e = (int)(((long long)k * t) % RC);
+        re += br[t] * cR[e] - bi[t] * sR[e];
+        im += br[t] * sR[e] + bi[t] * cR[e];
+      }
+      re /= RC;
+      im /= RC;
+      pr64[2 * k] = (double)cR[k];
+      pr64[2 * k + 1] = (double)sR[k];
+      pr64[2 * (RC + k)] = (double)re;
+      pr64[2 * (RC + k) + 1] = (double)im;
+      pr32[2 * k] = (float)cR[k];
+      pr32[2 * k + 1] = (float)sR[k];
+      pr32[2 * (RC + k)] = (float)re;
+      pr32[2 * (RC + k) + 1] = (float)im;
+    }
+  }
   const int Lf = 2 * (nx + 1);
   for (int t = 0; t < Lf; ++t) {
     long double a = -2.0L * PI * t / Lf;
@@ -928,6 +979,8 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   if (e == hipSuccess) e = up(L.chirp32, chirp32.data(), sizeof(float) * 2 * n);
   if (e == hipSuccess) e = up(L.bhat64, bhat64.data(), sizeof(double) * 2 * M);
   if (e == hipSuccess) e = up(L.bhat32, bhat32.data(), sizeof(float) * 2 * M);
+  if (e == hipSuccess && RC > 0) e = up(L.pr64, pr64.data(), sizeof(double) * 4 * RC);
+  if (e == hipSuccess && RC > 0) e = up(L.pr32, pr32.data(), sizeof(float) * 4 * RC);
   if (e == hipSuccess) e = up(L.twL64, twL64.data(), sizeof(double) * 2 * Lf);
   if (e == hipSuccess) e = up(L.twL32, twL32.data(), sizeof(float) * 2 * Lf);
   if (e == hipSuccess) e = up(L.mu1, mu1.data(), sizeof(double) * nx);
@@ -1079,6 +1132,8 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   tb.chirp32 = c->at<float>(L.chirp32);
   tb.bhat64 = c->at<double>(L.bhat64);
   tb.bhat32 = c->at<float>(L.bhat32);
+  tb.pr64 = L.RC > 0 ? c->at<double>(L.pr64) : nullptr;
+  tb.pr32 = L.RC > 0 ? c->at<float>(L.pr32) : nullptr;
   tb.time_cols = opts->time_cols;
   tb.dst_variant = (opts->dst_kernel >= 2) ? opts->dst_kernel - 1 : 0;
   c->nb_mdot.fill(opts->krylov_blocks > 0 ? opts->krylov_blocks : L.nblk);

@@ -137,6 +137,7 @@ static bool time_pass(bool fwd, const Geo& g, const double* v, cx<T>* spec, doub
   const int csz = (int)sizeof(cx<T>);
   if (tb.plan.bluestein) {
     const int c = bl_choice(tb.plan.M, g.n, csz, tb.time_cols);
+    if (c == 64 || c == -64) return launch_time_pr<T>(fwd, c, g, v, spec, w, tb, vscale, vs_stride, accum, st);
     if (c == 32 || c == -32) return launch_time_cz<T>(fwd, c, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st);
     return c != 0 && launch_time_bl<T>(fwd, c, g, v, spec, w, tb, tt, vscale, vs_stride, accum, st);
   }

@@ -296,6 +296,10 @@ static bool bl_exists(int M, int csz, int c) {
 }
 
 int bl_choice(int M, int n, int csz, int req) {
+  if (req == 64 || req == -64) {
+    if (pr_exists(n, csz, req)) return req;
+    req = 0;
+  }
   if (req == 32 || req == -32) {
     if (cz_exists(M, csz, req)) return req;
     req = 0;
@@ -307,9 +311,12 @@ int bl_choice(int M, int n, int csz, int req) {
       if (bl_exists(M, csz, c)) return c;
     }
   }
-  // automatic: the three-stage kernels (256 threads, else 512), else the
-  // two-FFT kernels with 256 threads and the widest tile that keeps two
-  // blocks per CU, else the widest that fits at all
+  // automatic: the prime-factor kernels with 16-point tiles where they exist
+  // (faster than chirp-z in both precisions at n = 511), else the three-stage
+  // kernels (256 threads, else 512), else the two-FFT kernels with 256
+  // threads and the widest tile that keeps two blocks per CU, else the
+  // widest that fits at all
+  if (pr_exists(n, csz, -64)) return -64;
   if (const int c = cz_auto(M, csz)) return c;
   for (int P = 16; P >= 1; P /= 2)
     if (bl_exists(M, csz, P) && bl_lds_bytes(M, P, n, csz) <= kLdsMax / 2) return P;

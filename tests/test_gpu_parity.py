@@ -255,7 +255,7 @@ def test_chirp_kernel_choices(dim, nx, nt, gammas, precision):
     for tc in (0, 32, -32, 16, 8, 4, -16, -8, -4):
         s = Solver(dim, nx, nt, list(gammas), precision=precision, side=side, time_cols=tc, device=DEV)
         eff = s.kernels["time_cols"]
-        assert eff in (32, -32, 16, 8, 4, 2, 1, -16, -8, -4), eff
+        assert eff in (64, -64, 32, -32, 16, 8, 4, 2, 1, -16, -8, -4), eff
         if tc != 0 and (eff < 0) == (tc < 0):
             assert abs(eff) <= abs(tc)
         if eff in seen:
@@ -270,6 +270,64 @@ def test_chirp_kernel_choices(dim, nx, nt, gammas, precision):
         else:
             assert rel(w, ref) < (tol32 if precision == "mixed" else 1e-13), (tc, eff, rel(w, ref))
     print(f"  shapes run: {sorted(seen)}", flush=True)
+
+
+PRIME_FACTOR_CASES = [
+    # dim, nx, nt, gammas: n = 511 = 7 x 73 (8-column tiles)
+    (2, 3, 512, (1e-6,)),          # m = 9: one full tile and a ragged one
+    (2, 7, 512, (1e-4, 1e-8)),     # m = 49: six full tiles and a ragged one, two members
+    (3, 3, 512, (1e-3,)),          # 3-D, m = 27
+]
+
+
+@pytest.mark.parametrize("dim,nx,nt,gammas", PRIME_FACTOR_CASES)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_prime_factor_time_kernels(dim, nx, nt, gammas, precision):
+    """time_cols = +-64: the time passes of n = 511 = 7 x 73 by the Good-Thomas
+    split with Rader transforms of 73 points (a 72-point cyclic convolution
+    in three LDS stages) against the oracle, and against the chirp-z kernels
+    (different operations: agreement to rounding; in FP32 the chirp-z bar of
+    the kernel-choice test, 2 u log2(1024) sqrt(n))."""
+    print(f"prime-factor time kernels {precision} dim={dim} nx={nx} nt={nt} B={len(gammas)}", flush=True)
+    side = "flexible" if precision == "mixed" else "right"
+    v = W.random_vector(dim, nx, nt, seed=31, batch=len(gammas))
+    wos = np.stack([P.EpsCirculantRBD(pb).apply(v[b].ravel()) for b, pb in enumerate(problems(dim, nx, nt, gammas))])
+    n = nt - 1
+    tol32 = 2 * 6e-8 * np.log2(1024) * np.sqrt(n)
+    tol = tol32 if precision == "mixed" else 1e-11
+    ws = {}
+    for tc in (64, -64, 32):
+        s = Solver(dim, nx, nt, list(gammas), precision=precision, side=side, time_cols=tc, device=DEV)
+        assert s.kernels["time_cols"] == tc, s.kernels
+        ws[tc] = s.precond_apply(to_dev(v)).cpu().numpy()
+    for tc in (64, -64):
+        for b in range(len(gammas)):
+            assert rel(ws[tc][b], wos[b]) < tol, (tc, b, rel(ws[tc][b], wos[b]))
+        check(ws[tc], wos, tol, len(gammas), n, nx ** dim, label=f"prime-factor {tc}")
+        assert rel(ws[tc], ws[32]) < (tol32 if precision == "mixed" else 1e-13), (tc, rel(ws[tc], ws[32]))
+    # the two tile widths run the same operations per element
+    assert rel(ws[64], ws[-64]) < (1e-6 if precision == "mixed" else 1e-15), rel(ws[64], ws[-64])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_prime_factor_solve_matches_chirp(precision):
+    """A whole solve with the prime-factor time kernels (scaled inputs of the
+    Krylov basis, accumulated outputs) takes the iterations of the chirp-z
+    solve and reaches the same solution."""
+    side = "flexible" if precision == "mixed" else "right"
+    gammas = [1e-4, 1e-6]
+    dim, nx, nt = 2, 15, 512
+    rng = np.random.default_rng(37)
+    out = {}
+    for tc in (-64, 32):
+        s = Solver(dim, nx, nt, gammas, precision=precision, side=side, time_cols=tc, device=DEV)
+        assert s.kernels["time_cols"] == tc
+        b = to_dev(rng.standard_normal(tuple(s.vec_shape))) if tc == -64 else b
+        x, infos, _ = s.solve(b)
+        out[tc] = (x.cpu().numpy(), [i.iters for i in infos])
+    print(f"prime-factor solve {precision}: iterations {out[-64][1]} vs chirp-z {out[32][1]}", flush=True)
+    assert out[-64][1] == out[32][1]
+    assert rel(out[-64][0], out[32][0]) < 1e-9
 
 
 def test_tuned_solve_matches_default():
