@@ -199,33 +199,47 @@ __global__ void __launch_bounds__(256) mg_prolong_kernel(int nxf, int mf, int nx
   if (i >= mf) return;
   int f[3];
   coords(i, nxf, DIM, f);
-  // per axis: coarse indices and weights contributing to fine index f
-  int ci[3][2];
-  T cw[3][2];
-  int cn[3];
-  for (int a = 0; a < 3; ++a) {
-    if (a >= DIM) {
-      ci[a][0] = 0;
+  // per axis two coarse candidates, clamped in bounds, with weights that are
+  // zero where a candidate does not contribute: fine 2I + 1 sits on coarse I
+  // (weights 1, 0); fine 2I lies between coarse I - 1 and I (1/2 each, 0 for
+  // a candidate outside the grid).  Every thread then issues the same
+  // 2^DIM unconditional loads per slice (no divergent loop over 1..8
+  // contributions), and indices and weights are formed once for SB slices.
+  int ci[DIM][2];
+  T cw[DIM][2];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const int I = f[a] >> 1;
+    if (f[a] & 1) {
+      ci[a][0] = I;
+      ci[a][1] = I;
       cw[a][0] = (T)1;
-      cn[a] = 1;
-      continue;
+      cw[a][1] = (T)0;
+    } else {
+      // (nxc = 0 on a one-point grid, where the launch only copies: every
+      // weight is then zero and every index 0, still a valid address)
+      ci[a][0] = I >= 1 ? I - 1 : 0;
+      ci[a][1] = I < nxc ? I : (nxc > 0 ? nxc - 1 : 0);
+      cw[a][0] = I >= 1 ? (T)0.5 : (T)0;
+      cw[a][1] = I < nxc ? (T)0.5 : (T)0;
     }
-    if (f[a] & 1) {  // fine 2I + 1 sits on coarse I
-      ci[a][0] = f[a] >> 1;
-      cw[a][0] = (T)1;
-      cn[a] = 1;
-    } else {         // fine 2I lies between coarse I - 1 and I
-      const int I = f[a] >> 1;
-      cn[a] = 0;
-      if (I - 1 >= 0) {
-        ci[a][cn[a]] = I - 1;
-        cw[a][cn[a]++] = (T)0.5;
-      }
-      if (I < nxc) {
-        ci[a][cn[a]] = I;
-        cw[a][cn[a]++] = (T)0.5;
-      }
+  }
+  constexpr int NC = 1 << DIM;
+  int cidx[NC];
+  T cwt[NC];
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    int I = 0, stride = 1;
+    T wt = (T)1;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const int b = (u >> a) & 1;
+      I += ci[a][b] * stride;
+      wt *= cw[a][b];
+      stride *= nxc;
     }
+    cidx[u] = I;
+    cwt[u] = wt;
   }
   const int s0 = bk.y * SB;
 #pragma unroll
@@ -235,12 +249,8 @@ __global__ void __launch_bounds__(256) mg_prolong_kernel(int nxf, int mf, int nx
     if (sh.active && !sh.active[s / sh.twoK]) continue;
     const cx<T>* zcs = zc + (size_t)s * mc;
     cx<T> acc = zf[(size_t)s * mf + i];
-    for (int u2 = 0; u2 < cn[2]; ++u2)
-      for (int u1 = 0; u1 < cn[1]; ++u1)
-        for (int u0 = 0; u0 < cn[0]; ++u0) {
-          const int I = ci[0][u0] + nxc * (ci[1][u1] + nxc * ci[2][u2]);
-          acc = acc + scale(zcs[I], cw[0][u0] * cw[1][u1] * cw[2][u2]);
-        }
+#pragma unroll
+    for (int u = 0; u < NC; ++u) acc = acc + scale(zcs[cidx[u]], cwt[u]);
     out[(size_t)s * mf + i] = acc;
   }
 }
