@@ -138,9 +138,12 @@ typedef struct {
  *              most that many points per block and 256 threads, -4 / -8 /
  *              -16 with 512 threads (a request that fits no kernel falls back
  *              to the automatic choice); 64 / -64 the prime-factor kernels
- *              with 8 / 16 spatial points per block and 256 / 512 threads
- *              (n = 511 = 7 x 73 by the Good-Thomas split with a Rader
- *              transform of 73 points; other n fall back to automatic).
+ *              with 256 / 512 threads (n = 511 = 7 x 73 by the Good-Thomas
+ *              split with a Rader transform of 73 points, 8 / 16 points per
+ *              block, the automatic choice there; n = 255 = 15 x 17, 15 / 30
+ *              points; n = 127 by a Rader transform, 16 / 32 points); for
+ *              other n, 64 / -64 are read as 16 / -16 (Stockham) or fall
+ *              back to the automatic choice (chirp-z).
  *   dst_kernel sine-transform kernels of step 2 (PCOP_DST): 0 automatic,
  *              1 register-resident lines, 2 lines staged through LDS,
  *              3 register-resident lines with twice as many strided lines

@@ -596,7 +596,7 @@ pcop_status tune_kernels(pcop_ctx c) {
     // kernels with every width; Stockham: two buffers and in place with 16,
     // 8, 4 points
     const std::vector<int> wants = c->tb.plan.bluestein ? std::vector<int>{0, 64, -64, 32, -32, 16, 8, 4, -16, -8, -4}
-                                                        : std::vector<int>{-8, -16, -4, 16, 8, 4};
+                                                        : std::vector<int>{-8, -16, -4, 16, 8, 4, 64, -64};
     for (int want : wants) {
       PrecondTables t = c->tb;
       t.time_cols = want;

@@ -124,6 +124,9 @@ bool time_lds_fits(int n, bool fp32) {
 }
 
 int time_choice(const Geo& g, const PrecondTables& tb, bool fp32) {
+  // the prime-factor kernels, requested explicitly, for any length that has a plan
+  if ((tb.time_cols == 64 || tb.time_cols == -64) && pr_exists(g.n, fp32 ? 8 : 16, tb.time_cols))
+    return tb.time_cols;
   if (tb.plan.bluestein) return bl_choice(tb.plan.M, g.n, fp32 ? 8 : 16, tb.time_cols);
   return time_block(tb.plan, g.n, fp32 ? 8 : 16, tb.time_cols);
 }
@@ -135,6 +138,8 @@ static bool time_pass(bool fwd, const Geo& g, const double* v, cx<T>* spec, doub
   TimeTables tt{f32 ? (const void*)tb.twn32 : (const void*)tb.twn64, f32 ? (const void*)tb.twM32 : (const void*)tb.twM64,
                 f32 ? (const void*)tb.chirp32 : (const void*)tb.chirp64, f32 ? (const void*)tb.bhat32 : (const void*)tb.bhat64};
   const int csz = (int)sizeof(cx<T>);
+  if ((tb.time_cols == 64 || tb.time_cols == -64) && pr_exists(g.n, csz, tb.time_cols))
+    return launch_time_pr<T>(fwd, tb.time_cols, g, v, spec, w, tb, vscale, vs_stride, accum, st);
   if (tb.plan.bluestein) {
     const int c = bl_choice(tb.plan.M, g.n, csz, tb.time_cols);
     if (c == 64 || c == -64) return launch_time_pr<T>(fwd, c, g, v, spec, w, tb, vscale, vs_stride, accum, st);

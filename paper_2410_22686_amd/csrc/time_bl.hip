@@ -311,12 +311,12 @@ int bl_choice(int M, int n, int csz, int req) {
       if (bl_exists(M, csz, c)) return c;
     }
   }
-  // automatic: the prime-factor kernels with 16-point tiles where they exist
-  // (faster than chirp-z in both precisions at n = 511), else the three-stage
+  // automatic: the prime-factor kernels where they were measured faster
+  // (16-point tiles at n = 511, in both precisions), else the three-stage
   // kernels (256 threads, else 512), else the two-FFT kernels with 256
   // threads and the widest tile that keeps two blocks per CU, else the
   // widest that fits at all
-  if (pr_exists(n, csz, -64)) return -64;
+  if (const int c = pr_auto(n, csz)) return c;
   if (const int c = cz_auto(M, csz)) return c;
   for (int P = 16; P >= 1; P /= 2)
     if (bl_exists(M, csz, P) && bl_lds_bytes(M, P, n, csz) <= kLdsMax / 2) return P;

@@ -103,11 +103,14 @@ bool launch_time_cz(bool fwd, int c, const Geo& g, const double* v, cx<T>* spec,
 bool cz_exists(int M, int csz, int c);
 int cz_auto(int M, int csz);
 // prime-factor kernels (time_pr.hip) for n = N1 PR with a Rader transform of
-// the prime PR: c = 64 (8 columns, 256 threads) or -64 (16 columns, 512)
+// the prime PR (n = 127, 255, 511): c = 64 (the plan's narrow tile, 256
+// threads) or -64 (its wide tile, 512 threads); pr_auto is the automatic
+// choice among them (0: none)
 template <class T>
 bool launch_time_pr(bool fwd, int c, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
                     const double* vscale, int vs_stride, int accum, hipStream_t st);
 bool pr_exists(int n, int csz, int c);
+int pr_auto(int n, int csz);
 // chirp-z kernels for the request req (pcop_options::time_cols): +-32 the
 // three-stage kernels with 256 / 512 threads; +P for P points per block of
 // the two-FFT kernels with 256 threads, -P with 512 threads; 0 when no shape

@@ -1,6 +1,9 @@
 // Time passes for lengths n = N1 PR (N1 and PR coprime, PR prime) by the
 // prime-factor (Good-Thomas) split and Rader's algorithm for the PR-point
-// transforms; built for n = 511 = 7 x 73.
+// transforms: built for n = 511 = 7 x 73, n = 255 = 15 x 17 and n = 127
+// (N1 = 1).  A plan without a Rader stage (RA = 0) would take the PR-point
+// DFTs directly in registers instead (for 17 points that needs more
+// registers than the Rader stages: 253 VGPRs in FP64).
 //
 // Index maps (t1 = PR^-1 mod N1, t2 = N1^-1 mod PR):
 //   input   j = (PR j1 + N1 j2) mod n,          j1 < N1, j2 < PR
@@ -47,15 +50,27 @@ constexpr int pr_inv_mod(int a, int m) {
   return m == 1 ? 0 : -1;
 }
 
-template <int N1_, int PR_, int G_, int RA_, int RB_>
+// N1 x PR with a Rader stage of RC = PR - 1 = RA RB (generator G), or, with
+// RA = RB = 0, the PR-point DFTs directly in registers; CP / CN spatial
+// points per tile for the 256- / 512-thread kernels (time_cols 64 / -64)
+template <int N1_, int PR_, int G_, int RA_, int RB_, int CP_, int CN_>
 struct PrPlan {
   static constexpr int N1 = N1_, PR = PR_, G = G_, RA = RA_, RB = RB_, RC = PR_ - 1, N = N1_ * PR_;
+  static constexpr bool DIRECT = RA_ == 0;
+  static constexpr int CP = CP_, CN = CN_;
   static constexpr int KM1 = PR_ * pr_inv_mod(PR_ % N1_, N1_);  // output map: k = (KM1 k1 + KM2 k2) mod N
   static constexpr int KM2 = N1_ * pr_inv_mod(N1_ % PR_, PR_);
-  static_assert(RA * RB == PR_ - 1, "the convolution length splits as RA RB");
+  static_assert(DIRECT || RA * RB == PR_ - 1, "the convolution length splits as RA RB");
 };
 // 511 = 7 x 73, generator 5 of the group mod 73, 72 = 9 x 8
-using Pr511 = PrPlan<7, 73, 5, 9, 8>;
+using Pr511 = PrPlan<7, 73, 5, 9, 8, 8, 16>;
+// 127 prime, generator 3, 126 = 9 x 14
+using Pr127 = PrPlan<1, 127, 3, 9, 14, 16, 32>;
+// 255 = 15 x 17, generator 3 of the group mod 17, 16 = 4 x 4; tiles of 15
+// and 30 points make the 17 stage-0 items per point fill 255 of 256 and 510
+// of 512 threads in one round (with 16 and 32 points a second round of 15
+// prefetch slots per thread costs 209 VGPRs in FP64 and spills in FP32)
+using Pr255 = PrPlan<15, 17, 3, 4, 4, 15, 30>;
 
 // cos and sin of 2 pi t / R, t = 1 .. (R - 1)/2, to 36 digits
 template <int R>
@@ -72,6 +87,22 @@ template <>
 __device__ __forceinline__ double root_sin<7>(int t) {
   constexpr double s[4] = {0.0, 0.781831482468029808708444526674057750, 0.974927912181823607018131682993931217,
                            0.433883739117558120475768332848358755};
+  return s[t];
+}
+template <>
+__device__ __forceinline__ double root_cos<17>(int t) {
+  constexpr double c[9] = {1.0, 0.932472229404355804573115891821563386, 0.739008917220659115924534309872648106,
+                           0.445738355776538267396457549379486855, 0.092268359463301995239651107154506480,
+                           -0.273662990072082863539077935436813432, -0.602634636379256389178588154986840622,
+                           -0.850217135729614152134143922949352058, -0.982973099683901778281948844855198716};
+  return c[t];
+}
+template <>
+__device__ __forceinline__ double root_sin<17>(int t) {
+  constexpr double s[9] = {0.0, 0.361241666187152948744714596183700164, 0.673695643646557211712691912425694616,
+                           0.895163291355062322067016499753785457, 0.995734176295034521871191178905481784,
+                           0.961825643172819070408796290731518550, 0.798017227280239503332805112796261369,
+                           0.526432162877355800244607799140699566, 0.183749517816570331574408839620727582};
   return s[t];
 }
 template <>
@@ -124,11 +155,67 @@ __device__ __forceinline__ void dft_odd_lit(cx<T>* a) {
   }
 }
 
-// LDS of one block: the [C][N] column tile, then the tables
+template <class T, int SG, int R>
+__device__ __forceinline__ void dft_small(cx<T>* a);
+
+// R1 R2-point DFT for coprime R1, R2 by the prime-factor index maps (input
+// j = (R2 j1 + R1 j2) mod R, output k = (R2 u1 k1 + R1 u2 k2) mod R with
+// u1 = R2^-1 mod R1, u2 = R1^-1 mod R2): R2 DFTs of R1 points, then R1 of R2
+// points, no twiddles; every index is a constant after unrolling
+template <class T, int SG, int R1, int R2>
+__device__ __forceinline__ void dft_pfa2(cx<T>* a) {
+  constexpr int R = R1 * R2;
+  constexpr int U1 = R2 * pr_inv_mod(R2 % R1, R1), U2 = R1 * pr_inv_mod(R1 % R2, R2);
+  cx<T> y[R];
+#pragma unroll
+  for (int j2 = 0; j2 < R2; ++j2) {
+    cx<T> t[R1];
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) t[j1] = a[(R2 * j1 + R1 * j2) % R];
+    dft_small<T, SG, R1>(t);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) y[k1 * R2 + j2] = t[k1];
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) {
+    cx<T> t[R2];
+#pragma unroll
+    for (int j2 = 0; j2 < R2; ++j2) t[j2] = y[k1 * R2 + j2];
+    dft_small<T, SG, R2>(t);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) a[(U1 * k1 + U2 * k2) % R] = t[k2];
+  }
+}
+
+// R-point DFT in registers, natural order, for the lengths the plans use
+template <class T, int SG, int R>
+__device__ __forceinline__ void dft_small(cx<T>* a) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2 || R == 4 || R == 8) {
+    dftR<T, SG, R>(a);
+  } else if constexpr (R == 3) {
+    dft3<T, SG>(a);
+  } else if constexpr (R == 5) {
+    dft5<T, SG>(a);
+  } else if constexpr (R == 7 || R == 9 || R == 17) {
+    dft_odd_lit<T, SG, R>(a);
+  } else if constexpr (R == 6) {
+    dft_pfa2<T, SG, 2, 3>(a);
+  } else if constexpr (R == 14) {
+    dft_pfa2<T, SG, 2, 7>(a);
+  } else if constexpr (R == 15) {
+    dft_pfa2<T, SG, 3, 5>(a);
+  } else {
+    static_assert(R == 1, "no register DFT of this length");
+  }
+}
+
+// LDS of one block: the [C][N] column tile, then the tables (the Rader
+// twiddles, filter and index tables only for Rader plans)
 template <class PL>
 constexpr size_t pr_lds_bytes(int C, int csz) {
-  return (size_t)C * PL::N * csz + (size_t)2 * PL::RC * csz + (size_t)2 * PL::N * 8 +
-         (size_t)(PL::RC + 2 * PL::PR) * 4;
+  return (size_t)C * PL::N * csz + (size_t)2 * PL::N * 8 +
+         (PL::DIRECT ? 0 : (size_t)2 * PL::RC * csz + (size_t)(PL::RC + 2 * PL::PR) * 4);
 }
 
 template <class T, class PL>
@@ -143,30 +230,32 @@ struct PrTables {
 
   __device__ __forceinline__ PrTables(unsigned char* tail, const void* prt, const double* dpow, bool fwd, int NT) {
     constexpr int RC = PL::RC, PR = PL::PR, N = PL::N;
-    const cx<T>* src = reinterpret_cast<const cx<T>*>(prt);
-    cx<T>* tw_l = reinterpret_cast<cx<T>*>(tail);
-    cx<T>* bh_l = tw_l + RC;
-    double* da_l = reinterpret_cast<double*>(bh_l + RC);
+    double* da_l = reinterpret_cast<double*>(tail);
     double* db_l = da_l + N;
-    int* gpw_l = reinterpret_cast<int*>(db_l + N);
+    cx<T>* tw_l = reinterpret_cast<cx<T>*>(db_l + N);
+    cx<T>* bh_l = tw_l + RC;
+    int* gpw_l = reinterpret_cast<int*>(bh_l + RC);
     int* lg_l = gpw_l + RC;
     int* slot_l = lg_l + PR;
-    for (int t = threadIdx.x; t < 2 * RC; t += NT) tw_l[t] = src[t];
     for (int t = threadIdx.x; t < N; t += NT) {
       const double d = dpow[t];
       da_l[t] = fwd ? d : d / (double)N;
       db_l[t] = fwd ? 1.0 / d : 1.0 / ((double)N * d);
     }
-    for (int q = threadIdx.x; q < RC; q += NT) {
-      int v = 1;
-      for (int s = 0; s < q; ++s) v = (v * PL::G) % PR;
-      gpw_l[q] = v;
-      lg_l[v] = q;
-      slot_l[v] = (RC - q) % RC;  // g^-p = g^q for p = -q mod RC
-    }
-    if (threadIdx.x == 0) {
-      lg_l[0] = RC;
-      slot_l[0] = RC;
+    if constexpr (!PL::DIRECT) {
+      const cx<T>* src = reinterpret_cast<const cx<T>*>(prt);
+      for (int t = threadIdx.x; t < 2 * RC; t += NT) tw_l[t] = src[t];
+      for (int q = threadIdx.x; q < RC; q += NT) {
+        int v = 1;
+        for (int s = 0; s < q; ++s) v = (v * PL::G) % PR;
+        gpw_l[q] = v;
+        lg_l[v] = q;
+        slot_l[v] = (RC - q) % RC;  // g^-p = g^q for p = -q mod RC
+      }
+      if (threadIdx.x == 0) {
+        lg_l[0] = RC;
+        slot_l[0] = RC;
+      }
     }
     tw = tw_l;
     bh = bh_l;
@@ -175,6 +264,13 @@ struct PrTables {
     gpw = gpw_l;
     lg = lg_l;
     slot = slot_l;
+  }
+  // slot of the transform input j2 (k2 in the inverse pass), of the output
+  // k2, and the output index held in slot s
+  __device__ __forceinline__ int in_slot(int j2) const { return PL::DIRECT ? j2 : slot[j2]; }
+  __device__ __forceinline__ int out_slot(int k2) const { return PL::DIRECT ? k2 : lg[k2]; }
+  __device__ __forceinline__ int slot_index(int s) const {
+    return PL::DIRECT ? s : (s == PL::RC ? 0 : gpw[s]);
   }
 };
 
@@ -220,7 +316,7 @@ __device__ __forceinline__ void pr_stages_ab(cx<T>* buf, const PrTables<T, PL>& 
       cx<T> a[RA];
 #pragma unroll
       for (int ja = 0; ja < RA; ++ja) a[ja] = row[ja * RB];
-      dft_odd_lit<T, -1, RA>(a);
+      dft_small<T, -1, RA>(a);
       pr_twiddle<T, PL, -1, RA>(a, jb, tb);
 #pragma unroll
       for (int ka = 0; ka < RA; ++ka) row[ka * RB] = a[ka];
@@ -237,7 +333,7 @@ __device__ __forceinline__ void pr_stages_ab(cx<T>* buf, const PrTables<T, PL>& 
       cx<T> cc[RB];
 #pragma unroll
       for (int jb = 0; jb < RB; ++jb) cc[jb] = rowk[ka * RB + jb];
-      dftR<T, -1, RB>(cc);  // A[ka + RA kb] = cc[kb]
+      dft_small<T, -1, RB>(cc);  // A[ka + RA kb] = cc[kb]
       if (ka == 0) {
         const cx<T> y0 = rowk[RC];
         rowk[RC] = y0 + cc[0];  // X[k1, 0]
@@ -248,13 +344,60 @@ __device__ __forceinline__ void pr_stages_ab(cx<T>* buf, const PrTables<T, PL>& 
 #pragma unroll
         for (int kb = 0; kb < RB; ++kb) cc[kb] = cc[kb] * tb.bh[ka + RA * kb];
       }
-      dftR<T, 1, RB>(cc);
+      dft_small<T, 1, RB>(cc);
       pr_twiddle<T, PL, 1, RB>(cc, ka, tb);
 #pragma unroll
       for (int qb = 0; qb < RB; ++qb) rowk[ka * RB + qb] = cc[qb];
     }
   }
   __syncthreads();
+}
+
+// The PR-point DFT of every (column, k1) row of the tile, in place, ending
+// with a barrier: Rader stages A, B and A' (row k1 then holds X[k1, g^q] at
+// slot q and X[k1, 0] at slot RC), or one register DFT per row (direct plans,
+// X[k1, k2] at slot k2)
+template <class T, class PL, int C, int NT>
+__device__ __forceinline__ void pr_rows(cx<T>* buf, const PrTables<T, PL>& tb, int lane) {
+  constexpr int N1 = PL::N1, PR = PL::PR, LDC = PL::N;
+  if constexpr (PL::DIRECT) {
+    constexpr int ID = C * N1, QD = (ID + NT - 1) / NT;
+#pragma unroll
+    for (int q = 0; q < QD; ++q) {
+      const int e = lane + q * NT;
+      if (e < ID) {
+        const int c = e % C, k1 = e / C;
+        cx<T>* row = buf + c * LDC + k1 * PR;
+        cx<T> a[PR];
+#pragma unroll
+        for (int j2 = 0; j2 < PR; ++j2) a[j2] = row[j2];
+        dft_small<T, -1, PR>(a);
+#pragma unroll
+        for (int k2 = 0; k2 < PR; ++k2) row[k2] = a[k2];
+      }
+    }
+    __syncthreads();
+  } else {
+    constexpr int RA = PL::RA, RB = PL::RB;
+    constexpr int IA = C * N1 * RB, QA = (IA + NT - 1) / NT;
+    pr_stages_ab<T, PL, C, NT>(buf, tb, lane);
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = lane + q * NT;
+      if (e < IA) {
+        const int c = e % C, r = e / C;
+        const int k1 = r / RB, qb = r - k1 * RB;
+        cx<T>* row = buf + c * LDC + k1 * PR + qb;
+        cx<T> a[RA];
+#pragma unroll
+        for (int ka = 0; ka < RA; ++ka) a[ka] = row[ka * RB];
+        dft_small<T, 1, RA>(a);
+#pragma unroll
+        for (int qa = 0; qa < RA; ++qa) row[qa * RB] = a[qa];
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // FP32 with 512 threads: at least 4 waves per SIMD, so that two blocks share
@@ -269,9 +412,8 @@ template <class T, class PL, int C, int NT>
 __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_fwd_pr(Geo g, const double* __restrict__ v, cx<T>* __restrict__ spec,
                                                    const double* __restrict__ dpow, const void* __restrict__ prt,
                                                    const double* __restrict__ vscale, int vs_stride, TileWalk tw) {
-  constexpr int N = PL::N, N1 = PL::N1, PR = PL::PR, RA = PL::RA, RB = PL::RB, LDC = N;
+  constexpr int N = PL::N, N1 = PL::N1, PR = PL::PR, LDC = N;
   constexpr int I0 = C * PR, Q0 = (I0 + NT - 1) / NT;
-  constexpr int IA = C * N1 * RB, QA = (IA + NT - 1) / NT;
   extern __shared__ __align__(16) unsigned char smem[];
   const int m = g.m, K = g.K;
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem);
@@ -318,8 +460,8 @@ __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_fwd_pr(Geo g
           const int j = (PR * j1 + N1 * j2) % N;
           a[j1] = cx<T>{(T)(s * tb.da[j] * r2[q][j1]), (T)(s * tb.db[j] * r1[q][j1])};
         }
-        dft_odd_lit<T, -1, N1>(a);
-        cx<T>* col = buf + c * LDC + tb.slot[j2];
+        dft_small<T, -1, N1>(a);
+        cx<T>* col = buf + c * LDC + tb.in_slot(j2);
 #pragma unroll
         for (int k1 = 0; k1 < N1; ++k1) col[k1 * PR] = a[k1];
       }
@@ -327,28 +469,11 @@ __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_fwd_pr(Geo g
     __syncthreads();
     const int nxt = tw.next(tile + stride, stride);
     if (nxt < tw.ntiles) fetch(nxt, lane);
-    pr_stages_ab<T, PL, C, NT>(buf, tb, lane);
-    // stage A', in place: row k1 then holds X[k1, g^q] at slot q
-#pragma unroll
-    for (int q = 0; q < QA; ++q) {
-      const int e = lane + q * NT;
-      if (e < IA) {
-        const int c = e % C, r = e / C;
-        const int k1 = r / RB, qb = r - k1 * RB;
-        cx<T>* row = buf + c * LDC + k1 * PR + qb;
-        cx<T> a[RA];
-#pragma unroll
-        for (int ka = 0; ka < RA; ++ka) a[ka] = row[ka * RB];
-        dft_odd_lit<T, 1, RA>(a);
-#pragma unroll
-        for (int qa = 0; qa < RA; ++qa) row[qa * RB] = a[qa];
-      }
-    }
-    __syncthreads();
+    pr_rows<T, PL, C, NT>(buf, tb, lane);
     cx<T>* out = spec + (size_t)b * (size_t)(2 * K) * m;
     unpack_store<T>(out, N, K, C, i0, m, [&](int k, int p) {
       const int k1 = k % N1, k2 = k % PR;
-      return buf[p * LDC + k1 * PR + tb.lg[k2]];
+      return buf[p * LDC + k1 * PR + tb.out_slot(k2)];
     });
     __syncthreads();
     tile = nxt;
@@ -366,9 +491,8 @@ template <class T, class PL, int C, int NT>
 __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_inv_pr(Geo g, const cx<T>* __restrict__ spec, double* __restrict__ w,
                                                    const double* __restrict__ dpow, const void* __restrict__ prt,
                                                    int accum, TileWalk tw) {
-  constexpr int N = PL::N, N1 = PL::N1, PR = PL::PR, RA = PL::RA, RB = PL::RB, RC = PL::RC, LDC = N;
+  constexpr int N = PL::N, N1 = PL::N1, PR = PL::PR, LDC = N;
   constexpr int I0 = C * PR, Q0 = (I0 + NT - 1) / NT;
-  constexpr int IA = C * N1 * RB, QA = (IA + NT - 1) / NT;
   constexpr int KS = N / 2 + 1;  // spectrum rows
   constexpr int QI = (KS * C + NT - 1) / NT;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -392,8 +516,8 @@ __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_inv_pr(Geo g
       r1[q] = in[o + m];
     }
   };
-  // LDS slot of input k: row k mod N1, Rader slot of k mod PR
-  auto kslot = [&](int k) { return (k % N1) * PR + tb.slot[k % PR]; };
+  // LDS slot of input k: row k mod N1, the transform slot of k mod PR
+  auto kslot = [&](int k) { return (k % N1) * PR + tb.in_slot(k % PR); };
   if (tile < tw.ntiles) fetch(tile, pr_lane());
   while (tile < tw.ntiles) {
     const int lane = pr_lane();
@@ -413,24 +537,7 @@ __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_inv_pr(Geo g
     __syncthreads();
     const int nxt = tw.next(tile + stride, stride);
     if (nxt < tw.ntiles) fetch(nxt, lane);
-    pr_stages_ab<T, PL, C, NT>(buf, tb, lane);
-    // stage A', in place: row k1 then holds its PR-point DFT at j2 = g^q in slot q, j2 = 0 in slot RC
-#pragma unroll
-    for (int q = 0; q < QA; ++q) {
-      const int e = lane + q * NT;
-      if (e < IA) {
-        const int c = e % C, r = e / C;
-        const int k1 = r / RB, qb = r - k1 * RB;
-        cx<T>* row = buf + c * LDC + k1 * PR + qb;
-        cx<T> a[RA];
-#pragma unroll
-        for (int ka = 0; ka < RA; ++ka) a[ka] = row[ka * RB];
-        dft_odd_lit<T, 1, RA>(a);
-#pragma unroll
-        for (int qa = 0; qa < RA; ++qa) row[qa * RB] = a[qa];
-      }
-    }
-    __syncthreads();
+    pr_rows<T, PL, C, NT>(buf, tb, lane);
     // N1-point DFTs over the rows and the output: R_j at j = (PR j1 + N1 j2) mod n;
     // e_j = conj(R_j); z_2 = Re(e)/(n d_j), z_1 = Im(e) d_j/n; w_1 = z_1 - z_2, w_2 = z_1 + z_2
     double* w1 = w + (size_t)b * g.vs;
@@ -444,9 +551,9 @@ __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_inv_pr(Geo g
         cx<T> a[N1];
 #pragma unroll
         for (int k1 = 0; k1 < N1; ++k1) a[k1] = buf[c * LDC + k1 * PR + sl];
-        dft_odd_lit<T, -1, N1>(a);
+        dft_small<T, -1, N1>(a);
         if (i < m) {
-          const int j2 = sl == RC ? 0 : tb.gpw[sl];
+          const int j2 = tb.slot_index(sl);
 #pragma unroll
           for (int j1 = 0; j1 < N1; ++j1) {
             const int j = (PR * j1 + N1 * j2) % N;
@@ -476,7 +583,7 @@ static bool pr_launch(bool fwd, const Geo& g, const double* v, cx<T>* spec, doub
   static_assert(lds <= kLdsMax, "tile and tables fit LDS");
   if (g.n != PL::N) return false;
   const void* prt = sizeof(T) == 8 ? (const void*)tb.pr64 : (const void*)tb.pr32;
-  if (!prt) return false;
+  if (!PL::DIRECT && !prt) return false;
   auto kf = time_fwd_pr<T, PL, C, NT>;
   auto ki = time_inv_pr<T, PL, C, NT>;
   if constexpr (lds > 65536) {
@@ -504,28 +611,55 @@ static bool pr_launch(bool fwd, const Geo& g, const double* v, cx<T>* spec, doub
   return true;
 }
 
+// the Rader plans need the twiddle and filter tables of pcop_setup
 bool pr_params(int n, int* pr, int* gen) {
   if (n == Pr511::N) {
     *pr = Pr511::PR;
     *gen = Pr511::G;
     return true;
   }
+  if (n == Pr127::N) {
+    *pr = Pr127::PR;
+    *gen = Pr127::G;
+    return true;
+  }
+  if (n == Pr255::N) {
+    *pr = Pr255::PR;
+    *gen = Pr255::G;
+    return true;
+  }
   return false;
 }
 
-// c = 64: 8 columns per block, 256 threads; c = -64: 16 columns, 512
-// threads (output rows of whole 128-byte lines in FP64, one block per CU)
+// the automatic choice: the wide-tile kernels where they were measured faster
+// than the alternatives (n = 511, both precisions); other lengths are left to
+// the tuner
+int pr_auto(int n, int csz) { return n == Pr511::N && pr_exists(n, csz, -64) ? -64 : 0; }
+
+// c = 64: the plan's narrower tile with 256 threads; c = -64: the wider tile
+// with 512 threads (for n = 511 FP64 output rows of whole 128-byte lines)
 bool pr_exists(int n, int csz, int c) {
   (void)csz;
-  return (c == 64 || c == -64) && n == Pr511::N;
+  return (c == 64 || c == -64) && (n == Pr511::N || n == Pr127::N || n == Pr255::N);
+}
+
+template <class T, class PL>
+static bool pr_launch_c(bool fwd, int c, const Geo& g, const double* v, cx<T>* spec, double* w,
+                        const PrecondTables& tb, const double* vscale, int vs_stride, int accum, hipStream_t st) {
+  if (c == -64) return pr_launch<T, PL, PL::CN, 512>(fwd, g, v, spec, w, tb, vscale, vs_stride, accum, st);
+  return pr_launch<T, PL, PL::CP, 256>(fwd, g, v, spec, w, tb, vscale, vs_stride, accum, st);
 }
 
 template <class T>
 bool launch_time_pr(bool fwd, int c, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
                     const double* vscale, int vs_stride, int accum, hipStream_t st) {
   if (!pr_exists(g.n, (int)sizeof(cx<T>), c)) return false;
-  if (c == -64) return pr_launch<T, Pr511, 16, 512>(fwd, g, v, spec, w, tb, vscale, vs_stride, accum, st);
-  return pr_launch<T, Pr511, 8, 256>(fwd, g, v, spec, w, tb, vscale, vs_stride, accum, st);
+  switch (g.n) {
+    case Pr511::N: return pr_launch_c<T, Pr511>(fwd, c, g, v, spec, w, tb, vscale, vs_stride, accum, st);
+    case Pr127::N: return pr_launch_c<T, Pr127>(fwd, c, g, v, spec, w, tb, vscale, vs_stride, accum, st);
+    case Pr255::N: return pr_launch_c<T, Pr255>(fwd, c, g, v, spec, w, tb, vscale, vs_stride, accum, st);
+    default: return false;
+  }
 }
 
 template bool launch_time_pr<double>(bool, int, const Geo&, const double*, cx<double>*, double*, const PrecondTables&,
