@@ -52,18 +52,23 @@ constexpr int pr_inv_mod(int a, int m) {
 
 // N1 x PR with a Rader stage of RC = PR - 1 = RA RB (generator G), or, with
 // RA = RB = 0, the PR-point DFTs directly in registers; CP / CN spatial
-// points per tile for the 256- / 512-thread kernels (time_cols 64 / -64)
-template <int N1_, int PR_, int G_, int RA_, int RB_, int CP_, int CN_>
+// points per tile for the 256- / 512-thread kernels (time_cols 64 / -64),
+// CN32 for the 512-thread FP32 kernels
+template <int N1_, int PR_, int G_, int RA_, int RB_, int CP_, int CN_, int CN32_ = CN_>
 struct PrPlan {
   static constexpr int N1 = N1_, PR = PR_, G = G_, RA = RA_, RB = RB_, RC = PR_ - 1, N = N1_ * PR_;
   static constexpr bool DIRECT = RA_ == 0;
-  static constexpr int CP = CP_, CN = CN_;
+  static constexpr int CP = CP_, CN = CN_, CN32 = CN32_;
   static constexpr int KM1 = PR_ * pr_inv_mod(PR_ % N1_, N1_);  // output map: k = (KM1 k1 + KM2 k2) mod N
   static constexpr int KM2 = N1_ * pr_inv_mod(N1_ % PR_, PR_);
   static_assert(DIRECT || RA * RB == PR_ - 1, "the convolution length splits as RA RB");
 };
-// 511 = 7 x 73, generator 5 of the group mod 73, 72 = 9 x 8
-using Pr511 = PrPlan<7, 73, 5, 9, 8, 8, 16>;
+// 511 = 7 x 73, generator 5 of the group mod 73, 72 = 9 x 8.  The FP32
+// wide tile has 14 points: its 1022 stage-0 items take two rounds of 512
+// threads (16 points take three, and the prefetch registers of the third
+// round spill under the 128-VGPR bound two blocks per CU need); FP64 keeps
+// 16 points, whose output rows are whole 128-byte lines
+using Pr511 = PrPlan<7, 73, 5, 9, 8, 8, 16, 14>;
 // 127 prime, generator 3, 126 = 9 x 14
 using Pr127 = PrPlan<1, 127, 3, 9, 14, 16, 32>;
 // 255 = 15 x 17, generator 3 of the group mod 17, 16 = 4 x 4; tiles of 15
@@ -646,7 +651,10 @@ bool pr_exists(int n, int csz, int c) {
 template <class T, class PL>
 static bool pr_launch_c(bool fwd, int c, const Geo& g, const double* v, cx<T>* spec, double* w,
                         const PrecondTables& tb, const double* vscale, int vs_stride, int accum, hipStream_t st) {
-  if (c == -64) return pr_launch<T, PL, PL::CN, 512>(fwd, g, v, spec, w, tb, vscale, vs_stride, accum, st);
+  if (c == -64) {
+    constexpr int CN = sizeof(T) == 4 ? PL::CN32 : PL::CN;
+    return pr_launch<T, PL, CN, 512>(fwd, g, v, spec, w, tb, vscale, vs_stride, accum, st);
+  }
   return pr_launch<T, PL, PL::CP, 256>(fwd, g, v, spec, w, tb, vscale, vs_stride, accum, st);
 }
 
