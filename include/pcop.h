@@ -176,7 +176,14 @@ typedef struct {
  *   gs_update  Gram-Schmidt update kernel: 0 automatic (with tune = 1:
  *              chosen per basis size), 1 one element per thread and step,
  *              2 double2 pairs.
- *   stream     hipStream_t on which all work is enqueued. */
+ *   stream     hipStream_t on which all work is enqueued.
+ *   mg_smoother  the V-cycle's Gauss-Seidel pre-smoother (PCOP_MG; Section
+ *              3, Example 2 names Gauss-Seidel without an ordering): 0
+ *              red-black (red = even index sum first; the default), 1 one
+ *              sweep in the natural order (x1 fastest), 2 that sweep and
+ *              one in the reverse order.  1 and 2 walk the grid's
+ *              hyperplanes x1 + x2 (+ x3) = const one after another (one
+ *              block per frequency slice), so they are much slower than 0. */
 typedef struct {
   int precision;
   int spatial;
@@ -195,6 +202,7 @@ typedef struct {
   int krylov_blocks;
   int gs_update;
   void* stream;
+  int mg_smoother;
 } pcop_options;
 
 /* Per-member outcome of pcop_solve. */

@@ -5,8 +5,11 @@ infrastructure only).
 Section 3 (Example 2) fixes only: one V-cycle, a Gauss-Seidel pre-smoother,
 no post-smoother.  The remaining choices are this project's reading, stated
 once here and implemented identically on the GPU:
-  * zero initial guess; one red-black Gauss-Seidel sweep per level, red
-    (even index sum) points first, then black;
+  * zero initial guess; one Gauss-Seidel sweep per level, by default
+    red-black (red = even index sum points first, then black); optionally
+    ``smoother="lex"``, one sweep in the natural (lexicographic, x1 fastest)
+    order, or ``smoother="sym"``, that sweep followed by one in the reverse
+    order (symmetric Gauss-Seidel);
   * vertex-centred coarsening nx -> (nx-1)/2 (nx = 2^p - 1) down to a single
     point, which is solved exactly;
   * coarse operators re-discretised: sigma I + tau K_a with the coarse mesh
@@ -20,6 +23,7 @@ from typing import Callable, List, Optional
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from .discretize import stiffness
 
@@ -60,11 +64,14 @@ def red_mask(dim: int, nx: int) -> np.ndarray:
 class ShiftedVCycle:
     """Hierarchy for sigma I + tau K_a; ``apply(r)`` is one V-cycle from z = 0."""
 
-    def __init__(self, dim: int, nx: int, tau: float, coeff: Optional[Callable] = None):
+    def __init__(self, dim: int, nx: int, tau: float, coeff: Optional[Callable] = None, smoother: str = "rb"):
         if nx < 1 or (nx + 1) & nx:
             raise ValueError("multigrid needs nx = 2^p - 1")
+        if smoother not in ("rb", "lex", "sym"):
+            raise ValueError(smoother)
         self.dim = dim
         self.tau = tau
+        self.smoother = smoother
         self.levels: List[dict] = []
         n = nx
         while True:
@@ -84,18 +91,32 @@ class ShiftedVCycle:
         return (sigma * sp.identity(m, format="csr", dtype=np.complex128)
                 + self.tau * lev["K"].astype(np.complex128)).tocsr()
 
+    def smooth(self, l: int, r: np.ndarray, sigma: complex) -> np.ndarray:
+        """The pre-smoothing sweep(s) on level l from z = 0."""
+        lev = self.levels[l]
+        A = self._matrix(lev, sigma)
+        if self.smoother == "rb":
+            d = A.diagonal()
+            off = A - sp.diags(d)
+            red = lev["red"]
+            z = np.zeros_like(r)
+            # one red-black Gauss-Seidel sweep: red points, then black points
+            z[red] = ((r - off @ z) / d)[red]
+            z[~red] = ((r - off @ z) / d)[~red]
+            return z
+        # a Gauss-Seidel sweep in the natural order from z = 0 solves with the
+        # lower triangle D + L of A; the reverse sweep corrects with D + U
+        z = spla.spsolve_triangular(sp.tril(A, format="csr"), r, lower=True)
+        if self.smoother == "sym":
+            z = z + spla.spsolve_triangular(sp.triu(A, format="csr"), r - A @ z, lower=False)
+        return z
+
     def _cycle(self, l: int, r: np.ndarray, sigma: complex) -> np.ndarray:
         lev = self.levels[l]
         A = self._matrix(lev, sigma)
         if lev["nx"] == 1:
             return r / A.diagonal()
-        d = A.diagonal()
-        off = A - sp.diags(d)
-        red = lev["red"]
-        z = np.zeros_like(r)
-        # one red-black Gauss-Seidel sweep: red points, then black points
-        z[red] = ((r - off @ z) / d)[red]
-        z[~red] = ((r - off @ z) / d)[~red]
+        z = self.smooth(l, r, sigma)
         res = r - A @ z
         ec = self._cycle(l + 1, lev["R"] @ res, sigma)
         return z + lev["P"] @ ec

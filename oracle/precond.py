@@ -43,9 +43,10 @@ class EpsCirculantRBD:
     ``spatial="lu"`` solves the shifted systems of Step 2 exactly (sparse
     LU per frequency); ``spatial="mg"`` replaces each solve by one V-cycle of
     the multigrid in :mod:`oracle.multigrid` (Section 3, Example 2), which
-    needs the coefficient function ``coeff`` (None means a = 1)."""
+    needs the coefficient function ``coeff`` (None means a = 1) and takes
+    the V-cycle's ``smoother`` ("rb", "lex" or "sym")."""
 
-    def __init__(self, pb: Problem, spatial: str = "lu", coeff=None):
+    def __init__(self, pb: Problem, spatial: str = "lu", coeff=None, smoother: str = "rb"):
         self.pb = pb
         n, m = pb.n, pb.m
         self.F = fourier_matrix(n)
@@ -60,7 +61,7 @@ class EpsCirculantRBD:
             self.lu = [spla.splu(((self.lam[k] + pb.alpha) * Mc + pb.tau * Kc).tocsc()) for k in range(n)]
         elif spatial == "mg":
             from .multigrid import ShiftedVCycle
-            self.mg = ShiftedVCycle(pb.dim, pb.nx, pb.tau, coeff)
+            self.mg = ShiftedVCycle(pb.dim, pb.nx, pb.tau, coeff, smoother)
         else:
             raise ValueError(spatial)
 
@@ -133,7 +134,7 @@ class IdealRBD:
     1 + alpha instead, as for the non-diagonalisable K of Example 2
     (Section 3)."""
 
-    def __init__(self, pb: Problem, spatial: str = "lu", coeff=None):
+    def __init__(self, pb: Problem, spatial: str = "lu", coeff=None, smoother: str = "rb"):
         self.pb = pb
         m = pb.m
         self.spatial = spatial
@@ -142,7 +143,7 @@ class IdealRBD:
             self.lu = spla.splu(T0.tocsc())
         elif spatial == "mg":
             from .multigrid import ShiftedVCycle
-            self.mg = ShiftedVCycle(pb.dim, pb.nx, pb.tau, coeff)
+            self.mg = ShiftedVCycle(pb.dim, pb.nx, pb.tau, coeff, smoother)
         else:
             raise ValueError(spatial)
 

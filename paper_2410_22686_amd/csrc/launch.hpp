@@ -83,6 +83,7 @@ struct PrecondTables {
   const KTimer* timer;   // or null
   FftPlan plan;          // radices of n
   int mg_levels;
+  int mg_smoother;       // 0 red-black, 1 lexicographic, 2 symmetric lexicographic Gauss-Seidel
   MgLevel mg[kMaxMgLevels];
   const void* mg_res;    // finest-level residual scratch [B][2K][m] complex
 };

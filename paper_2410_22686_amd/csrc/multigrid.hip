@@ -3,7 +3,8 @@
 // Section 3, Example 2: one V-cycle, Gauss-Seidel pre-smoother, no
 // post-smoother).  All slices of all members go through one launch per level.
 //
-// Cycle (from z = 0):
+// Cycle (from z = 0; the lexicographic smoothers of mg_smoother = 1, 2 are
+// described at their kernels):
 //   smooth    one red-black Gauss-Seidel sweep, red = even index sum first.
 //             Red points: z = r / d; black points use the red values
 //             z_nb = r_nb / d_nb, recomputed on the fly, so the sweep is one
@@ -160,8 +161,9 @@ __global__ void __launch_bounds__(256) mg_residual_kernel(int nx, int m, int sli
 }
 
 // coarse right-hand side by full weighting of the fine residual (red points
-// only; the black ones are zero)
-template <class T, int DIM>
+// only after a red-black sweep, where the black ones are zero; ALL: every
+// point, after the lexicographic sweeps)
+template <class T, int DIM, bool ALL>
 __global__ void __launch_bounds__(256) mg_restrict_kernel(int nxf, int mf, int nxc, int mc,
                                                           const cx<T>* __restrict__ res, cx<T>* __restrict__ rc,
                                                           MgShift sh) {
@@ -179,7 +181,7 @@ __global__ void __launch_bounds__(256) mg_restrict_kernel(int nxf, int mf, int n
     for (int d1 = -1; d1 <= 1; ++d1)
       for (int d0 = -1; d0 <= 1; ++d0) {
         const int f0 = 2 * C[0] + 1 + d0, f1 = 2 * C[1] + 1 + d1, f2 = (DIM == 3) ? 2 * C[2] + 1 + d2 : 0;
-        if (((f0 + f1 + f2) & 1) != 0) continue;
+        if (!ALL && ((f0 + f1 + f2) & 1) != 0) continue;
         const T w = (d0 == 0 ? (T)1 : (T)0.5) * (d1 == 0 ? (T)1 : (T)0.5) * (d2 == 0 ? (T)1 : (T)0.5);
         acc = acc + scale(rs[f0 + nxf * (f1 + nxf * f2)], w);
       }
@@ -255,6 +257,97 @@ __global__ void __launch_bounds__(256) mg_prolong_kernel(int nxf, int mf, int nx
   }
 }
 
+// ---------------------------------------------------------------------------
+// Lexicographic Gauss-Seidel (mg_smoother = 1, and = 2 followed by the
+// reverse sweep): the natural order (x1 fastest) makes point x depend on its
+// minus neighbours, which lie on the hyperplane x1 + x2 (+ x3) one below.
+// One block per slice walks the hyperplanes in order (reverse order for the
+// backward sweep) with a block barrier between them; the points of one
+// hyperplane are independent.  z lives in global memory (a slice does not fit
+// LDS); within a block the barrier orders the stores and the later loads.
+//   forward   z_x = (r_x - sum_{minus nb} off z_nb) / d_x          (z = 0 before)
+//   backward  z_x = (r_x - sum_{all nb} off z_nb) / d_x             (in place)
+// ---------------------------------------------------------------------------
+template <class T, int DIM, bool BACK>
+__global__ void __launch_bounds__(256) mg_sweep_lex_kernel(int nx, int m, const T* __restrict__ coef,
+                                                           const cx<T>* __restrict__ r, cx<T>* z, MgShift sh) {
+  const int s = blockIdx.x;
+  if (sh.active && !sh.active[s / sh.twoK]) return;
+  const cx<T> sig = slice_sigma<T>(sh, s);
+  const cx<T>* rs = r + (size_t)s * m;
+  cx<T>* zs = z + (size_t)s * m;
+  const int top = DIM * (nx - 1);
+  for (int step = 0; step <= top; ++step) {
+    const int w = BACK ? top - step : step;
+    // points with x1 + x2 (+ x3) = w: x3 (3-D) and x1 over a box, x2 from w
+    const int x3lo = DIM == 3 ? max(0, w - 2 * (nx - 1)) : 0;
+    const int x3hi = DIM == 3 ? min(w, nx - 1) : 0;
+    const int box = (x3hi - x3lo + 1) * nx;
+    for (int t = threadIdx.x; t < box; t += blockDim.x) {
+      const int x3 = x3lo + t / nx, x1 = t - (t / nx) * nx;
+      const int x2 = w - x3 - x1;
+      if (x2 < 0 || x2 >= nx) continue;
+      const int c[3] = {x1, x2, x3};
+      const int i = x1 + nx * (x2 + nx * x3);
+      cx<T> acc = rs[i];
+      int stride = 1;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        if (c[a] > 0) acc = acc - scale(zs[i - stride], coef[(size_t)(1 + 2 * a) * m + i]);
+        if (BACK && c[a] < nx - 1) acc = acc - scale(zs[i + stride], coef[(size_t)(2 + 2 * a) * m + i]);
+        stride *= nx;
+      }
+      zs[i] = cdiv(acc, cx<T>{sig.x + coef[i], sig.y});
+    }
+    __syncthreads();
+  }
+}
+
+// r <- r - A z at every point (in place: each point reads only its own r),
+// for the lexicographic sweeps, after which the residual is nonzero everywhere
+template <class T, int DIM, int SB>
+__global__ void __launch_bounds__(256) mg_residual_full_kernel(int nx, int m, int slices, const T* __restrict__ coef,
+                                                               const cx<T>* __restrict__ z, cx<T>* res, MgShift sh) {
+  const int2 bk = mg_block();
+  const int i = bk.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  int f[3];
+  coords(i, nx, DIM, f);
+  int nbo[2 * DIM];
+  bool has[2 * DIM];
+  T off[2 * DIM];
+  {
+    int stride = 1;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      has[2 * a] = f[a] > 0;
+      has[2 * a + 1] = f[a] < nx - 1;
+      nbo[2 * a] = -stride;
+      nbo[2 * a + 1] = stride;
+      off[2 * a] = has[2 * a] ? coef[(size_t)(1 + 2 * a) * m + i] : (T)0;
+      off[2 * a + 1] = has[2 * a + 1] ? coef[(size_t)(2 + 2 * a) * m + i] : (T)0;
+      stride *= nx;
+    }
+  }
+  const T cdg = coef[i];
+  const int s0 = bk.y * SB;
+#pragma unroll
+  for (int k = 0; k < SB; ++k) {
+    const int s = s0 + k;
+    if (s >= slices) break;
+    if (sh.active && !sh.active[s / sh.twoK]) continue;
+    const cx<T> sig = slice_sigma<T>(sh, s);
+    const cx<T>* zs = z + (size_t)s * m;
+    const cx<T> zi = zs[i];
+    // (sigma + cdg) z_i
+    cx<T> acc = res[(size_t)s * m + i] - cx<T>{(sig.x + cdg) * zi.x - sig.y * zi.y, (sig.x + cdg) * zi.y + sig.y * zi.x};
+#pragma unroll
+    for (int n = 0; n < 2 * DIM; ++n)
+      if (has[n]) acc = acc - scale(zs[i + nbo[n]], off[n]);
+    res[(size_t)s * m + i] = acc;
+  }
+}
+
 // slices per thread of the smoother, the residual and the prolongation on
 // levels where that still gives at least kMgMinBlocks blocks (one slice per
 // thread below)
@@ -267,6 +360,8 @@ static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, int spm
   const int NL = tb.mg_levels;
   const int slices = g.B * spm;
   MgShift sh{lam, tb.alpha, tb.active, spm};
+  // the smoother: red-black (0), lexicographic (1), symmetric lexicographic (2)
+  const bool lex = tb.mg_smoother != 0;
   auto coefp = [&](int l) -> const T* {
     return reinterpret_cast<const T*>(sizeof(T) == 4 ? (const void*)tb.mg[l].coef : (const void*)tb.mg[l].coef64);
   };
@@ -288,8 +383,15 @@ static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, int spm
     const int m = (int)tb.mg[l].m;
     const dim3 gridb = grid_sb(m);
     tbeg(tb.timer, KF_MG_SMOOTH, 2.0 * cs * m);
-    if (wide(m)) mg_smooth_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), rbuf(l), zbuf(l), sh);
-    else mg_smooth_kernel<T, DIM, 1><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), rbuf(l), zbuf(l), sh);
+    if (lex) {
+      mg_sweep_lex_kernel<T, DIM, false><<<slices, 256, 0, st>>>(nx, m, coefp(l), rbuf(l), zbuf(l), sh);
+      if (tb.mg_smoother == 2)
+        mg_sweep_lex_kernel<T, DIM, true><<<slices, 256, 0, st>>>(nx, m, coefp(l), rbuf(l), zbuf(l), sh);
+    } else if (wide(m)) {
+      mg_smooth_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), rbuf(l), zbuf(l), sh);
+    } else {
+      mg_smooth_kernel<T, DIM, 1><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), rbuf(l), zbuf(l), sh);
+    }
     tend(tb.timer);
     if (l + 1 < NL) {
       const int nxc = tb.mg[l + 1].nx;
@@ -297,10 +399,22 @@ static void mg_cycle(const Geo& g, cx<T>* spec, const PrecondTables& tb, int spm
       dim3 gc((mc + 255) / 256, slices);
       // residual into the consumed right-hand side (half the points), then
       // full weighting
-      tbeg(tb.timer, KF_MG_RESTRICT, cs * (m + 0.5 * m + 0.5 * m + mc));
-      if (wide(m)) mg_residual_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), zbuf(l), rbuf(l), sh);
-      else mg_residual_kernel<T, DIM, 1><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), zbuf(l), rbuf(l), sh);
-      mg_restrict_kernel<T, DIM><<<gc, 256, 0, st>>>(nx, m, nxc, mc, rbuf(l), rbuf(l + 1), sh);
+      if (lex) {
+        // r - A z at every point, in place, then full weighting of all points
+        tbeg(tb.timer, KF_MG_RESTRICT, cs * (3.0 * m + m + mc));
+        if (wide(m))
+          mg_residual_full_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), zbuf(l), rbuf(l), sh);
+        else
+          mg_residual_full_kernel<T, DIM, 1><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), zbuf(l), rbuf(l), sh);
+        mg_restrict_kernel<T, DIM, true><<<gc, 256, 0, st>>>(nx, m, nxc, mc, rbuf(l), rbuf(l + 1), sh);
+      } else {
+        tbeg(tb.timer, KF_MG_RESTRICT, cs * (m + 0.5 * m + 0.5 * m + mc));
+        if (wide(m))
+          mg_residual_kernel<T, DIM, kMgSB><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), zbuf(l), rbuf(l), sh);
+        else
+          mg_residual_kernel<T, DIM, 1><<<gridb, 256, 0, st>>>(nx, m, slices, coefp(l), zbuf(l), rbuf(l), sh);
+        mg_restrict_kernel<T, DIM, false><<<gc, 256, 0, st>>>(nx, m, nxc, mc, rbuf(l), rbuf(l + 1), sh);
+      }
       tend(tb.timer);
     }
   }

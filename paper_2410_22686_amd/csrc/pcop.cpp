@@ -134,6 +134,7 @@ pcop_status validate(const pcop_problem* p, const pcop_options* o) {
   if (o->krylov_blocks < 0 || o->krylov_blocks > 4096)
     return fail(PCOP_ERR_INVALID_ARG, "krylov_blocks must be in 0..4096");
   if (o->gs_update < 0 || o->gs_update > 2) return fail(PCOP_ERR_INVALID_ARG, "gs_update must be 0, 1 or 2");
+  if (o->mg_smoother < 0 || o->mg_smoother > 2) return fail(PCOP_ERR_INVALID_ARG, "mg_smoother must be 0, 1 or 2");
   if (o->precision == PCOP_MIXED && o->side != PCOP_FLEXIBLE)
     return fail(PCOP_ERR_INVALID_ARG, "the mixed-precision preconditioner needs side = PCOP_FLEXIBLE");
   if (o->spatial == PCOP_DST) {
@@ -1135,6 +1136,7 @@ pcop_status pcop_setup(pcop_ctx* out, const pcop_problem* prob, const pcop_optio
   tb.pr64 = L.RC > 0 ? c->at<double>(L.pr64) : nullptr;
   tb.pr32 = L.RC > 0 ? c->at<float>(L.pr32) : nullptr;
   tb.time_cols = opts->time_cols;
+  tb.mg_smoother = opts->mg_smoother;
   tb.dst_variant = (opts->dst_kernel >= 2) ? opts->dst_kernel - 1 : 0;
   c->nb_mdot.fill(opts->krylov_blocks > 0 ? opts->krylov_blocks : L.nblk);
   c->nb_upd = c->nb_mdot;

@@ -58,7 +58,7 @@ class c_options(ctypes.Structure):
                 ("graph", ctypes.c_int), ("graph_chunk", ctypes.c_int), ("reorth_tol", ctypes.c_double),
                 ("time_cols", ctypes.c_int), ("dst_kernel", ctypes.c_int), ("tune", ctypes.c_int),
                 ("precond", ctypes.c_int), ("kkt_jchunk", ctypes.c_int), ("krylov_blocks", ctypes.c_int),
-                ("gs_update", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("gs_update", ctypes.c_int), ("stream", ctypes.c_void_p), ("mg_smoother", ctypes.c_int)]
 
 
 class c_kernel_stat(ctypes.Structure):
@@ -146,6 +146,7 @@ _SPAT = {"dst": PCOP_DST, "mg": PCOP_MG}
 _SIDE = {"right": PCOP_RIGHT, "left": PCOP_LEFT, "flexible": PCOP_FLEXIBLE}
 _PRECOND = {"eps": PCOP_PRECOND_EPS, "ideal": PCOP_PRECOND_IDEAL}
 _MASS = {"identity": PCOP_MASS_IDENTITY, "q1": PCOP_MASS_Q1}
+_MG_SMOOTHER = {"rb": 0, "lex": 1, "sym": 2}
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -173,7 +174,8 @@ class Solver:
                  rtol: float = 1e-8, graph: bool = False, graph_chunk: int = 4, reorth_tol: float = 1e-8,
                  time_cols: int = 0, dst_kernel: int = 0, tune: bool = False, precond: str = "eps",
                  kkt_jchunk: int = 0, krylov_blocks: int = 0, gs_update: int = 0, mass: str = "identity",
-                 device: Union[str, torch.device] = "cuda", stream: Optional[torch.cuda.Stream] = None):
+                 device: Union[str, torch.device] = "cuda", stream: Optional[torch.cuda.Stream] = None,
+                 mg_smoother: str = "rb"):
         import numpy as np
         self.lib = load_library()
         if not torch.cuda.is_available():
@@ -205,6 +207,7 @@ class Solver:
         opts.time_cols, opts.dst_kernel, opts.tune = int(time_cols), int(dst_kernel), int(bool(tune))
         opts.precond = _PRECOND[precond]
         opts.kkt_jchunk, opts.krylov_blocks, opts.gs_update = int(kkt_jchunk), int(krylov_blocks), int(gs_update)
+        opts.mg_smoother = _MG_SMOOTHER[mg_smoother]
         self.stream = stream
         with torch.cuda.device(self.device):
             st = stream if stream is not None else torch.cuda.current_stream(self.device)

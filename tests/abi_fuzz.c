@@ -63,6 +63,7 @@ static void random_options(pcop_options* o) {
   if (pick(4) == 0) o->kkt_jchunk = pick(140) - 70;
   if (pick(4) == 0) o->krylov_blocks = pick(5000) - 2;
   if (pick(4) == 0) o->gs_update = pick(5) - 1;
+  if (pick(6) == 0) o->mg_smoother = pick(5) - 1;
 }
 
 int main(int argc, char** argv) {

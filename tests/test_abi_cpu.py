@@ -85,7 +85,8 @@ def test_invalid_options_are_rejected(lib):
                dict(precision=1, side=0), dict(graph=1, graph_chunk=0), dict(time_cols=2),
                dict(time_cols=-2), dict(time_cols=128), dict(time_cols=-128), dict(dst_kernel=6), dict(dst_kernel=-1), dict(tune=2),
                dict(precond=2), dict(precond=-1), dict(kkt_jchunk=65), dict(kkt_jchunk=-65),
-               dict(krylov_blocks=4097), dict(krylov_blocks=-2), dict(gs_update=3)]:
+               dict(krylov_blocks=4097), dict(krylov_blocks=-2), dict(gs_update=3),
+               dict(mg_smoother=3), dict(mg_smoother=-1)]:
         assert lib.pcop_validate(ctypes.byref(p), ctypes.byref(_opts(lib, **kw))) == 1, kw
 
 
@@ -96,7 +97,8 @@ def test_kernel_choice_options_validate(lib):
     for kw in [dict(time_cols=-1), dict(time_cols=4), dict(time_cols=8), dict(time_cols=16),
                dict(time_cols=-4), dict(time_cols=-8), dict(time_cols=-16), dict(time_cols=32), dict(time_cols=-32), dict(time_cols=64), dict(time_cols=-64), dict(precond=1),
                dict(kkt_jchunk=4), dict(kkt_jchunk=-16), dict(krylov_blocks=512), dict(gs_update=2),
-               dict(dst_kernel=1), dict(dst_kernel=2), dict(dst_kernel=3), dict(dst_kernel=4), dict(dst_kernel=5), dict(tune=1)]:
+               dict(dst_kernel=1), dict(dst_kernel=2), dict(dst_kernel=3), dict(dst_kernel=4), dict(dst_kernel=5), dict(tune=1),
+               dict(mg_smoother=1), dict(mg_smoother=2)]:
         assert lib.pcop_validate(ctypes.byref(p), ctypes.byref(_opts(lib, **kw))) == 0, kw
 
 

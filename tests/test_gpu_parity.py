@@ -401,6 +401,35 @@ def test_precond_apply_multigrid(dim, nx, nt, gammas, coeff, precision):
     check(w, wo, 1e-11 if precision == "fp64" else 1e-5, len(gammas), nt - 1, nx ** dim, label="mg apply")
 
 
+LEX_CASES = [
+    # dim, nx, nt, gammas, coefficient: the lexicographic smoothers
+    (2, 15, 12, (1e-3, 1e-8), W.coeff_sines3d),
+    (2, 31, 20, (1e-2,), W.coeff_example2),
+    (3, 7, 9, (1e-5,), W.coeff_sines3d),
+    (2, 1, 5, (1e-3,), W.coeff_sines3d),       # single point: the sweep is the exact solve
+    (2, 127, 130, (1e-4,), W.coeff_example2),  # the residual kernel with eight slices per thread
+    (3, 31, 38, (1e-3, 1e-7), W.coeff_sines3d),
+]
+
+
+@pytest.mark.parametrize("dim,nx,nt,gammas,coeff", LEX_CASES)
+@pytest.mark.parametrize("smoother", ["lex", "sym"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_precond_apply_multigrid_lexicographic(dim, nx, nt, gammas, coeff, smoother, precision):
+    """mg_smoother = 1 / 2: the V-cycle with a Gauss-Seidel sweep in the
+    natural order (then the reverse order) against the oracle's cycle with
+    the same smoother."""
+    print(f"precond mg {smoother} {precision} dim={dim} nx={nx} nt={nt} B={len(gammas)}", flush=True)
+    side = "flexible" if precision == "mixed" else "right"
+    s = Solver(dim, nx, nt, list(gammas), coeff=coeff, spatial="mg", precision=precision, side=side,
+               mg_smoother=smoother, device=DEV)
+    v = W.random_vector(dim, nx, nt, seed=19, batch=len(gammas))
+    w = s.precond_apply(to_dev(v)).cpu().numpy()
+    wo = np.stack([P.EpsCirculantRBD(pb, spatial="mg", coeff=coeff, smoother=smoother).apply(v[b].ravel())
+                   for b, pb in enumerate(problems(dim, nx, nt, gammas, coeff=coeff))])
+    check(w, wo, 1e-11 if precision == "fp64" else 1e-5, len(gammas), nt - 1, nx ** dim, label=f"mg {smoother}")
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_multigrid_flexible_solve(precision):
     # 3-D sparse direct solves grow quickly on the host: keep the oracle side small

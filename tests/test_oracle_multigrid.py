@@ -91,3 +91,48 @@ def test_vcycle_is_linear():
 def test_vcycle_rejects_non_dyadic_grid():
     with pytest.raises(ValueError):
         ShiftedVCycle(2, 6, 0.1)
+
+
+def _gauss_seidel_points(A, r, order):
+    """Gauss-Seidel by its definition, one point at a time in the given order
+    (dense, tiny grids only)."""
+    A = A.toarray()
+    z = np.zeros_like(r)
+    for i in order:
+        z[i] = (r[i] - A[i] @ z + A[i, i] * z[i]) / A[i, i]
+    return z
+
+
+@pytest.mark.parametrize("dim,nx,coeff", [(2, 7, None), (2, 7, W.coeff_example2), (3, 3, W.coeff_sines3d)])
+@pytest.mark.parametrize("smoother", ["lex", "sym", "rb"])
+def test_smoother_is_gauss_seidel_in_its_order(dim, nx, coeff, smoother):
+    """The smoothers are Gauss-Seidel sweeps from z = 0: lexicographic (natural
+    index order), symmetric (that order, then the reverse), red-black (even
+    index sums first); checked against point-by-point sweeps."""
+    tau, sigma = 0.1, 0.7 - 0.3j
+    mg = ShiftedVCycle(dim, nx, tau, coeff, smoother=smoother)
+    A = (sigma * sp.identity(nx ** dim) + tau * D.stiffness(dim, nx, coeff)).astype(np.complex128).tocsr()
+    r = np.random.default_rng(3).standard_normal(nx ** dim) + 1j * np.random.default_rng(4).standard_normal(nx ** dim)
+    m = nx ** dim
+    if smoother == "rb":
+        red = red_mask(dim, nx)
+        order = list(np.flatnonzero(red)) + list(np.flatnonzero(~red))
+    else:
+        order = list(range(m))
+        if smoother == "sym":
+            order = order + order[::-1]
+    z_ref = _gauss_seidel_points(A, r, order)
+    assert np.linalg.norm(mg.smooth(0, r, sigma) - z_ref) < 1e-13 * np.linalg.norm(z_ref)
+
+
+@pytest.mark.parametrize("smoother", ["lex", "sym"])
+def test_lexicographic_vcycle_is_a_convergent_iteration(smoother):
+    dim, nx, tau, sigma = 2, 31, 1 / 32, 1.1 + 0.3j
+    mg = ShiftedVCycle(dim, nx, tau, W.coeff_example2, smoother=smoother)
+    A = (sigma * sp.identity(nx ** dim) + tau * D.stiffness(dim, nx, W.coeff_example2)).tocsc()
+    r = np.random.default_rng(0).standard_normal(nx ** dim) + 0j
+    z_ex = spla.spsolve(A, r)
+    z = np.zeros_like(r)
+    for _ in range(8):
+        z = z + mg.apply(r - A @ z, sigma)
+    assert np.linalg.norm(z - z_ex) < 1e-3 * np.linalg.norm(z_ex)
