@@ -64,6 +64,28 @@ def test_ideal_precond_apply(dim, nx, nt, gammas, coeff, spatial, precision):
         assert err < tol
 
 
+@pytest.mark.parametrize("dim,nx,nt,gammas,coeff", [(2, 15, 12, (1e-3,), W.coeff_sines3d),
+                                                     (3, 7, 6, (1e-5, 1e-1), W.coeff_sines3d),
+                                                     (2, 31, 10, (1e-2,), W.coeff_example2)])
+@pytest.mark.parametrize("smoother", ["lex", "sym"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_ideal_precond_apply_lexicographic(dim, nx, nt, gammas, coeff, smoother, precision):
+    """The ideal preconditioner with the lexicographic / symmetric
+    Gauss-Seidel V-cycle against the oracle's IdealRBD with the same smoother."""
+    side = "flexible" if precision == "mixed" else "right"
+    s = Solver(dim, nx, nt, list(gammas), coeff=coeff, spatial="mg", precision=precision, side=side,
+               precond="ideal", mg_smoother=smoother, device=DEV)
+    v = W.random_vector(dim, nx, nt, seed=29, batch=len(gammas))
+    w = s.precond_apply(to_dev(v)).cpu().numpy()
+    tol = 1e-5 if precision == "mixed" else 1e-12
+    for b, gm in enumerate(gammas):
+        pb = D.make_problem(dim, nx, nt, gm, coeff=coeff)
+        wo = P.IdealRBD(pb, spatial="mg", coeff=coeff, smoother=smoother).apply(v[b].ravel())
+        err = rel(w[b], wo)
+        print(f"ideal {smoother} {precision} member {b}: rel err {err:.2e}", flush=True)
+        assert err < tol
+
+
 @pytest.mark.parametrize("side", ["right", "left", "flexible"])
 def test_ideal_solve_converges_to_direct_solution(side):
     """The right-preconditioned solve adds P^{-1}(V y) into x (accumulating
