@@ -137,9 +137,53 @@ __global__ void __launch_bounds__(NT) dst_lines_kernel(Geo g, cx<T>* __restrict_
 // positions (element s = q + r 8/R), so the first stage reads the odd
 // extension straight from the input and the last stage (Ns R = L) leaves the
 // transform in natural order in registers; between stages one LDS exchange.
-// LDS index is padded by one complex per 8 to spread the stage writes.
+// LDS slots are swizzled rather than padded (pidx below).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int pidx(int pos) { return pos + (pos >> 3); }
+
+// LDS slot of position p of a line.  gfx950's LDS serves a 16-byte read to
+// 16 lanes per pass, without conflict when their slots differ modulo 16, a
+// 16-byte write to 8 lanes per pass (slots differing modulo 8), and 8-byte
+// reads and writes to 16 lanes (8-byte slots differing modulo 16); this was
+// measured with single-instruction loops over fixed lane patterns.  The
+// accesses of a line are runs of consecutive positions (stage reads, the
+// post-pass writes), stride-8 runs (first-stage writes, p = 8t + r) and
+// stride-4 runs (the post-pass reads, p = 4t + i).  XOR-ing the low three
+// bits of p with a function h of its 8-slot block b = p / 8 keeps all three
+// conflict-free: h takes eight distinct values on any eight consecutive
+// blocks (stride-8 writes), and distinct low two bits on the four blocks of
+// equal parity inside eight (stride-4 reads).  With 8-byte slots a stride-8
+// run of 16 lanes covers sixteen blocks, so bit 3 of p is also flipped by
+// bit 3 of b.  Every slot stays in the aligned group of 8 (16-byte slots, or
+// positions below 64) or 16 of its position, so a line of X positions needs
+// X slots when X is a multiple of 16.
+template <class T>
+__device__ __forceinline__ int pidx(int p) {
+  const int b = p >> 3;
+  if constexpr (sizeof(T) == 8) return p ^ (((b >> 1) & 3) | ((b & 1) << 2));
+  else return p ^ (((b >> 1) & 7) | (b & 8));
+}
+
+// Synchronisation of the threads of one line around an exchange through the
+// line's own LDS slots.  A line of at most 64 threads lies inside one
+// wavefront, whose LDS instructions complete in issue order, so a compiler
+// barrier suffices to keep its writes before its reads (and its reads
+// before the next writes); longer lines span several wavefronts and take
+// the block barrier.
+template <int TL>
+__device__ __forceinline__ void line_sync() {
+  if constexpr (TL <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// LDS row length of a line of X positions: X once a line fills whole lane
+// groups (X >= 128); shorter lines share a wave's lane groups, and one pad
+// slot per 8 then keeps neighbouring lines on different banks
+constexpr int line_ld(int X) { return X <= 64 ? X + X / 8 : X; }
 
 template <class T, int L, int TL, int SG, int NS>
 struct RegStages {
@@ -179,18 +223,18 @@ struct RegStages {
     }
     if constexpr (NS * R < L) {
       // exchange: outputs to LDS, next stage's inputs back
-      __syncthreads();
+      line_sync<TL>();
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const int jb = t + TL * q;
         const int jl = jb % NS;
         const int base = (jb - jl) * R + jl;
 #pragma unroll
-        for (int r = 0; r < R; ++r) lbuf[pidx(base + r * NS)] = v[q + r * Q];
+        for (int r = 0; r < R; ++r) lbuf[pidx<T>(base + r * NS)] = v[q + r * Q];
       }
-      __syncthreads();
+      line_sync<TL>();
 #pragma unroll
-      for (int s = 0; s < 8; ++s) v[s] = lbuf[pidx(t + TL * s)];
+      for (int s = 0; s < 8; ++s) v[s] = lbuf[pidx<T>(t + TL * s)];
       RegStages<T, L, TL, SG, NS * R>::run(v, t, lbuf, twL);
     }
   }
@@ -230,18 +274,18 @@ __device__ __forceinline__ void divide_line(cx<T> (&v)[8], int t, const Geo& g, 
 template <class T, int L, int TL>
 __device__ __forceinline__ void odd_extend(cx<T> (&v)[8], int t, cx<T>* lbuf) {
   constexpr int N = L / 2 - 1;
-  __syncthreads();
+  line_sync<TL>();
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     const int pos = t + TL * s;
-    if (pos >= 1 && pos <= N) lbuf[pidx(pos)] = v[s];
+    if (pos >= 1 && pos <= N) lbuf[pidx<T>(pos)] = v[s];
   }
-  __syncthreads();
+  line_sync<TL>();
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     const int pos = t + TL * s;
     if (pos >= N + 2) {
-      const cx<T> z = lbuf[pidx(L - pos)];
+      const cx<T> z = lbuf[pidx<T>(L - pos)];
       v[s] = cx<T>{-z.x, -z.y};
     } else if (pos == 0 || pos == N + 1) {
       v[s] = cx<T>{0, 0};
@@ -257,7 +301,7 @@ __global__ void __launch_bounds__(256) dst_reg_kernel(Geo g, cx<T>* __restrict__
   constexpr int N = L / 2 - 1;
   constexpr int TL = L / 8;
   constexpr int LPB = 256 / TL;
-  constexpr int LD = L + L / 8 + 1;
+  constexpr int LD = line_ld(L);
   __shared__ cx<T> buf[LPB * LD];
   const int tiles = (lg.lines + LPB - 1) / LPB;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -314,7 +358,7 @@ __global__ void __launch_bounds__(NT) dst_col_kernel(Geo g, cx<T>* __restrict__ 
   constexpr int N = L / 2 - 1;
   constexpr int TL = L / 8;
   constexpr int LPB = NT / TL;
-  constexpr int LD = L + L / 8 + 1;
+  constexpr int LD = line_ld(L);
   constexpr int QS = (N * LPB + NT - 1) / NT;  // tile elements per thread
   __shared__ cx<T> buf[LPB * LD];
   // twiddles and 1-D eigenvalues in LDS: inside the loop the only global
@@ -366,7 +410,7 @@ __global__ void __launch_bounds__(NT) dst_col_kernel(Geo g, cx<T>* __restrict__ 
       const int idx = threadIdx.x + NT * q;
       if (idx < N * LPB) {
         const int e = idx / LPB, l = idx - (idx / LPB) * LPB;
-        buf[l * LD + pidx(e)] = pre[q];
+        buf[l * LD + pidx<T>(e)] = pre[q];
       }
     }
     __syncthreads();
@@ -377,9 +421,9 @@ __global__ void __launch_bounds__(NT) dst_col_kernel(Geo g, cx<T>* __restrict__ 
     for (int s = 0; s < 8; ++s) {
       const int pos = t + TL * s;
       if (pos >= 1 && pos <= N) {
-        v[s] = lbuf[pidx(pos - 1)];
+        v[s] = lbuf[pidx<T>(pos - 1)];
       } else if (pos >= N + 2) {
-        const cx<T> z = lbuf[pidx(L - 1 - pos)];
+        const cx<T> z = lbuf[pidx<T>(L - 1 - pos)];
         v[s] = cx<T>{-z.x, -z.y};
       } else {
         v[s] = cx<T>{0, 0};
@@ -395,7 +439,7 @@ __global__ void __launch_bounds__(NT) dst_col_kernel(Geo g, cx<T>* __restrict__ 
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       const int pos = t + TL * s;
-      if (pos >= 1 && pos <= N) lbuf[pidx(pos - 1)] = v[s];
+      if (pos >= 1 && pos <= N) lbuf[pidx<T>(pos - 1)] = v[s];
     }
     __syncthreads();
 #pragma unroll
@@ -403,7 +447,7 @@ __global__ void __launch_bounds__(NT) dst_col_kernel(Geo g, cx<T>* __restrict__ 
       const int idx = threadIdx.x + NT * q;
       const int e = idx / LPB, l = idx - (idx / LPB) * LPB;
       if (idx < N * LPB && l0 + l < lg.lines)
-        data[pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride] = buf[l * LD + pidx(e)];
+        data[pbase + (long long)(l0 + l) * lg.line_stride + (long long)e * lg.elem_stride] = buf[l * LD + pidx<T>(e)];
     }
     __syncthreads();
     blk = nxt;
@@ -435,7 +479,7 @@ struct HalfDst {
       if (j == 0) {
         v[s] = cx<T>{0, 0};
       } else {
-        const cx<T> a = lbuf[pidx(j - 1)], b = lbuf[pidx(M - j - 1)];
+        const cx<T> a = lbuf[pidx<T>(j - 1)], b = lbuf[pidx<T>(M - j - 1)];
         const T sj = sinl[j];
         const cx<T> sum = a + b, dif = a - b;
         v[s] = cx<T>{sj * sum.x + (T)0.5 * dif.x, sj * sum.y + (T)0.5 * dif.y};
@@ -446,16 +490,16 @@ struct HalfDst {
   // 8t .. 8t + 7 (o[r] = Y_{8t + r}); the prefix sum runs over the TM
   // threads of the line, which sit in one wavefront
   static __device__ __forceinline__ void post(cx<T> (&v)[8], cx<T> (&o)[8], int t, cx<T>* lbuf) {
-    __syncthreads();
+    line_sync<TM>();
 #pragma unroll
-    for (int s = 0; s < 8; ++s) lbuf[pidx(t + TM * s)] = v[s];
-    __syncthreads();
+    for (int s = 0; s < 8; ++s) lbuf[pidx<T>(t + TM * s)] = v[s];
+    line_sync<TM>();
     cx<T> c[4], e[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int k = 4 * t + i;
-      const cx<T> uk = lbuf[pidx(k)];
-      const cx<T> um = lbuf[pidx(k == 0 ? 0 : M - k)];
+      const cx<T> uk = lbuf[pidx<T>(k)];
+      const cx<T> um = lbuf[pidx<T>(k == 0 ? 0 : M - k)];
       c[i] = (k == 0) ? uk : uk + um;
       e[i] = uk - um;
     }
@@ -492,12 +536,16 @@ __global__ void __launch_bounds__(NT) dst_half_kernel(Geo g, cx<T>* __restrict__
   constexpr bool DIVIDE = DIVIDE_ != 0;
   constexpr int M = H::M, N = H::N, TM = H::TM;
   constexpr int LPB = NT / TM;
-  constexpr int LD = M + M / 8 + 1;
+  // tile rows: with four lanes on four elements of one line (QUAD below),
+  // a row length of 4 mod 16 slots puts a 16-lane read of 4 lines x 4
+  // elements and an 8-lane write of 2 lines x 4 elements on distinct banks
+  constexpr bool QUAD = TM >= 4;
+  constexpr int LD = M >= 128 ? M + 4 : line_ld(M);
   constexpr int QS = (N * LPB + NT - 1) / NT;  // tile elements per thread
   static_assert(LPB * TM == NT, "a tile is a whole number of lines");
   __shared__ cx<T> buf[LPB * LD];
   // length-M twiddles exp(-2 pi i t/M) = twL[2t], sines sin(pi j/M) = -Im twL[j],
-  // 1-D eigenvalues: in LDS, so that the prefetch is the only global load in the loop
+  // 1-D eigenvalues: in LDS, so that the tile's loads are the only global loads in the loop
   __shared__ cx<T> twm[M];
   __shared__ T sinl[M];
   __shared__ double mul[DIVIDE ? N : 1];
@@ -518,37 +566,40 @@ __global__ void __launch_bounds__(NT) dst_half_kernel(Geo g, cx<T>* __restrict__
       while (blk < total && !dp.active[(int)((blk / tiles) / dp.spm)]) blk += gridDim.x;
     return blk;
   };
-  cx<T> pre[QS];
   // element e of line l0 + l sits at (l0 + l) line_stride + e elem_stride
-  // inside its plane (an in-plane offset, below 2^31); a thread always
-  // handles line l = threadIdx.x mod LPB of the tile
-  const int tl = threadIdx.x % LPB, te = threadIdx.x / LPB;
-  auto fetch = [&](long long blk) {
-    const long long plane = blk / tiles;
-    const int l0 = (int)(blk - plane * tiles) * LPB;
-    const cx<T>* src = data + plane * lg.plane_stride;
-    const bool lok = l0 + tl < lg.lines;
-    const int off = (l0 + tl) * lg.line_stride + te * lg.elem_stride;
-#pragma unroll
-    for (int q = 0; q < QS; ++q) {
-      const bool ok = threadIdx.x + NT * q < N * LPB && lok;
-      pre[q] = ok ? src[off + q * (NT / LPB) * lg.elem_stride] : cx<T>{0, 0};
-    }
-  };
+  // inside its plane (an in-plane offset, below 2^31).  A thread always
+  // handles line tl of the tile, elements te + TM q: with QUAD, thread
+  // 4 LPB a + 4 l + c takes line l and te = c + 4a, else line
+  // threadIdx.x mod LPB and te = threadIdx.x / LPB (both cover every
+  // (line, element) pair once; a wave's loads span the same rows either way)
+  const int tl = QUAD ? (threadIdx.x >> 2) % LPB : threadIdx.x % LPB;
+  const int te = QUAD ? (threadIdx.x & 3) + 4 * (threadIdx.x / (4 * LPB)) : threadIdx.x / LPB;
   long long blk = next(xcd_remap(blockIdx.x, gridDim.x));
-  if (blk < total) fetch(blk);
   while (blk < total) {
     const long long plane = blk / tiles;
     const int l0 = (int)(blk - plane * tiles) * LPB;
     const long long pbase = plane * lg.plane_stride;
     const int line = l0 + lid;
     const bool valid = line < lg.lines;
+    {
+      // the tile's loads, straight into LDS (a register prefetch of the
+      // next tile was measured slower: its 32 extra registers per thread
+      // cost a wave per SIMD in FP64 and stalled the FP32 kernel)
+      const cx<T>* src = data + pbase;
+      const bool lok = l0 + tl < lg.lines;
+      const int off = (l0 + tl) * lg.line_stride + te * lg.elem_stride;
+      cx<T> cur[QS];
 #pragma unroll
-    for (int q = 0; q < QS; ++q)
-      if (threadIdx.x + NT * q < N * LPB) buf[tl * LD + pidx(te + q * (NT / LPB))] = pre[q];
+      for (int q = 0; q < QS; ++q) {
+        const bool ok = te + TM * q < N && lok;
+        cur[q] = ok ? src[off + q * TM * lg.elem_stride] : cx<T>{0, 0};
+      }
+#pragma unroll
+      for (int q = 0; q < QS; ++q)
+        if (te + TM * q < N) buf[tl * LD + pidx<T>(te + TM * q)] = cur[q];
+    }
     __syncthreads();
     const long long nxt = next(blk + gridDim.x);
-    if (nxt < total) fetch(nxt);
     cx<T> v[8], o[8];
     H::pre(v, t, lbuf, sinl);
     RegStages<T, M, TM, -1, 1>::run(v, t, lbuf, twm);
@@ -578,22 +629,22 @@ __global__ void __launch_bounds__(NT) dst_half_kernel(Geo g, cx<T>* __restrict__
         }
       }
       // the divided values become the input of the inverse transform
-      __syncthreads();
+      line_sync<TM>();
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int pos = 8 * t + r;
-        if (pos >= 1 && pos <= N) lbuf[pidx(pos - 1)] = o[r];
+        if (pos >= 1 && pos <= N) lbuf[pidx<T>(pos - 1)] = o[r];
       }
-      __syncthreads();
+      line_sync<TM>();
       H::pre(v, t, lbuf, sinl);
       RegStages<T, M, TM, -1, 1>::run(v, t, lbuf, twm);
       H::post(v, o, t, lbuf);
     }
-    __syncthreads();
+    line_sync<TM>();
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const int pos = 8 * t + r;
-      if (pos >= 1 && pos <= N) lbuf[pidx(pos - 1)] = o[r];
+      if (pos >= 1 && pos <= N) lbuf[pidx<T>(pos - 1)] = o[r];
     }
     __syncthreads();
     if (l0 + tl < lg.lines) {
@@ -601,8 +652,8 @@ __global__ void __launch_bounds__(NT) dst_half_kernel(Geo g, cx<T>* __restrict__
       const int off = (l0 + tl) * lg.line_stride + te * lg.elem_stride;
 #pragma unroll
       for (int q = 0; q < QS; ++q) {
-        const int e = te + q * (NT / LPB);
-        if (threadIdx.x + NT * q < N * LPB) dstp[off + q * (NT / LPB) * lg.elem_stride] = buf[tl * LD + pidx(e)];
+        const int e = te + TM * q;
+        if (e < N) dstp[off + q * TM * lg.elem_stride] = buf[tl * LD + pidx<T>(e)];
       }
     }
     __syncthreads();
@@ -622,7 +673,7 @@ __global__ void __launch_bounds__(NT) dst_half_rows_kernel(Geo g, cx<T>* __restr
   using H = HalfDst<T, L>;
   constexpr int M = H::M, N = H::N, TM = H::TM;
   constexpr int LPB = NT / TM;
-  constexpr int LD = M + M / 8 + 1;
+  constexpr int LD = line_ld(M);
   constexpr int QS = (N * LPB + NT - 1) / NT;
   static_assert(LPB * TM == NT, "a tile is a whole number of lines");
   __shared__ cx<T> buf[LPB * LD];
@@ -666,7 +717,7 @@ __global__ void __launch_bounds__(NT) dst_half_rows_kernel(Geo g, cx<T>* __restr
     const int l0 = (int)(blk - plane * tiles) * LPB;
 #pragma unroll
     for (int q = 0; q < QS; ++q)
-      if (threadIdx.x + NT * q < N * LPB) buf[sl[q] * LD + pidx(se[q])] = pre[q];
+      if (threadIdx.x + NT * q < N * LPB) buf[sl[q] * LD + pidx<T>(se[q])] = pre[q];
     __syncthreads();
     const long long nxt = blk + gridDim.x;
     if (nxt < total) fetch(nxt);
@@ -674,18 +725,18 @@ __global__ void __launch_bounds__(NT) dst_half_rows_kernel(Geo g, cx<T>* __restr
     H::pre(v, t, lbuf, sinl);
     RegStages<T, M, TM, -1, 1>::run(v, t, lbuf, twm);
     H::post(v, o, t, lbuf);
-    __syncthreads();
+    line_sync<TM>();
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const int pos = 8 * t + r;
-      if (pos >= 1 && pos <= N) lbuf[pidx(pos - 1)] = o[r];
+      if (pos >= 1 && pos <= N) lbuf[pidx<T>(pos - 1)] = o[r];
     }
     __syncthreads();
     cx<T>* dstp = data + plane * lg.plane_stride;
 #pragma unroll
     for (int q = 0; q < QS; ++q)
       if (threadIdx.x + NT * q < N * LPB && l0 + sl[q] < lg.lines)
-        dstp[(l0 + sl[q]) * lg.line_stride + se[q] * lg.elem_stride] = buf[sl[q] * LD + pidx(se[q])];
+        dstp[(l0 + sl[q]) * lg.line_stride + se[q] * lg.elem_stride] = buf[sl[q] * LD + pidx<T>(se[q])];
     __syncthreads();
     blk = nxt;
   }
