@@ -687,9 +687,13 @@ pcop_status tune_kernels(pcop_ctx c) {
   // the restart length, and the best block count moves with the number of
   // vectors streamed (more blocks hide more latency once the kernels hold
   // many vectors in registers, fewer finish short sweeps sooner).  The
+  // samples are dense where the compiled multi-dot changes shape: from 19
+  // vectors on it keeps fewer loads in flight per thread, and with 512
+  // blocks it was measured at 4.3 TB/s against 6.7 with 1024 (at 18 vectors
+  // 512 blocks are the fastest), so 18 and 20 are both sampled.  The
   // vectors are zeroed first, the coefficients and skip flags too.
   std::vector<int> nvs;
-  for (int nv : {1, 4, 8, 16, 24, 32, 40})
+  for (int nv : {1, 2, 4, 8, 12, 16, 18, 20, 24, 28, 32, 36, 40})
     if (nv < c->opt.restart) nvs.push_back(nv);
   nvs.push_back(c->opt.restart);
   if (err == hipSuccess)
