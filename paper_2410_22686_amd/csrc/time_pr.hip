@@ -64,10 +64,11 @@ struct PrPlan {
   static_assert(DIRECT || RA * RB == PR_ - 1, "the convolution length splits as RA RB");
 };
 // 511 = 7 x 73, generator 5 of the group mod 73, 72 = 9 x 8.  The FP32
-// wide tile has 14 points: its 1022 stage-0 items take two rounds of 512
-// threads (16 points take three, and the prefetch registers of the third
-// round spill under the 128-VGPR bound two blocks per CU need); FP64 keeps
-// 16 points, whose output rows are whole 128-byte lines
+// wide forward tile has 14 points: its 1022 stage-0 items take two rounds of
+// 512 threads (16 points take three, and the prefetch registers of the third
+// round spill under the 128-VGPR bound two blocks per CU need); FP64, and
+// the FP32 inverse, keep 16 points, whose output rows are whole 128-byte
+// lines
 using Pr511 = PrPlan<7, 73, 5, 9, 8, 8, 16, 14>;
 // 127 prime, generator 3, 126 = 9 x 14
 using Pr127 = PrPlan<1, 127, 3, 9, 14, 16, 32>;
@@ -581,38 +582,33 @@ __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_inv_pr(Geo g
   }
 }
 
-template <class T, class PL, int C, int NT>
-static bool pr_launch(bool fwd, const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
+template <class T, class PL, int C, int NT, bool FWD>
+static bool pr_launch(const Geo& g, const double* v, cx<T>* spec, double* w, const PrecondTables& tb,
                       const double* vscale, int vs_stride, int accum, hipStream_t st) {
   constexpr size_t lds = pr_lds_bytes<PL>(C, (int)sizeof(cx<T>));
   static_assert(lds <= kLdsMax, "tile and tables fit LDS");
   if (g.n != PL::N) return false;
   const void* prt = sizeof(T) == 8 ? (const void*)tb.pr64 : (const void*)tb.pr32;
   if (!PL::DIRECT && !prt) return false;
-  auto kf = time_fwd_pr<T, PL, C, NT>;
-  auto ki = time_inv_pr<T, PL, C, NT>;
-  if constexpr (lds > 65536) {
-    // above 64 KiB of dynamic LDS the kernels must opt in (once each)
-    static bool attr_set = false;
-    if (!attr_set) {
-      attr_set = true;
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kf), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)kLdsMax);
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(ki), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)kLdsMax);
-      (void)hipGetLastError();
-    }
-  }
   TileWalk twk{(g.m + C - 1) / C, 0, tb.active};
   twk.ntiles = twk.tpm * g.B;
-  // persistent grid: as many blocks as stay resident on every CU
-  if (fwd) {
-    const int grid = std::min(twk.ntiles, resident_blocks(kf, NT, lds) * std::max(1, tb.ncu));
-    kf<<<std::max(grid, 1), NT, lds, st>>>(g, v, spec, tb.dpow, prt, vscale, vs_stride, twk);
-  } else {
-    const int grid = std::min(twk.ntiles, resident_blocks(ki, NT, lds) * std::max(1, tb.ncu));
-    ki<<<std::max(grid, 1), NT, lds, st>>>(g, spec, w, tb.dpow, prt, accum, twk);
-  }
+  auto launch = [&](auto kern, auto... args) {
+    if constexpr (lds > 65536) {
+      // above 64 KiB of dynamic LDS the kernel must opt in (once)
+      static bool attr_set = false;
+      if (!attr_set) {
+        attr_set = true;
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)kLdsMax);
+        (void)hipGetLastError();
+      }
+    }
+    // persistent grid: as many blocks as stay resident on every CU
+    const int grid = std::min(twk.ntiles, resident_blocks(kern, NT, lds) * std::max(1, tb.ncu));
+    kern<<<std::max(grid, 1), NT, lds, st>>>(args...);
+  };
+  if constexpr (FWD) launch(time_fwd_pr<T, PL, C, NT>, g, v, spec, tb.dpow, prt, vscale, vs_stride, twk);
+  else launch(time_inv_pr<T, PL, C, NT>, g, spec, w, tb.dpow, prt, accum, twk);
   return true;
 }
 
@@ -652,10 +648,15 @@ template <class T, class PL>
 static bool pr_launch_c(bool fwd, int c, const Geo& g, const double* v, cx<T>* spec, double* w,
                         const PrecondTables& tb, const double* vscale, int vs_stride, int accum, hipStream_t st) {
   if (c == -64) {
-    constexpr int CN = sizeof(T) == 4 ? PL::CN32 : PL::CN;
-    return pr_launch<T, PL, CN, 512>(fwd, g, v, spec, w, tb, vscale, vs_stride, accum, st);
+    // the FP32 forward kernel takes the narrower CN32 tile; the inverse
+    // holds fewer registers per item and keeps the full CN tile, whose
+    // output rows are whole 128-byte lines in FP64 words
+    constexpr int CF = sizeof(T) == 4 ? PL::CN32 : PL::CN;
+    if (fwd) return pr_launch<T, PL, CF, 512, true>(g, v, spec, w, tb, vscale, vs_stride, accum, st);
+    return pr_launch<T, PL, PL::CN, 512, false>(g, v, spec, w, tb, vscale, vs_stride, accum, st);
   }
-  return pr_launch<T, PL, PL::CP, 256>(fwd, g, v, spec, w, tb, vscale, vs_stride, accum, st);
+  if (fwd) return pr_launch<T, PL, PL::CP, 256, true>(g, v, spec, w, tb, vscale, vs_stride, accum, st);
+  return pr_launch<T, PL, PL::CP, 256, false>(g, v, spec, w, tb, vscale, vs_stride, accum, st);
 }
 
 template <class T>
