@@ -134,10 +134,12 @@ def test_config3_mixed_vs_fp64():
             print(f"  fp64: ||P w - v|| / ||v|| = {res:.2e}", flush=True)
             assert res < 2e-9
         else:
-            # FP32 chirp-z time passes (n = 511, convolution length M = 1024): the
-            # two length-M FFTs round by about u log2 M (u = 6e-8), which D_eps^{-1}
-            # amplifies by up to 1/eps = sqrt(n) in the last levels; the bar is
-            # twice that product, as for the chirp-z kernel choices
+            # FP32 time passes at n = 511: the tuner takes the prime-factor
+            # kernels (7 x 73, Rader convolutions of length 72) or the chirp-z
+            # ones (convolution length M = 1024); the bar is that of the
+            # looser, chirp-z: two length-M FFTs round by about u log2 M
+            # (u = 6e-8), which D_eps^{-1} amplifies by up to 1/eps = sqrt(n)
+            # in the last levels, and the bar is twice that product
             tol32 = 2 * 6e-8 * math.log2(1024) * math.sqrt(cfg.n)
             check(ws["mixed"], ws["fp64"], tol32, 1, cfg.n, cfg.m, label="FP32 apply vs FP64 apply")
         b = s.rhs(torch.tensor(g, device=DEV), torch.tensor(f, device=DEV), torch.tensor(y0, device=DEV))
