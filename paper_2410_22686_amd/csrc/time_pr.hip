@@ -295,12 +295,16 @@ __device__ __forceinline__ void pr_twiddle(cx<T>* a, int base, const PrTables<T,
       w = w * w1;
     }
   } else {
-    // FP32: every twiddle from the correctly rounded table
+    // FP32: every twiddle from the correctly rounded table, at r base mod RC
+    // kept reduced by a conditional subtraction (base < RC)
+    int e = base;
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      cx<T> w = tb.tw[(r * base) % PL::RC];
+      cx<T> w = tb.tw[e];
       if (SG > 0) w.y = -w.y;
       a[r] = a[r] * w;
+      e += base;
+      if (e >= PL::RC) e -= PL::RC;
     }
   }
 }
@@ -438,13 +442,18 @@ __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_fwd_pr(Geo g
     for (int q = 0; q < Q0; ++q) {
       const int e = lane + q * NT;
       const int c = e % C, j2 = e / C, i = i0 + c;
+      // level j = (PR j1 + N1 j2) mod N: N1 j2 < N for the tile's items, and
+      // each step of j1 adds PR < N, so one conditional subtraction reduces it
+      int j = N1 * j2;
 #pragma unroll
       for (int j1 = 0; j1 < N1; ++j1) {
         // unconditional loads from an in-bounds index: items e >= I0 are
         // not committed and columns i >= m are never stored
-        const size_t o = (e < I0 && i < m) ? (size_t)((PR * j1 + N1 * j2) % N) * m + i : 0;
+        const size_t o = (e < I0 && i < m) ? (size_t)j * m + i : 0;
         r1[q][j1] = v1[o];
         r2[q][j1] = v2[o];
+        j += PR;
+        if (j >= N) j -= N;
       }
     }
   };
@@ -461,10 +470,12 @@ __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_fwd_pr(Geo g
       if (e < I0) {
         const int c = e % C, j2 = e / C;
         cx<T> a[N1];
+        int j = N1 * j2;  // (PR j1 + N1 j2) mod N, as in the fetch
 #pragma unroll
         for (int j1 = 0; j1 < N1; ++j1) {
-          const int j = (PR * j1 + N1 * j2) % N;
           a[j1] = cx<T>{(T)(s * tb.da[j] * r2[q][j1]), (T)(s * tb.db[j] * r1[q][j1])};
+          j += PR;
+          if (j >= N) j -= N;
         }
         dft_small<T, -1, N1>(a);
         cx<T>* col = buf + c * LDC + tb.in_slot(j2);
@@ -523,7 +534,7 @@ __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_inv_pr(Geo g
     }
   };
   // LDS slot of input k: row k mod N1, the transform slot of k mod PR
-  auto kslot = [&](int k) { return (k % N1) * PR + tb.in_slot(k % PR); };
+  auto kslot = [&](int k1, int k2) { return k1 * PR + tb.in_slot(k2); };
   if (tile < tw.ntiles) fetch(tile, pr_lane());
   while (tile < tw.ntiles) {
     const int lane = pr_lane();
@@ -536,8 +547,11 @@ __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_inv_pr(Geo g
       if (e < KS * C) {
         const int k = e / C, p = e - k * C;
         const cx<T> z2 = r2[q], z1 = r1[q];
-        buf[p * LDC + kslot(k)] = cx<T>{z2.x - z1.y, -(z2.y + z1.x)};
-        if (k != 0 && 2 * k != N) buf[p * LDC + kslot(N - k)] = cx<T>{z2.x + z1.y, -(z1.x - z2.y)};
+        // residues of n - k from those of k (N1 and PR divide n)
+        const int k1 = k % N1, k2 = k % PR;
+        buf[p * LDC + kslot(k1, k2)] = cx<T>{z2.x - z1.y, -(z2.y + z1.x)};
+        if (k != 0 && 2 * k != N)
+          buf[p * LDC + kslot(k1 ? N1 - k1 : 0, k2 ? PR - k2 : 0)] = cx<T>{z2.x + z1.y, -(z1.x - z2.y)};
       }
     }
     __syncthreads();
@@ -560,9 +574,12 @@ __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_inv_pr(Geo g
         dft_small<T, -1, N1>(a);
         if (i < m) {
           const int j2 = tb.slot_index(sl);
+          int jn = N1 * j2;  // (PR j1 + N1 j2) mod N, one conditional subtraction per step
 #pragma unroll
           for (int j1 = 0; j1 < N1; ++j1) {
-            const int j = (PR * j1 + N1 * j2) % N;
+            const int j = jn;
+            jn += PR;
+            if (jn >= N) jn -= N;
             const double z2 = (double)a[j1].x * tb.db[j];
             const double z1 = -(double)a[j1].y * tb.da[j];
             const size_t o = (size_t)j * m + i;
