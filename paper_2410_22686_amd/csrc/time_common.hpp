@@ -53,6 +53,32 @@ __device__ __forceinline__ void unpack_store(cx<T>* out, int n, int K, int P, in
   }
 }
 
+// unpack_store with the tile shape fixed at compile time (KP = K P items over
+// NT threads) and every store unconditional: an item past the tile's last
+// column (or past KP) is replaced by the tile's last valid one and stores the
+// same value to the same place.  With no store behind a branch, the wait for
+// the next tile's prefetched loads need not wait for this tile's stores.
+template <class T, int NT, int K, int P, class GET>
+__device__ __forceinline__ void unpack_store_u(cx<T>* out, int n, int i0, int m, int lane, GET get) {
+  constexpr int KP = K * P, Q = (KP + NT - 1) / NT;
+  const int pmax = (m - i0 < P ? m - i0 : P) - 1;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    int t = lane + q * NT;
+    if (KP % NT != 0 && t >= KP) t = KP - 1;
+    const int k = t / P;
+    int p = t - k * P;
+    if (p > pmax) p = pmax;
+    const int i = i0 + p;
+    const int kn = (k == 0) ? 0 : n - k;
+    const cx<T> X = get(k, p);
+    const cx<T> Y = conj(get(kn, p));
+    const cx<T> sum = X + Y, dif = X - Y;
+    out[(size_t)(2 * k) * m + i] = cx<T>{sum.x * (T)0.5, sum.y * (T)0.5};
+    out[(size_t)(2 * k + 1) * m + i] = cx<T>{dif.y * (T)0.5, -dif.x * (T)0.5};  // dif / (2i)
+  }
+}
+
 // w_1 = z_1 - z_2, w_2 = z_1 + z_2 with z_2 = Re(e)/(n d_j), z_1 = Im(e) d_j/n
 // (factors 1/(n d_j) and d_j/n formed first, as in every time kernel)
 __device__ __forceinline__ void combine_store(double* w1, double* w2, const double* dpow, int n, int m, int j,
@@ -78,9 +104,14 @@ struct TileWalk {
   int tpm;     // tiles per member
   int ntiles;  // B * tpm
   const int* active;
-  // first tile at or after t (stepping by stride) whose member is active
+  // first tile at or after t (stepping by stride) whose member is active.
+  // t is uniform over the block and the flags do not change during a launch,
+  // so they are read through the constant address space (scalar loads): a
+  // vector load here would make the wave wait for every store it has in flight
   __device__ __forceinline__ int next(int t, int stride) const {
-    while (t < ntiles && active && !active[t / tpm]) t += stride;
+    if (!active) return t;
+    const __attribute__((address_space(4))) int* a = (const __attribute__((address_space(4))) int*)active;
+    while (t < ntiles && !a[t / tpm]) t += stride;
     return t;
   }
 };

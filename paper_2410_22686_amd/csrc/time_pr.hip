@@ -441,15 +441,17 @@ __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_fwd_pr(Geo g
 #pragma unroll
     for (int q = 0; q < Q0; ++q) {
       const int e = lane + q * NT;
-      const int c = e % C, j2 = e / C, i = i0 + c;
-      // level j = (PR j1 + N1 j2) mod N: N1 j2 < N for the tile's items, and
-      // each step of j1 adds PR < N, so one conditional subtraction reduces it
+      // a wave past the last item skips the round (a uniform branch)
+      if (I0 % NT != 0 && q == Q0 - 1 && __builtin_amdgcn_readfirstlane(e) >= I0) continue;
+      // loads from a clamped in-bounds index: items e >= I0 are not
+      // committed and columns i >= m are never stored
+      const int c = e % C, j2 = min(e / C, PR - 1), i = min(i0 + c, m - 1);
+      // level j = (PR j1 + N1 j2) mod N: N1 j2 < N, and each step of j1 adds
+      // PR < N, so one conditional subtraction reduces it
       int j = N1 * j2;
 #pragma unroll
       for (int j1 = 0; j1 < N1; ++j1) {
-        // unconditional loads from an in-bounds index: items e >= I0 are
-        // not committed and columns i >= m are never stored
-        const size_t o = (e < I0 && i < m) ? (size_t)j * m + i : 0;
+        const size_t o = (size_t)j * m + i;
         r1[q][j1] = v1[o];
         r2[q][j1] = v2[o];
         j += PR;
@@ -457,13 +459,11 @@ __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_fwd_pr(Geo g
       }
     }
   };
-  if (tile < tw.ntiles) fetch(tile, pr_lane());
-  while (tile < tw.ntiles) {
-    const int lane = pr_lane();
-    const int b = tile / tw.tpm;
-    const int i0 = (tile - b * tw.tpm) * C;
+  // stage 0 of a tile: x_j = s (d_j v2_j + i v1_j / d_j) from the prefetch
+  // registers, N1-point DFTs over j1, into the Rader slots
+  auto stage0 = [&](int t, int lane) {
+    const int b = t / tw.tpm;
     const double s = vscale ? vscale[(size_t)b * vs_stride] : 1.0;
-    // stage 0: x_j = s (d_j v2_j + i v1_j / d_j), N1-point DFTs over j1, into the Rader slots
 #pragma unroll
     for (int q = 0; q < Q0; ++q) {
       const int e = lane + q * NT;
@@ -483,17 +483,30 @@ __global__ void __launch_bounds__(NT, (pr_min_waves<T, NT>())) time_fwd_pr(Geo g
         for (int k1 = 0; k1 < N1; ++k1) col[k1 * PR] = a[k1];
       }
     }
+  };
+  // The first tile's stage 0 is peeled off the loop, so that inside it stage
+  // 0 always follows the previous tile's (unconditional) stores and the wait
+  // for its prefetched inputs leaves those stores in flight.
+  if (tile < tw.ntiles) {
+    fetch(tile, pr_lane());
+    stage0(tile, pr_lane());
+  }
+  while (tile < tw.ntiles) {
+    const int lane = pr_lane();
+    const int b = tile / tw.tpm;
+    const int i0 = (tile - b * tw.tpm) * C;
     __syncthreads();
     const int nxt = tw.next(tile + stride, stride);
     if (nxt < tw.ntiles) fetch(nxt, lane);
     pr_rows<T, PL, C, NT>(buf, tb, lane);
     cx<T>* out = spec + (size_t)b * (size_t)(2 * K) * m;
-    unpack_store<T>(out, N, K, C, i0, m, [&](int k, int p) {
+    unpack_store_u<T, NT, N / 2 + 1, C>(out, N, i0, m, lane, [&](int k, int p) {
       const int k1 = k % N1, k2 = k % PR;
       return buf[p * LDC + k1 * PR + tb.out_slot(k2)];
     });
     __syncthreads();
     tile = nxt;
+    if (tile < tw.ntiles) stage0(tile, lane);
   }
 }
 
