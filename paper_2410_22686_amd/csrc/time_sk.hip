@@ -28,6 +28,16 @@ struct PlanRT {};
 template <int... R>
 struct PlanCT {};
 
+// the transform length of a compile-time plan (0 for the run-time plan)
+template <class PL>
+struct plan_len {
+  static constexpr int value = 0;
+};
+template <int... R>
+struct plan_len<PlanCT<R...>> {
+  static constexpr int value = (R * ...);
+};
+
 template <class T, int P, int SG, bool LASTOUT, int NS, int R, int... RS>
 struct StagesCT {
   template <class LAST>
@@ -107,18 +117,19 @@ __global__ void __launch_bounds__(NT) time_fwd_sk(Geo g, const double* __restric
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int e = threadIdx.x + q * NT;
-      const int j = e / P, i = i0 + (e % P);
-      const bool in = e < nP && i < m;
-      r1[q] = in ? v1[(size_t)j * m + i] : 0.0;
-      r2[q] = in ? v2[(size_t)j * m + i] : 0.0;
+      // a wave past the tile's last element skips the round (a uniform
+      // branch); the others load from a clamped in-bounds index (elements
+      // e >= nP are not committed and columns i >= m are never stored)
+      if (__builtin_amdgcn_readfirstlane(e) >= nP) continue;
+      const int j = min(e / P, n - 1), i = min(i0 + (e % P), m - 1);
+      r1[q] = v1[(size_t)j * m + i];
+      r2[q] = v2[(size_t)j * m + i];
     }
   };
-  if (tile < tw.ntiles) fetch(tile);
-  while (tile < tw.ntiles) {
-    const int b = tile / tw.tpm;
-    const int i0 = (tile - b * tw.tpm) * P;
+  // c_j = s (d_j v2_j + i v1_j / d_j), stored at [j][p] = element e
+  auto stage0 = [&](int t) {
+    const int b = t / tw.tpm;
     const double s = vscale ? vscale[(size_t)b * vs_stride] : 1.0;
-    // c_j = s (d_j v2_j + i v1_j / d_j), stored at [j][p] = element e
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int e = threadIdx.x + q * NT;
@@ -127,15 +138,34 @@ __global__ void __launch_bounds__(NT) time_fwd_sk(Geo g, const double* __restric
         bufA[e] = cx<T>{(T)(s * dp_l[j] * r2[q]), (T)(s * di_l[j] * r1[q])};
       }
     }
+  };
+  // The first tile's stage 0 is peeled off the loop: inside it stage 0
+  // follows the previous tile's stores, and with the compile-time plan
+  // (every store unconditional) its wait for the prefetched inputs leaves
+  // those stores in flight.
+  if (tile < tw.ntiles) {
+    fetch(tile);
+    stage0(tile);
+  }
+  while (tile < tw.ntiles) {
+    const int b = tile / tw.tpm;
+    const int i0 = (tile - b * tw.tpm) * P;
     __syncthreads();
     const int nxt = tw.next(tile + stride, stride);
     if (nxt < tw.ntiles) fetch(nxt);
     auto none = [](int, int, cx<T>) {};
     cx<T>* src = run_stages<T, P, -1, false>(PL{}, plan, n, tw_l, bufA, bufB, none);
     cx<T>* out = spec + (size_t)b * (size_t)(2 * K) * m;
-    unpack_store<T>(out, n, K, P, i0, m, [&](int k, int p) { return src[k * P + p]; });
+    // the unrolled store rounds cost registers: only the 512-thread tiles
+    // (one block per CU, below 256 registers either way) take them
+    constexpr int NL = plan_len<PL>::value;
+    if constexpr (NL > 0 && NT == 512)
+      unpack_store_u<T, NT, NL / 2 + 1, P>(out, n, i0, m, threadIdx.x, [&](int k, int p) { return src[k * P + p]; });
+    else
+      unpack_store<T>(out, n, K, P, i0, m, [&](int k, int p) { return src[k * P + p]; });
     __syncthreads();
     tile = nxt;
+    if (tile < tw.ntiles) stage0(tile);
   }
 }
 
