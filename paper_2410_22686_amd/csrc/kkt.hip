@@ -234,6 +234,141 @@ __global__ void __launch_bounds__(256) kkt_lds_kernel(
   }
 }
 
+// The 2-D matvec with the residual form a compile-time switch and no store
+// behind a per-lane branch (operations per element as in kkt_lds_kernel).
+// A lane past the last point repeats the last point, the first level is
+// peeled off the level loop, and the staging loads use clamped indices
+// with the zeros outside the grid applied at the LDS commit; the wait for
+// the next level's prefetched values then leaves this level's stores in
+// flight.  (In 3-D the same structure took more registers, one wave per
+// SIMD fewer, and ran slower; kkt_lds_kernel serves 3-D.)
+template <bool VAR, int PT, int HQ, bool RES>
+__global__ void __launch_bounds__(256) kkt_lds2_kernel(
+    Geo g, const double* __restrict__ x, double* __restrict__ y, const double* __restrict__ c,
+    const double* __restrict__ alpha, const double* __restrict__ xscale, int xs_stride,
+    const int* __restrict__ active, double sgn, const double* __restrict__ ecoef, double ediag,
+    double eoff, int jchunk) {
+  constexpr int DIM = 2, NT = 256, TS = NT * PT;
+  constexpr int QW = PT + HQ;  // staging slots per thread: TS + 2 nx <= QW NT (nx <= 128 HQ)
+  extern __shared__ double kkt_sm[];
+  const int total = gridDim.x * gridDim.y * gridDim.z;
+  const int hw = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int lg = xcd_remap(hw, total);
+  const int bx = lg % gridDim.x;
+  const int by = (lg / gridDim.x) % gridDim.y;
+  const int b = lg / (gridDim.x * gridDim.y);
+  if (active && !active[b]) return;
+  const int nx = g.nx, n = g.n, m = g.m, H = nx;
+  const int W = TS + 2 * H;
+  double* s1 = kkt_sm;
+  double* s2 = kkt_sm + W;
+  const int i0 = bx * TS;
+  const int j0 = by * jchunk;
+  const int j1 = min(n, j0 + jchunk);
+  if (j0 >= j1) return;
+  const double a = alpha[b];
+  const double sc = xscale ? xscale[(size_t)b * xs_stride] : 1.0;
+  const size_t mb = (size_t)b * (size_t)g.vs;
+  const double* x1 = x + mb;
+  const double* x2 = x + mb + (size_t)n * m;
+  double* y1 = y + mb;
+  double* y2 = y + mb + (size_t)n * m;
+  const double* cc1 = RES ? c + mb : nullptr;
+  const double* cc2 = RES ? c + mb + (size_t)n * m : nullptr;
+
+  // A lane past the last point takes the last point (m - 1) and repeats its
+  // owner's arithmetic and stores (the same values to the same places), so
+  // that no store sits behind a per-lane branch: the wait for the next
+  // level's prefetched values then leaves this level's stores in flight.
+  StencilW sw[PT];
+  double x1prev[PT], pex2[PT], px1[PT];
+  int cr1[PT], cr2[PT], cr3[PT];  // grid coordinates of the thread's points
+  int ip[PT];                      // the thread's points (clamped)
+#pragma unroll
+  for (int r = 0; r < PT; ++r) {
+    const int ii = min(i0 + threadIdx.x + NT * r, m - 1);
+    ip[r] = ii;
+    cr1[r] = ii % nx;
+    cr2[r] = (ii / nx) % nx;
+    cr3[r] = 0;
+    sw[r] = load_stencil<DIM, VAR>(ii, m, ecoef, ediag, eoff);
+    x1prev[r] = (j0 > 0) ? x1[(size_t)(j0 - 1) * m + ii] : 0.0;
+    pex2[r] = px1[r] = 0.0;
+  }
+  // staging slot e holds point i0 - H + e (zero outside the grid); the
+  // loads use a clamped in-bounds index and the zeros are applied when the
+  // values are committed to LDS, so no select waits on a load
+  double p1[QW], p2[QW];
+  auto fetch = [&](int j) {
+    const size_t o = (size_t)j * m;
+#pragma unroll
+    for (int q = 0; q < QW; ++q) {
+      const int gi = min(max(i0 - H + (int)threadIdx.x + NT * q, 0), m - 1);
+      p1[q] = x1[o + gi];
+      p2[q] = x2[o + gi];
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int q = 0; q < QW; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int gi = i0 - H + e;
+      const bool ok = gi >= 0 && gi < m;
+      if (e < W) {
+        s1[e] = ok ? p1[q] : 0.0;
+        s2[e] = ok ? p2[q] : 0.0;
+      }
+    }
+  };
+  // block row 1 of level j: alpha x1 + T^T x2 with x2^{j+1} = x2n
+  auto finish_row1 = [&](int r, int j, int i, double x2n) {
+    double r1 = a * px1[r] + sgn * (pex2[r] - x2n);
+    r1 *= sc;
+    if constexpr (RES) r1 = cc1[(size_t)j * m + i] - r1;
+    y1[(size_t)j * m + i] = r1;
+  };
+  // level j's stencils; row 1 of level j - 1 is completed when FIRST is false
+  auto level = [&](int j, bool first) {
+    const size_t o = (size_t)j * m;
+#pragma unroll
+    for (int r = 0; r < PT; ++r) {
+      const int i = ip[r];
+      const int li = H + (i - i0);
+      const int c1 = cr1[r], c2 = cr2[r], c3 = cr3[r];
+      const double x2c = s2[li];
+      if (!first) finish_row1(r, j - 1, i, x2c);
+      const double ex2 = apply_E_lds<DIM, VAR>(s2, li, x2 + o, i, c1, c2, c3, nx, sw[r]);
+      const double ex1 = apply_E_lds<DIM, VAR>(s1, li, x1 + o, i, c1, c2, c3, nx, sw[r]);
+      const double x1c = s1[li];
+      // block row 2: -T x1 + alpha x2
+      double r2 = a * x2c - sgn * (ex1 - x1prev[r]);
+      r2 *= sc;
+      if constexpr (RES) r2 = cc2[o + i] - r2;
+      y2[o + i] = r2;
+      pex2[r] = ex2;
+      px1[r] = x1c;
+      x1prev[r] = x1c;
+    }
+  };
+  // the first level is peeled off the loop (no row 1 to complete), so that
+  // inside it every level follows the previous level's stores
+  fetch(j0);
+  commit();
+  __syncthreads();
+  if (j0 + 1 < j1) fetch(j0 + 1);
+  level(j0, true);
+  __syncthreads();
+  for (int j = j0 + 1; j < j1; ++j) {
+    commit();
+    __syncthreads();
+    if (j + 1 < j1) fetch(j + 1);
+    level(j, false);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < PT; ++r) finish_row1(r, j1 - 1, ip[r], (j1 < n) ? x2[(size_t)j1 * m + ip[r]] : 0.0);
+}
+
 void launch_kkt_apply(const Geo& g, const double* x, double* y, const double* c, const double* alpha,
                       const double* xscale, int xs_stride, const int* active, bool transpose,
                       const double* ecoef, double ediag, double eoff, int jchunk, hipStream_t st) {
@@ -248,8 +383,16 @@ void launch_kkt_apply(const Geo& g, const double* x, double* y, const double* c,
     const int jc = -jchunk;
     dim3 grid((g.m + 256 * PT - 1) / (256 * PT), (g.n + jc - 1) / jc, g.B);
     const size_t lds = 2 * sizeof(double) * (256 * PT + 2 * (size_t)g.nx);
-#define PCOP_KKT_LDS_H(D, V, HQ) \
-  kkt_lds_kernel<D, V, PT, HQ><<<grid, 256, lds, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn, ecoef, ediag, eoff, jc)
+#define PCOP_KKT_LDS_H(D, V, HQ)                                                                                  \
+  if (D == 3)                                                                                                     \
+    kkt_lds_kernel<3, V, PT, HQ><<<grid, 256, lds, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn, ecoef,  \
+                                                         ediag, eoff, jc);                                        \
+  else if (c)                                                                                                     \
+    kkt_lds2_kernel<V, PT, HQ, true><<<grid, 256, lds, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn,     \
+                                                             ecoef, ediag, eoff, jc);                             \
+  else                                                                                                            \
+    kkt_lds2_kernel<V, PT, HQ, false><<<grid, 256, lds, st>>>(g, x, y, c, alpha, xscale, xs_stride, active, sgn,    \
+                                                              ecoef, ediag, eoff, jc)
 #define PCOP_KKT_LDS(D, V)                                        \
   if (g.nx <= 256) PCOP_KKT_LDS_H(D, V, 2);                       \
   else if (g.nx <= 512) PCOP_KKT_LDS_H(D, V, 4);                  \
