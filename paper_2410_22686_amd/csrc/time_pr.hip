@@ -52,24 +52,21 @@ constexpr int pr_inv_mod(int a, int m) {
 
 // N1 x PR with a Rader stage of RC = PR - 1 = RA RB (generator G), or, with
 // RA = RB = 0, the PR-point DFTs directly in registers; CP / CN spatial
-// points per tile for the 256- / 512-thread kernels (time_cols 64 / -64),
-// CN32 for the 512-thread FP32 kernels
-template <int N1_, int PR_, int G_, int RA_, int RB_, int CP_, int CN_, int CN32_ = CN_>
+// points per tile for the 256- / 512-thread kernels (time_cols 64 / -64)
+template <int N1_, int PR_, int G_, int RA_, int RB_, int CP_, int CN_>
 struct PrPlan {
   static constexpr int N1 = N1_, PR = PR_, G = G_, RA = RA_, RB = RB_, RC = PR_ - 1, N = N1_ * PR_;
   static constexpr bool DIRECT = RA_ == 0;
-  static constexpr int CP = CP_, CN = CN_, CN32 = CN32_;
+  static constexpr int CP = CP_, CN = CN_;
   static constexpr int KM1 = PR_ * pr_inv_mod(PR_ % N1_, N1_);  // output map: k = (KM1 k1 + KM2 k2) mod N
   static constexpr int KM2 = N1_ * pr_inv_mod(N1_ % PR_, PR_);
   static_assert(DIRECT || RA * RB == PR_ - 1, "the convolution length splits as RA RB");
 };
-// 511 = 7 x 73, generator 5 of the group mod 73, 72 = 9 x 8.  The FP32
-// wide forward tile has 14 points: its 1022 stage-0 items take two rounds of
-// 512 threads (16 points take three, and the prefetch registers of the third
-// round spill under the 128-VGPR bound two blocks per CU need); FP64, and
-// the FP32 inverse, keep 16 points, whose output rows are whole 128-byte
-// lines
-using Pr511 = PrPlan<7, 73, 5, 9, 8, 8, 16, 14>;
+// 511 = 7 x 73, generator 5 of the group mod 73, 72 = 9 x 8.  Wide tiles
+// of 16 points (FP64, 512 threads: one block per CU); in FP32 the wide
+// kernels take 1024 threads with 28 points forward and 32 inverse (the
+// launcher below: stage-0 items in two rounds, longer row segments)
+using Pr511 = PrPlan<7, 73, 5, 9, 8, 8, 16>;
 // 127 prime, generator 3, 126 = 9 x 14
 using Pr127 = PrPlan<1, 127, 3, 9, 14, 16, 32>;
 // 255 = 15 x 17, generator 3 of the group mod 17, 16 = 4 x 4; tiles of 15
@@ -411,8 +408,9 @@ __device__ __forceinline__ void pr_rows(cx<T>* buf, const PrTables<T, PL>& tb, i
 }
 
 // FP32 with 512 threads: at least 4 waves per SIMD, so that two blocks share
-// a CU (their tiles fit LDS twice); the forward kernel then spills 4 registers
-// and still runs 1.2x faster than with one block (measured at n = 511)
+// a CU (their tiles fit LDS twice); measured at n = 511 (before its FP32
+// kernels took 1024-thread tiles), the forward kernel then spilled 4
+// registers and still ran 1.2x faster than with one block
 template <class T, int NT>
 constexpr int pr_min_waves() {
   return NT == 512 && sizeof(T) == 4 ? 4 : 1;
@@ -678,12 +676,21 @@ template <class T, class PL>
 static bool pr_launch_c(bool fwd, int c, const Geo& g, const double* v, cx<T>* spec, double* w,
                         const PrecondTables& tb, const double* vscale, int vs_stride, int accum, hipStream_t st) {
   if (c == -64) {
-    // the FP32 forward kernel takes the narrower CN32 tile; the inverse
-    // holds fewer registers per item and keeps the full CN tile, whose
-    // output rows are whole 128-byte lines in FP64 words
-    constexpr int CF = sizeof(T) == 4 ? PL::CN32 : PL::CN;
-    if (fwd) return pr_launch<T, PL, CF, 512, true>(g, v, spec, w, tb, vscale, vs_stride, accum, st);
-    return pr_launch<T, PL, PL::CN, 512, false>(g, v, spec, w, tb, vscale, vs_stride, accum, st);
+    if constexpr (sizeof(T) == 4 && PL::N == Pr511::N) {
+      // n = 511 in FP32: one 1024-thread block per CU with twice the points
+      // of the FP64 tile (114 / 131 KiB of LDS), so that each time level's
+      // row segment spans 224 / 256 bytes.  A level's row of m doubles starts
+      // 8 bytes further into a cache line than the previous one (m odd), so
+      // each segment shares a partly written line with the neighbouring
+      // tile at both ends; wider segments halve those shared lines.  The
+      // forward pass takes 28 points (2044 stage-0 items, two rounds of 1024
+      // threads; 32 points would take three and spill), the inverse 32.
+      if (fwd) return pr_launch<T, PL, 28, 1024, true>(g, v, spec, w, tb, vscale, vs_stride, accum, st);
+      return pr_launch<T, PL, 32, 1024, false>(g, v, spec, w, tb, vscale, vs_stride, accum, st);
+    } else {
+      if (fwd) return pr_launch<T, PL, PL::CN, 512, true>(g, v, spec, w, tb, vscale, vs_stride, accum, st);
+      return pr_launch<T, PL, PL::CN, 512, false>(g, v, spec, w, tb, vscale, vs_stride, accum, st);
+    }
   }
   if (fwd) return pr_launch<T, PL, PL::CP, 256, true>(g, v, spec, w, tb, vscale, vs_stride, accum, st);
   return pr_launch<T, PL, PL::CP, 256, false>(g, v, spec, w, tb, vscale, vs_stride, accum, st);
