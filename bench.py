@@ -159,7 +159,7 @@ def workload_name(cfg, legs, mass):
     return name + ("-q1" if mass == "q1" else "")
 
 
-def cpu_baseline(cfg, iters, budget_s, mass="identity"):
+def cpu_baseline(cfg, iters, budget_s, mass="identity", flexible=False):
     """Time the FP64 oracle on this host on a bounded sample of the workload
     and scale it to solves/s.
 
@@ -172,10 +172,14 @@ def cpu_baseline(cfg, iters, budget_s, mass="identity"):
     large, scaled).  A right-preconditioned solve of k iterations costs
     k (apply + matvec) + sum_{j<k} (j+1) MGS steps + one final apply, with
     apply = 4 dense DFTs + 2n LU solves (the four steps of Section 2.1);
-    factorisations are setup and excluded, as on the GPU."""
+    factorisations are setup and excluded, as on the GPU.  On the multigrid
+    workloads the spatial solve is the oracle's V-cycle (Section 3, Example
+    2), timed on a few of the frequency shifts, and the solve is flexible
+    GMRES: k (apply + matvec) + the MGS steps + k axpys for x = Z y."""
     import numpy as np
     from oracle import discretize as D, precond as P
     import scipy.sparse.linalg as spla
+    import workloads as W
 
     t_start = time.perf_counter()
     try:
@@ -185,12 +189,15 @@ def cpu_baseline(cfg, iters, budget_s, mass="identity"):
         threads = 1
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     gamma = cfg.gammas[0]
-    pb = D.make_problem(cfg.dim, cfg.nx, cfg.nt, gamma, T=cfg.T, eps=cfg.eps, mass=mass)
+    mg = cfg.spatial == "mg"
+    coeff = W.coeff_function(cfg.coeff) if cfg.coeff != "one" else None
+    pb = D.make_problem(cfg.dim, cfg.nx, cfg.nt, gamma, T=cfg.T, eps=cfg.eps, mass=mass, coeff=coeff)
     n, m = pb.n, pb.m
     # the sparse KKT matvec costs O(n m): time it on the same grid with 8 time
     # blocks (the oracle's assembly of the full matrix alone takes minutes)
     n_mv = min(8, n)
-    pb_mv = D.make_problem(cfg.dim, cfg.nx, n_mv + 1, gamma, T=cfg.T * (n_mv + 1) / cfg.nt, eps=pb.eps, mass=mass)
+    pb_mv = D.make_problem(cfg.dim, cfg.nx, n_mv + 1, gamma, T=cfg.T * (n_mv + 1) / cfg.nt, eps=pb.eps, mass=mass,
+                           coeff=coeff)
     A = D.kkt_scaled(pb_mv)
     rng = np.random.default_rng(0)
     x = rng.standard_normal(A.shape[0])
@@ -212,10 +219,28 @@ def cpu_baseline(cfg, iters, budget_s, mass="identity"):
     t_dft = (time.perf_counter() - t0) * (m / m_dft)
     del V
     lam = P.lambda_eps(n, pb.eps)
+    rhs = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    if mg:
+        # one V-cycle per shifted solve; the hierarchy is setup (excluded)
+        from oracle.multigrid import ShiftedVCycle
+        t0 = time.perf_counter()
+        vc = ShiftedVCycle(cfg.dim, cfg.nx, pb.tau, coeff)
+        t_fac = time.perf_counter() - t0
+        nfac, nlu, t_lu = 1, 0, 0.0
+        while nlu < n:
+            t0 = time.perf_counter()
+            vc.apply(rhs, lam[(nlu * 37) % n] + pb.alpha)
+            t_lu += time.perf_counter() - t0
+            nlu += 1
+            if time.perf_counter() - t_start > 0.6 * budget_s:
+                break
+        return _compose_cpu(cfg, iters, pb, t_start, threads, cores, t_mv, n_mv, t_dft, m_dft, t_lu / nlu, rng,
+                            flexible, mass,
+                            f"{nlu} of {2 * n} per-frequency V-cycles (Example 2's cycle, red-black smoother; "
+                            f"hierarchy setup {t_fac:.2f} s excluded)")
     Kc = pb.K.tocsc().astype(np.complex128)
     I = pb.Mm.tocsc().astype(np.complex128)  # M (the identity for finite differences)
     nfac, t_fac, t_lu, nlu = 0, 0.0, 0.0, 0
-    rhs = rng.standard_normal(m) + 1j * rng.standard_normal(m)
     while nfac < min(64, n):  # as many as fit about 60% of the time budget
         t0 = time.perf_counter()
         lu = spla.splu(((lam[nfac] + pb.alpha) * I + pb.tau * Kc).tocsc())
@@ -229,6 +254,16 @@ def cpu_baseline(cfg, iters, budget_s, mass="identity"):
         if time.perf_counter() - t_start > 0.6 * budget_s:
             break
     t_lu /= nlu
+    return _compose_cpu(cfg, iters, pb, t_start, threads, cores, t_mv, n_mv, t_dft, m_dft, t_lu, rng, flexible, mass,
+                        f"{nfac} of {n} per-frequency splu factorisations and {nlu} LU solves (factorisation: setup, "
+                        f"{t_fac / max(nfac, 1):.2f} s each, {n} needed, excluded)")
+
+
+def _compose_cpu(cfg, iters, pb, t_start, threads, cores, t_mv, n_mv, t_dft, m_dft, t_solve, rng, flexible, mass,
+                 solve_note):
+    """Compose the timed oracle pieces into solves/s (see cpu_baseline)."""
+    import numpy as np
+    n, m = pb.n, pb.m
     # one MGS step (a dot product and an axpy over a member vector): O(n m),
     # on at most 2^25 of the 2 n m values, scaled
     vlen = 2 * n * m
@@ -242,20 +277,21 @@ def cpu_baseline(cfg, iters, budget_s, mass="identity"):
         w = w - h * v
         times.append(time.perf_counter() - t0)
     t_mgs = min(times[1:]) * (vlen / vsub)
-    apply_s = 4 * t_dft + 2 * n * t_lu
+    apply_s = 4 * t_dft + 2 * n * t_solve
     total = 0.0
     for k in iters:
-        total += k * (apply_s + t_mv) + sum(j + 1 for j in range(k)) * t_mgs + apply_s
+        total += k * (apply_s + t_mv) + sum(j + 1 for j in range(k)) * t_mgs
+        total += k * t_mgs if flexible else apply_s  # x = Z y, or x = P^{-1} (V y)
     solves_per_s = len(iters) / total
+    kind = "flexible" if flexible else "right-preconditioned"
     return {
         "value": solves_per_s, "unit": "solves/s", "cores": int(threads), "host_cores_visible": int(cores),
         "kind": "oracle",
-        "sample": (f"FP64 NumPy/SciPy oracle pieces at full size ({cfg.name}, {mass} mass matrix, one member): {nfac} of {n} "
-                   f"per-frequency splu factorisations and {nlu} LU solves, the dense time-DFT product on {m_dft} of "
-                   f"{m} columns (scaled), sparse KKT matvecs on {n_mv} of {n} time blocks (scaled by {n}/{n_mv}), "
-                   f"one MGS step on {vsub} of {vlen} values (scaled); composed into {len(iters)} right-preconditioned "
-                   f"FP64 solves with the GPU's FP64 iteration counts {list(iters)}; factorisation (setup, "
-                   f"{t_fac / max(nfac, 1):.2f} s each, {n} needed) excluded"),
+        "sample": (f"FP64 NumPy/SciPy oracle pieces at full size ({cfg.name}, {mass} mass matrix, one member): "
+                   f"{solve_note}, the dense time-DFT product on {m_dft} of {m} columns (scaled), sparse KKT "
+                   f"matvecs on {n_mv} of {n} time blocks (scaled by {n}/{n_mv}), one MGS step on {vsub} of {vlen} "
+                   f"values (scaled); composed into {len(iters)} {kind} FP64 solves with the GPU's iteration "
+                   f"counts {list(iters)}"),
         "sample_wall_s": round(time.perf_counter() - t_start, 2),
         "per_apply_s": apply_s, "per_matvec_s": t_mv,
     }
@@ -434,13 +470,12 @@ def main():
         "precond_apply": {leg: precond_stats(stats_of[leg], opts_of[leg]["precision"], cfg) for leg in legs},
         "tune_cache": os.environ.get("PCOP_TUNE_CACHE"),
     }
-    if not args.no_cpu_baseline and cfg.spatial == "mg":
-        out["cpu_baseline"] = {"value": None, "note": "the oracle's multigrid path is timed only for the DST workloads"}
-    elif not args.no_cpu_baseline:
+    if not args.no_cpu_baseline:
         print("# bench: cpu baseline", file=sys.stderr, flush=True)
         iters = leg_out["fp64"]["iters"] if "fp64" in leg_out else leg_out[legs[0]]["iters"]
         try:
-            out["cpu_baseline"] = cpu_baseline(cfg, iters, args.cpu_sample_seconds, args.mass)
+            out["cpu_baseline"] = cpu_baseline(cfg, iters, args.cpu_sample_seconds, args.mass,
+                                               flexible=cfg.spatial == "mg")
         except Exception as e:  # pragma: no cover
             out["cpu_baseline"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
