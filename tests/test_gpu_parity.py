@@ -645,6 +645,38 @@ def test_graph_solve_matches_eager(chunk):
         torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("spatial,precision", [("mg", "fp64"), ("mg", "mixed"), ("dst", "mixed")])
+def test_graph_flexible_solve_matches_eager(spatial, precision):
+    """Graph mode on the flexible paths: the multigrid V-cycle (FP64 and
+    FP32) and the FP32 sine-transform preconditioner inside flexible GMRES,
+    replayed across solves with eager work in between, give the eager
+    iterates (no reductions by atomics, so the same kernels give the same
+    bits)."""
+    if spatial == "mg":
+        dim, nx, nt, gammas, coeff = 3, 7, 12, (1e-3, 1e-6), W.coeff_sines3d
+    else:
+        dim, nx, nt, gammas, coeff = 2, 15, 16, (1e-2, 1e-7), None
+    print(f"graph flexible {spatial} {precision} dim={dim} nx={nx} nt={nt}", flush=True)
+    fields = [W.random_fields(dim, nx, nt, seed=60 + b) for b in range(len(gammas))]
+    g = np.stack([fl[0] for fl in fields])
+    f = np.stack([fl[1] for fl in fields])
+    y0 = np.stack([fl[2] for fl in fields])
+    kw = dict(coeff=coeff, spatial=spatial, precision=precision, side="flexible", device=DEV)
+    se = Solver(dim, nx, nt, list(gammas), **kw)
+    xe, ie, he = se.solve(se.rhs(to_dev(g), to_dev(f), to_dev(y0)), history=True)
+    assert all(i.converged for i in ie)
+    sg = Solver(dim, nx, nt, list(gammas), graph=True, graph_chunk=3, **kw)
+    b = sg.rhs(to_dev(g), to_dev(f), to_dev(y0))
+    for rep in range(3):
+        xg, ig, hg = sg.solve(b, history=True)
+        for k in range(len(gammas)):
+            assert ig[k].converged and ig[k].iters == ie[k].iters, (rep, k, ig[k].iters, ie[k].iters)
+        assert rel(xg.cpu().numpy(), xe.cpu().numpy()) < 1e-14, rep
+        np.testing.assert_array_equal(np.nan_to_num(hg), np.nan_to_num(he))
+        sg.kkt_apply(b)  # eager work between replays
+        torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("dim,nx,nt", [(2, 1, 4), (2, 3, 5), (3, 3, 6), (2, 7, 33), (2, 15, 20)])
 def test_tuned_solve_tiny_shapes(dim, nx, nt):
     """With tune = 1 every kernel candidate runs on tiny shapes (a one-point
