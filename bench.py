@@ -20,7 +20,9 @@ Prints one JSON line.  Fields beyond the common contract:
   mixed_vs_fp64 -- ||x_mixed - x_fp64|| / ||x_fp64|| per member;
   roofline      -- the kernel family with the largest summed event time in
                    the timed region (both legs), its algorithmic bytes per
-                   launch over its mean launch duration, against 8 TB/s HBM;
+                   launch over its mean launch duration, against 8 TB/s HBM,
+                   and beside it (copy_GBs) the rate of a plain 1 GiB
+                   device copy timed after the timed region;
   precond_apply -- per leg, the same for the whole preconditioner apply;
   cpu_baseline  -- the FP64 oracle timed on this host on a bounded sample.
 
@@ -104,6 +106,8 @@ def parse():
                     help="workload: 1 2d-nx31-nt32, 2 2d-nx255-nt256, 3 2d-nx511-nt512 (default; FP64 and mixed "
                          "legs), 4 2d-nx127-nt128-batch64, 5 3d-nx63-nt128-vara-mg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-copy-ceiling", action="store_true",
+                    help="skip the plain device-copy rate reported beside the roofline")
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
                     help="run one leg in this precision (default: both legs on workload 3, the workload's own "
@@ -316,6 +320,25 @@ def precond_stats(stats, precision, cfg):
             "pass_bytes_per_member_apply": pre_bytes / member_applies}
 
 
+def copy_rate_gbs(dev, nbytes=1 << 30, reps=5):
+    """GB/s (read + write bytes) of torch's device copy of nbytes, the
+    average of reps copies timed with HIP events on the current stream."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def kernel_table(stats):
     return {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                 "GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
@@ -435,6 +458,12 @@ def main():
                 "traffic_unit": "bytes/launch",
                 "bytes_per_launch": dom_bytes_per_launch, "ms_per_launch": dom_ms_per_launch,
                 "launches": dom["launches"]}
+    if not args.no_copy_ceiling:
+        # what a plain device-to-device copy reaches on this GPU right now
+        # (outside the timed region): the streaming rate the kernels compete with
+        cp = copy_rate_gbs(dev)
+        roofline["copy_GBs"] = round(cp, 1)
+        roofline["frac_of_copy"] = round(achieved / cp, 4)
     leg_out = {}
     for leg in legs:
         n_solves = len(members) * args.steps
