@@ -273,9 +273,10 @@ def test_chirp_kernel_choices(dim, nx, nt, gammas, precision):
 
 
 PRIME_FACTOR_CASES = [
-    # dim, nx, nt, gammas: n = 511 = 7 x 73 (8- and 16-point tiles)
-    (2, 3, 512, (1e-6,)),          # m = 9: one full tile and a ragged one
-    (2, 7, 512, (1e-4, 1e-8)),     # m = 49: six full tiles and a ragged one, two members
+    # dim, nx, nt, gammas: n = 511 = 7 x 73 (8-point tiles, and 16-point ones
+    # in FP64 or 28 / 32-point ones with 1024 threads in FP32)
+    (2, 3, 512, (1e-6,)),          # m = 9: one full 8-point tile and a ragged one; one ragged wide tile
+    (2, 7, 512, (1e-4, 1e-8)),     # m = 49: six full 8-point tiles and a ragged one, two members; ragged wide tiles
     (3, 3, 512, (1e-3,)),          # 3-D, m = 27
     # n = 127 prime (16- and 32-point tiles, a 126-point Rader convolution)
     (2, 7, 128, (1e-4, 1e-8)),     # m = 49, ragged, two members
