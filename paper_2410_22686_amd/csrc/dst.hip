@@ -554,13 +554,13 @@ __global__ void __launch_bounds__(NT) dst_half_kernel(Geo g, cx<T>* __restrict__
   // 1-D eigenvalues: in LDS, so that the tile's loads are the only global loads in the loop
   __shared__ cx<T> twm[M];
   __shared__ T sinl[M];
-  __shared__ double mul[DIVIDE ? N : 1];
+  __shared__ T mul[DIVIDE ? N : 1];
   for (int k = threadIdx.x; k < M; k += NT) {
     twm[k] = twL[2 * k];
     sinl[k] = -twL[k].y;
   }
   if (DIVIDE)
-    for (int k = threadIdx.x; k < N; k += NT) mul[k] = dp.mu1[k];
+    for (int k = threadIdx.x; k < N; k += NT) mul[k] = (T)dp.mu1[k];
   __syncthreads();
   const long long tiles = (lg.lines + LPB - 1) / LPB;
   const long long total = tiles * lg.nplanes;
@@ -624,14 +624,32 @@ __global__ void __launch_bounds__(NT) dst_half_kernel(Geo g, cx<T>* __restrict__
         psl = dp.im1[line % g.nx];
         if (g.dim == 3) psl *= dp.im1[(line / g.nx) % g.nx];
       }
+      if constexpr (sizeof(T) == 4) {
+        // the FP32 preconditioner forms the shift factor in FP32 with the
+        // hardware reciprocal (about 1 ulp; the denominator is bounded away
+        // from zero and well inside the normal range)
+        const float srf = (float)sre, sif = (float)sim, tf = (float)g.tau, mlf = (float)ml;
+        const float cn = (float)(psl * dp.cnorm);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const int pos = 8 * t + r;
-        if (pos >= 1 && pos <= N && valid) {
-          const double dre = sre + g.tau * (ml + mul[pos - 1]);
-          const double psi = dp.im1 ? psl * dp.im1[pos - 1] : 1.0;
-          const double f = psi * dp.cnorm / (dre * dre + sim * sim);
-          o[r] = o[r] * cx<T>{(T)(f * dre), (T)(-f * sim)};
+        for (int r = 0; r < 8; ++r) {
+          const int pos = 8 * t + r;
+          if (pos >= 1 && pos <= N && valid) {
+            const float dre = srf + tf * (mlf + mul[pos - 1]);
+            const float psi = dp.im1 ? (float)dp.im1[pos - 1] : 1.0f;
+            const float f = psi * cn * recip(dre * dre + sif * sif);
+            o[r] = o[r] * cx<T>{f * dre, -f * sif};
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int pos = 8 * t + r;
+          if (pos >= 1 && pos <= N && valid) {
+            const double dre = sre + g.tau * (ml + mul[pos - 1]);
+            const double psi = dp.im1 ? psl * dp.im1[pos - 1] : 1.0;
+            const double f = psi * dp.cnorm / (dre * dre + sim * sim);
+            o[r] = o[r] * cx<T>{(T)(f * dre), (T)(-f * sim)};
+          }
         }
       }
       // the divided values become the input of the inverse transform
