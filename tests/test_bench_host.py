@@ -65,3 +65,14 @@ def test_recorded_traffic_needs_the_counted_kernel_choice():
     other = {leg: dict(ch, gs_update=3 - ch["gs_update"]) for leg, ch in choices.items()}
     assert bench.recorded_traffic(rec["workload"], fam, other) is None
     assert bench.recorded_traffic("no-such-workload", fam, choices) is None
+
+
+def test_paper_context_for_every_workload():
+    for cid in (1, 2, 3, 4, 5):
+        ctx = bench.paper_context(cid)
+        json.dumps(ctx)
+        assert "M4 Pro" in ctx["setup"] and ctx["rows"]
+        for row in ctx["rows"]:
+            assert row["iters"] > 0 and row["cpu_s"] > 0 and row["source"].startswith("Table")
+    # the workloads the paper has no run of say so
+    assert "not reported" in bench.paper_context(3)["note"]
