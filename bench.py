@@ -24,6 +24,8 @@ Prints one JSON line.  Fields beyond the common contract:
                    and beside it (copy_GBs) the rate of a plain 1 GiB
                    device copy timed after the timed region;
   precond_apply -- per leg, the same for the whole preconditioner apply;
+  whole_step    -- every timed kernel family's algorithmic bytes per step,
+                   over the summed kernel time and over the step's wall time;
   cpu_baseline  -- the FP64 oracle timed on this host on a bounded sample;
   paper         -- the paper's iteration counts and wall times at or nearest
                    to the workload, with the hardware they were measured on.
@@ -491,12 +493,23 @@ def main():
                 "traffic_unit": "bytes/launch",
                 "bytes_per_launch": dom_bytes_per_launch, "ms_per_launch": dom_ms_per_launch,
                 "launches": dom["launches"]}
+    # every timed family's algorithmic bytes over the step: their rate over
+    # the summed kernel time and over the step's wall time
+    # (with graphs the kernel table comes from one eager step after the timed region)
+    stat_steps = 1 if any(opts_of[leg]["graph"] for leg in legs) else args.steps
+    step_bytes = sum(v["bytes"] for v in total.values()) / stat_steps
+    step_kernel_ms = sum(v["ms"] for v in total.values()) / stat_steps
+    whole_step = {"algorithmic_GB": round(step_bytes / 1e9, 1),
+                  "GBs_over_kernel_time": round(step_bytes / (step_kernel_ms * 1e-3) / 1e9, 1),
+                  "GBs_over_wall_time": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+                  "kernel_ms": round(step_kernel_ms, 3)}
     if not args.no_copy_ceiling:
         # what a plain device-to-device copy reaches on this GPU right now
         # (outside the timed region): the streaming rate the kernels compete with
         cp = copy_rate_gbs(dev)
         roofline["copy_GBs"] = round(cp, 1)
         roofline["frac_of_copy"] = round(achieved / cp, 4)
+        whole_step["frac_of_copy"] = round(whole_step["GBs_over_wall_time"] / cp, 4)
     leg_out = {}
     for leg in legs:
         n_solves = len(members) * args.steps
@@ -530,6 +543,7 @@ def main():
         "converged": ok, "mixed_vs_fp64": mixed_vs_fp64, "legs": leg_out,
         "roofline": roofline,
         "precond_apply": {leg: precond_stats(stats_of[leg], opts_of[leg]["precision"], cfg) for leg in legs},
+        "whole_step": whole_step,
         "tune_cache": os.environ.get("PCOP_TUNE_CACHE"),
         "paper": paper_context(cfg.config_id),
     }
